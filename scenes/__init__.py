@@ -1,0 +1,159 @@
+"""Seeded synthetic inputs shared by the GPU library's tests/benchmarks and the oracle.
+
+This module only draws random numbers and arranges them into grid-shaped arrays.
+It holds none of the simulation method's arithmetic (no fractions, no
+advection, no projection).  Every array is float64 numpy in the canonical
+layout used throughout the project:
+
+* velocity: x-faces ``(nz, ny, nx+1)``, then y-faces ``(nz, ny+1, nx)``, then
+  z-faces ``(nz+1, ny, nx)``, each raveled with x fastest and concatenated;
+* cells: ``(nz, ny, nx)`` raveled with x fastest.
+
+Random-number recipe (numpy ``default_rng(seed)``, PCG64):
+
+* curl noise: a vector potential on MAC edges is drawn i.i.d. N(0,1) in the
+  order psi_x, psi_y, psi_z (C order over ``[k][j][i]``), blurred by a
+  separable Gaussian (sigma in cells, truncated at 4 sigma, reflecting at the
+  domain ends), its tangential components are zeroed on wall planes (so the
+  normal velocity on walls is zero), the discrete curl is taken on faces
+  (exactly divergence-free), and the field is scaled so max |u_f| = 1;
+* scene parameters are drawn after the noise, from the same generator.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.ndimage
+
+__all__ = [
+    "face_shapes", "n_faces", "curl_noise", "ellipsoid_theta0", "controls",
+    "sphere_center", "random_spheres", "face_noise", "Scene",
+    "scene_sphere_rollout", "scene_ellipsoid_rollout", "scene_spheres_projection",
+]
+
+
+def face_shapes(n):
+    nx, ny, nz = n
+    return [(nz, ny, nx + 1), (nz, ny + 1, nx), (nz + 1, ny, nx)]
+
+
+def n_faces(n):
+    return sum(int(np.prod(s)) for s in face_shapes(n))
+
+
+def _blur(a, sigma):
+    if sigma <= 0:
+        return a
+    return scipy.ndimage.gaussian_filter(a, sigma=sigma, mode="reflect", truncate=4.0)
+
+
+def curl_noise(n, dx, rng, sigma=2.0, walls=(True, True, True)):
+    """Discretely divergence-free random velocity, max |u_f| = 1 (float64, canonical).
+
+    ``walls[a]`` zeroes the potential's tangential components on both domain
+    planes normal to axis ``a`` so that the face velocity normal to them is 0.
+    """
+    nx, ny, nz = n
+    psx = _blur(rng.standard_normal((nz + 1, ny + 1, nx)), sigma)
+    psy = _blur(rng.standard_normal((nz + 1, ny, nx + 1)), sigma)
+    psz = _blur(rng.standard_normal((nz, ny + 1, nx + 1)), sigma)
+    if walls[0]:  # planes x = 0, x = X carry psi_y and psi_z
+        psy[:, :, 0] = psy[:, :, -1] = 0.0
+        psz[:, :, 0] = psz[:, :, -1] = 0.0
+    if walls[1]:  # planes y = 0, y = Y carry psi_x and psi_z
+        psx[:, 0, :] = psx[:, -1, :] = 0.0
+        psz[:, 0, :] = psz[:, -1, :] = 0.0
+    if walls[2]:  # planes z = 0, z = Z carry psi_x and psi_y
+        psx[0, :, :] = psx[-1, :, :] = 0.0
+        psy[0, :, :] = psy[-1, :, :] = 0.0
+    ux = (psz[:, 1:, :] - psz[:, :-1, :]) - (psy[1:, :, :] - psy[:-1, :, :])
+    uy = (psx[1:, :, :] - psx[:-1, :, :]) - (psz[:, :, 1:] - psz[:, :, :-1])
+    uz = (psy[:, :, 1:] - psy[:, :, :-1]) - (psx[:, 1:, :] - psx[:, :-1, :])
+    u = np.concatenate([ux.ravel(), uy.ravel(), uz.ravel()]) / dx
+    m = np.abs(u).max()
+    return u / m if m > 0 else u
+
+
+def sphere_center(rng, lo=0.35, hi=0.65):
+    return rng.uniform(lo, hi, size=3)
+
+
+def ellipsoid_theta0(rng):
+    """(centre c in U[0.35,0.65]^3, semi-axes a in U[0.08,0.2]^3, rotation vector r
+    uniform in the ball of radius pi), concatenated as 9 float64."""
+    c = rng.uniform(0.35, 0.65, size=3)
+    a = rng.uniform(0.08, 0.2, size=3)
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    r = d * (math.pi * rng.uniform() ** (1.0 / 3.0))
+    return np.concatenate([c, a, r])
+
+
+def controls(rng, steps, lo=-0.5, hi=0.5):
+    """Per-step rigid-body controls (v_x, v_y, v_z, w_x, w_y, w_z)."""
+    return rng.uniform(lo, hi, size=(steps, 6))
+
+
+def random_spheres(rng, count=20, rmin=0.03, rmax=0.1):
+    """(count, 4) array of (cx, cy, cz, r): centres U[0,1]^3, radii U[rmin, rmax]."""
+    c = rng.uniform(0.0, 1.0, size=(count, 3))
+    r = rng.uniform(rmin, rmax, size=(count, 1))
+    return np.concatenate([c, r], axis=1)
+
+
+def face_noise(n, rng, lo=-1.0, hi=1.0):
+    return rng.uniform(lo, hi, size=n_faces(n))
+
+
+@dataclass
+class Scene:
+    """A seeded scene: grid, time step, solid description and initial velocity."""
+    n: tuple
+    dx: float
+    dt: float
+    u0: np.ndarray
+    geom: str                       # "none" | "spheres" | "ellipsoid"
+    spheres: np.ndarray = None      # (m, 4) for geom == "spheres"
+    theta0: np.ndarray = None       # (9,) for geom == "ellipsoid"
+    ctrl: np.ndarray = None         # (steps, 6) for geom == "ellipsoid"
+    steps: int = 1
+    extra: dict = field(default_factory=dict)
+
+
+def scene_sphere_rollout(seed=0, n=32, steps=10):
+    """Closed unit box, static sphere r = 0.2 with centre in [0.35,0.65]^3,
+    curl-noise initial velocity (sigma = 2 cells), dt = dx/2."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    u0 = curl_noise((n, n, n), dx, rng)
+    c = sphere_center(rng)
+    sph = np.array([[c[0], c[1], c[2], 0.2]])
+    return Scene((n, n, n), dx, 0.5 * dx, u0, "spheres", spheres=sph, steps=steps)
+
+
+def scene_ellipsoid_rollout(seed=0, n=128, steps=64):
+    """Closed unit box with a moving ellipsoid (9 shape parameters, 6 controls per
+    step), curl-noise initial velocity, dt = dx/2.  The shape parameters and the
+    controls do not depend on ``n`` (same draws at every resolution)."""
+    rng = np.random.default_rng(seed)
+    theta0 = ellipsoid_theta0(rng)
+    ctrl = controls(rng, steps)
+    noise_rng = np.random.default_rng([seed, n])
+    dx = 1.0 / n
+    u0 = curl_noise((n, n, n), dx, noise_rng)
+    return Scene((n, n, n), dx, 0.5 * dx, u0, "ellipsoid", theta0=theta0, ctrl=ctrl,
+                 steps=steps)
+
+
+def scene_spheres_projection(seed=0, n=256, count=20):
+    """Closed unit box with ``count`` static overlapping spheres.  The field to be
+    projected is curl noise plus U[-1,1] noise on every face (adding the noise on
+    faces, before the weighted divergence, keeps every connected fluid pocket's
+    right-hand side compatible without labelling pockets)."""
+    rng = np.random.default_rng(seed)
+    sph = random_spheres(rng, count)
+    dx = 1.0 / n
+    u = curl_noise((n, n, n), dx, rng) + face_noise((n, n, n), rng)
+    return Scene((n, n, n), dx, 0.5 * dx, u, "spheres", spheres=sph, steps=1)
