@@ -1,0 +1,185 @@
+/*
+ * neuralfluid.h -- C ABI of the MI355X (gfx950) library for one differentiable
+ * Navier-Stokes step on a 3D staggered (MAC) grid with cut-cell solids.
+ *
+ * Method: NeuralFluid (arXiv 2405.14903), Sec. "Differentiable Navier-Stokes
+ * Simulation": operator splitting into semi-Lagrangian advection
+ * (Eq. advection_matrix; two-stage back-trace of App. B, Eqs. advection_1/2),
+ * an optional body force (App. B, Eq. apply_force), and a variational pressure
+ * projection with per-face fluid fractions alpha (Eq. projection_matrix,
+ * Eq. u_next_matrix), solved matrix-free by multigrid-preconditioned CG; plus
+ * the adjoint of each stage (Sec. "Back-propagation through Time" and
+ * "Back-propagation through Geometry").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: n = (nx, ny, nz) cells of width dx; cell (i,j,k) centre at
+ * ((i+1/2)dx, (j+1/2)dx, (k+1/2)dx).  Layouts (all x fastest):
+ *   cells    : i + nx*(j + ny*k)                       (nx*ny*nz values)
+ *   velocity : x-faces (nx+1)*ny*nz, then y-faces nx*(ny+1)*nz, then
+ *              z-faces nx*ny*(nz+1), concatenated; x-face (i,j,k) sits at
+ *              (i dx, (j+1/2)dx, (k+1/2)dx) and lies between cells i-1 and i.
+ * Pressure scaling: with k = dt/(rho dx), the step solves
+ *   (G^T S G) P = G^T (S U^ + (I-S) U_s) / k,   U^{n+1} = U^ - k G P
+ * where (G p)_f = p(cell on the + side) - p(cell on the - side) and a ghost
+ * pressure 0 lies beyond OUTFLOW sides.  Faces with alpha = 0 take the solid
+ * (or wall / inflow) velocity.
+ *
+ * Memory: every float / double array argument named u_*, p_*, b, x, alpha,
+ * g_* is DEVICE memory owned by the caller.  theta and ctrl are HOST double
+ * arrays read at call time.  sim_stats is a host struct (nullable).
+ * Streams: work is enqueued on the caller's hipStream_t (0 = null stream).
+ * Calls that solve a Poisson system wait on that stream for the solver's
+ * convergence checks; the final kernels of a call may still be running when it
+ * returns (synchronise the stream before reading outputs).
+ * Errors: arguments are validated before anything is enqueued; a negative
+ * status means nothing was launched.  Non-convergence and non-finite values
+ * are reported in sim_stats (status SIM_OK).  No exception crosses the ABI.
+ * Threading: a handle is not thread-safe; use one handle per concurrent
+ * episode.  Distinct handles may be used from distinct threads and streams.
+ */
+#ifndef NEURALFLUID_H
+#define NEURALFLUID_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_ctx* sim_handle;
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_EINVAL = -1,        /* invalid argument or descriptor               */
+  SIM_ENOMEM = -2,        /* device allocation failed in sim_create       */
+  SIM_EHIP = -3,          /* a HIP runtime call failed                    */
+  SIM_EUNSUPPORTED = -4   /* valid request this library does not implement */
+} sim_status;
+
+typedef enum { SIM_FP32 = 0, SIM_MIXED_FP16 = 1, SIM_MIXED_BF16 = 2 } sim_precision;
+
+/* Kind of each domain side (order: x-, x+, y-, y+, z-, z+).
+ * WALL: closed, no-penetration (alpha = 0, u_s = 0).  INFLOW: alpha = 0 and
+ * the normal velocity is inflow_speed into the domain.  OUTFLOW: Dirichlet
+ * p = 0 beyond the side (App. B, Eq. bd:dirichlet).  PERIODIC is reserved. */
+typedef enum { SIM_BC_WALL = 0, SIM_BC_INFLOW = 1, SIM_BC_OUTFLOW = 2, SIM_BC_PERIODIC = 3 } sim_bc;
+
+/* Solid description (Sec. Projection: the SDF phi and the solid velocity u_s
+ * come from the geometry; phi > 0 is fluid).
+ *  SIM_GEOM_NONE      : no solid (alpha = 1 except on WALL/INFLOW sides).
+ *  SIM_GEOM_SPHERES   : static union of m spheres; theta = m x (cx,cy,cz,r),
+ *                       n_params = 4m (m <= SIM_MAX_SPHERES); u_s = 0.
+ *  SIM_GEOM_ELLIPSOID : rigid ellipsoid; theta (15) = centre c(3), semi-axes
+ *                       a(3), rotation R(9, row-major, body -> world);
+ *                       phi = k0 (k0 - 1)/k1 with p = R^T (x - c),
+ *                       k0 = |p/a|, k1 = |p/a^2|; ctrl (6) = (v, w),
+ *                       u_s(x) = v + w x (x - c).                          */
+typedef enum { SIM_GEOM_NONE = 0, SIM_GEOM_SPHERES = 1, SIM_GEOM_ELLIPSOID = 2 } sim_geom;
+
+#define SIM_MAX_SPHERES 32
+
+typedef struct {
+  int32_t n[3];           /* cells per axis                                   */
+  double dx;              /* cell width                                       */
+  double dt;              /* time step                                        */
+  double rho;             /* density (k = dt/(rho dx))                        */
+  double nu;              /* kinematic viscosity: must be 0 (unsupported)     */
+  double gravity[3];      /* body force added to every face: U^ += dt g       */
+  int32_t bc[6];          /* sim_bc per side                                  */
+  double inflow_speed;    /* speed on INFLOW sides                            */
+  int32_t precision;      /* sim_precision of the multigrid preconditioner    */
+  double tol;             /* relative residual target ||b - A x|| / ||b||     */
+  int32_t max_iter;       /* CG iteration cap                                 */
+  int32_t geom;           /* sim_geom                                         */
+  int32_t n_params;       /* length of theta                                  */
+  int32_t n_ctrl;         /* length of ctrl                                   */
+} sim_desc;
+
+typedef struct {
+  int32_t iters;          /* CG iterations taken                              */
+  int32_t converged;      /* 1 if the recursive residual reached tol          */
+  int32_t nonfinite;      /* 1 if a NaN/Inf was met in the residual           */
+  int32_t pad;
+  double rel_res;         /* recursive relative residual (FP64 norm)          */
+  double true_rel_res;    /* ||b - A x|| / ||b|| recomputed in FP64 at the end */
+} sim_stats;
+
+/* Static description of the library build (for loaders / tests). */
+const char* sim_version(void);
+const char* sim_status_string(int32_t status);
+
+/* Device bytes sim_create would allocate for desc (host only; no allocation).
+ * Used for admission control.  Returns SIM_EINVAL for an invalid desc. */
+int32_t sim_footprint(const sim_desc* desc, size_t* bytes);
+
+/* Allocate all workspace for desc on the current HIP device.  Grid sizes must
+ * coarsen by halving to a level of at most 4096 cells (e.g. multiples of 16).
+ * nu != 0 or PERIODIC sides return SIM_EUNSUPPORTED. */
+int32_t sim_create(const sim_desc* desc, sim_handle* out);
+int32_t sim_destroy(sim_handle h);
+
+/* Sizes (in elements) of the velocity and cell arrays of this handle. */
+int32_t sim_layout(sim_handle h, size_t* vel_elems, size_t* cell_elems);
+
+/* One step n -> n+1 (Eqs. advection_matrix, projection_matrix, u_next_matrix).
+ * u_n, u_n1: velocity (float, distinct).  theta: geometry at time n+1,
+ * ctrl: solid velocity controls for this step (host doubles; may be NULL when
+ * n_params / n_ctrl are 0).  p_n1: optional cell pressure output (NULL: kept
+ * inside the handle).  The solve starts from P = 0. */
+int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const double* ctrl,
+                 float* u_n1, float* p_n1, sim_stats* st, hipStream_t stream);
+
+/* Projection only (Eqs. projection_matrix, u_next_matrix) of a given face
+ * field u_in (no advection, no body force): u_out = projected field. */
+int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const double* ctrl,
+                    float* u_out, float* p_out, sim_stats* st, hipStream_t stream);
+
+/* Adjoint of sim_step (Sec. Back-propagation through Time / Geometry).
+ * Inputs: u_n (the step's input), u_n1 (its output), theta, ctrl (as given to
+ * sim_step), g_u_n1 = dJ/dU^{n+1}.  Output: g_u_n = dJ/dU^n (overwritten;
+ * must not alias g_u_n1).  g_theta (n_params doubles) and g_ctrl (n_ctrl
+ * doubles), device, are ACCUMULATED (+=) with this step's direct partials
+ * dJ/dtheta and dJ/dctrl (SIM_GEOM_ELLIPSOID only; NULL to skip).  The
+ * adjoint pressure system is solved with the same operator (it is symmetric).
+ * Float atomics make g_u_n reproducible only to rounding. */
+int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* u_n1, const double* theta,
+                         const double* ctrl, const float* g_u_n1, float* g_u_n, double* g_theta,
+                         double* g_ctrl, sim_stats* st, hipStream_t stream);
+
+/* Solve (G^T S G) x = b (unit scale) by MGPCG to relative residual tol (<= 0:
+ * desc.tol) within max_iter (<= 0: desc.max_iter) iterations.  alpha: face
+ * fractions (velocity layout) or NULL to reuse the fractions of the last
+ * geometry this handle evaluated (sim_step / sim_project / sim_set_geometry).
+ * x: initial guess on entry, solution on exit.  On domains without an OUTFLOW
+ * side, b must sum to zero over every connected fluid region (compatible);
+ * x is then defined up to a constant per region. */
+int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x, double tol,
+                      int32_t max_iter, sim_stats* st, hipStream_t stream);
+
+/* Evaluate the geometry (phi at nodes, alpha per face) for theta / ctrl and
+ * optionally copy alpha out (velocity layout, may be NULL). */
+int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, float* alpha_out,
+                         hipStream_t stream);
+
+/* Rigid ellipsoid pose dynamics (host, FP64).  theta0 (9) = centre c0(3),
+ * semi-axes a(3), rotation vector r0(3); R0 = exp([r0]x).  For step n with
+ * ctrl[n] = (v, w): c^{n+1} = c^n + dt v, R^{n+1} = exp([dt w]x) R^n.
+ * Writes theta_steps[n*15 .. n*15+14] = (c^{n+1}, a, R^{n+1}) for n < T. */
+int32_t sim_ellipsoid_poses(const double* theta0, const double* ctrl, int32_t T, double dt,
+                            double* theta_steps);
+
+/* Adjoint of sim_ellipsoid_poses: given per-step direct partials
+ * g_theta_steps (T x 15) and g_ctrl_direct (T x 6), writes dJ/dtheta0 (9) and
+ * the total dJ/dctrl (T x 6). */
+int32_t sim_ellipsoid_poses_adjoint(const double* theta0, const double* ctrl, int32_t T, double dt,
+                                    const double* g_theta_steps, const double* g_ctrl_direct,
+                                    double* g_theta0, double* g_ctrl);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEURALFLUID_H */

@@ -1,0 +1,472 @@
+// C ABI of the library: handle management, argument validation and the
+// orchestration of one step (NeuralFluid, Sec. Numerical Simulation:
+// advection -> body force -> projection) and of its adjoint (Sec.
+// Back-propagation through Time: projection first, then advection), plus the
+// host-side rigid pose dynamics used to drive the ellipsoid.
+#include "nf_solver.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+using namespace nf;
+
+struct sim_ctx {
+  sim_desc desc;
+  Domain dom;
+  int device = 0;
+  Solver S;
+  // fine-grid buffers
+  float* alpha = nullptr;   // face fractions (velocity layout)
+  double* phi = nullptr;    // SDF at nodes
+  float* uhat = nullptr;    // advected field
+  float* gu = nullptr;      // dJ/dU^ (adjoint)
+  float* b = nullptr;       // right-hand side
+  float* P = nullptr;       // pressure (when the caller passes none)
+  float* y = nullptr;       // adjoint pressure
+  std::vector<void*> allocs;
+  GeomParams last_geom;
+  bool have_geom = false;
+};
+
+namespace {
+
+struct Plan {
+  int nlev = 0;
+  Dims dims[kMaxLevels];
+  size_t bytes = 0;
+};
+
+bool plan_levels(const sim_desc* d, Plan& p) {
+  Dims cur{d->n[0], d->n[1], d->n[2]};
+  p.nlev = 0;
+  p.dims[p.nlev++] = cur;
+  while (p.nlev < kMaxLevels && cur.nx % 2 == 0 && cur.ny % 2 == 0 && cur.nz % 2 == 0 && cur.nx >= 4 &&
+         cur.ny >= 4 && cur.nz >= 4) {
+    cur = Dims{cur.nx / 2, cur.ny / 2, cur.nz / 2};
+    p.dims[p.nlev++] = cur;
+  }
+  return p.dims[p.nlev - 1].cells() <= (size_t)kCoarseMaxCells;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int validate_desc(const sim_desc* d) {
+  if (!d) return SIM_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (d->n[a] < 2 || d->n[a] > 4096) return SIM_EINVAL;
+  if ((long)d->n[0] * d->n[1] * d->n[2] > (1L << 30)) return SIM_EINVAL;
+  if (!(d->dx > 0) || !(d->dt > 0) || !(d->rho > 0) || !(d->tol > 0) || d->max_iter <= 0) return SIM_EINVAL;
+  if (d->precision < SIM_FP32 || d->precision > SIM_MIXED_BF16) return SIM_EINVAL;
+  for (int s = 0; s < 6; ++s) {
+    if (d->bc[s] < SIM_BC_WALL || d->bc[s] > SIM_BC_PERIODIC) return SIM_EINVAL;
+    if (d->bc[s] == SIM_BC_PERIODIC) return SIM_EUNSUPPORTED;
+  }
+  if (d->nu != 0.0) return SIM_EUNSUPPORTED;
+  if (!std::isfinite(d->gravity[0]) || !std::isfinite(d->gravity[1]) || !std::isfinite(d->gravity[2]))
+    return SIM_EINVAL;
+  switch (d->geom) {
+    case SIM_GEOM_NONE:
+      if (d->n_params != 0 || d->n_ctrl != 0) return SIM_EINVAL;
+      break;
+    case SIM_GEOM_SPHERES:
+      if (d->n_params < 4 || d->n_params % 4 || d->n_params > 4 * SIM_MAX_SPHERES || d->n_ctrl != 0)
+        return SIM_EINVAL;
+      break;
+    case SIM_GEOM_ELLIPSOID:
+      if (d->n_params != 15 || d->n_ctrl != 6) return SIM_EINVAL;
+      break;
+    default:
+      return SIM_EINVAL;
+  }
+  Plan p;
+  if (!plan_levels(d, p)) return SIM_EINVAL;
+  return SIM_OK;
+}
+
+// Every device buffer of a handle, in allocation order.  `alloc` is called
+// with the byte size and the address of the pointer to fill.
+template <typename F>
+void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
+  const Dims& d0 = p.dims[0];
+  const size_t C = d0.cells(), F_ = d0.faces();
+  const size_t es = d->precision == SIM_FP32 ? 4 : 2;
+  alloc(F_ * 4, (void**)&t->alpha);
+  alloc(d0.nodes() * 8, (void**)&t->phi);
+  alloc(F_ * 4, (void**)&t->uhat);
+  alloc(F_ * 4, (void**)&t->gu);
+  alloc(C * 4, (void**)&t->b);
+  alloc(C * 4, (void**)&t->P);
+  alloc(C * 4, (void**)&t->y);
+  alloc(C * 4, (void**)&t->S.r);
+  alloc(C * 4, (void**)&t->S.z);
+  alloc(C * 4, (void**)&t->S.q);
+  alloc(C * 4, (void**)&t->S.p0);
+  alloc(C * 4, (void**)&t->S.p1);
+  size_t nb_faces = (F_ + kBlock - 1) / kBlock, nb_cells = (C + kBlock - 1) / kBlock;
+  size_t npart = nb_faces * 21 > nb_cells * 2 ? nb_faces * 21 : nb_cells * 2;
+  alloc(npart * 8, (void**)&t->S.partials);
+  alloc(sizeof(CGScalars), (void**)&t->S.sc);
+  for (int l = 0; l < p.nlev; ++l) {
+    const Dims& dl = p.dims[l];
+    Level& L = t->S.lev[l];
+    if (l > 0 || d->precision != SIM_FP32) {
+      alloc(dl.nfx() * es, &L.a[0]);
+      alloc(dl.nfy() * es, &L.a[1]);
+      alloc(dl.nfz() * es, &L.a[2]);
+    }
+    alloc(dl.cells() * es, &L.invd);
+    if (l > 0) {
+      alloc(dl.cells() * es, &L.r);
+      alloc(dl.cells() * es, &L.z);
+    }
+    alloc(dl.cells() * es, &L.ta);
+    alloc(dl.cells() * es, &L.tb);
+  }
+  if (d->precision != SIM_FP32) {
+    size_t tot = 0;
+    for (int l = 1; l < p.nlev; ++l) {
+      t->S.scratch_off[l] = tot;
+      tot += p.dims[l].faces();
+    }
+    alloc((tot ? tot : 1) * 4, (void**)&t->S.scratch_a);
+    alloc(C * 4, (void**)&t->S.scratch_inv);
+  }
+}
+
+int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g) {
+  std::memset(&g, 0, sizeof(g));
+  g.kind = c->desc.geom;
+  if (g.kind == SIM_GEOM_SPHERES) {
+    if (!theta) return SIM_EINVAL;
+    g.nsph = c->desc.n_params / 4;
+    for (int s = 0; s < 4 * g.nsph; ++s) {
+      if (!std::isfinite(theta[s])) return SIM_EINVAL;
+      g.sph[s] = theta[s];
+    }
+  } else if (g.kind == SIM_GEOM_ELLIPSOID) {
+    if (!theta || !ctrl) return SIM_EINVAL;
+    for (int s = 0; s < 15; ++s)
+      if (!std::isfinite(theta[s])) return SIM_EINVAL;
+    for (int s = 0; s < 6; ++s)
+      if (!std::isfinite(ctrl[s])) return SIM_EINVAL;
+    for (int s = 0; s < 3; ++s) {
+      g.c[s] = theta[s];
+      g.a[s] = theta[3 + s];
+      if (!(g.a[s] > 0)) return SIM_EINVAL;
+      g.v[s] = ctrl[s];
+      g.w[s] = ctrl[3 + s];
+    }
+    for (int s = 0; s < 9; ++s) g.R[s] = theta[6 + s];
+  }
+  return SIM_OK;
+}
+
+int last_hip_error() { return hipGetLastError() == hipSuccess ? SIM_OK : SIM_EHIP; }
+
+void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st) {
+  launch_phi_nodes(c->dom, g, c->phi, st);
+  launch_alpha(c->dom, c->phi, c->alpha, st);
+  solver_setup_levels(c->S, c->alpha, st);
+  c->last_geom = g;
+  c->have_geom = true;
+}
+
+double k_factor(const sim_desc& d) { return d.dt / (d.rho * d.dx); }
+
+}  // namespace
+
+extern "C" {
+
+const char* sim_version(void) { return "neuralfluid-gfx950 1.0"; }
+
+const char* sim_status_string(int32_t s) {
+  switch (s) {
+    case SIM_OK: return "ok";
+    case SIM_EINVAL: return "invalid argument";
+    case SIM_ENOMEM: return "device allocation failed";
+    case SIM_EHIP: return "HIP runtime error";
+    case SIM_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+int32_t sim_footprint(const sim_desc* desc, size_t* bytes) {
+  int v = validate_desc(desc);
+  if (v != SIM_OK) return v;
+  if (!bytes) return SIM_EINVAL;
+  Plan p;
+  plan_levels(desc, p);
+  size_t tot = 0;
+  sim_ctx tmp;
+  for_each_buffer(desc, p, &tmp, [&](size_t b, void**) { tot += align256(b); });
+  *bytes = tot;
+  return SIM_OK;
+}
+
+int32_t sim_create(const sim_desc* desc, sim_handle* out) {
+  int v = validate_desc(desc);
+  if (v != SIM_OK) return v;
+  if (!out) return SIM_EINVAL;
+  sim_ctx* c = new (std::nothrow) sim_ctx();
+  if (!c) return SIM_ENOMEM;
+  c->desc = *desc;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+  Plan p;
+  plan_levels(desc, p);
+  c->dom.d = p.dims[0];
+  for (int s = 0; s < 6; ++s) c->dom.bc[s] = desc->bc[s];
+  c->dom.dx = desc->dx;
+  c->dom.inflow = desc->inflow_speed;
+  c->S.nlev = p.nlev;
+  c->S.precision = desc->precision;
+  for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
+  bool ok = true;
+  for_each_buffer(desc, p, c, [&](size_t b, void** ptr) {
+    if (!ok) return;
+    void* q = nullptr;
+    if (hipMalloc(&q, align256(b)) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    c->allocs.push_back(q);
+    *ptr = q;
+  });
+  if (ok && hipHostMalloc((void**)&c->S.host_sc, sizeof(CGScalars), hipHostMallocDefault) != hipSuccess) ok = false;
+  if (ok && hipMemset(c->S.sc, 0, sizeof(CGScalars)) != hipSuccess) ok = false;
+  if (!ok) {
+    (void)hipGetLastError();
+    sim_destroy(c);
+    return SIM_ENOMEM;
+  }
+  *out = c;
+  return SIM_OK;
+}
+
+int32_t sim_destroy(sim_handle h) {
+  if (!h) return SIM_EINVAL;
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->S.host_sc) (void)hipHostFree(h->S.host_sc);
+  delete h;
+  return SIM_OK;
+}
+
+int32_t sim_layout(sim_handle h, size_t* vel_elems, size_t* cell_elems) {
+  if (!h) return SIM_EINVAL;
+  if (vel_elems) *vel_elems = h->dom.d.faces();
+  if (cell_elems) *cell_elems = h->dom.d.cells();
+  return SIM_OK;
+}
+
+int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, float* alpha_out,
+                         hipStream_t stream) {
+  if (!h) return SIM_EINVAL;
+  GeomParams g;
+  int v = make_geom(h, theta, ctrl, g);
+  if (v != SIM_OK) return v;
+  eval_geometry(h, g, stream);
+  if (alpha_out &&
+      hipMemcpyAsync(alpha_out, h->alpha, h->dom.d.faces() * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return SIM_EHIP;
+  return last_hip_error();
+}
+
+static int32_t project_common(sim_handle h, const float* uhat, const GeomParams& g, float* u_out, float* p_out,
+                              sim_stats* st, hipStream_t stream) {
+  const double kk = k_factor(h->desc);
+  launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream);
+  float* P = p_out ? p_out : h->P;
+  launch_fill(P, h->dom.d.cells(), 0.0f, stream);
+  int r = solver_solve(h->S, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
+  if (r != SIM_OK) return r;
+  launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream);
+  return last_hip_error();
+}
+
+int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const double* ctrl, float* u_n1, float* p_n1,
+                 sim_stats* st, hipStream_t stream) {
+  if (!h || !u_n || !u_n1 || u_n == u_n1) return SIM_EINVAL;
+  GeomParams g;
+  int v = make_geom(h, theta, ctrl, g);
+  if (v != SIM_OK) return v;
+  eval_geometry(h, g, stream);
+  launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream);
+  return project_common(h, h->uhat, g, u_n1, p_n1, st, stream);
+}
+
+int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const double* ctrl, float* u_out,
+                    float* p_out, sim_stats* st, hipStream_t stream) {
+  if (!h || !u_in || !u_out || u_in == u_out) return SIM_EINVAL;
+  GeomParams g;
+  int v = make_geom(h, theta, ctrl, g);
+  if (v != SIM_OK) return v;
+  eval_geometry(h, g, stream);
+  return project_common(h, u_in, g, u_out, p_out, st, stream);
+}
+
+int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* u_n1, const double* theta, const double* ctrl,
+                         const float* g_u_n1, float* g_u_n, double* g_theta, double* g_ctrl, sim_stats* st,
+                         hipStream_t stream) {
+  if (!h || !u_n || !u_n1 || !g_u_n1 || !g_u_n || g_u_n == g_u_n1) return SIM_EINVAL;
+  GeomParams g;
+  int v = make_geom(h, theta, ctrl, g);
+  if (v != SIM_OK) return v;
+  const bool grad = h->desc.geom == SIM_GEOM_ELLIPSOID && (g_theta || g_ctrl);
+  eval_geometry(h, g, stream);
+  // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T M g
+  launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream);
+  launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
+  int r = solver_solve(h->S, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
+  if (r != SIM_OK) return r;
+  launch_adj_faces(h->dom, g, grad, h->alpha, h->phi, g_u_n1, h->y, u_n1, h->gu, h->S.partials,
+                   &h->S.sc->ticket[5], g_theta, g_ctrl, stream);
+  launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->gu, g_u_n, stream);
+  return last_hip_error();
+}
+
+int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x, double tol, int32_t max_iter,
+                      sim_stats* st, hipStream_t stream) {
+  if (!h || !b || !x) return SIM_EINVAL;
+  if (!alpha && !h->have_geom) return SIM_EINVAL;
+  if (alpha) {
+    if (hipMemcpyAsync(h->alpha, alpha, h->dom.d.faces() * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+      return SIM_EHIP;
+    solver_setup_levels(h->S, h->alpha, stream);
+    h->have_geom = true;
+  }
+  int r = solver_solve(h->S, b, x, tol > 0 ? tol : h->desc.tol, max_iter > 0 ? max_iter : h->desc.max_iter, st,
+                       stream);
+  if (r != SIM_OK) return r;
+  return last_hip_error();
+}
+
+// ---------------------------------------------------------------------------
+// rigid pose dynamics (host, FP64)
+// ---------------------------------------------------------------------------
+
+static void skew3(const double v[3], double K[9]) {
+  K[0] = 0; K[1] = -v[2]; K[2] = v[1];
+  K[3] = v[2]; K[4] = 0; K[5] = -v[0];
+  K[6] = -v[1]; K[7] = v[0]; K[8] = 0;
+}
+
+static void matmul3(const double A[9], const double B[9], double C[9]) {
+  double T[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) T[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+  std::memcpy(C, T, sizeof(T));
+}
+
+// exp([r]x) by the Rodrigues formula.
+static void expmap(const double r[3], double R[9]) {
+  double t = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  for (int i = 0; i < 9; ++i) R[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  if (t == 0.0) return;
+  double K[9], K2[9];
+  skew3(r, K);
+  matmul3(K, K, K2);
+  double s = std::sin(t) / t, c = (1.0 - std::cos(t)) / (t * t);
+  for (int i = 0; i < 9; ++i) R[i] += s * K[i] + c * K2[i];
+}
+
+// dR/dr_i of the exponential map (Gallego & Yezzi 2015):
+// (r_i [r]x + [r x ((I - R) e_i)]x) R / |r|^2, and [e_i]x at r = 0.
+static void expmap_grad(const double r[3], double dR[3][9]) {
+  double t2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  for (int i = 0; i < 3; ++i) {
+    double e[3] = {0, 0, 0};
+    e[i] = 1.0;
+    if (t2 == 0.0) {
+      skew3(e, dR[i]);
+      continue;
+    }
+    double R[9], K[9];
+    expmap(r, R);
+    skew3(r, K);
+    double ImRe[3];
+    for (int a = 0; a < 3; ++a) ImRe[a] = e[a] - R[3 * a + i];
+    double cr[3] = {r[1] * ImRe[2] - r[2] * ImRe[1], r[2] * ImRe[0] - r[0] * ImRe[2],
+                    r[0] * ImRe[1] - r[1] * ImRe[0]};
+    double Kc[9], M[9];
+    skew3(cr, Kc);
+    for (int a = 0; a < 9; ++a) M[a] = (r[i] * K[a] + Kc[a]) / t2;
+    matmul3(M, R, dR[i]);
+  }
+}
+
+int32_t sim_ellipsoid_poses(const double* theta0, const double* ctrl, int32_t T, double dt, double* out) {
+  if (!theta0 || (!ctrl && T > 0) || !out || T < 0) return SIM_EINVAL;
+  double c[3] = {theta0[0], theta0[1], theta0[2]};
+  double R[9];
+  expmap(theta0 + 6, R);
+  for (int n = 0; n < T; ++n) {
+    const double* v = ctrl + 6 * n;
+    double rw[3] = {dt * v[3], dt * v[4], dt * v[5]}, E[9];
+    expmap(rw, E);
+    for (int a = 0; a < 3; ++a) c[a] += dt * v[a];
+    matmul3(E, R, R);
+    double* o = out + 15 * n;
+    for (int a = 0; a < 3; ++a) {
+      o[a] = c[a];
+      o[3 + a] = theta0[3 + a];
+    }
+    for (int a = 0; a < 9; ++a) o[6 + a] = R[a];
+  }
+  return SIM_OK;
+}
+
+int32_t sim_ellipsoid_poses_adjoint(const double* theta0, const double* ctrl, int32_t T, double dt,
+                                    const double* g_steps, const double* g_ctrl_direct, double* g_theta0,
+                                    double* g_ctrl) {
+  if (!theta0 || !g_theta0 || T < 0 || (T > 0 && (!ctrl || !g_steps || !g_ctrl_direct || !g_ctrl)))
+    return SIM_EINVAL;
+  std::vector<double> poses((size_t)15 * (T > 0 ? T : 1));
+  if (T > 0) sim_ellipsoid_poses(theta0, ctrl, T, dt, poses.data());
+  double R0[9];
+  expmap(theta0 + 6, R0);
+  double gc[3] = {0, 0, 0}, ga[3] = {0, 0, 0}, gR[9] = {0};
+  for (int n = T - 1; n >= 0; --n) {
+    const double* gs = g_steps + 15 * n;
+    const double* v = ctrl + 6 * n;
+    for (int a = 0; a < 3; ++a) {
+      gc[a] += gs[a];
+      ga[a] += gs[3 + a];
+    }
+    for (int a = 0; a < 9; ++a) gR[a] += gs[6 + a];
+    double* go = g_ctrl + 6 * n;
+    for (int a = 0; a < 6; ++a) go[a] = g_ctrl_direct[6 * n + a];
+    // c^{n+1} = c^n + dt v^n
+    for (int a = 0; a < 3; ++a) go[a] += dt * gc[a];
+    // R^{n+1} = E R^n, E = exp([dt w]x): dJ/dE = gR R^n^T, dJ/dR^n = E^T gR
+    const double* Rn = n > 0 ? poses.data() + 15 * (n - 1) + 6 : R0;
+    double rw[3] = {dt * v[3], dt * v[4], dt * v[5]}, E[9], dE[3][9];
+    expmap(rw, E);
+    expmap_grad(rw, dE);
+    double gE[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) gE[3 * i + j] = gR[3 * i] * Rn[3 * j] + gR[3 * i + 1] * Rn[3 * j + 1] +
+                                                 gR[3 * i + 2] * Rn[3 * j + 2];
+    for (int q = 0; q < 3; ++q) {
+      double s = 0;
+      for (int a = 0; a < 9; ++a) s += dE[q][a] * gE[a];
+      go[3 + q] += dt * s;
+    }
+    double nR[9];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) nR[3 * i + j] = E[i] * gR[j] + E[3 + i] * gR[3 + j] + E[6 + i] * gR[6 + j];
+    std::memcpy(gR, nR, sizeof(nR));
+  }
+  double dR0[3][9];
+  expmap_grad(theta0 + 6, dR0);
+  for (int a = 0; a < 3; ++a) {
+    g_theta0[a] = gc[a];
+    g_theta0[3 + a] = ga[a];
+    double s = 0;
+    for (int q = 0; q < 9; ++q) s += dR0[a][q] * gR[q];
+    g_theta0[6 + a] = s;
+  }
+  return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,204 @@
+// Geometry: signed distance at grid nodes, per-face fluid fractions by 2D
+// marching squares, and the multigrid hierarchy of face fractions.
+//
+// NeuralFluid, Sec. Projection (cut-cell paragraph): alpha_f is the fluid
+// share of face f, from the zero contour of the solid SDF phi (phi > 0 fluid)
+// intersected with the face; the printed one-fluid-corner case is
+// alpha = 1/2 * phi_A/(phi_A - phi_B) * phi_A/(phi_A - phi_D).  The other
+// corner configurations use the same linear edge intersections; a saddle is
+// resolved by the sign of the corner mean.  phi and alpha are evaluated in
+// FP64 so that the decision alpha > 0 (which selects the update of a face) is
+// taken in double precision; alpha is then stored in FP32 and never rounded
+// down to zero when positive.
+#include "nf_internal.h"
+
+namespace nf {
+
+__device__ inline double phi_at(const GeomParams& G, double x, double y, double z) {
+  if (G.kind == SIM_GEOM_SPHERES) {
+    double best = 1e300;
+    for (int s = 0; s < G.nsph; ++s) {
+      double dx = x - G.sph[4 * s], dy = y - G.sph[4 * s + 1], dz = z - G.sph[4 * s + 2];
+      double d = sqrt(dx * dx + dy * dy + dz * dz) - G.sph[4 * s + 3];
+      best = d < best ? d : best;
+    }
+    return best;
+  }
+  if (G.kind == SIM_GEOM_ELLIPSOID) {
+    double r0 = x - G.c[0], r1 = y - G.c[1], r2 = z - G.c[2];
+    // p = R^T r (R maps body to world)
+    double p0 = G.R[0] * r0 + G.R[3] * r1 + G.R[6] * r2;
+    double p1 = G.R[1] * r0 + G.R[4] * r1 + G.R[7] * r2;
+    double p2 = G.R[2] * r0 + G.R[5] * r1 + G.R[8] * r2;
+    double q0 = p0 / G.a[0], q1 = p1 / G.a[1], q2 = p2 / G.a[2];
+    double s0 = q0 / G.a[0], s1 = q1 / G.a[1], s2 = q2 / G.a[2];
+    double k0 = sqrt(q0 * q0 + q1 * q1 + q2 * q2);
+    double k1 = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
+    if (k1 == 0.0) {
+      double m = G.a[0] < G.a[1] ? G.a[0] : G.a[1];
+      return -(m < G.a[2] ? m : G.a[2]);
+    }
+    return k0 * (k0 - 1.0) / k1;
+  }
+  return 1.0;
+}
+
+__global__ void k_phi_nodes(Dims d, double dx, GeomParams G, double* __restrict__ phi) {
+  long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  long total = (long)d.nodes();
+  if (n >= total) return;
+  int sx = d.nx + 1, sy = d.ny + 1;
+  int i = (int)(n % sx);
+  long t = n / sx;
+  int j = (int)(t % sy);
+  int k = (int)(t / sy);
+  phi[n] = phi_at(G, i * dx, j * dx, k * dx);
+}
+
+// Fraction along an edge from the corner with value a to the sign change.
+__device__ inline double edge_t(double a, double b) { return a / (a - b); }
+
+// Marching-squares fluid fraction of a face with cyclic corner values p[0..3].
+__device__ inline double face_fraction(const double p[4]) {
+  int f[4], cnt = 0;
+  for (int q = 0; q < 4; ++q) {
+    f[q] = p[q] > 0.0;
+    cnt += f[q];
+  }
+  if (cnt == 0) return 0.0;
+  if (cnt == 4) return 1.0;
+  if (cnt == 1 || cnt == 3) {
+    // the odd corner k: fluid if cnt == 1, solid if cnt == 3
+    int k = 0;
+    for (int q = 0; q < 4; ++q)
+      if (f[q] == (cnt == 1)) k = q;
+    double a = p[k], b = p[(k + 1) & 3], dd = p[(k + 3) & 3];
+    double tri = 0.5 * edge_t(a, b) * edge_t(a, dd);
+    return cnt == 1 ? tri : 1.0 - tri;
+  }
+  // two fluid corners
+  for (int k = 0; k < 4; ++k) {
+    if (f[k] && f[(k + 1) & 3]) {
+      double a0 = p[k], a1 = p[(k + 1) & 3], a2 = p[(k + 2) & 3], a3 = p[(k + 3) & 3];
+      return 0.5 * (edge_t(a0, a3) + edge_t(a1, a2));
+    }
+  }
+  // diagonal pair: k and k+2 fluid
+  int k = f[0] ? 0 : 1;
+  double a0 = p[k], a1 = p[(k + 1) & 3], a2 = p[(k + 2) & 3], a3 = p[(k + 3) & 3];
+  double mean = 0.25 * (a0 + a1 + a2 + a3);
+  if (mean > 0.0)
+    return 1.0 - 0.5 * edge_t(a1, a0) * edge_t(a1, a2) - 0.5 * edge_t(a3, a0) * edge_t(a3, a2);
+  return 0.5 * edge_t(a0, a1) * edge_t(a0, a3) + 0.5 * edge_t(a2, a1) * edge_t(a2, a3);
+}
+
+// Cyclic corner node values of face (comp, i, j, k).
+__device__ inline void face_corners(const Dims& d, const double* __restrict__ phi, int comp, int i,
+                                    int j, int k, double p[4]) {
+  if (comp == 0) {
+    p[0] = phi[d.node(i, j, k)];
+    p[1] = phi[d.node(i, j + 1, k)];
+    p[2] = phi[d.node(i, j + 1, k + 1)];
+    p[3] = phi[d.node(i, j, k + 1)];
+  } else if (comp == 1) {
+    p[0] = phi[d.node(i, j, k)];
+    p[1] = phi[d.node(i + 1, j, k)];
+    p[2] = phi[d.node(i + 1, j, k + 1)];
+    p[3] = phi[d.node(i, j, k + 1)];
+  } else {
+    p[0] = phi[d.node(i, j, k)];
+    p[1] = phi[d.node(i + 1, j, k)];
+    p[2] = phi[d.node(i + 1, j + 1, k)];
+    p[3] = phi[d.node(i, j + 1, k)];
+  }
+}
+
+__device__ inline float store_fraction(double a) {
+  float f = (float)a;
+  if (a > 0.0 && !(f > 0.0f)) f = 1.17549435e-38f;  // keep alpha > 0 decisions exact
+  return f;
+}
+
+__global__ void k_alpha(Domain D, const double* __restrict__ phi, float* __restrict__ alpha) {
+  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long)D.d.faces()) return;
+  int comp, i, j, k;
+  face_decode(D.d, f, comp, i, j, k);
+  int own = comp == 0 ? i : (comp == 1 ? j : k);
+  int sk = side_kind(D, comp, own);
+  if (sk == SIM_BC_WALL || sk == SIM_BC_INFLOW) {
+    alpha[f] = 0.0f;
+    return;
+  }
+  double p[4];
+  face_corners(D.d, phi, comp, i, j, k, p);
+  alpha[f] = store_fraction(face_fraction(p));
+}
+
+// Inverse diagonal of G^T S G on one level: 1 / sum(alpha over the 6 faces), 0
+// for inactive cells.
+__global__ void k_invdiag(Dims d, const float* __restrict__ ax, const float* __restrict__ ay,
+                          const float* __restrict__ az, float* __restrict__ invd) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i = (int)(c % d.nx);
+  long t = c / d.nx;
+  int j = (int)(t % d.ny);
+  int k = (int)(t / d.ny);
+  float s = ax[d.fx(i, j, k)] + ax[d.fx(i + 1, j, k)] + ay[d.fy(i, j, k)] + ay[d.fy(i, j + 1, k)] +
+            az[d.fz(i, j, k)] + az[d.fz(i, j, k + 1)];
+  invd[c] = s > 0.0f ? 1.0f / s : 0.0f;
+}
+
+// Coarse face fractions: a coarse face covers 2 x 2 fine faces; its weight is
+// kCoarseAlphaScale times their sum (the piecewise-constant Galerkin operator
+// scaled by 1/2).
+__global__ void k_coarsen_alpha(Dims fd, Dims cd, const float* __restrict__ fax,
+                                const float* __restrict__ fay, const float* __restrict__ faz,
+                                float* __restrict__ cax, float* __restrict__ cay,
+                                float* __restrict__ caz) {
+  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long)cd.faces()) return;
+  int comp, I, J, K;
+  face_decode(cd, f, comp, I, J, K);
+  float s;
+  if (comp == 0) {
+    int i = 2 * I, j = 2 * J, k = 2 * K;
+    s = fax[fd.fx(i, j, k)] + fax[fd.fx(i, j + 1, k)] + fax[fd.fx(i, j, k + 1)] +
+        fax[fd.fx(i, j + 1, k + 1)];
+    cax[cd.fx(I, J, K)] = kCoarseAlphaScale * s;
+  } else if (comp == 1) {
+    int i = 2 * I, j = 2 * J, k = 2 * K;
+    s = fay[fd.fy(i, j, k)] + fay[fd.fy(i + 1, j, k)] + fay[fd.fy(i, j, k + 1)] +
+        fay[fd.fy(i + 1, j, k + 1)];
+    cay[cd.fy(I, J, K)] = kCoarseAlphaScale * s;
+  } else {
+    int i = 2 * I, j = 2 * J, k = 2 * K;
+    s = faz[fd.fz(i, j, k)] + faz[fd.fz(i + 1, j, k)] + faz[fd.fz(i, j + 1, k)] +
+        faz[fd.fz(i + 1, j + 1, k)];
+    caz[cd.fz(I, J, K)] = kCoarseAlphaScale * s;
+  }
+}
+
+static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+void launch_phi_nodes(const Domain& D, const GeomParams& G, double* phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_phi_nodes, dim3(nblocks(D.d.nodes())), dim3(kBlock), 0, s, D.d, D.dx, G, phi);
+}
+
+void launch_alpha(const Domain& D, const double* phi, float* alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_alpha, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, phi, alpha);
+}
+
+void launch_invdiag(const Dims& d, const float* ax, const float* ay, const float* az, float* invd,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_invdiag, dim3(nblocks(d.cells())), dim3(kBlock), 0, s, d, ax, ay, az, invd);
+}
+
+void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, const float* fay,
+                          const float* faz, float* cax, float* cay, float* caz, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarsen_alpha, dim3(nblocks(cd.faces())), dim3(kBlock), 0, s, fd, cd, fax, fay,
+                     faz, cax, cay, caz);
+}
+
+}  // namespace nf

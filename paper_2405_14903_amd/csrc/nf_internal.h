@@ -1,0 +1,206 @@
+// Internal types and device helpers of the gfx950 MAC-grid library.
+// Layouts are those documented in neuralfluid.h (x fastest, velocity =
+// x-faces | y-faces | z-faces).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "neuralfluid.h"
+
+namespace nf {
+
+constexpr int kBlock = 256;          // 4 waves of 64 lanes
+constexpr int kMaxLevels = 12;
+constexpr int kCoarseMaxCells = 4096;
+constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coarse correction
+constexpr float kOmega = 0.8f;
+constexpr int kCoarseSweeps = 40;
+constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces
+
+struct Dims {
+  int nx, ny, nz;
+  __host__ __device__ size_t cells() const { return (size_t)nx * ny * nz; }
+  __host__ __device__ size_t nfx() const { return (size_t)(nx + 1) * ny * nz; }
+  __host__ __device__ size_t nfy() const { return (size_t)nx * (ny + 1) * nz; }
+  __host__ __device__ size_t nfz() const { return (size_t)nx * ny * (nz + 1); }
+  __host__ __device__ size_t faces() const { return nfx() + nfy() + nfz(); }
+  __host__ __device__ size_t nodes() const { return (size_t)(nx + 1) * (ny + 1) * (nz + 1); }
+  __host__ __device__ int c(int i, int j, int k) const { return i + nx * (j + ny * k); }
+  __host__ __device__ int fx(int i, int j, int k) const { return i + (nx + 1) * (j + ny * k); }
+  __host__ __device__ int fy(int i, int j, int k) const { return i + nx * (j + (ny + 1) * k); }
+  __host__ __device__ int fz(int i, int j, int k) const { return i + nx * (j + ny * k); }
+  __host__ __device__ int node(int i, int j, int k) const { return i + (nx + 1) * (j + (ny + 1) * k); }
+};
+
+// Geometry parameters, passed by value to kernels.
+struct GeomParams {
+  int kind;                    // sim_geom
+  int nsph;
+  double sph[4 * SIM_MAX_SPHERES];
+  double c[3], a[3], R[9], v[3], w[3];
+};
+
+struct Domain {
+  Dims d;
+  int bc[6];
+  double dx;
+  double inflow;
+};
+
+// Face fractions and inverse diagonal of one multigrid level.
+struct LevelView {
+  Dims d;
+  const float* ax;
+  const float* ay;
+  const float* az;
+  const float* invd;
+};
+
+// CG scalars kept on the device (no host round trip per iteration).
+struct CGScalars {
+  double rho;        // r . z
+  double alpha;      // step length
+  double beta;       // direction update
+  double rr;         // r . r
+  double bb;         // b . b
+  double tol2bb;     // tol^2 * b . b
+  double true_rr;    // ||b - A x||^2 recomputed in FP64
+  int iters;
+  int done;
+  int first;
+  int nonfinite;
+  int maxit;
+  int pad;
+  unsigned ticket[8];   // last-block counters of the reducing kernels
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+
+// Map the hardware workgroup order (round-robin over the 8 XCDs) to a logical
+// order in which each XCD owns one contiguous run of tiles, so neighbouring
+// tiles (which share halo data) hit the same L2.
+__device__ inline int xcd_block(int b, int nb) {
+  const int nx = 8;
+  int q = nb / nx, r = nb % nx;
+  int x = b % nx, s = b / nx;
+  return x * q + (x < r ? x : r) + s;
+}
+
+__device__ inline int side_kind(const Domain& D, int d, int own) {
+  int nd = d == 0 ? D.d.nx : (d == 1 ? D.d.ny : D.d.nz);
+  if (own == 0) return D.bc[2 * d];
+  if (own == nd) return D.bc[2 * d + 1];
+  return -1;
+}
+
+// Normal component of the solid velocity at face (d, i, j, k), with the
+// domain-side overrides (WALL: 0, INFLOW: speed into the domain).
+__device__ inline double face_solid_velocity(const Domain& D, const GeomParams& G, int d, int i,
+                                             int j, int k) {
+  int own = d == 0 ? i : (d == 1 ? j : k);
+  int sk = side_kind(D, d, own);
+  if (sk == SIM_BC_WALL) return 0.0;
+  if (sk == SIM_BC_INFLOW) return own == 0 ? D.inflow : -D.inflow;
+  if (G.kind != SIM_GEOM_ELLIPSOID) return 0.0;
+  double x[3] = {(i + (d == 0 ? 0.0 : 0.5)) * D.dx, (j + (d == 1 ? 0.0 : 0.5)) * D.dx,
+                 (k + (d == 2 ? 0.0 : 0.5)) * D.dx};
+  double r0 = x[0] - G.c[0], r1 = x[1] - G.c[1], r2 = x[2] - G.c[2];
+  if (d == 0) return G.v[0] + G.w[1] * r2 - G.w[2] * r1;
+  if (d == 1) return G.v[1] + G.w[2] * r0 - G.w[0] * r2;
+  return G.v[2] + G.w[0] * r1 - G.w[1] * r0;
+}
+
+// Decode a flat velocity index into (component, i, j, k).
+__device__ inline void face_decode(const Dims& d, long f, int& comp, int& i, int& j, int& k) {
+  long nfx = (long)d.nfx(), nfy = (long)d.nfy();
+  if (f < nfx) {
+    comp = 0;
+    int sx = d.nx + 1;
+    i = (int)(f % sx);
+    long t = f / sx;
+    j = (int)(t % d.ny);
+    k = (int)(t / d.ny);
+  } else if (f < nfx + nfy) {
+    comp = 1;
+    f -= nfx;
+    i = (int)(f % d.nx);
+    long t = f / d.nx;
+    j = (int)(t % (d.ny + 1));
+    k = (int)(t / (d.ny + 1));
+  } else {
+    comp = 2;
+    f -= nfx + nfy;
+    i = (int)(f % d.nx);
+    long t = f / d.nx;
+    j = (int)(t % d.ny);
+    k = (int)(t / d.ny);
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Fixed-order block sum of N doubles per thread (deterministic).  Result valid
+// in thread 0.  `sh` must hold N * (kBlock / 64) doubles.
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) sh[q * (kBlock / 64) + wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) s += sh[q * (kBlock / 64) + w];
+      v[q] = s;
+    }
+  }
+}
+
+// Write this block's N partial sums; the last block to arrive sums all
+// partials in fixed order and returns true (thread 0 then holds the totals in
+// `tot`).  The ticket counter is reset by the last block.
+template <int N>
+__device__ inline bool grid_sum(double (&v)[N], double* partials, unsigned* ticket, double (&tot)[N]) {
+  __shared__ double sh[N * (kBlock / 64) + 1];
+  __shared__ int last;
+  block_sum<N>(v, sh);
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) partials[(size_t)q * nb + blockIdx.x] = v[q];
+    __threadfence();
+    unsigned t = atomicAdd(ticket, 1u);
+    last = (t == (unsigned)nb - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double acc[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)q * nb + b];
+    acc[q] = s;
+  }
+  __syncthreads();
+  block_sum<N>(acc, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) tot[q] = acc[q];
+    *ticket = 0u;
+  }
+  return true;
+}
+
+}  // namespace nf

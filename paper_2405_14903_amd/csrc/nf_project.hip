@@ -1,0 +1,342 @@
+// Pressure projection with cut-cell fractions and its adjoint.
+//
+// NeuralFluid, Sec. Projection: with S = diag(alpha), k = dt/(rho dx),
+//   Eq. projection_matrix:  k G^T S G P = G^T S U^ + G^T (I - S) U_s
+//   Eq. u_next_matrix:      U^{n+1} = U^ - k G P
+// (faces with alpha = 0 take the solid velocity).  The unit-scaled system
+// (G^T S G) P = b / k is solved by the MGPCG in nf_solver.hip.
+//
+// Adjoint (Sec. Back-propagation through Time, Projection paragraph, and Sec.
+// Back-propagation through Geometry), derived as the exact transpose of the
+// forward with M = diag(alpha > 0) and g = dJ/dU^{n+1}:
+//   (G^T S G) y = -G^T M g          (the k factors cancel)
+//   dJ/dU^      = M g + S G y
+//   dJ/dU_s     = (I - M) g + (I - S) G y
+//   dJ/dalpha_f = (G y)_f (U^{n+1}_f - U_s,f)
+// and dJ/dalpha, dJ/dU_s are carried to the ellipsoid's pose and controls
+// through the marching-squares fraction and the rigid velocity field.
+#include "nf_internal.h"
+
+namespace nf {
+
+__device__ inline void cell_decode(const Dims& d, long c, int& i, int& j, int& k) {
+  i = (int)(c % d.nx);
+  long t = c / d.nx;
+  j = (int)(t % d.ny);
+  k = (int)(t / d.ny);
+}
+
+// Flux alpha u + (1 - alpha) u_s through face f of component comp.
+__device__ inline double face_flux(const Domain& D, const GeomParams& G, const float* __restrict__ alpha,
+                                   const float* __restrict__ u, long f, int comp, int i, int j, int k) {
+  float a = alpha[f];
+  double fl = (double)a * (double)u[f];
+  if (a < 1.0f) fl += (1.0 - (double)a) * face_solid_velocity(D, G, comp, i, j, k);
+  return fl;
+}
+
+// b_c / k = (sum over lower faces - sum over upper faces of the flux) / k.
+__global__ __launch_bounds__(kBlock) void k_rhs(Domain D, GeomParams G, float inv_k,
+                                                 const float* __restrict__ alpha,
+                                                 const float* __restrict__ uhat, float* __restrict__ b) {
+  const Dims& d = D.d;
+  long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cell_decode(d, c, i, j, k);
+  long oy = (long)d.nfx(), oz = oy + (long)d.nfy();
+  double s = face_flux(D, G, alpha, uhat, d.fx(i, j, k), 0, i, j, k) -
+             face_flux(D, G, alpha, uhat, d.fx(i + 1, j, k), 0, i + 1, j, k) +
+             face_flux(D, G, alpha, uhat, oy + d.fy(i, j, k), 1, i, j, k) -
+             face_flux(D, G, alpha, uhat, oy + d.fy(i, j + 1, k), 1, i, j + 1, k) +
+             face_flux(D, G, alpha, uhat, oz + d.fz(i, j, k), 2, i, j, k) -
+             face_flux(D, G, alpha, uhat, oz + d.fz(i, j, k + 1), 2, i, j, k + 1);
+  b[c] = (float)s * inv_k;
+}
+
+// Pressure of the cells on both sides of face (comp, i, j, k); 0 beyond the
+// domain (the Dirichlet ghost; on WALL / INFLOW sides alpha = 0 hides it).
+__device__ inline void face_cells(const Dims& d, const float* __restrict__ p, int comp, int i, int j,
+                                  int k, float& pp, float& pm) {
+  if (comp == 0) {
+    pp = i < d.nx ? p[d.c(i, j, k)] : 0.0f;
+    pm = i > 0 ? p[d.c(i - 1, j, k)] : 0.0f;
+  } else if (comp == 1) {
+    pp = j < d.ny ? p[d.c(i, j, k)] : 0.0f;
+    pm = j > 0 ? p[d.c(i, j - 1, k)] : 0.0f;
+  } else {
+    pp = k < d.nz ? p[d.c(i, j, k)] : 0.0f;
+    pm = k > 0 ? p[d.c(i, j, k - 1)] : 0.0f;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(Domain D, GeomParams G, float kk,
+                                                    const float* __restrict__ alpha,
+                                                    const float* __restrict__ uhat,
+                                                    const float* __restrict__ p, float* __restrict__ out) {
+  const Dims& d = D.d;
+  long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (f >= (long)d.faces()) return;
+  int comp, i, j, k;
+  face_decode(d, f, comp, i, j, k);
+  if (alpha[f] > 0.0f) {
+    float pp, pm;
+    face_cells(d, p, comp, i, j, k, pp, pm);
+    out[f] = uhat[f] - kk * (pp - pm);
+  } else {
+    out[f] = (float)face_solid_velocity(D, G, comp, i, j, k);
+  }
+}
+
+// rhs_c = -(G^T M g)_c
+__global__ __launch_bounds__(kBlock) void k_adj_div(Dims d, const float* __restrict__ alpha,
+                                                     const float* __restrict__ g, float* __restrict__ rhs) {
+  long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cell_decode(d, c, i, j, k);
+  long oy = (long)d.nfx(), oz = oy + (long)d.nfy();
+  long f[6] = {d.fx(i, j, k), d.fx(i + 1, j, k), oy + d.fy(i, j, k), oy + d.fy(i, j + 1, k),
+               oz + d.fz(i, j, k), oz + d.fz(i, j, k + 1)};
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    float m = alpha[f[q]] > 0.0f ? g[f[q]] : 0.0f;
+    s += (q & 1) ? -m : m;
+  }
+  rhs[c] = -s;
+}
+
+// ---- geometry partials (FP64) --------------------------------------------
+
+__device__ inline double et(double a, double b) { return a / (a - b); }
+__device__ inline void det(double a, double b, double& da, double& db) {
+  double den = (a - b) * (a - b);
+  da = -b / den;
+  db = a / den;
+}
+
+// d alpha / d phi for the 4 cyclic corners (same cases as the forward).
+__device__ inline void fraction_grad(const double p[4], double g[4]) {
+  int f[4], cnt = 0;
+  for (int q = 0; q < 4; ++q) {
+    f[q] = p[q] > 0.0;
+    cnt += f[q];
+    g[q] = 0.0;
+  }
+  if (cnt == 0 || cnt == 4) return;
+  if (cnt == 1 || cnt == 3) {
+    int k = 0;
+    for (int q = 0; q < 4; ++q)
+      if (f[q] == (cnt == 1)) k = q;
+    int kb = (k + 1) & 3, kd = (k + 3) & 3;
+    double a = p[k], b = p[kb], dd = p[kd];
+    double tb = et(a, b), td = et(a, dd), da1, db, da2, ddd;
+    det(a, b, da1, db);
+    det(a, dd, da2, ddd);
+    double sg = cnt == 1 ? 0.5 : -0.5;
+    g[k] = sg * (da1 * td + tb * da2);
+    g[kb] = sg * db * td;
+    g[kd] = sg * tb * ddd;
+    return;
+  }
+  for (int k = 0; k < 4; ++k) {
+    if (f[k] && f[(k + 1) & 3]) {
+      int k1 = (k + 1) & 3, k2 = (k + 2) & 3, k3 = (k + 3) & 3;
+      double d0, d3, d1, d2;
+      det(p[k], p[k3], d0, d3);
+      det(p[k1], p[k2], d1, d2);
+      g[k] = 0.5 * d0;
+      g[k3] = 0.5 * d3;
+      g[k1] = 0.5 * d1;
+      g[k2] = 0.5 * d2;
+      return;
+    }
+  }
+  int k = f[0] ? 0 : 1;
+  int k1 = (k + 1) & 3, k2 = (k + 2) & 3, k3 = (k + 3) & 3;
+  double a0 = p[k], a1 = p[k1], a2 = p[k2], a3 = p[k3];
+  if (0.25 * (a0 + a1 + a2 + a3) > 0.0) {
+    // 1 - 1/2 t(a1,a0) t(a1,a2) - 1/2 t(a3,a0) t(a3,a2)
+    double s10 = et(a1, a0), s12 = et(a1, a2), s30 = et(a3, a0), s32 = et(a3, a2);
+    double x1a, x0a, x1b, x2b, x3a, x0c, x3b, x2c;
+    det(a1, a0, x1a, x0a);
+    det(a1, a2, x1b, x2b);
+    det(a3, a0, x3a, x0c);
+    det(a3, a2, x3b, x2c);
+    g[k1] = -0.5 * (x1a * s12 + s10 * x1b);
+    g[k3] = -0.5 * (x3a * s32 + s30 * x3b);
+    g[k] = -0.5 * (x0a * s12 + x0c * s32);
+    g[k2] = -0.5 * (s10 * x2b + s30 * x2c);
+  } else {
+    // 1/2 t(a0,a1) t(a0,a3) + 1/2 t(a2,a1) t(a2,a3)
+    double f01 = et(a0, a1), f03 = et(a0, a3), f21 = et(a2, a1), f23 = et(a2, a3);
+    double y0a, y1a, y0b, y3b, y2a, y1b, y2b, y3c;
+    det(a0, a1, y0a, y1a);
+    det(a0, a3, y0b, y3b);
+    det(a2, a1, y2a, y1b);
+    det(a2, a3, y2b, y3c);
+    g[k] = 0.5 * (y0a * f03 + f01 * y0b);
+    g[k2] = 0.5 * (y2a * f23 + f21 * y2b);
+    g[k1] = 0.5 * (y1a * f03 + f23 * y1b);
+    g[k3] = 0.5 * (f01 * y3b + f21 * y3c);
+  }
+}
+
+// d phi / d(c, a, R) of the ellipsoid distance estimate at x (15 values).
+__device__ inline void ellipsoid_phi_grad(const GeomParams& G, double x, double y, double z, double out[15]) {
+  double r[3] = {x - G.c[0], y - G.c[1], z - G.c[2]};
+  double p[3], q[3], s[3];
+  for (int jj = 0; jj < 3; ++jj) {
+    p[jj] = G.R[0 + jj] * r[0] + G.R[3 + jj] * r[1] + G.R[6 + jj] * r[2];
+    q[jj] = p[jj] / G.a[jj];
+    s[jj] = q[jj] / G.a[jj];
+  }
+  double k0 = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+  double k1 = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  for (int t = 0; t < 15; ++t) out[t] = 0.0;
+  if (k1 == 0.0 || k0 == 0.0) return;
+  double dk0 = (2.0 * k0 - 1.0) / k1, dk1 = -k0 * (k0 - 1.0) / (k1 * k1);
+  double gp[3];
+  for (int jj = 0; jj < 3; ++jj) {
+    double a = G.a[jj];
+    gp[jj] = dk0 * q[jj] / (k0 * a) + dk1 * s[jj] / (k1 * a * a);
+    out[3 + jj] = dk0 * (-q[jj] * q[jj] / (k0 * a)) + dk1 * (-2.0 * s[jj] * s[jj] / (k1 * a));
+  }
+  for (int ii = 0; ii < 3; ++ii) {
+    out[ii] = -(G.R[3 * ii + 0] * gp[0] + G.R[3 * ii + 1] * gp[1] + G.R[3 * ii + 2] * gp[2]);
+    for (int jj = 0; jj < 3; ++jj) out[6 + 3 * ii + jj] = r[ii] * gp[jj];
+  }
+}
+
+__device__ inline void node_xyz(const Dims& d, double dx, int comp, int i, int j, int k, int q, double xyz[3]) {
+  // cyclic corners: x-face (j,k) offsets, y-face (i,k), z-face (i,j)
+  const int o1[4] = {0, 1, 1, 0}, o2[4] = {0, 0, 1, 1};
+  int n[3] = {i, j, k};
+  int t1 = comp == 0 ? 1 : 0, t2 = comp == 2 ? 1 : 2;
+  n[t1] += o1[q];
+  n[t2] += o2[q];
+  xyz[0] = n[0] * dx;
+  xyz[1] = n[1] * dx;
+  xyz[2] = n[2] * dx;
+}
+
+__device__ inline int corner_node(const Dims& d, int comp, int i, int j, int k, int q) {
+  const int o1[4] = {0, 1, 1, 0}, o2[4] = {0, 0, 1, 1};
+  int n[3] = {i, j, k};
+  int t1 = comp == 0 ? 1 : 0, t2 = comp == 2 ? 1 : 2;
+  n[t1] += o1[q];
+  n[t2] += o2[q];
+  return d.node(n[0], n[1], n[2]);
+}
+
+// Per face: dJ/dU^ into gu; with GRAD, the ellipsoid's pose (15) and control
+// (6) partials are reduced (fixed order, FP64) and added to g_theta / g_ctrl.
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, const float* __restrict__ alpha,
+                                                       const double* __restrict__ phi,
+                                                       const float* __restrict__ g,
+                                                       const float* __restrict__ y,
+                                                       const float* __restrict__ un1,
+                                                       float* __restrict__ gu, double* __restrict__ partials,
+                                                       unsigned* __restrict__ ticket,
+                                                       double* __restrict__ g_theta,
+                                                       double* __restrict__ g_ctrl) {
+  const Dims& d = D.d;
+  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc[21];
+#pragma unroll
+  for (int t = 0; t < 21; ++t) acc[t] = 0.0;
+  if (f < (long)d.faces()) {
+    int comp, i, j, k;
+    face_decode(d, f, comp, i, j, k);
+    float a = alpha[f];
+    float gf = g[f];
+    float yp, ym;
+    face_cells(d, y, comp, i, j, k, yp, ym);
+    float Gy = yp - ym;
+    bool m = a > 0.0f;
+    gu[f] = (m ? gf : 0.0f) + a * Gy;
+    if (GRAD) {
+      int own = comp == 0 ? i : (comp == 1 ? j : k);
+      int sk = side_kind(D, comp, own);
+      bool fixed = sk == SIM_BC_WALL || sk == SIM_BC_INFLOW;
+      if (!fixed) {
+        double us = face_solid_velocity(D, G, comp, i, j, k);
+        double galpha = m ? (double)Gy * ((double)un1[f] - us) : 0.0;
+        double gus = (m ? 0.0 : (double)gf) + (1.0 - (double)a) * (double)Gy;
+        if (galpha != 0.0 && a < 1.0f) {
+          double p[4], dg[4];
+          for (int q = 0; q < 4; ++q) p[q] = phi[corner_node(d, comp, i, j, k, q)];
+          fraction_grad(p, dg);
+          for (int q = 0; q < 4; ++q) {
+            if (dg[q] == 0.0) continue;
+            double xyz[3], gp[15];
+            node_xyz(d, D.dx, comp, i, j, k, q, xyz);
+            ellipsoid_phi_grad(G, xyz[0], xyz[1], xyz[2], gp);
+            double w = galpha * dg[q];
+            for (int t = 0; t < 15; ++t) acc[t] += w * gp[t];
+          }
+        }
+        if (gus != 0.0) {
+          double x[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * D.dx, (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
+                         (k + (comp == 2 ? 0.0 : 0.5)) * D.dx};
+          double r0 = x[0] - G.c[0], r1 = x[1] - G.c[1], r2 = x[2] - G.c[2];
+          // u_s,comp = v_comp + (w x r)_comp
+          acc[15 + comp] += gus;
+          if (comp == 0) {
+            acc[19] += gus * r2;  acc[20] -= gus * r1;     // d/dw
+            acc[1] += gus * G.w[2]; acc[2] -= gus * G.w[1];  // d/dc = -d/dr
+          } else if (comp == 1) {
+            acc[18] -= gus * r2;  acc[20] += gus * r0;
+            acc[0] -= gus * G.w[2]; acc[2] += gus * G.w[0];
+          } else {
+            acc[18] += gus * r1;  acc[19] -= gus * r0;
+            acc[0] += gus * G.w[1]; acc[1] -= gus * G.w[0];
+          }
+        }
+      }
+    }
+  }
+  if (GRAD) {
+    double tot[21];
+    if (grid_sum<21>(acc, partials, ticket, tot) && threadIdx.x == 0) {
+      if (g_theta)
+        for (int t = 0; t < 15; ++t) g_theta[t] += tot[t];
+      if (g_ctrl)
+        for (int t = 0; t < 6; ++t) g_ctrl[t] += tot[15 + t];
+    }
+  }
+}
+
+static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+void launch_rhs(const Domain& D, const GeomParams& G, double inv_k, const float* alpha, const float* uhat,
+                float* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_rhs, dim3(nblocks(D.d.cells())), dim3(kBlock), 0, s, D, G, (float)inv_k, alpha, uhat, b);
+}
+
+void launch_update(const Domain& D, const GeomParams& G, double kk, const float* alpha, const float* uhat,
+                   const float* p, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_update, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, (float)kk, alpha, uhat,
+                     p, out);
+}
+
+void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rhs, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_div, dim3(nblocks(d.cells())), dim3(kBlock), 0, s, d, alpha, g, rhs);
+}
+
+size_t adj_faces_partials(const Dims& d) { return (size_t)nblocks(d.faces()) * 21; }
+
+void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, const float* alpha, const double* phi,
+                      const float* g, const float* y, const float* un1, float* gu, double* partials,
+                      unsigned* ticket, double* g_theta, double* g_ctrl, hipStream_t s) {
+  if (grad)
+    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, alpha, phi, g, y,
+                       un1, gu, partials, ticket, g_theta, g_ctrl);
+  else
+    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, alpha, phi, g,
+                       y, un1, gu, partials, ticket, g_theta, g_ctrl);
+}
+
+}  // namespace nf

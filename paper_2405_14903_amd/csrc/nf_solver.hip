@@ -1,0 +1,565 @@
+// Matrix-free multigrid-preconditioned CG for (G^T S G) x = b on the MAC grid.
+//
+// NeuralFluid solves the projection system of Eq. projection_matrix with a
+// matrix-free geometric-multigrid-preconditioned CG (Sec. Time Performance
+// Profiling: MGPCG with custom prolongation / restriction between a
+// hierarchy of grids).  This solver:
+//   * applies A x = sum over faces of alpha_f (x_c - x_nb) as a 7-point
+//     stencil read straight from the face fractions (no stored matrix);
+//   * keeps every CG scalar on the device, with FP64 dot products reduced in a
+//     fixed order (per-block partials, summed by the last block to finish), so
+//     a solve is bitwise reproducible;
+//   * preconditions with one V-cycle: level l+1 halves each axis, coarse face
+//     weight = 1/2 * sum of the 2x2 fine faces it covers, restriction = sum of
+//     the 8 child residuals, prolongation = injection (the transpose), two
+//     damped-Jacobi sweeps (omega = 0.8) before and after the correction, and
+//     40 Jacobi sweeps on the coarsest level (<= 4096 cells) in one workgroup.
+//     Every piece is a fixed linear symmetric map, so the preconditioner is
+//     symmetric and plain CG applies;
+//   * on the multigrid levels the arrays may be stored in FP32, FP16 or BF16
+//     (template parameter T); fine-level CG vectors are always FP32 and the
+//     scalars FP64.
+#include "nf_internal.h"
+#include "nf_solver.h"
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+namespace nf {
+
+template <typename T> __device__ inline float ld(const T* p, long i);
+template <> __device__ inline float ld<float>(const float* p, long i) { return p[i]; }
+template <> __device__ inline float ld<__half>(const __half* p, long i) { return __half2float(p[i]); }
+template <> __device__ inline float ld<__hip_bfloat16>(const __hip_bfloat16* p, long i) {
+  return __bfloat162float(p[i]);
+}
+template <typename T> __device__ inline T cvt(float v);
+template <> __device__ inline float cvt<float>(float v) { return v; }
+template <> __device__ inline __half cvt<__half>(float v) { return __float2half(v); }
+template <> __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+
+__device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) {
+  i = (int)(c % d.nx);
+  long t = c / d.nx;
+  j = (int)(t % d.ny);
+  k = (int)(t / d.ny);
+}
+
+// The 6 face weights of cell (i,j,k): lower / upper along x, y, z.
+template <typename A>
+struct Faces {
+  float w[6];
+  __device__ Faces(const Dims& d, const A* ax, const A* ay, const A* az, int i, int j, int k) {
+    w[0] = ld(ax, d.fx(i, j, k));
+    w[1] = ld(ax, d.fx(i + 1, j, k));
+    w[2] = ld(ay, d.fy(i, j, k));
+    w[3] = ld(ay, d.fy(i, j + 1, k));
+    w[4] = ld(az, d.fz(i, j, k));
+    w[5] = ld(az, d.fz(i, j, k + 1));
+  }
+  __device__ float diag() const { return ((w[0] + w[1]) + (w[2] + w[3])) + (w[4] + w[5]); }
+};
+
+// sum over interior neighbours of alpha_f * v(nb); `val(c)` gives v at cell c.
+template <typename A, typename F>
+__device__ inline float offdiag(const Dims& d, const Faces<A>& fw, int i, int j, int k, long c, F val) {
+  float s = 0.0f;
+  if (i > 0) s += fw.w[0] * val(c - 1);
+  if (i < d.nx - 1) s += fw.w[1] * val(c + 1);
+  if (j > 0) s += fw.w[2] * val(c - d.nx);
+  if (j < d.ny - 1) s += fw.w[3] * val(c + d.nx);
+  long sxy = (long)d.nx * d.ny;
+  if (k > 0) s += fw.w[4] * val(c - sxy);
+  if (k < d.nz - 1) s += fw.w[5] * val(c + sxy);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// CG kernels (fine level, FP32 vectors, FP64 scalars)
+// ---------------------------------------------------------------------------
+
+// r = b - A x; bb, rr -> scalars; decides `done` for a zero / already solved b.
+__global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restrict__ ax,
+                                                     const float* __restrict__ ay,
+                                                     const float* __restrict__ az,
+                                                     const float* __restrict__ b,
+                                                     const float* __restrict__ x, float* __restrict__ r,
+                                                     double tol, int maxit, CGScalars* sc,
+                                                     double* partials) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[2] = {0.0, 0.0};
+  if (c < (long)d.cells()) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<float> fw(d, ax, ay, az, i, j, k);
+    float xc = x[c];
+    float Ax = fw.diag() * xc - offdiag(d, fw, i, j, k, c, [&](long q) { return x[q]; });
+    float bc = fw.diag() > 0.0f ? b[c] : 0.0f;
+    float rc = bc - Ax;
+    r[c] = rc;
+    v[0] = (double)bc * bc;
+    v[1] = (double)rc * rc;
+  }
+  double tot[2];
+  if (grid_sum<2>(v, partials, &sc->ticket[0], tot) && threadIdx.x == 0) {
+    sc->bb = tot[0];
+    sc->rr = tot[1];
+    sc->tol2bb = tol * tol * tot[0];
+    sc->iters = 0;
+    sc->first = 1;
+    sc->maxit = maxit;
+    sc->nonfinite = !isfinite(tot[1]);
+    sc->done = (tot[0] == 0.0) || (tot[1] <= sc->tol2bb) || sc->nonfinite || maxit <= 0;
+    sc->rho = 0.0;
+    sc->beta = 0.0;
+  }
+}
+
+// p_new = z + beta p_old (p_new = z on the first iteration); q = A p_new;
+// alpha = rho / (p_new . q).
+__global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __restrict__ ax,
+                                                          const float* __restrict__ ay,
+                                                          const float* __restrict__ az,
+                                                          const float* __restrict__ z,
+                                                          const float* __restrict__ pold,
+                                                          float* __restrict__ pnew, float* __restrict__ q,
+                                                          CGScalars* sc, double* partials) {
+  if (sc->done) return;
+  const bool first = sc->first;
+  const float beta = (float)sc->beta;
+  long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < (long)d.cells()) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<float> fw(d, ax, ay, az, i, j, k);
+    auto pv = [&](long t) { return first ? z[t] : z[t] + beta * pold[t]; };
+    float pc = pv(c);
+    float qc = fw.diag() * pc - offdiag(d, fw, i, j, k, c, pv);
+    pnew[c] = pc;
+    q[c] = qc;
+    v[0] = (double)pc * qc;
+  }
+  double tot[1];
+  if (grid_sum<1>(v, partials, &sc->ticket[1], tot) && threadIdx.x == 0) {
+    sc->alpha = tot[0] != 0.0 ? sc->rho / tot[0] : 0.0;
+    sc->first = 0;
+  }
+}
+
+// x += alpha p; r -= alpha q; convergence test on r . r.
+__global__ __launch_bounds__(kBlock) void k_cg_update(long n, float* __restrict__ x, float* __restrict__ r,
+                                                       const float* __restrict__ p,
+                                                       const float* __restrict__ q, CGScalars* sc,
+                                                       double* partials) {
+  if (sc->done) return;
+  const float a = (float)sc->alpha;
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < n) {
+    x[c] += a * p[c];
+    float rc = r[c] - a * q[c];
+    r[c] = rc;
+    v[0] = (double)rc * rc;
+  }
+  double tot[1];
+  if (grid_sum<1>(v, partials, &sc->ticket[2], tot) && threadIdx.x == 0) {
+    sc->rr = tot[0];
+    sc->iters += 1;
+    if (!isfinite(tot[0])) sc->nonfinite = 1;
+    if (tot[0] <= sc->tol2bb || sc->iters >= sc->maxit || sc->nonfinite) sc->done = 1;
+  }
+}
+
+// rho = r . z (and beta = rho_new / rho_old after the first V-cycle).
+__device__ inline void finish_rz(CGScalars* sc, double rz) {
+  if (sc->first) {
+    sc->rho = rz;
+  } else {
+    sc->beta = sc->rho != 0.0 ? rz / sc->rho : 0.0;
+    sc->rho = rz;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_rz_dot(long n, const float* __restrict__ r,
+                                                    const float* __restrict__ z, CGScalars* sc,
+                                                    double* partials) {
+  if (sc->done) return;
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {c < n ? (double)r[c] * (double)z[c] : 0.0};
+  double tot[1];
+  if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
+}
+
+// ||b - A x||^2 with A x accumulated in FP64.
+__global__ __launch_bounds__(kBlock) void k_true_residual(Dims d, const float* __restrict__ ax,
+                                                           const float* __restrict__ ay,
+                                                           const float* __restrict__ az,
+                                                           const float* __restrict__ b,
+                                                           const float* __restrict__ x, CGScalars* sc,
+                                                           double* partials) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < (long)d.cells()) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<float> fw(d, ax, ay, az, i, j, k);
+    double diag = (double)fw.w[0] + fw.w[1] + fw.w[2] + fw.w[3] + fw.w[4] + fw.w[5];
+    if (diag > 0.0) {
+      double s = diag * (double)x[c];
+      long sxy = (long)d.nx * d.ny;
+      if (i > 0) s -= (double)fw.w[0] * x[c - 1];
+      if (i < d.nx - 1) s -= (double)fw.w[1] * x[c + 1];
+      if (j > 0) s -= (double)fw.w[2] * x[c - d.nx];
+      if (j < d.ny - 1) s -= (double)fw.w[3] * x[c + d.nx];
+      if (k > 0) s -= (double)fw.w[4] * x[c - sxy];
+      if (k < d.nz - 1) s -= (double)fw.w[5] * x[c + sxy];
+      double rr = (double)b[c] - s;
+      v[0] = rr * rr;
+    }
+  }
+  double tot[1];
+  if (grid_sum<1>(v, partials, &sc->ticket[4], tot) && threadIdx.x == 0) sc->true_rr = tot[0];
+}
+
+// ---------------------------------------------------------------------------
+// multigrid kernels (storage type T for level vectors and fractions; the
+// fine-level residual R and output Z are FP32 at level 0)
+// ---------------------------------------------------------------------------
+
+// Two damped-Jacobi sweeps from z = 0:  z1 = w D^-1 r,  z2 = z1 + w D^-1 (r - A z1).
+template <typename A, typename R, typename Z>
+__global__ __launch_bounds__(kBlock) void k_mg_pre(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
+                                                    const A* __restrict__ az, const A* __restrict__ invd,
+                                                    const R* __restrict__ r, Z* __restrict__ z2,
+                                                    const CGScalars* sc) {
+  if (sc->done) return;
+  long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cdec(d, c, i, j, k);
+  Faces<A> fw(d, ax, ay, az, i, j, k);
+  float idc = ld(invd, c);
+  auto z1 = [&](long t) { return kOmega * ld(invd, t) * ld(r, t); };
+  float rc = ld(r, c);
+  float z1c = kOmega * idc * rc;
+  float Az = fw.diag() * z1c - offdiag(d, fw, i, j, k, c, z1);
+  z2[c] = cvt<Z>(z1c + kOmega * idc * (rc - Az));
+}
+
+// r_coarse(I,J,K) = sum over the 8 children of (r - A z).
+template <typename A, typename R, typename Z, typename RC>
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(Dims d, Dims cd, const A* __restrict__ ax,
+                                                         const A* __restrict__ ay, const A* __restrict__ az,
+                                                         const R* __restrict__ r, const Z* __restrict__ z,
+                                                         RC* __restrict__ rc, const CGScalars* sc) {
+  if (sc->done) return;
+  long C = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (C >= (long)cd.cells()) return;
+  int I, J, K;
+  cdec(cd, C, I, J, K);
+  float s = 0.0f;
+  auto zv = [&](long t) { return ld(z, t); };
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    int i = 2 * I + (b & 1), j = 2 * J + ((b >> 1) & 1), k = 2 * K + (b >> 2);
+    long c = d.c(i, j, k);
+    Faces<A> fw(d, ax, ay, az, i, j, k);
+    float Az = fw.diag() * ld(z, c) - offdiag(d, fw, i, j, k, c, zv);
+    s += ld(r, c) - Az;
+  }
+  rc[C] = cvt<RC>(s);
+}
+
+// z' = z_in + P e (injection from the parent cell); z_out = z' + w D^-1 (r - A z').
+template <typename A, typename R, typename Z, typename E>
+__global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* __restrict__ ax,
+                                                      const A* __restrict__ ay, const A* __restrict__ az,
+                                                      const A* __restrict__ invd, const R* __restrict__ r,
+                                                      const Z* __restrict__ zin, const E* __restrict__ e,
+                                                      Z* __restrict__ zout, const CGScalars* sc) {
+  if (sc->done) return;
+  long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cdec(d, c, i, j, k);
+  Faces<A> fw(d, ax, ay, az, i, j, k);
+  const int cnx = cd.nx, cny = cd.ny;
+  auto zp = [&](long t) {
+    int ti = (int)(t % d.nx);
+    long tt = t / d.nx;
+    int tj = (int)(tt % d.ny), tk = (int)(tt / d.ny);
+    return ld(zin, t) + ld(e, (ti >> 1) + (long)cnx * ((tj >> 1) + (long)cny * (tk >> 1)));
+  };
+  float zc = zp(c);
+  float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zp);
+  zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (ld(r, c) - Az));
+}
+
+// z_out = z_in + w D^-1 (r - A z_in); optionally rho = r . z_out (level 0).
+template <typename A, typename R, typename Z, typename O, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
+                                                      const A* __restrict__ az, const A* __restrict__ invd,
+                                                      const R* __restrict__ r, const Z* __restrict__ zin,
+                                                      O* __restrict__ zout, CGScalars* sc, double* partials) {
+  if (sc->done) return;
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (c < (long)d.cells()) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<A> fw(d, ax, ay, az, i, j, k);
+    auto zv = [&](long t) { return ld(zin, t); };
+    float zc = ld(zin, c);
+    float rc = ld(r, c);
+    float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zv);
+    float zo = zc + kOmega * ld(invd, c) * (rc - Az);
+    zout[c] = cvt<O>(zo);
+    v[0] = (double)rc * (double)zo;
+  }
+  if (DOT) {
+    double tot[1];
+    if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
+  }
+}
+
+// Coarsest level: kCoarseSweeps damped-Jacobi sweeps from zero, one workgroup,
+// vectors in LDS.
+template <typename A, typename R, typename Z>
+__global__ __launch_bounds__(1024) void k_mg_coarse(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
+                                                     const A* __restrict__ az, const A* __restrict__ invd,
+                                                     const R* __restrict__ r, Z* __restrict__ z,
+                                                     const CGScalars* sc) {
+  if (sc->done) return;
+  __shared__ float zs[2][kCoarseMaxCells];
+  __shared__ float rs[kCoarseMaxCells];
+  __shared__ float ids[kCoarseMaxCells];
+  const long n = (long)d.cells();
+  for (long c = threadIdx.x; c < n; c += blockDim.x) {
+    rs[c] = ld(r, c);
+    ids[c] = ld(invd, c);
+    zs[0][c] = 0.0f;
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int s = 0; s < kCoarseSweeps; ++s) {
+    for (long c = threadIdx.x; c < n; c += blockDim.x) {
+      int i, j, k;
+      cdec(d, c, i, j, k);
+      Faces<A> fw(d, ax, ay, az, i, j, k);
+      const float* zc = zs[cur];
+      float Az = fw.diag() * zc[c] - offdiag(d, fw, i, j, k, c, [&](long t) { return zc[t]; });
+      zs[cur ^ 1][c] = zc[c] + kOmega * ids[c] * (rs[c] - Az);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  for (long c = threadIdx.x; c < n; c += blockDim.x) z[c] = cvt<Z>(zs[cur][c]);
+}
+
+template <typename T>
+__global__ void k_cast_alpha(long n, const float* __restrict__ src, T* __restrict__ dst) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = cvt<T>(src[i]);
+}
+
+static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------------------
+// host driver
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) {
+  const int L = S.nlev;
+  CGScalars* sc = S.sc;
+  auto A = [&](int l) { return (const T*)S.lev[l].a[0]; };
+  auto Ay = [&](int l) { return (const T*)S.lev[l].a[1]; };
+  auto Az = [&](int l) { return (const T*)S.lev[l].a[2]; };
+  auto ID = [&](int l) { return (const T*)S.lev[l].invd; };
+  if (L == 1) {
+    hipLaunchKernelGGL((k_mg_coarse<T, float, float>), dim3(1), dim3(1024), 0, st, S.lev[0].d, A(0), Ay(0), Az(0),
+                       ID(0), r0, z0, sc);
+    hipLaunchKernelGGL(k_rz_dot, dim3(nblocks(S.lev[0].d.cells())), dim3(kBlock), 0, st,
+                       (long)S.lev[0].d.cells(), r0, z0, sc, S.partials);
+    return;
+  }
+  // down
+  for (int l = 0; l < L - 1; ++l) {
+    const Dims& d = S.lev[l].d;
+    const Dims& cd = S.lev[l + 1].d;
+    T* ta = (T*)S.lev[l].ta;
+    T* rc = (T*)S.lev[l + 1].r;
+    if (l == 0) {
+      hipLaunchKernelGGL((k_mg_pre<T, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(0), Ay(0),
+                         Az(0), ID(0), r0, ta, sc);
+      hipLaunchKernelGGL((k_mg_restrict<T, float, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d, cd,
+                         A(0), Ay(0), Az(0), r0, (const T*)ta, rc, sc);
+    } else {
+      const T* rl = (const T*)S.lev[l].r;
+      hipLaunchKernelGGL((k_mg_pre<T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l), Ay(l),
+                         Az(l), ID(l), rl, ta, sc);
+      hipLaunchKernelGGL((k_mg_restrict<T, T, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d, cd, A(l),
+                         Ay(l), Az(l), rl, (const T*)ta, rc, sc);
+    }
+  }
+  // coarsest
+  {
+    const int l = L - 1;
+    hipLaunchKernelGGL((k_mg_coarse<T, T, T>), dim3(1), dim3(1024), 0, st, S.lev[l].d, A(l), Ay(l), Az(l), ID(l),
+                       (const T*)S.lev[l].r, (T*)S.lev[l].z, sc);
+  }
+  // up
+  for (int l = L - 2; l >= 0; --l) {
+    const Dims& d = S.lev[l].d;
+    const Dims& cd = S.lev[l + 1].d;
+    const T* ta = (const T*)S.lev[l].ta;
+    T* tb = (T*)S.lev[l].tb;
+    const T* e = (const T*)S.lev[l + 1].z;
+    if (l == 0) {
+      hipLaunchKernelGGL((k_mg_post1<T, float, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(0),
+                         Ay(0), Az(0), ID(0), r0, ta, e, tb, sc);
+      hipLaunchKernelGGL((k_mg_post2<T, float, T, float, true>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
+                         A(0), Ay(0), Az(0), ID(0), r0, (const T*)tb, z0, sc, S.partials);
+    } else {
+      const T* rl = (const T*)S.lev[l].r;
+      hipLaunchKernelGGL((k_mg_post1<T, T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(l),
+                         Ay(l), Az(l), ID(l), rl, ta, e, tb, sc);
+      hipLaunchKernelGGL((k_mg_post2<T, T, T, T, false>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l),
+                         Ay(l), Az(l), ID(l), rl, (const T*)tb, (T*)S.lev[l].z, sc, S.partials);
+    }
+  }
+}
+
+static void vcycle_dispatch(const Solver& S, const float* r0, float* z0, hipStream_t st) {
+  if (S.precision == SIM_MIXED_FP16)
+    vcycle<__half>(S, r0, z0, st);
+  else if (S.precision == SIM_MIXED_BF16)
+    vcycle<__hip_bfloat16>(S, r0, z0, st);
+  else
+    vcycle<float>(S, r0, z0, st);
+}
+
+// Multigrid copies of the fine fractions and inverse diagonals.
+void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
+  const Dims& d0 = S.lev[0].d;
+  const float* fx = fine_alpha;
+  const float* fy = fx + d0.nfx();
+  const float* fz = fy + d0.nfy();
+  // FP32 fine fractions for the CG operator
+  S.ax = fx;
+  S.ay = fy;
+  S.az = fz;
+  if (S.precision == SIM_FP32) {
+    S.lev[0].a[0] = (void*)fx;
+    S.lev[0].a[1] = (void*)fy;
+    S.lev[0].a[2] = (void*)fz;
+    launch_invdiag(d0, fx, fy, fz, (float*)S.lev[0].invd, st);
+    for (int l = 1; l < S.nlev; ++l) {
+      const Dims& fd = S.lev[l - 1].d;
+      const Dims& cd = S.lev[l].d;
+      launch_coarsen_alpha(fd, cd, (const float*)S.lev[l - 1].a[0], (const float*)S.lev[l - 1].a[1],
+                           (const float*)S.lev[l - 1].a[2], (float*)S.lev[l].a[0], (float*)S.lev[l].a[1],
+                           (float*)S.lev[l].a[2], st);
+      launch_invdiag(cd, (const float*)S.lev[l].a[0], (const float*)S.lev[l].a[1], (const float*)S.lev[l].a[2],
+                     (float*)S.lev[l].invd, st);
+    }
+    return;
+  }
+  // mixed: build the hierarchy in FP32 scratch (level by level), cast to T
+  float* sx = S.scratch_a;
+  float* sinv = S.scratch_inv;
+  for (int l = 0; l < S.nlev; ++l) {
+    const Dims& d = S.lev[l].d;
+    const float *lx, *ly, *lz;
+    if (l == 0) {
+      lx = fx;
+      ly = fy;
+      lz = fz;
+    } else {
+      const Dims& fd = S.lev[l - 1].d;
+      float* cx = sx + S.scratch_off[l];
+      float* cy = cx + d.nfx();
+      float* cz = cy + d.nfy();
+      const float* px = sx + S.scratch_off[l - 1];
+      const float* py = px + fd.nfx();
+      const float* pz = py + fd.nfy();
+      if (l == 1) {
+        px = fx;
+        py = fy;
+        pz = fz;
+      }
+      launch_coarsen_alpha(fd, d, px, py, pz, cx, cy, cz, st);
+      lx = cx;
+      ly = cy;
+      lz = cz;
+    }
+    launch_invdiag(d, lx, ly, lz, sinv, st);
+    long n = (long)d.faces();
+    if (S.precision == SIM_MIXED_FP16) {
+      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfx())), dim3(kBlock), 0, st, (long)d.nfx(), lx,
+                         (__half*)S.lev[l].a[0]);
+      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfy())), dim3(kBlock), 0, st, (long)d.nfy(), ly,
+                         (__half*)S.lev[l].a[1]);
+      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfz())), dim3(kBlock), 0, st, (long)d.nfz(), lz,
+                         (__half*)S.lev[l].a[2]);
+      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, (long)d.cells(), sinv,
+                         (__half*)S.lev[l].invd);
+    } else {
+      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfx())), dim3(kBlock), 0, st, (long)d.nfx(),
+                         lx, (__hip_bfloat16*)S.lev[l].a[0]);
+      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfy())), dim3(kBlock), 0, st, (long)d.nfy(),
+                         ly, (__hip_bfloat16*)S.lev[l].a[1]);
+      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfz())), dim3(kBlock), 0, st, (long)d.nfz(),
+                         lz, (__hip_bfloat16*)S.lev[l].a[2]);
+      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st,
+                         (long)d.cells(), sinv, (__hip_bfloat16*)S.lev[l].invd);
+    }
+    (void)n;
+  }
+}
+
+int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st) {
+  const Dims& d = S.lev[0].d;
+  const long n = (long)d.cells();
+  CGScalars* sc = S.sc;
+  float* r = S.r;
+  float* z = S.z;
+  float* q = S.q;
+  float* p[2] = {S.p0, S.p1};
+  hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, r, tol, maxit, sc,
+                     S.partials);
+  vcycle_dispatch(S, r, z, st);
+  int cur = 0;
+  int enq = 0;
+  const int chunk = S.check_every > 0 ? S.check_every : 2;
+  for (;;) {
+    // device scalars -> pinned host copy, then test `done`
+    if (hipMemcpyAsync(S.host_sc, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
+    if (S.host_sc->done || enq >= maxit) break;
+    for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
+      hipLaunchKernelGGL(k_cg_dir_apply, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, z, p[cur],
+                         p[cur ^ 1], q, sc, S.partials);
+      hipLaunchKernelGGL(k_cg_update, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, r, p[cur ^ 1], q, sc, S.partials);
+      vcycle_dispatch(S, r, z, st);
+      cur ^= 1;
+    }
+  }
+  if (stats) {
+    hipLaunchKernelGGL(k_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, sc,
+                       S.partials);
+    if (hipMemcpyAsync(S.host_sc, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
+    const CGScalars& h = *S.host_sc;
+    stats->iters = h.iters;
+    stats->nonfinite = h.nonfinite;
+    stats->converged = !h.nonfinite && (h.bb == 0.0 || h.rr <= h.tol2bb);
+    stats->pad = 0;
+    stats->rel_res = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
+    stats->true_rel_res = h.bb > 0.0 ? sqrt(h.true_rr / h.bb) : 0.0;
+  }
+  return SIM_OK;
+}
+
+}  // namespace nf

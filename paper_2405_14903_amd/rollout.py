@@ -1,0 +1,140 @@
+"""Differentiable rollouts: back-propagation through time with step checkpointing.
+
+NeuralFluid, Sec. Back-propagation through Time: the per-step adjoint runs in
+reverse order over the whole sequence; Sec. Back-propagation through Geometry:
+shape and control gradients are accumulated along the way.  Memory is kept
+bounded by storing the velocity only every ``every`` steps (``"sqrt"``:
+ceil(sqrt(T))) and recomputing each segment's forward before walking it
+backwards; the forward is deterministic (fixed-order reductions, zero initial
+pressure guess), so the recomputed states equal the original ones bitwise.
+The adjoint pressure solve does not depend on the forward solver's iterates
+(only on the converged operator), so no solver state is stored.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from .sim import Sim, ellipsoid_poses, ellipsoid_poses_adjoint
+
+
+def checkpoint_stride(T: int, every) -> int:
+    if every == "sqrt":
+        return max(1, math.ceil(math.sqrt(T)))
+    return max(1, int(every))
+
+
+class Rollout:
+    """Forward + adjoint of T steps of one handle.
+
+    ``schedule(n)`` returns the host (theta, ctrl) arrays of step n; for the
+    ellipsoid use :meth:`ellipsoid`.
+    """
+
+    def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None):
+        self.sim, self.T, self.schedule = sim, int(T), schedule
+        self.K = checkpoint_stride(self.T, every)
+        self.grad_geometry = grad_geometry
+        self.timer = timer
+        self.last_stats = []
+
+    @staticmethod
+    def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None):
+        ctrl = np.asarray(ctrl, np.float64).reshape(-1, 6)
+        poses = ellipsoid_poses(theta0, ctrl, sim.cfg.dt)
+        ro = Rollout(sim, ctrl.shape[0], lambda n: (poses[n], ctrl[n]), every, grad_geometry=True, timer=timer)
+        ro.theta0 = np.asarray(theta0, np.float64).ravel()
+        ro.ctrl = ctrl
+        return ro
+
+    def _step(self, n, u, out):
+        th, ct = self.schedule(n)
+        if self.timer:
+            self.timer.begin("fwd")
+        self.sim.step(u, th, ct, u_out=out, stats=False)
+        if self.timer:
+            self.timer.end("fwd")
+
+    def forward(self, u0: torch.Tensor) -> torch.Tensor:
+        self.ckpt = {0: u0.detach().clone()}
+        a = u0.detach().clone()
+        b = torch.empty_like(a)
+        for n in range(self.T):
+            self._step(n, a, b)
+            a, b = b, a
+            if (n + 1) % self.K == 0 and n + 1 < self.T:
+                self.ckpt[n + 1] = a.clone()
+        return a
+
+    def backward(self, gT: torch.Tensor):
+        sim, T, K = self.sim, self.T, self.K
+        dev = gT.device
+        g = gT.detach().clone().contiguous()
+        gprev = torch.empty_like(g)
+        g_steps = torch.zeros((T, sim.n_params), dtype=torch.float64, device=dev) if self.grad_geometry else None
+        g_ctrl = torch.zeros((T, sim.n_ctrl), dtype=torch.float64, device=dev) if self.grad_geometry else None
+        seg_starts = list(range(0, T, K))
+        states = [torch.empty_like(g) for _ in range(K + 1)]
+        for s in reversed(seg_starts):
+            e = min(s + K, T)
+            states[0].copy_(self.ckpt[s])
+            for n in range(s, e):
+                self._step(n, states[n - s], states[n - s + 1])
+            for n in range(e - 1, s - 1, -1):
+                th, ct = self.schedule(n)
+                if self.timer:
+                    self.timer.begin("adj")
+                sim.step_adjoint(states[n - s], states[n - s + 1], g, th, ct, g_u_n=gprev,
+                                 g_theta=g_steps[n] if g_steps is not None else None,
+                                 g_ctrl=g_ctrl[n] if g_ctrl is not None else None, stats=False)
+                if self.timer:
+                    self.timer.end("adj")
+                g, gprev = gprev, g
+        self.g_steps, self.g_ctrl_direct = g_steps, g_ctrl
+        return g
+
+    def geometry_gradients(self):
+        """(dJ/dtheta0 (9,), dJ/dctrl (T, 6)) after :meth:`backward` of an ellipsoid rollout."""
+        gs = self.g_steps.cpu().numpy()
+        gd = self.g_ctrl_direct.cpu().numpy()
+        return ellipsoid_poses_adjoint(self.theta0, self.ctrl, self.sim.cfg.dt, gs, gd)
+
+
+class EllipsoidRolloutFn(torch.autograd.Function):
+    """u_T = rollout(u_0, theta_0, ctrl) as a torch.autograd.Function.
+
+    u0: device float32 velocity; theta0 (9,) and ctrl (T, 6): CPU float64.
+    Backward runs the hand-written adjoint kernels with checkpointing.
+    """
+
+    @staticmethod
+    def forward(ctx, u0, theta0, ctrl, sim: Sim, every=8):
+        ro = Rollout.ellipsoid(sim, theta0.detach().cpu().numpy(), ctrl.detach().cpu().numpy(), every)
+        uT = ro.forward(u0)
+        ctx.ro = ro
+        ctx.theta_dev = theta0.device
+        return uT
+
+    @staticmethod
+    def backward(ctx, gT):
+        ro = ctx.ro
+        g0 = ro.backward(gT.contiguous())
+        gth, gct = ro.geometry_gradients()
+        return (g0, torch.from_numpy(gth).to(ctx.theta_dev), torch.from_numpy(gct).to(ctx.theta_dev), None, None)
+
+
+class StaticRolloutFn(torch.autograd.Function):
+    """u_T = rollout(u_0) with a static solid (theta fixed); gradient w.r.t. u_0."""
+
+    @staticmethod
+    def forward(ctx, u0, sim: Sim, T: int, theta=None, every=8):
+        ro = Rollout(sim, T, lambda n: (theta, None), every)
+        uT = ro.forward(u0)
+        ctx.ro = ro
+        return uT
+
+    @staticmethod
+    def backward(ctx, gT):
+        return ctx.ro.backward(gT.contiguous()), None, None, None, None

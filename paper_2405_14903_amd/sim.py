@@ -1,0 +1,243 @@
+"""PyTorch-facing binding of the C ABI: argument checking and marshalling.
+
+Every array is a CUDA/HIP torch tensor handed to the library by pointer on the
+caller's current stream; shapes, dtypes and devices are checked here before
+any pointer crosses the ABI (a wrong size would otherwise be an out-of-bounds
+access on the GPU).  No numerical work happens in Python.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_BC = {"wall": L.SIM_BC_WALL, "inflow": L.SIM_BC_INFLOW, "outflow": L.SIM_BC_OUTFLOW,
+       "periodic": L.SIM_BC_PERIODIC}
+_PREC = {"fp32": L.SIM_FP32, "fp16": L.SIM_MIXED_FP16, "bf16": L.SIM_MIXED_BF16}
+_GEOM = {"none": L.SIM_GEOM_NONE, "spheres": L.SIM_GEOM_SPHERES, "ellipsoid": L.SIM_GEOM_ELLIPSOID}
+
+
+@dataclass
+class Config:
+    n: tuple
+    dx: float
+    dt: float
+    rho: float = 1.0
+    gravity: tuple = (0.0, 0.0, 0.0)
+    bc: tuple = ("wall",) * 6
+    inflow_speed: float = 0.0
+    precision: str = "fp32"
+    tol: float = 1e-6
+    max_iter: int = 200
+    geom: str = "none"
+    n_spheres: int = 0
+
+    def desc(self) -> L.SimDesc:
+        d = L.SimDesc()
+        for a in range(3):
+            d.n[a] = int(self.n[a])
+            d.gravity[a] = float(self.gravity[a])
+        d.dx, d.dt, d.rho, d.nu = float(self.dx), float(self.dt), float(self.rho), 0.0
+        for s in range(6):
+            b = self.bc[s]
+            d.bc[s] = _BC[b] if isinstance(b, str) else int(b)
+        d.inflow_speed = float(self.inflow_speed)
+        d.precision = _PREC[self.precision] if isinstance(self.precision, str) else int(self.precision)
+        d.tol, d.max_iter = float(self.tol), int(self.max_iter)
+        d.geom = _GEOM[self.geom] if isinstance(self.geom, str) else int(self.geom)
+        if d.geom == L.SIM_GEOM_SPHERES:
+            d.n_params, d.n_ctrl = 4 * int(self.n_spheres), 0
+        elif d.geom == L.SIM_GEOM_ELLIPSOID:
+            d.n_params, d.n_ctrl = 15, 6
+        else:
+            d.n_params, d.n_ctrl = 0, 0
+        return d
+
+    @property
+    def nfaces(self):
+        nx, ny, nz = self.n
+        return (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+
+    @property
+    def ncells(self):
+        nx, ny, nz = self.n
+        return nx * ny * nz
+
+
+def _ptr(t: torch.Tensor | None, n: int, dtype, name: str):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: expected contiguous {dtype} with {n} elements, got {t.dtype} "
+                         f"{tuple(t.shape)} contiguous={t.is_contiguous()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _host_doubles(a, n: int, name: str):
+    if n == 0:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel())
+    if arr.size != n:
+        raise ValueError(f"{name}: expected {n} values, got {arr.size}")
+    return arr, arr.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def sim_footprint(cfg: Config) -> int:
+    lib = L.load()
+    out = C.c_size_t(0)
+    d = cfg.desc()
+    L.check(lib.sim_footprint(C.byref(d), C.byref(out)), "sim_footprint")
+    return int(out.value)
+
+
+class Sim:
+    """One library handle (workspace for one grid / configuration)."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self.lib = L.load()
+        self._desc = cfg.desc()
+        h = C.c_void_p()
+        L.check(self.lib.sim_create(C.byref(self._desc), C.byref(h)), "sim_create")
+        self.h = h
+        self.nf, self.nc = cfg.nfaces, cfg.ncells
+        self.n_params, self.n_ctrl = self._desc.n_params, self._desc.n_ctrl
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            self.lib.sim_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- entry points --------------------------------------------------
+    def _geom(self, theta, ctrl):
+        th, thp = _host_doubles(theta, self.n_params, "theta")
+        ct, ctp = _host_doubles(ctrl, self.n_ctrl, "ctrl")
+        return (th, ct), thp, ctp
+
+    def step(self, u_n, theta=None, ctrl=None, u_out=None, p_out=None, stats=True):
+        f32 = torch.float32
+        if u_out is None:
+            u_out = torch.empty_like(u_n)
+        keep, thp, ctp = self._geom(theta, ctrl)
+        st = L.SimStats() if stats else None
+        L.check(self.lib.sim_step(self.h, _ptr(u_n, self.nf, f32, "u_n"), thp, ctp,
+                                  _ptr(u_out, self.nf, f32, "u_n1"), _ptr(p_out, self.nc, f32, "p_n1"),
+                                  C.byref(st) if st is not None else None, _stream()), "sim_step")
+        return u_out, (st.as_dict() if st is not None else None)
+
+    def project(self, u_in, theta=None, ctrl=None, u_out=None, p_out=None, stats=True):
+        f32 = torch.float32
+        if u_out is None:
+            u_out = torch.empty_like(u_in)
+        keep, thp, ctp = self._geom(theta, ctrl)
+        st = L.SimStats() if stats else None
+        L.check(self.lib.sim_project(self.h, _ptr(u_in, self.nf, f32, "u_in"), thp, ctp,
+                                     _ptr(u_out, self.nf, f32, "u_out"), _ptr(p_out, self.nc, f32, "p_out"),
+                                     C.byref(st) if st is not None else None, _stream()), "sim_project")
+        return u_out, (st.as_dict() if st is not None else None)
+
+    def step_adjoint(self, u_n, u_n1, g_u_n1, theta=None, ctrl=None, g_u_n=None, g_theta=None, g_ctrl=None,
+                     stats=True):
+        f32, f64 = torch.float32, torch.float64
+        if g_u_n is None:
+            g_u_n = torch.empty_like(g_u_n1)
+        keep, thp, ctp = self._geom(theta, ctrl)
+        st = L.SimStats() if stats else None
+        L.check(self.lib.sim_step_adjoint(
+            self.h, _ptr(u_n, self.nf, f32, "u_n"), _ptr(u_n1, self.nf, f32, "u_n1"), thp, ctp,
+            _ptr(g_u_n1, self.nf, f32, "g_u_n1"), _ptr(g_u_n, self.nf, f32, "g_u_n"),
+            _ptr(g_theta, self.n_params, f64, "g_theta") if g_theta is not None else None,
+            _ptr(g_ctrl, self.n_ctrl, f64, "g_ctrl") if g_ctrl is not None else None,
+            C.byref(st) if st is not None else None, _stream()), "sim_step_adjoint")
+        return g_u_n, (st.as_dict() if st is not None else None)
+
+    def poisson_solve(self, b, x, alpha=None, tol=0.0, max_iter=0, stats=True):
+        f32 = torch.float32
+        st = L.SimStats() if stats else None
+        L.check(self.lib.poisson_solve(self.h, _ptr(alpha, self.nf, f32, "alpha"), _ptr(b, self.nc, f32, "b"),
+                                       _ptr(x, self.nc, f32, "x"), float(tol), int(max_iter),
+                                       C.byref(st) if st is not None else None, _stream()), "poisson_solve")
+        return x, (st.as_dict() if st is not None else None)
+
+    def set_geometry(self, theta=None, ctrl=None, alpha_out=None):
+        keep, thp, ctp = self._geom(theta, ctrl)
+        L.check(self.lib.sim_set_geometry(self.h, thp, ctp, _ptr(alpha_out, self.nf, torch.float32, "alpha"),
+                                          _stream()), "sim_set_geometry")
+        return alpha_out
+
+
+# ---- function-style aliases with the C ABI's names -----------------------
+
+def sim_create(cfg: Config) -> Sim:
+    return Sim(cfg)
+
+
+def sim_step(sim: Sim, u_n, theta=None, ctrl=None, u_n1=None, p_n1=None):
+    return sim.step(u_n, theta, ctrl, u_n1, p_n1)
+
+
+def sim_project(sim: Sim, u_in, theta=None, ctrl=None, u_out=None, p_out=None):
+    return sim.project(u_in, theta, ctrl, u_out, p_out)
+
+
+def sim_step_adjoint(sim: Sim, u_n, u_n1, g_u_n1, theta=None, ctrl=None, g_u_n=None, g_theta=None, g_ctrl=None):
+    return sim.step_adjoint(u_n, u_n1, g_u_n1, theta, ctrl, g_u_n, g_theta, g_ctrl)
+
+
+def poisson_solve(sim: Sim, b, x, alpha=None, tol=0.0, max_iter=0):
+    return sim.poisson_solve(b, x, alpha, tol, max_iter)
+
+
+def ellipsoid_poses(theta0, ctrl, dt) -> np.ndarray:
+    """(T, 15) per-step ellipsoid geometry (c, a, R) from theta0 (9) and ctrl (T, 6)."""
+    lib = L.load()
+    th = np.ascontiguousarray(np.asarray(theta0, np.float64).ravel())
+    ct = np.ascontiguousarray(np.asarray(ctrl, np.float64).reshape(-1, 6))
+    if th.size != 9:
+        raise ValueError("theta0 must hold 9 values")
+    T = ct.shape[0]
+    out = np.zeros((T, 15))
+    dp = C.POINTER(C.c_double)
+    L.check(lib.sim_ellipsoid_poses(th.ctypes.data_as(dp), ct.ctypes.data_as(dp), T, float(dt),
+                                    out.ctypes.data_as(dp)), "sim_ellipsoid_poses")
+    return out
+
+
+def ellipsoid_poses_adjoint(theta0, ctrl, dt, g_steps, g_ctrl_direct):
+    """Chain per-step partials through the pose dynamics: returns (dJ/dtheta0 (9), dJ/dctrl (T, 6))."""
+    lib = L.load()
+    th = np.ascontiguousarray(np.asarray(theta0, np.float64).ravel())
+    ct = np.ascontiguousarray(np.asarray(ctrl, np.float64).reshape(-1, 6))
+    T = ct.shape[0]
+    gs = np.ascontiguousarray(np.asarray(g_steps, np.float64).reshape(T, 15))
+    gd = np.ascontiguousarray(np.asarray(g_ctrl_direct, np.float64).reshape(T, 6))
+    gth = np.zeros(9)
+    gct = np.zeros((T, 6))
+    dp = C.POINTER(C.c_double)
+    L.check(lib.sim_ellipsoid_poses_adjoint(th.ctypes.data_as(dp), ct.ctypes.data_as(dp), T, float(dt),
+                                            gs.ctypes.data_as(dp), gd.ctypes.data_as(dp),
+                                            gth.ctypes.data_as(dp), gct.ctypes.data_as(dp)),
+            "sim_ellipsoid_poses_adjoint")
+    return gth, gct

@@ -1,0 +1,262 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bars: velocity relative L2 <= 1e-5 per teacher-forced step; gradients within
+1e-3 relative; Poisson solutions to the requested relative residual.
+"""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle.mac import Grid
+from oracle.geometry import sphere_geometry, EllipsoidGeometry
+from oracle.projection import Projection, Operators
+from oracle.step import Step, StepParams
+from oracle.rollout import EllipsoidRollout, StaticRollout, octant_loss, octant_mask, rodrigues
+from paper_2405_14903_amd.sim import Sim, Config, ellipsoid_poses
+from tests.gpu_common import (announce, dev, host, rel_l2, sphere_cfg, ellipsoid_cfg, ellipsoid_step_params,
+                              remove_floating_means)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    yield
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Poisson solve
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,precision", [((32, 32, 32), "fp32"), ((24, 20, 12), "fp32"), ((32, 48, 16), "fp32"),
+                                         ((32, 32, 32), "fp16"), ((32, 32, 32), "bf16")])
+def test_poisson_solve_matches_oracle(n, precision):
+    announce(f"poisson_solve n={n} {precision}")
+    sc = scenes.scene_spheres_projection(seed=3, n=n[0])
+    g = Grid(n, 1.0 / n[0])
+    rng = np.random.default_rng(11)
+    u = scenes.curl_noise(n, g.dx, rng) + scenes.face_noise(n, rng)
+    geo = sphere_geometry(g, sc.spheres)
+    ops = Operators(g, geo.alpha)
+    b = ops.remove_null(np.where(ops.active, ops.GT @ (geo.alpha * u), 0.0))
+    from oracle.projection import solve
+    P, _ = solve(ops, b, tol=1e-12)
+    cfg = sphere_cfg(n, sc.spheres, tol=1e-6, precision=precision)
+    with Sim(cfg) as sim:
+        x = torch.zeros(g.ncells, device="cuda")
+        _, st = sim.poisson_solve(dev(b), x, alpha=dev(geo.alpha), tol=1e-6, max_iter=100)
+        torch.cuda.synchronize()
+    assert st["converged"] and not st["nonfinite"], st
+    assert st["true_rel_res"] <= 2e-6, st
+    assert st["iters"] <= 30, st
+    xg = remove_floating_means(ops, host(x))
+    # error of the pressure gradient (what the velocity sees), relative
+    e = rel_l2(ops.G @ xg, ops.G @ P, mask=geo.alpha > 0)
+    assert e <= 1e-4, e
+
+
+def test_poisson_zero_rhs_and_iteration_cap():
+    announce("poisson edge cases")
+    n = (16, 16, 16)
+    g = Grid(n, 1 / 16)
+    sph = np.array([[0.5, 0.5, 0.5, 0.25]])
+    geo = sphere_geometry(g, sph)
+    with Sim(sphere_cfg(n, sph)) as sim:
+        x = torch.zeros(g.ncells, device="cuda")
+        _, st = sim.poisson_solve(torch.zeros(g.ncells, device="cuda"), x, alpha=dev(geo.alpha))
+        torch.cuda.synchronize()
+        assert st["iters"] == 0 and st["converged"] and float(x.abs().max()) == 0.0
+        ops = Operators(g, geo.alpha)
+        rng = np.random.default_rng(0)
+        b = ops.remove_null(np.where(ops.active, ops.GT @ (geo.alpha * rng.uniform(-1, 1, g.nfaces)), 0))
+        x.zero_()
+        _, st = sim.poisson_solve(dev(b), x, alpha=dev(geo.alpha), tol=1e-12, max_iter=1)
+        torch.cuda.synchronize()
+        assert st["iters"] == 1 and not st["converged"] and 0 < st["rel_res"] < 1
+
+
+# ---------------------------------------------------------------------------
+# forward step (teacher forced)
+# ---------------------------------------------------------------------------
+
+def test_sphere_step_parity_32():
+    announce("sphere step parity 32^3")
+    sc = scenes.scene_sphere_rollout(seed=0, n=32, steps=3)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-12)
+    geo = sphere_geometry(g, sc.spheres)
+    cfg = sphere_cfg(sc.n, sc.spheres, tol=1e-7)
+    u = sc.u0
+    with Sim(cfg) as sim:
+        for n in range(3):
+            st_o = Step(prm, u, geo.alpha, geo.us)
+            ug, st = sim.step(dev(u), sc.spheres.ravel())
+            torch.cuda.synchronize()
+            e = rel_l2(host(ug), st_o.result)
+            announce(f"  step {n}: rel-L2 {e:.2e} iters {st['iters']} res {st['true_rel_res']:.1e}")
+            assert st["converged"]
+            assert e <= 1e-5, (n, e)
+            u = st_o.result
+
+
+def test_ellipsoid_step_parity_32():
+    announce("ellipsoid step parity 32^3")
+    sc = scenes.scene_ellipsoid_rollout(seed=0, n=32, steps=4)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-12)
+    poses = ellipsoid_poses(sc.theta0, sc.ctrl, sc.dt)
+    u = sc.u0
+    with Sim(ellipsoid_cfg(sc.n, tol=1e-7)) as sim:
+        for n in range(4):
+            c, a, R, v, w = ellipsoid_step_params(poses[n], sc.ctrl[n])
+            geo = EllipsoidGeometry(g, c, a, R, v, w)
+            st_o = Step(prm, u, geo.alpha, geo.us)
+            ug, st = sim.step(dev(u), poses[n], sc.ctrl[n])
+            torch.cuda.synchronize()
+            e = rel_l2(host(ug), st_o.result)
+            announce(f"  step {n}: rel-L2 {e:.2e} iters {st['iters']}")
+            assert e <= 1e-5, (n, e)
+            u = st_o.result
+
+
+def test_geometry_fractions_match_oracle():
+    announce("geometry fractions")
+    sc = scenes.scene_ellipsoid_rollout(seed=4, n=32, steps=1)
+    g = Grid(sc.n, sc.dx)
+    poses = ellipsoid_poses(sc.theta0, sc.ctrl, sc.dt)
+    c, a, R, v, w = ellipsoid_step_params(poses[0], sc.ctrl[0])
+    geo = EllipsoidGeometry(g, c, a, R, v, w)
+    with Sim(ellipsoid_cfg(sc.n)) as sim:
+        out = torch.empty(g.nfaces, device="cuda")
+        sim.set_geometry(poses[0], sc.ctrl[0], alpha_out=out)
+        torch.cuda.synchronize()
+    ag = host(out)
+    assert np.array_equal(ag > 0, geo.alpha > 0)
+    np.testing.assert_allclose(ag, geo.alpha, atol=1e-7, rtol=0)
+
+
+def test_forward_is_deterministic():
+    announce("determinism")
+    sc = scenes.scene_ellipsoid_rollout(seed=1, n=32, steps=1)
+    poses = ellipsoid_poses(sc.theta0, sc.ctrl, sc.dt)
+    with Sim(ellipsoid_cfg(sc.n, tol=1e-6)) as sim:
+        u = dev(sc.u0)
+        a, _ = sim.step(u, poses[0], sc.ctrl[0])
+        b, _ = sim.step(u, poses[0], sc.ctrl[0])
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)
+
+
+def test_rest_stays_at_rest_and_nonfinite_flag():
+    announce("rest / nonfinite")
+    n = (16, 16, 16)
+    sph = np.array([[0.5, 0.45, 0.55, 0.2]])
+    with Sim(sphere_cfg(n, sph)) as sim:
+        z = torch.zeros(sim.nf, device="cuda")
+        out, st = sim.step(z, sph.ravel())
+        torch.cuda.synchronize()
+        assert float(out.abs().max()) == 0.0 and st["iters"] == 0
+        bad = dev(scenes.curl_noise(n, 1 / 16, np.random.default_rng(0)))
+        bad[123] = float("nan")
+        out, st = sim.step(bad, sph.ravel())
+        torch.cuda.synchronize()
+        assert st["nonfinite"] and not st["converged"]
+
+
+# ---------------------------------------------------------------------------
+# adjoint (teacher forced) and rollout gradients
+# ---------------------------------------------------------------------------
+
+def test_step_adjoint_parity_32():
+    announce("ellipsoid step adjoint parity 32^3")
+    sc = scenes.scene_ellipsoid_rollout(seed=2, n=32, steps=2)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-12)
+    poses = ellipsoid_poses(sc.theta0, sc.ctrl, sc.dt)
+    c, a, R, v, w = ellipsoid_step_params(poses[0], sc.ctrl[0])
+    geo = EllipsoidGeometry(g, c, a, R, v, w)
+    st_o = Step(prm, sc.u0, geo.alpha, geo.us)
+    rng = np.random.default_rng(5)
+    gbar = rng.standard_normal(g.nfaces)
+    gu_o, galpha, gus = st_o.vjp(gbar)
+    d = geo.vjp(galpha, gus)
+    with Sim(ellipsoid_cfg(sc.n, tol=1e-7)) as sim:
+        u0 = dev(sc.u0)
+        u1, _ = sim.step(u0, poses[0], sc.ctrl[0])
+        gth = torch.zeros(15, dtype=torch.float64, device="cuda")
+        gct = torch.zeros(6, dtype=torch.float64, device="cuda")
+        gu, st = sim.step_adjoint(u0, u1, dev(gbar), poses[0], sc.ctrl[0], g_theta=gth, g_ctrl=gct)
+        torch.cuda.synchronize()
+    e = rel_l2(host(gu), gu_o)
+    announce(f"  dJ/du rel-L2 {e:.2e}  iters {st['iters']}")
+    assert e <= 1e-4, e
+    th_o = np.concatenate([d["c"], d["a"], d["R"].ravel()])
+    ct_o = np.concatenate([d["v"], d["w"]])
+    e_th = rel_l2(host(gth), th_o)
+    e_ct = rel_l2(host(gct), ct_o)
+    announce(f"  dJ/dtheta rel {e_th:.2e}  dJ/dctrl rel {e_ct:.2e}")
+    assert e_th <= 1e-3 and e_ct <= 1e-3, (e_th, e_ct)
+
+
+def test_sphere_rollout_gradient_wrt_initial_velocity():
+    """Configuration 'plain method': 32^3, static sphere, 10 steps, octant loss."""
+    announce("sphere rollout gradient 32^3 x 10")
+    from paper_2405_14903_amd.rollout import Rollout
+    sc = scenes.scene_sphere_rollout(seed=0, n=32, steps=10)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-10)
+    ro_o = StaticRollout(prm, sc.u0, sc.spheres)
+    J_o, gT = octant_loss(g, ro_o.forward(10))
+    gu_o = ro_o.backward(gT)
+    with Sim(sphere_cfg(sc.n, sc.spheres, tol=1e-7)) as sim:
+        ro = Rollout(sim, 10, lambda n: (sc.spheres.ravel(), None), every=4)
+        uT = ro.forward(dev(sc.u0))
+        m = torch.tensor(octant_mask(g), device="cuda")
+        J = float((uT.double() ** 2 * m).sum())
+        gu = ro.backward((2 * uT * m).float())
+        torch.cuda.synchronize()
+    assert abs(J - J_o) <= 1e-4 * abs(J_o), (J, J_o)
+    e = rel_l2(host(gu), gu_o)
+    announce(f"  loss {J:.6f} vs {J_o:.6f}; dJ/du0 rel-L2 {e:.2e}")
+    assert e <= 1e-3, e
+
+
+def test_ellipsoid_rollout_gradients_vs_oracle_and_fd():
+    """Differentiable-rollout configuration on a 32^3 copy: shape and control
+    gradients against the oracle adjoint and its central differences (h = 1e-3)."""
+    announce("ellipsoid rollout gradients 32^3 x 8")
+    from paper_2405_14903_amd.rollout import EllipsoidRolloutFn
+    T = 8
+    sc = scenes.scene_ellipsoid_rollout(seed=0, n=32, steps=T)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-11)
+    ro_o = EllipsoidRollout(prm, sc.u0, sc.theta0, sc.ctrl)
+    J_o, gT = octant_loss(g, ro_o.forward())
+    gu_o, gth_o, gct_o = ro_o.backward(gT)
+
+    def J_of(th):
+        r = EllipsoidRollout(prm, sc.u0, th, sc.ctrl)
+        return octant_loss(g, r.forward(keep=False))[0]
+    h = 1e-3
+    fd = np.array([(J_of(sc.theta0 + h * e) - J_of(sc.theta0 - h * e)) / (2 * h) for e in np.eye(9)[[0, 4, 7]]])
+    with Sim(ellipsoid_cfg(sc.n, tol=1e-7)) as sim:
+        u0 = dev(sc.u0)
+        th = torch.tensor(sc.theta0, requires_grad=True)
+        ct = torch.tensor(sc.ctrl, requires_grad=True)
+        uT = EllipsoidRolloutFn.apply(u0, th, ct, sim, 4)
+        m = torch.tensor(octant_mask(g), device="cuda")
+        J = (uT.double() ** 2 * m).sum()
+        J.backward()
+        torch.cuda.synchronize()
+    gth = th.grad.numpy()
+    gct = ct.grad.numpy()
+    e_th = rel_l2(gth, gth_o)
+    e_ct = rel_l2(gct, gct_o)
+    announce(f"  J {float(J):.6f} vs {J_o:.6f}; theta rel {e_th:.2e} ctrl rel {e_ct:.2e}")
+    assert abs(float(J) - J_o) <= 1e-4 * abs(J_o)
+    assert e_th <= 1e-3 and e_ct <= 1e-3, (e_th, e_ct)
+    assert rel_l2(gth[[0, 4, 7]], fd) <= 1e-3, (gth[[0, 4, 7]], fd)
