@@ -9,8 +9,13 @@ Paper, Sec. Projection: with S = diag(alpha) and k = dt / (rho dx),
 i.e. the fluid flux alpha u plus the solid flux (1 - alpha) u_s through the
 faces of every cell balances.  Readings (listed in the design notes):
 
-* on faces with alpha = 0 the new velocity is the solid's, U^{n+1}_f = U_s,f
-  (such faces carry no fluid; Eq. u_next_matrix is applied where alpha > 0);
+* the fluid velocity of a face is W = U^ - k G P (Eq. u_next_matrix); the
+  velocity stored on a face is its area average over the fluid and solid
+  parts, U^{n+1} = alpha W + (1 - alpha) U_s.  On fully fluid faces this is
+  Eq. u_next_matrix itself; on faces with alpha = 0 it is the solid velocity;
+  it is continuous in alpha (so in the shape parameters), and the stored
+  field is exactly divergence free, G^T U^{n+1} = 0 -- which is the balance
+  of Eq. projection_matrix;
 * cells with sum(alpha over their faces) = 0 are inactive (fully solid) and
   carry no pressure unknown;
 * a connected set of active cells (joined through faces with alpha > 0) that
@@ -23,9 +28,10 @@ faces of every cell balances.  Readings (listed in the design notes):
   serves for tiny grids.
 
 Pinned by: tests/test_oracle_projection.py (dense direct solve at tiny sizes
-with solids, walls, outflow and periodic sides; zero weighted divergence after
-projection; idempotence; energy decrease and orthogonality; constant shifts of
-P leave U unchanged; rest and hydrostatic cases).
+with solids, walls, outflow and periodic sides; zero divergence of the stored
+field; the fluid velocity is a fixed point of a second projection; energy
+decrease and S-orthogonality of the fluid velocity; constant shifts of P leave
+U unchanged; rest and hydrostatic cases).
 """
 from __future__ import annotations
 
@@ -156,7 +162,8 @@ class Projection:
     """Eq. projection_matrix + Eq. u_next_matrix, with tangent and adjoint.
 
     ``uhat``: advected (+ viscous) face velocity; ``us``: solid face velocity;
-    ``alpha``: face fractions.  ``k = dt / (rho dx)``.
+    ``alpha``: face fractions.  ``k = dt / (rho dx)``.  ``W`` is the fluid
+    velocity, ``result`` the stored face-average velocity.
     """
 
     def __init__(self, grid: Grid, uhat, alpha, us, k, tol=1e-12, method="pcg"):
@@ -166,12 +173,12 @@ class Projection:
         # right-hand side of Eq. projection_matrix (divided by k: unit-scaled system)
         self.b = ops.GT @ (alpha * uhat + (1.0 - alpha) * us)
         self.P, self.info = solve(ops, self.b / k, tol, method)
-        m = ops.mask
-        self.result = np.where(m, uhat - k * (ops.G @ self.P), us)
+        self.W = uhat - k * (ops.G @ self.P)
+        self.result = alpha * self.W + (1.0 - alpha) * us
 
-    def weighted_divergence(self, u):
-        """G^T (S u + (I - S) u_s): zero after projection."""
-        return self.ops.GT @ (self.alpha * u + (1.0 - self.alpha) * self.us)
+    def divergence(self, u):
+        """G^T u (= -dx * discrete divergence): zero for the stored field."""
+        return self.ops.GT @ u
 
     def jvp(self, duhat, dalpha, dus):
         ops, k, a = self.ops, self.k, self.alpha
@@ -180,25 +187,21 @@ class Projection:
         db = ops.GT @ (a * duhat + (1.0 - a) * dus + dalpha * (self.uhat - self.us))
         rhs = db / k - ops.GT @ (dalpha * GP)
         dP, _ = solve(ops, rhs, self.tol, self.method)
-        return np.where(ops.mask, duhat - k * (ops.G @ dP), dus)
+        dW = duhat - k * (ops.G @ dP)
+        return a * dW + dalpha * (self.W - self.us) + (1.0 - a) * dus
 
     def vjp(self, g):
         """Returns (dJ/duhat, dJ/dalpha, dJ/dus) for dJ/dU^{n+1} = g.
 
         Derived as the transpose of the forward map (Sec. Back-propagation
-        through Time, Projection paragraph, and through Geometry):
-          dJ/dP = -k G^T M g; solve A y = dJ/dP with A = k G^T S G;
-          dJ/dU^ = M g + S G y; dJ/dU_s = (I - M) g + (I - S) G y;
-          dJ/dalpha_f = (G y)_f (U^_f - U_s,f - k (G P)_f).
+        through Time, Projection paragraph, and through Geometry), with
+        A = k G^T S G:
+          dJ/dP = -k G^T S g;  A y = dJ/dP;  h = g + G y;
+          dJ/dU^ = S h;  dJ/dU_s = (I - S) h;  dJ/dalpha_f = h_f (W_f - U_s,f).
         """
         ops, k, a = self.ops, self.k, self.alpha
-        m = ops.mask.astype(float)
-        gP = -k * (ops.GT @ (m * g))
+        gP = -k * (ops.GT @ (a * g))
         y, _ = solve(ops, gP / k, self.tol, self.method)    # A y = gP  <=>  (G^T S G) y = gP / k
-        Gy = ops.G @ y
-        GP = ops.G @ self.P
-        g_uhat = m * g + a * Gy
-        g_us = (1.0 - m) * g + (1.0 - a) * Gy
-        g_alpha = Gy * (self.uhat - self.us - k * GP)
+        h = g + ops.G @ y
         self.y = y
-        return g_uhat, g_alpha, g_us
+        return a * h, h * (self.W - self.us), (1.0 - a) * h

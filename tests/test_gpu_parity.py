@@ -47,7 +47,7 @@ def test_poisson_solve_matches_oracle(n, precision):
     P, _ = solve(ops, b, tol=1e-12)
     cfg = sphere_cfg(n, sc.spheres, tol=1e-6, precision=precision)
     with Sim(cfg) as sim:
-        x = torch.zeros(g.ncells, device="cuda")
+        x = torch.zeros(g.ncells, dtype=torch.float32, device="cuda")
         _, st = sim.poisson_solve(dev(b), x, alpha=dev(geo.alpha), tol=1e-6, max_iter=100)
         torch.cuda.synchronize()
     assert st["converged"] and not st["nonfinite"], st
@@ -66,8 +66,8 @@ def test_poisson_zero_rhs_and_iteration_cap():
     sph = np.array([[0.5, 0.5, 0.5, 0.25]])
     geo = sphere_geometry(g, sph)
     with Sim(sphere_cfg(n, sph)) as sim:
-        x = torch.zeros(g.ncells, device="cuda")
-        _, st = sim.poisson_solve(torch.zeros(g.ncells, device="cuda"), x, alpha=dev(geo.alpha))
+        x = torch.zeros(g.ncells, dtype=torch.float32, device="cuda")
+        _, st = sim.poisson_solve(torch.zeros(g.ncells, dtype=torch.float32, device="cuda"), x, alpha=dev(geo.alpha))
         torch.cuda.synchronize()
         assert st["iters"] == 0 and st["converged"] and float(x.abs().max()) == 0.0
         ops = Operators(g, geo.alpha)
@@ -131,7 +131,7 @@ def test_geometry_fractions_match_oracle():
     c, a, R, v, w = ellipsoid_step_params(poses[0], sc.ctrl[0])
     geo = EllipsoidGeometry(g, c, a, R, v, w)
     with Sim(ellipsoid_cfg(sc.n)) as sim:
-        out = torch.empty(g.nfaces, device="cuda")
+        out = torch.empty(g.nfaces, dtype=torch.float32, device="cuda")
         sim.set_geometry(poses[0], sc.ctrl[0], alpha_out=out)
         torch.cuda.synchronize()
     ag = host(out)
@@ -156,7 +156,7 @@ def test_rest_stays_at_rest_and_nonfinite_flag():
     n = (16, 16, 16)
     sph = np.array([[0.5, 0.45, 0.55, 0.2]])
     with Sim(sphere_cfg(n, sph)) as sim:
-        z = torch.zeros(sim.nf, device="cuda")
+        z = torch.zeros(sim.nf, dtype=torch.float32, device="cuda")
         out, st = sim.step(z, sph.ravel())
         torch.cuda.synchronize()
         assert float(out.abs().max()) == 0.0 and st["iters"] == 0

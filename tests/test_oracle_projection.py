@@ -46,14 +46,21 @@ def test_pcg_matches_dense_direct_solve(bc):
 
 
 @pytest.mark.parametrize("bc", ["closed", "outflow"])
-def test_weighted_divergence_vanishes_and_idempotent(bc):
+def test_stored_field_divergence_free_and_fluid_velocity_fixed_point(bc):
     g, geo, uhat = _setup(bc, n=8, seed=1)
     pr = Projection(g, uhat, geo.alpha, geo.us, 0.5, tol=1e-13)
-    wd = pr.weighted_divergence(pr.result)
+    # the balance of Eq. projection_matrix: G^T (S W + (I - S) U_s) = G^T U^{n+1} = 0
+    assert np.linalg.norm(pr.divergence(pr.result)) <= 1e-11 * np.linalg.norm(pr.b)
+    wd = pr.divergence(geo.alpha * pr.W + (1 - geo.alpha) * geo.us)
     assert np.linalg.norm(wd) <= 1e-11 * np.linalg.norm(pr.b)
-    again = Projection(g, pr.result, geo.alpha, geo.us, 0.5, tol=1e-13)
+    # projecting the fluid velocity again changes nothing
+    again = Projection(g, pr.W, geo.alpha, geo.us, 0.5, tol=1e-13)
     assert np.abs(again.P).max() <= 1e-10 * np.abs(pr.P).max()
     np.testing.assert_allclose(again.result, pr.result, atol=1e-11)
+    # faces with alpha = 1 follow Eq. u_next_matrix, faces with alpha = 0 the solid
+    full, none = geo.alpha == 1.0, geo.alpha == 0.0
+    np.testing.assert_allclose(pr.result[full], (uhat - 0.5 * pr.ops.G @ pr.P)[full], atol=1e-14)
+    np.testing.assert_array_equal(pr.result[none], geo.us[none])
 
 
 def test_energy_and_orthogonality_with_static_solid():
@@ -61,9 +68,10 @@ def test_energy_and_orthogonality_with_static_solid():
     pr = Projection(g, uhat, geo.alpha, geo.us, 1.0, tol=1e-13)
     a = geo.alpha
     e_before = np.sum(a * uhat ** 2)
-    e_after = np.sum(a * pr.result ** 2)
+    e_after = np.sum(a * pr.W ** 2)
     assert e_after <= e_before
-    orth = np.sum(a * (uhat - pr.result) * pr.result)
+    # the fluid velocity is the S-orthogonal projection of U^
+    orth = np.sum(a * (uhat - pr.W) * pr.W)
     assert abs(orth) <= 1e-11 * e_before
 
 
@@ -71,9 +79,9 @@ def test_pressure_constant_shift_leaves_velocity():
     g, geo, uhat = _setup("closed", n=6, seed=3)
     pr = Projection(g, uhat, geo.alpha, geo.us, 0.8, tol=1e-13)
     G = pr.ops.G
-    m = pr.ops.mask
+    a = geo.alpha
     shifted = np.where(pr.ops.active, pr.P + 3.25, 0.0)
-    u2 = np.where(m, uhat - 0.8 * (G @ shifted), geo.us)
+    u2 = a * (uhat - 0.8 * (G @ shifted)) + (1 - a) * geo.us
     np.testing.assert_allclose(u2, pr.result, atol=1e-12)
 
 
@@ -89,8 +97,7 @@ def test_floating_pocket_components():
     uhat = rng.uniform(-1, 1, g.nfaces)
     pr = Projection(g, uhat, alpha, geo.us, 1.0, tol=1e-13)
     assert ops.n_floating == 8
-    wd = pr.weighted_divergence(pr.result)
-    assert np.linalg.norm(wd) <= 1e-10 * np.linalg.norm(pr.b)
+    assert np.linalg.norm(pr.divergence(pr.result)) <= 1e-10 * np.linalg.norm(pr.b)
     pd = Projection(g, uhat, alpha, geo.us, 1.0, method="dense")
     np.testing.assert_allclose(pr.result, pd.result, atol=1e-10)
 

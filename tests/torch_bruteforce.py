@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-torch.set_default_dtype(torch.float64)
+F64 = torch.float64
 
 
 def _skew(v):
@@ -24,7 +24,7 @@ def _skew(v):
 def _rot(r):
     t = torch.sqrt(torch.sum(r * r))
     K = _skew(r)
-    return torch.eye(3) + torch.sin(t) / t * K + (1 - torch.cos(t)) / (t * t) * (K @ K)
+    return torch.eye(3, dtype=F64) + torch.sin(t) / t * K + (1 - torch.cos(t)) / (t * t) * (K @ K)
 
 
 class TinyBox:
@@ -65,11 +65,11 @@ class TinyBox:
                             cs.append(q[0] + (nx + 1) * (q[1] + (ny + 1) * q[2]))
                         corners.append(cs)
                         f += 1
-        self.pos = torch.tensor(pos)
+        self.pos = torch.tensor(pos, dtype=F64)
         self.axis = torch.tensor(axis)
         self.onwall = torch.tensor(onwall)
         self.corners = torch.tensor(corners)
-        self.G = torch.tensor(G)
+        self.G = torch.tensor(G, dtype=F64)
         kk, jj, ii = np.indices((nz + 1, ny + 1, nx + 1))
         self.nodes = torch.tensor(np.stack([ii.ravel(), jj.ravel(), kk.ravel()], 1) * dx, dtype=torch.float64)
 
@@ -78,7 +78,7 @@ class TinyBox:
         P = phi_nodes[self.corners]                      # (F, 4)
         fl = (P > 0).detach()
         cnt = fl.sum(1)
-        out = torch.zeros(self.F)
+        out = torch.zeros(self.F, dtype=F64)
         mean = P.mean(1)
         for k in range(4):
             r = [(k + s) % 4 for s in range(4)]
@@ -90,18 +90,18 @@ class TinyBox:
                 den = torch.where(dif, a - b, torch.ones_like(a))
                 return torch.where(dif, a / den, torch.zeros_like(a))
             one = (cnt == 1) & f0
-            out = out + torch.where(one, 0.5 * safe(p0, p1) * safe(p0, p3), torch.zeros(self.F))
+            out = out + torch.where(one, 0.5 * safe(p0, p1) * safe(p0, p3), torch.zeros(self.F, dtype=F64))
             three = (cnt == 3) & ~f0
-            out = out + torch.where(three, 1 - 0.5 * safe(p0, p1) * safe(p0, p3), torch.zeros(self.F))
+            out = out + torch.where(three, 1 - 0.5 * safe(p0, p1) * safe(p0, p3), torch.zeros(self.F, dtype=F64))
             adj = (cnt == 2) & f0 & f1
-            out = out + torch.where(adj, 0.5 * (safe(p0, p3) + safe(p1, p2)), torch.zeros(self.F))
+            out = out + torch.where(adj, 0.5 * (safe(p0, p3) + safe(p1, p2)), torch.zeros(self.F, dtype=F64))
             if k < 2:
                 dg = (cnt == 2) & f0 & f2
                 conn = 1 - 0.5 * safe(p1, p0) * safe(p1, p2) - 0.5 * safe(p3, p0) * safe(p3, p2)
                 sep = 0.5 * safe(p0, p1) * safe(p0, p3) + 0.5 * safe(p2, p1) * safe(p2, p3)
-                out = out + torch.where(dg, torch.where(mean > 0, conn, sep), torch.zeros(self.F))
-        out = torch.where(cnt == 4, torch.ones(self.F), out)
-        return torch.where(self.onwall, torch.zeros(self.F), out)
+                out = out + torch.where(dg, torch.where(mean > 0, conn, sep), torch.zeros(self.F, dtype=F64))
+        out = torch.where(cnt == 4, torch.ones(self.F, dtype=F64), out)
+        return torch.where(self.onwall, torch.zeros(self.F, dtype=F64), out)
 
     def phi_ellipsoid(self, c, a, R):
         p = (self.nodes - c) @ R
@@ -112,7 +112,7 @@ class TinyBox:
     def rigid(self, c, v, w):
         vel = v + torch.cross(w.expand(self.F, 3), self.pos - c, dim=1)
         us = vel.gather(1, self.axis[:, None]).squeeze(1)
-        return torch.where(self.onwall, torch.zeros(self.F), us)
+        return torch.where(self.onwall, torch.zeros(self.F, dtype=F64), us)
 
     # ---- advection ---------------------------------------------------------
     def _interp(self, comp, e, x):
@@ -158,11 +158,10 @@ class TinyBox:
         Aa = A[ia][:, ia]
         na = ia.numel()
         # one floating component (closed box): pin its mean to zero
-        Aa = Aa + torch.ones(na, na) / na
+        Aa = Aa + torch.ones(na, na, dtype=F64) / na
         Pa = torch.linalg.solve(Aa, b[ia] / k)
-        P = torch.zeros(self.C).index_put((ia,), Pa)
-        mask = (alpha > 0).detach()
-        return torch.where(mask, uhat - k * (G @ P), us)
+        P = torch.zeros(self.C, dtype=F64).index_put((ia,), Pa)
+        return alpha * (uhat - k * (G @ P)) + (1 - alpha) * us
 
 
 def ellipsoid_rollout_loss(box: TinyBox, u0, theta0, ctrl, dt, octant_lo=0.5):
