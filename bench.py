@@ -1,0 +1,227 @@
+"""Benchmark: forward + adjoint cell-steps/s of the differentiable rollout.
+
+Workload (one bench step): the 128^3 closed box with a moving ellipsoid
+(9 shape parameters, 6 controls per step, seeded), curl-noise initial velocity,
+dt = dx/2, 64 steps forward with a checkpoint every 8 steps, then the octant
+loss, and the full adjoint (segment recomputation + per-step adjoint kernels +
+shape / control gradients through the pose dynamics).  Inputs are resident on
+the GPU before timing starts.  value = 128^3 * 64 * K / (wall time of K bench
+steps), for the mixed-precision form (FP16 multigrid preconditioner); the
+plain FP32 form is timed beside it.  Per-step latencies (HIP events around each
+sim_step / sim_step_adjoint) give p50 / p99.
+
+The roofline object reports the dominant kernel (the finest-level multigrid
+post-smoother), timed live with HIP events on the launch stream, against the
+MI355X HBM peak.  The cpu_baseline object times the FP64 oracle on a bounded
+sample (the same scene at 32^3, a few steps forward + adjoint).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 128
+T = 64
+EVERY = 8
+HBM_PEAK_GBS = 8000.0
+ROOFLINE_KERNEL = "mg_post2"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+class StepTimer:
+    """HIP event pairs on torch's current stream (the stream the library uses)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {"fwd": [], "adj": []}
+        self.open = None
+
+    def begin(self, kind):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.open = (kind, e)
+
+    def end(self, kind):
+        e = self.torch.cuda.Event(enable_timing=True)
+        e.record()
+        self.pairs[kind].append((self.open[1], e))
+
+    def latencies(self, kind):
+        return [a.elapsed_time(b) for a, b in self.pairs[kind]]
+
+
+def run_form(precision, steps, warmup, scene, torch, profile_kernel=None):
+    from paper_2405_14903_amd.sim import Config, Sim
+    from paper_2405_14903_amd.rollout import Rollout
+    cfg = Config(n=scene.n, dx=scene.dx, dt=scene.dt, geom="ellipsoid", tol=1e-6, precision=precision,
+                 max_iter=200)
+    sim = Sim(cfg)
+    u0 = torch.tensor(scene.u0, dtype=torch.float32, device="cuda")
+    J = torch.empty(1, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(u0)
+    grads = None
+
+    def one(timer):
+        nonlocal grads
+        ro = Rollout.ellipsoid(sim, scene.theta0, scene.ctrl, every=EVERY, timer=timer)
+        uT = ro.forward(u0)
+        sim.loss_box(uT, J=J, g=g)
+        g0 = ro.backward(g)
+        grads = (g0, ro.geometry_gradients())
+
+    for _ in range(warmup):
+        one(None)
+    print(f"[bench] {precision}: warmup done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    if profile_kernel:
+        sim.profile(profile_kernel)
+    timer = StepTimer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one(timer)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"[bench] {precision}: {steps} rollouts in {wall:.2f} s", file=sys.stderr, flush=True)
+    prof = sim.profile_read() if profile_kernel else None
+    sim.profile(None)
+    fwd = timer.latencies("fwd")
+    adj = timer.latencies("adj")
+    stats = sim.step(u0, *Rollout.ellipsoid(sim, scene.theta0, scene.ctrl).schedule(0))[1]
+    out = {
+        "wall_s": wall,
+        "cell_steps_per_s": (N ** 3) * T * steps / wall,
+        "ms_per_rollout": 1e3 * wall / steps,
+        "fwd_ms_p50": pct(fwd, 50), "fwd_ms_p99": pct(fwd, 99),
+        "adj_ms_p50": pct(adj, 50), "adj_ms_p99": pct(adj, 99),
+        "step_ms_p50": pct(fwd + adj, 50), "step_ms_p99": pct(fwd + adj, 99),
+        "first_step_cg_iters": stats["iters"], "first_step_true_rel_res": stats["true_rel_res"],
+        "loss": float(J.item()),
+    }
+    sim.close()
+    return out, prof, grads
+
+
+def pct(v, q):
+    if not v:
+        return None
+    s = sorted(v)
+    i = min(len(s) - 1, max(0, int(math.ceil(q / 100.0 * len(s))) - 1))
+    return round(s[i], 4)
+
+
+def roofline(prof, precision):
+    """Algorithmic bytes per launch of the finest-level post-smoother
+    z_out = z_in + w D^-1 (r - A z_in), plus the r.z reduction: it reads z_in
+    (storage type), r (FP32), 1/diag (storage type) and the three face-fraction
+    arrays (storage type; each face read once), and writes z_out (FP32)."""
+    es = 4 if precision == "fp32" else 2
+    C = N ** 3
+    F = (N + 1) * N * N * 3
+    bytes_per_launch = C * es + C * 4 + C * es + F * es + C * 4
+    ms, cnt = prof
+    if not cnt:
+        return None
+    avg_s = ms / cnt / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_mg_post2 (finest level, " + precision + ")", "launches": cnt,
+            "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch}
+
+
+def cpu_baseline(steps):
+    """The FP64 oracle as it stands, single-threaded numpy/scipy, on the same
+    scene at 32^3: `steps` steps forward + the full adjoint."""
+    import numpy as np
+    import scenes
+    from oracle.mac import Grid
+    from oracle.step import StepParams
+    from oracle.rollout import EllipsoidRollout, octant_loss
+    n = 32
+    sc = scenes.scene_ellipsoid_rollout(seed=0, n=n, steps=steps)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-10)
+    t0 = time.perf_counter()
+    ro = EllipsoidRollout(prm, sc.u0, sc.theta0, sc.ctrl)
+    _, gT = octant_loss(g, ro.forward())
+    ro.backward(gT)
+    wall = time.perf_counter() - t0
+    return {"value": round(n ** 3 * steps / wall, 1), "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"same moving-ellipsoid scene at 32^3, {steps} steps forward + adjoint (FP64, "
+                      f"solve to 1e-10), {wall:.1f} s wall, single-threaded numpy/scipy"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the rollout of one episode is a "
+              f"single-GPU workload here, and no multi-GPU path is built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import scenes
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
+    main_form, prof, _ = run_form(args.precision, args.steps, args.warmup, scene, torch,
+                                  profile_kernel=ROOFLINE_KERNEL)
+    cmp_form = None
+    if not args.no_compare and args.precision != "fp32":
+        cmp_form, _, _ = run_form("fp32", args.steps, args.warmup, scene, torch)
+    rec = {
+        "metric": "fwd+adjoint cell-steps/s at 128^3 (mixed vs FP32); p50/p99 step latency",
+        "value": round(main_form["cell_steps_per_s"], 1),
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_form["ms_per_rollout"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": "128^3 closed box, moving ellipsoid (9 shape params, 6 controls/step), "
+                               "64 steps forward + adjoint, checkpoint every 8, octant loss",
+                   "grid": [N, N, N], "steps_per_rollout": T, "checkpoint_every": EVERY,
+                   "precision": args.precision, "cg_tol": 1e-6},
+        "latency_ms": {"step_p50": main_form["step_ms_p50"], "step_p99": main_form["step_ms_p99"],
+                       "fwd_p50": main_form["fwd_ms_p50"], "fwd_p99": main_form["fwd_ms_p99"],
+                       "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"]},
+        "first_step_cg_iters": main_form["first_step_cg_iters"],
+        "roofline": roofline(prof, args.precision),
+    }
+    if cmp_form:
+        rec["fp32"] = {"value": round(cmp_form["cell_steps_per_s"], 1),
+                       "ms_per_step": round(cmp_form["ms_per_rollout"], 3),
+                       "step_p50_ms": cmp_form["step_ms_p50"], "step_p99_ms": cmp_form["step_ms_p99"],
+                       "first_step_cg_iters": cmp_form["first_step_cg_iters"]}
+        rec["mixed_over_fp32"] = round(main_form["cell_steps_per_s"] / cmp_form["cell_steps_per_s"], 3)
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -20,10 +20,13 @@
  *              z-faces nx*ny*(nz+1), concatenated; x-face (i,j,k) sits at
  *              (i dx, (j+1/2)dx, (k+1/2)dx) and lies between cells i-1 and i.
  * Pressure scaling: with k = dt/(rho dx), the step solves
- *   (G^T S G) P = G^T (S U^ + (I-S) U_s) / k,   U^{n+1} = U^ - k G P
+ *   (G^T S G) P = G^T (S U^ + (I-S) U_s) / k,   W = U^ - k G P,
+ *   U^{n+1} = S W + (I - S) U_s
  * where (G p)_f = p(cell on the + side) - p(cell on the - side) and a ghost
- * pressure 0 lies beyond OUTFLOW sides.  Faces with alpha = 0 take the solid
- * (or wall / inflow) velocity.
+ * pressure 0 lies beyond OUTFLOW sides.  W is the fluid velocity of
+ * Eq. u_next_matrix; the stored face velocity is the area average of the
+ * fluid and solid (or wall / inflow) velocities over the face, so fully fluid
+ * faces carry W, closed faces the solid velocity, and G^T U^{n+1} = 0.
  *
  * Memory: every float / double array argument named u_*, p_*, b, x, alpha,
  * g_* is DEVICE memory owned by the caller.  theta and ctrl are HOST double
@@ -100,7 +103,7 @@ typedef struct {
 
 typedef struct {
   int32_t iters;          /* CG iterations taken                              */
-  int32_t converged;      /* 1 if the recursive residual reached tol          */
+  int32_t converged;      /* 1 if the true residual (FP64) reached tol        */
   int32_t nonfinite;      /* 1 if a NaN/Inf was met in the residual           */
   int32_t pad;
   double rel_res;         /* recursive relative residual (FP64 norm)          */
@@ -138,14 +141,17 @@ int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const 
                     float* u_out, float* p_out, sim_stats* st, hipStream_t stream);
 
 /* Adjoint of sim_step (Sec. Back-propagation through Time / Geometry).
- * Inputs: u_n (the step's input), u_n1 (its output), theta, ctrl (as given to
- * sim_step), g_u_n1 = dJ/dU^{n+1}.  Output: g_u_n = dJ/dU^n (overwritten;
- * must not alias g_u_n1).  g_theta (n_params doubles) and g_ctrl (n_ctrl
+ * Inputs: u_n (the step's input), p_n1 (the pressure sim_step returned for
+ * it, or NULL: the forward system is solved again when shape / control
+ * gradients are requested), theta, ctrl (as given to sim_step), and
+ * g_u_n1 = dJ/dU^{n+1}.  Output: g_u_n = dJ/dU^n (overwritten; must alias
+ * neither g_u_n1 nor u_n).  g_theta (n_params doubles) and g_ctrl (n_ctrl
  * doubles), device, are ACCUMULATED (+=) with this step's direct partials
  * dJ/dtheta and dJ/dctrl (SIM_GEOM_ELLIPSOID only; NULL to skip).  The
- * adjoint pressure system is solved with the same operator (it is symmetric).
- * Float atomics make g_u_n reproducible only to rounding. */
-int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* u_n1, const double* theta,
+ * adjoint pressure system (G^T S G) y = -G^T S g_u_n1 is solved with the same
+ * operator (it is symmetric); st reports that solve.  Float atomics make
+ * g_u_n reproducible only to rounding. */
+int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, const double* theta,
                          const double* ctrl, const float* g_u_n1, float* g_u_n, double* g_theta,
                          double* g_ctrl, sim_stats* st, hipStream_t stream);
 
@@ -163,6 +169,27 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
  * optionally copy alpha out (velocity layout, may be NULL). */
 int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, float* alpha_out,
                          hipStream_t stream);
+
+/* Loss helper (the octant loss of the benchmark scenes): J = sum of u_f^2
+ * over faces whose centre lies in the box [lo, hi] (physical coordinates,
+ * inclusive), and g = dJ/du = 2 u on those faces, 0 elsewhere.  J: one device
+ * double (overwritten, FP64 fixed-order sum); g: device floats (velocity
+ * layout, overwritten).  lo / hi: host double[3]. */
+int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
+                     hipStream_t stream);
+
+/* Kernel timing for measurement: while enabled, HIP events are recorded on
+ * the launch stream around every launch of one kernel family (multigrid
+ * kernels: finest level only).  sim_profile_read synchronises those events and
+ * returns the summed duration (ms) and the number of launches timed, then
+ * clears them.  kernel: one of sim_kernel, or -1 to disable. */
+typedef enum {
+  SIM_K_GEOM_PHI = 0, SIM_K_GEOM_ALPHA, SIM_K_ADVECT, SIM_K_RHS, SIM_K_UPDATE, SIM_K_ADJ_DIV,
+  SIM_K_ADJ_FACES, SIM_K_ADVECT_ADJ, SIM_K_CG_INIT, SIM_K_CG_APPLY, SIM_K_CG_UPDATE, SIM_K_CG_TRUE,
+  SIM_K_MG_PRE, SIM_K_MG_RESTRICT, SIM_K_MG_POST1, SIM_K_MG_POST2, SIM_K_MG_COARSE, SIM_K_COUNT
+} sim_kernel;
+int32_t sim_profile(sim_handle h, int32_t kernel);
+int32_t sim_profile_read(sim_handle h, double* total_ms, int64_t* count);
 
 /* Rigid ellipsoid pose dynamics (host, FP64).  theta0 (9) = centre c0(3),
  * semi-axes a(3), rotation vector r0(3); R0 = exp([r0]x).  For step n with

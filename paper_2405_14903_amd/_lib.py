@@ -21,8 +21,12 @@ SIM_MAX_SPHERES = 32
 EXPORTS = [
     "sim_version", "sim_status_string", "sim_footprint", "sim_create", "sim_destroy", "sim_layout",
     "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
-    "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint",
+    "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_profile", "sim_profile_read",
 ]
+
+#: sim_kernel ids (include/neuralfluid.h)
+KERNELS = ["geom_phi", "geom_alpha", "advect", "rhs", "update", "adj_div", "adj_faces", "advect_adj", "cg_init",
+           "cg_apply", "cg_update", "cg_true", "mg_pre", "mg_restrict", "mg_post1", "mg_post2", "mg_coarse"]
 
 
 class SimDesc(C.Structure):
@@ -87,6 +91,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_set_geometry": (C.c_int32, [_vp, _dp, _dp, _fp, _vp]),
         "sim_ellipsoid_poses": (C.c_int32, [_dp, _dp, C.c_int32, C.c_double, _dp]),
         "sim_ellipsoid_poses_adjoint": (C.c_int32, [_dp, _dp, C.c_int32, C.c_double, _dp, _dp, _dp, _dp]),
+        "sim_loss_box": (C.c_int32, [_vp, _fp, _dp, _dp, _vp, _fp, _vp]),
+        "sim_profile": (C.c_int32, [_vp, C.c_int32]),
+        "sim_profile_read": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -99,10 +99,6 @@ __device__ inline void tap_scatter(float* __restrict__ g, const Tap& t, float w)
       }
 }
 
-struct VelPtrs {
-  const float* c[3];
-};
-
 __device__ inline void face_pos(int comp, int i, int j, int k, float X[3]) {
   X[0] = (float)i + (comp == 0 ? 0.0f : 0.5f);
   X[1] = (float)j + (comp == 1 ? 0.0f : 0.5f);
@@ -205,7 +201,6 @@ void launch_advect(const Dims& d, double dx, double dt, const double* grav, cons
 
 void launch_advect_adjoint(const Dims& d, double dx, double dt, const float* u, const float* gout,
                            float* gin, hipStream_t s) {
-  launch_fill(gin, d.faces(), 0.0f, s);
   hipLaunchKernelGGL(k_advect_adjoint, dim3(nblocks(d.faces())), dim3(kBlock), 0, s, d,
                      (float)(dt / dx), u, gout, gin);
 }

@@ -28,6 +28,7 @@ struct sim_ctx {
   std::vector<void*> allocs;
   GeomParams last_geom;
   bool have_geom = false;
+  Profiler prof;
 };
 
 namespace {
@@ -99,6 +100,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(C * 4, (void**)&t->b);
   alloc(C * 4, (void**)&t->P);
   alloc(C * 4, (void**)&t->y);
+  alloc(C * 8, (void**)&t->S.x);
   alloc(C * 4, (void**)&t->S.r);
   alloc(C * 4, (void**)&t->S.z);
   alloc(C * 4, (void**)&t->S.q);
@@ -166,8 +168,8 @@ int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomPar
 int last_hip_error() { return hipGetLastError() == hipSuccess ? SIM_OK : SIM_EHIP; }
 
 void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st) {
-  launch_phi_nodes(c->dom, g, c->phi, st);
-  launch_alpha(c->dom, c->phi, c->alpha, st);
+  NF_TIMED(&c->prof, SIM_K_GEOM_PHI, st, launch_phi_nodes(c->dom, g, c->phi, st));
+  NF_TIMED(&c->prof, SIM_K_GEOM_ALPHA, st, launch_alpha(c->dom, c->phi, c->alpha, st));
   solver_setup_levels(c->S, c->alpha, st);
   c->last_geom = g;
   c->have_geom = true;
@@ -220,6 +222,7 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   c->dom.dx = desc->dx;
   c->dom.inflow = desc->inflow_speed;
   c->S.nlev = p.nlev;
+  c->S.prof = &c->prof;
   c->S.precision = desc->precision;
   for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
   bool ok = true;
@@ -275,12 +278,12 @@ int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, 
 static int32_t project_common(sim_handle h, const float* uhat, const GeomParams& g, float* u_out, float* p_out,
                               sim_stats* st, hipStream_t stream) {
   const double kk = k_factor(h->desc);
-  launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream);
+  NF_TIMED(&h->prof, SIM_K_RHS, stream, launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream));
   float* P = p_out ? p_out : h->P;
   launch_fill(P, h->dom.d.cells(), 0.0f, stream);
   int r = solver_solve(h->S, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
   if (r != SIM_OK) return r;
-  launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream);
+  NF_TIMED(&h->prof, SIM_K_UPDATE, stream, launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream));
   return last_hip_error();
 }
 
@@ -291,7 +294,8 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
   int v = make_geom(h, theta, ctrl, g);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
-  launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream);
+  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream));
   return project_common(h, h->uhat, g, u_n1, p_n1, st, stream);
 }
 
@@ -305,23 +309,39 @@ int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const 
   return project_common(h, u_in, g, u_out, p_out, st, stream);
 }
 
-int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* u_n1, const double* theta, const double* ctrl,
+int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, const double* theta, const double* ctrl,
                          const float* g_u_n1, float* g_u_n, double* g_theta, double* g_ctrl, sim_stats* st,
                          hipStream_t stream) {
-  if (!h || !u_n || !u_n1 || !g_u_n1 || !g_u_n || g_u_n == g_u_n1) return SIM_EINVAL;
+  if (!h || !u_n || !g_u_n1 || !g_u_n || g_u_n == g_u_n1 || (const float*)g_u_n == u_n) return SIM_EINVAL;
   GeomParams g;
   int v = make_geom(h, theta, ctrl, g);
   if (v != SIM_OK) return v;
   const bool grad = h->desc.geom == SIM_GEOM_ELLIPSOID && (g_theta || g_ctrl);
+  const double kk = k_factor(h->desc);
   eval_geometry(h, g, stream);
-  // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T M g
-  launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream);
+  // the step's advected field (the fluid velocity W on cut faces needs it)
+  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream));
+  const float* P = p_n1;
+  if (!P && grad) {
+    // no stored pressure: solve the forward system again
+    launch_rhs(h->dom, g, 1.0 / kk, h->alpha, h->uhat, h->b, stream);
+    launch_fill(h->P, h->dom.d.cells(), 0.0f, stream);
+    int r = solver_solve(h->S, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream);
+    if (r != SIM_OK) return r;
+    P = h->P;
+  }
+  // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T S g
+  NF_TIMED(&h->prof, SIM_K_ADJ_DIV, stream, launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream));
   launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
   int r = solver_solve(h->S, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
   if (r != SIM_OK) return r;
-  launch_adj_faces(h->dom, g, grad, h->alpha, h->phi, g_u_n1, h->y, u_n1, h->gu, h->S.partials,
-                   &h->S.sc->ticket[5], g_theta, g_ctrl, stream);
-  launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->gu, g_u_n, stream);
+  NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
+           launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
+                            h->S.partials, &h->S.sc->ticket[5], g_theta, g_ctrl, stream));
+  launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
+  NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
+           launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->gu, g_u_n, stream));
   return last_hip_error();
 }
 
@@ -339,6 +359,35 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
                        stream);
   if (r != SIM_OK) return r;
   return last_hip_error();
+}
+
+int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
+                     hipStream_t stream) {
+  if (!h || !u || !lo || !hi || !J || !g || (const float*)g == u) return SIM_EINVAL;
+  launch_loss_box(h->dom, lo, hi, u, J, g, h->S.partials, &h->S.sc->ticket[6], stream);
+  return last_hip_error();
+}
+
+int32_t sim_profile(sim_handle h, int32_t kernel) {
+  if (!h || kernel < -1 || kernel >= SIM_K_COUNT) return SIM_EINVAL;
+  h->prof.active = kernel;
+  h->prof.used = 0;
+  return SIM_OK;
+}
+
+int32_t sim_profile_read(sim_handle h, double* total_ms, int64_t* count) {
+  if (!h || !total_ms || !count) return SIM_EINVAL;
+  double tot = 0.0;
+  for (size_t q = 0; q + 1 < h->prof.used; q += 2) {
+    if (hipEventSynchronize(h->prof.ev[q + 1]) != hipSuccess) return SIM_EHIP;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, h->prof.ev[q], h->prof.ev[q + 1]) != hipSuccess) return SIM_EHIP;
+    tot += ms;
+  }
+  *total_ms = tot;
+  *count = (int64_t)(h->prof.used / 2);
+  h->prof.used = 0;
+  return SIM_OK;
 }
 
 // ---------------------------------------------------------------------------

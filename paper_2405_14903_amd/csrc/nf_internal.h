@@ -18,6 +18,8 @@ constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coar
 constexpr float kOmega = 0.8f;
 constexpr int kCoarseSweeps = 40;
 constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces
+constexpr double kVcycleRms = 1.0 / 64.0;   // RMS of the (scaled) residual entering the V-cycle
+constexpr float kHalfInvDiagMax = 1024.0f;  // cap of 1/diag in FP16 storage
 
 struct Dims {
   int nx, ny, nz;
@@ -67,12 +69,13 @@ struct CGScalars {
   double bb;         // b . b
   double tol2bb;     // tol^2 * b . b
   double true_rr;    // ||b - A x||^2 recomputed in FP64
+  double vscale;     // scale applied to the fine residual before the V-cycle
   int iters;
   int done;
   int first;
   int nonfinite;
   int maxit;
-  int pad;
+  int converged;     // true residual reached the tolerance
   unsigned ticket[8];   // last-block counters of the reducing kernels
 };
 

@@ -6,13 +6,17 @@
 // (faces with alpha = 0 take the solid velocity).  The unit-scaled system
 // (G^T S G) P = b / k is solved by the MGPCG in nf_solver.hip.
 //
+// The stored face velocity is the area average over the face's fluid and
+// solid parts: U^{n+1} = alpha W + (1 - alpha) U_s with the fluid velocity
+// W = U^ - k G P (Eq. u_next_matrix on fully fluid faces; the solid velocity
+// on closed faces; continuous in alpha).
+//
 // Adjoint (Sec. Back-propagation through Time, Projection paragraph, and Sec.
 // Back-propagation through Geometry), derived as the exact transpose of the
-// forward with M = diag(alpha > 0) and g = dJ/dU^{n+1}:
-//   (G^T S G) y = -G^T M g          (the k factors cancel)
-//   dJ/dU^      = M g + S G y
-//   dJ/dU_s     = (I - M) g + (I - S) G y
-//   dJ/dalpha_f = (G y)_f (U^{n+1}_f - U_s,f)
+// forward with g = dJ/dU^{n+1}:
+//   (G^T S G) y = -G^T S g          (the k factors cancel)
+//   h = g + G y
+//   dJ/dU^ = S h,  dJ/dU_s = (I - S) h,  dJ/dalpha_f = h_f (W_f - U_s,f)
 // and dJ/dalpha, dJ/dU_s are carried to the ellipsoid's pose and controls
 // through the marching-squares fraction and the rigid velocity field.
 #include "nf_internal.h"
@@ -79,16 +83,18 @@ __global__ __launch_bounds__(kBlock) void k_update(Domain D, GeomParams G, float
   if (f >= (long)d.faces()) return;
   int comp, i, j, k;
   face_decode(d, f, comp, i, j, k);
-  if (alpha[f] > 0.0f) {
+  const float a = alpha[f];
+  float v = 0.0f;
+  if (a > 0.0f) {
     float pp, pm;
     face_cells(d, p, comp, i, j, k, pp, pm);
-    out[f] = uhat[f] - kk * (pp - pm);
-  } else {
-    out[f] = (float)face_solid_velocity(D, G, comp, i, j, k);
+    v = a * (uhat[f] - kk * (pp - pm));
   }
+  if (a < 1.0f) v += (1.0f - a) * (float)face_solid_velocity(D, G, comp, i, j, k);
+  out[f] = v;
 }
 
-// rhs_c = -(G^T M g)_c
+// rhs_c = -(G^T S g)_c
 __global__ __launch_bounds__(kBlock) void k_adj_div(Dims d, const float* __restrict__ alpha,
                                                      const float* __restrict__ g, float* __restrict__ rhs) {
   long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
@@ -101,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_div(Dims d, const float* __restr
   float s = 0.0f;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    float m = alpha[f[q]] > 0.0f ? g[f[q]] : 0.0f;
+    float m = alpha[f[q]] * g[f[q]];
     s += (q & 1) ? -m : m;
   }
   rhs[c] = -s;
@@ -232,12 +238,15 @@ __device__ inline int corner_node(const Dims& d, int comp, int i, int j, int k, 
 
 // Per face: dJ/dU^ into gu; with GRAD, the ellipsoid's pose (15) and control
 // (6) partials are reduced (fixed order, FP64) and added to g_theta / g_ctrl.
+// uhat and p are the step's advected field and pressure (for W on cut faces).
 template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, const float* __restrict__ alpha,
+__global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, float kk,
+                                                       const float* __restrict__ alpha,
                                                        const double* __restrict__ phi,
                                                        const float* __restrict__ g,
                                                        const float* __restrict__ y,
-                                                       const float* __restrict__ un1,
+                                                       const float* __restrict__ uhat,
+                                                       const float* __restrict__ p,
                                                        float* __restrict__ gu, double* __restrict__ partials,
                                                        unsigned* __restrict__ ticket,
                                                        double* __restrict__ g_theta,
@@ -250,25 +259,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, co
   if (f < (long)d.faces()) {
     int comp, i, j, k;
     face_decode(d, f, comp, i, j, k);
-    float a = alpha[f];
-    float gf = g[f];
+    const float a = alpha[f];
     float yp, ym;
     face_cells(d, y, comp, i, j, k, yp, ym);
-    float Gy = yp - ym;
-    bool m = a > 0.0f;
-    gu[f] = (m ? gf : 0.0f) + a * Gy;
-    if (GRAD) {
+    const float hf = g[f] + (yp - ym);
+    gu[f] = a * hf;
+    if (GRAD && hf != 0.0f && a < 1.0f) {
       int own = comp == 0 ? i : (comp == 1 ? j : k);
       int sk = side_kind(D, comp, own);
       bool fixed = sk == SIM_BC_WALL || sk == SIM_BC_INFLOW;
       if (!fixed) {
         double us = face_solid_velocity(D, G, comp, i, j, k);
-        double galpha = m ? (double)Gy * ((double)un1[f] - us) : 0.0;
-        double gus = (m ? 0.0 : (double)gf) + (1.0 - (double)a) * (double)Gy;
-        if (galpha != 0.0 && a < 1.0f) {
-          double p[4], dg[4];
-          for (int q = 0; q < 4; ++q) p[q] = phi[corner_node(d, comp, i, j, k, q)];
-          fraction_grad(p, dg);
+        if (a > 0.0f) {
+          // dJ/dalpha = h (W - U_s), W = U^ - k G P
+          float pp, pm;
+          face_cells(d, p, comp, i, j, k, pp, pm);
+          double W = (double)uhat[f] - (double)kk * ((double)pp - (double)pm);
+          double galpha = (double)hf * (W - us);
+          double ph[4], dg[4];
+          for (int q = 0; q < 4; ++q) ph[q] = phi[corner_node(d, comp, i, j, k, q)];
+          fraction_grad(ph, dg);
           for (int q = 0; q < 4; ++q) {
             if (dg[q] == 0.0) continue;
             double xyz[3], gp[15];
@@ -278,22 +288,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, co
             for (int t = 0; t < 15; ++t) acc[t] += w * gp[t];
           }
         }
-        if (gus != 0.0) {
-          double x[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * D.dx, (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
-                         (k + (comp == 2 ? 0.0 : 0.5)) * D.dx};
-          double r0 = x[0] - G.c[0], r1 = x[1] - G.c[1], r2 = x[2] - G.c[2];
-          // u_s,comp = v_comp + (w x r)_comp
-          acc[15 + comp] += gus;
-          if (comp == 0) {
-            acc[19] += gus * r2;  acc[20] -= gus * r1;     // d/dw
-            acc[1] += gus * G.w[2]; acc[2] -= gus * G.w[1];  // d/dc = -d/dr
-          } else if (comp == 1) {
-            acc[18] -= gus * r2;  acc[20] += gus * r0;
-            acc[0] -= gus * G.w[2]; acc[2] += gus * G.w[0];
-          } else {
-            acc[18] += gus * r1;  acc[19] -= gus * r0;
-            acc[0] += gus * G.w[1]; acc[1] -= gus * G.w[0];
-          }
+        // dJ/dU_s = (1 - alpha) h, through u_s = v + w x (x - c)
+        double gus = (1.0 - (double)a) * (double)hf;
+        double x[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * D.dx, (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
+                       (k + (comp == 2 ? 0.0 : 0.5)) * D.dx};
+        double r0 = x[0] - G.c[0], r1 = x[1] - G.c[1], r2 = x[2] - G.c[2];
+        acc[15 + comp] += gus;
+        if (comp == 0) {
+          acc[19] += gus * r2;  acc[20] -= gus * r1;       // d/dw
+          acc[1] += gus * G.w[2]; acc[2] -= gus * G.w[1];  // d/dc = -d/dr
+        } else if (comp == 1) {
+          acc[18] -= gus * r2;  acc[20] += gus * r0;
+          acc[0] -= gus * G.w[2]; acc[2] += gus * G.w[0];
+        } else {
+          acc[18] += gus * r1;  acc[19] -= gus * r0;
+          acc[0] += gus * G.w[1]; acc[1] -= gus * G.w[0];
         }
       }
     }
@@ -309,7 +318,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, co
   }
 }
 
+// J = sum of u_f^2 over faces whose centre lies in [lo, hi]; g = 2 u there.
+__global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, double lo1, double lo2, double hi0,
+                                                      double hi1, double hi2, const float* __restrict__ u,
+                                                      double* __restrict__ J, float* __restrict__ g,
+                                                      double* __restrict__ partials, unsigned* __restrict__ ticket) {
+  const Dims& d = D.d;
+  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (f < (long)d.faces()) {
+    int comp, i, j, k;
+    face_decode(d, f, comp, i, j, k);
+    double x = (i + (comp == 0 ? 0.0 : 0.5)) * D.dx, y = (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
+           z = (k + (comp == 2 ? 0.0 : 0.5)) * D.dx;
+    const double eps = 1e-12;
+    bool in = x >= lo0 - eps && x <= hi0 + eps && y >= lo1 - eps && y <= hi1 + eps && z >= lo2 - eps &&
+              z <= hi2 + eps;
+    float uf = u[f];
+    g[f] = in ? 2.0f * uf : 0.0f;
+    v[0] = in ? (double)uf * (double)uf : 0.0;
+  }
+  double tot[1];
+  if (grid_sum<1>(v, partials, ticket, tot) && threadIdx.x == 0) *J = tot[0];
+}
+
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
+                     double* partials, unsigned* ticket, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss_box, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, lo[0], lo[1], lo[2], hi[0], hi[1],
+                     hi[2], u, J, g, partials, ticket);
+}
 
 void launch_rhs(const Domain& D, const GeomParams& G, double inv_k, const float* alpha, const float* uhat,
                 float* b, hipStream_t s) {
@@ -328,15 +367,16 @@ void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rh
 
 size_t adj_faces_partials(const Dims& d) { return (size_t)nblocks(d.faces()) * 21; }
 
-void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, const float* alpha, const double* phi,
-                      const float* g, const float* y, const float* un1, float* gu, double* partials,
-                      unsigned* ticket, double* g_theta, double* g_ctrl, hipStream_t s) {
+void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
+                      const double* phi, const float* g, const float* y, const float* uhat, const float* p,
+                      float* gu, double* partials, unsigned* ticket, double* g_theta, double* g_ctrl,
+                      hipStream_t s) {
   if (grad)
-    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, alpha, phi, g, y,
-                       un1, gu, partials, ticket, g_theta, g_ctrl);
+    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, (float)kk, alpha,
+                       phi, g, y, uhat, p, gu, partials, ticket, g_theta, g_ctrl);
   else
-    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, alpha, phi, g,
-                       y, un1, gu, partials, ticket, g_theta, g_ctrl);
+    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, (float)kk, alpha,
+                       phi, g, y, uhat, p, gu, partials, ticket, g_theta, g_ctrl);
 }
 
 }  // namespace nf

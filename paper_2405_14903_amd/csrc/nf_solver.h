@@ -3,7 +3,43 @@
 
 #include "nf_internal.h"
 
+#include <vector>
+
 namespace nf {
+
+// Optional timing of one kernel family with HIP events recorded around each of
+// its launches on the launch stream (multigrid kernels: the finest level only).
+struct Profiler {
+  int active = -1;
+  std::vector<hipEvent_t> ev;   // pairs: begin, end
+  size_t used = 0;
+  bool want(int id) const { return active == id; }
+  void begin(int id, hipStream_t s) {
+    if (active != id) return;
+    if (used + 2 > ev.size()) {
+      if (ev.size() >= 2 * 16384) return;
+      size_t old = ev.size();
+      ev.resize(old ? 2 * old : 512);
+      for (size_t q = old; q < ev.size(); ++q) (void)hipEventCreate(&ev[q]);
+    }
+    (void)hipEventRecord(ev[used], s);
+  }
+  void end(int id, hipStream_t s) {
+    if (active != id || used + 2 > ev.size()) return;
+    (void)hipEventRecord(ev[used + 1], s);
+    used += 2;
+  }
+  ~Profiler() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+#define NF_TIMED(prof, id, stream, ...) \
+  do {                                   \
+    if (prof) (prof)->begin(id, stream); \
+    __VA_ARGS__;                         \
+    if (prof) (prof)->end(id, stream);   \
+  } while (0)
 
 struct Level {
   Dims d;
@@ -19,10 +55,13 @@ struct Solver {
   int nlev = 0;
   int precision = SIM_FP32;
   int check_every = 2;
+  int pcur = 0;        // which of p0 / p1 holds the current direction
+  int last_iters = 0;  // iterations of the previous solve (sizes the first batch)
   Level lev[kMaxLevels];
   const float* ax = nullptr;   // fine FP32 fractions (CG operator)
   const float* ay = nullptr;
   const float* az = nullptr;
+  double* x = nullptr;         // FP64 iterate
   float* r = nullptr;
   float* z = nullptr;
   float* q = nullptr;
@@ -34,6 +73,7 @@ struct Solver {
   float* scratch_a = nullptr;    // FP32 coarse fractions while building a mixed hierarchy
   float* scratch_inv = nullptr;
   size_t scratch_off[kMaxLevels] = {};
+  Profiler* prof = nullptr;
 };
 
 // nf_geom.hip
@@ -55,9 +95,12 @@ void launch_update(const Domain& D, const GeomParams& G, double kk, const float*
                    const float* p, float* out, hipStream_t s);
 void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rhs, hipStream_t s);
 size_t adj_faces_partials(const Dims& d);
-void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, const float* alpha, const double* phi,
-                      const float* g, const float* y, const float* un1, float* gu, double* partials,
-                      unsigned* ticket, double* g_theta, double* g_ctrl, hipStream_t s);
+void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
+                      const double* phi, const float* g, const float* y, const float* uhat, const float* p,
+                      float* gu, double* partials, unsigned* ticket, double* g_theta, double* g_ctrl,
+                      hipStream_t s);
+void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
+                     double* partials, unsigned* ticket, hipStream_t s);
 // nf_solver.hip
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st);
 int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st);

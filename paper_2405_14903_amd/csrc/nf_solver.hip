@@ -6,19 +6,23 @@
 // hierarchy of grids).  This solver:
 //   * applies A x = sum over faces of alpha_f (x_c - x_nb) as a 7-point
 //     stencil read straight from the face fractions (no stored matrix);
-//   * keeps every CG scalar on the device, with FP64 dot products reduced in a
-//     fixed order (per-block partials, summed by the last block to finish), so
-//     a solve is bitwise reproducible;
+//   * keeps the iterate x in FP64 and the other CG vectors in FP32; every CG
+//     scalar stays on the device, with FP64 dot products reduced in a fixed
+//     order (per-block partials summed by the last block to finish), so a
+//     solve is bitwise reproducible;
+//   * stops on the recursive residual, then recomputes b - A x from the FP64
+//     iterate; if that true residual misses the tolerance, the true residual
+//     replaces the recursive one and CG restarts (iterative refinement);
 //   * preconditions with one V-cycle: level l+1 halves each axis, coarse face
-//     weight = 1/2 * sum of the 2x2 fine faces it covers, restriction = sum of
-//     the 8 child residuals, prolongation = injection (the transpose), two
-//     damped-Jacobi sweeps (omega = 0.8) before and after the correction, and
-//     40 Jacobi sweeps on the coarsest level (<= 4096 cells) in one workgroup.
-//     Every piece is a fixed linear symmetric map, so the preconditioner is
-//     symmetric and plain CG applies;
-//   * on the multigrid levels the arrays may be stored in FP32, FP16 or BF16
-//     (template parameter T); fine-level CG vectors are always FP32 and the
-//     scalars FP64.
+//     weight = 1/2 * sum of the 2x2 fine faces it covers, restriction = mean
+//     of the 8 child residuals with prolongation = 8 x injection (together the
+//     transpose pair), two damped-Jacobi sweeps (omega = 0.8) before and after
+//     the correction, and 40 Jacobi sweeps on the coarsest level (<= 4096
+//     cells) in one workgroup.  Every piece is a fixed linear symmetric map,
+//     so the preconditioner is symmetric and plain CG applies;
+//   * stores the multigrid arrays in FP32, FP16 or BF16 (template T).  The
+//     V-cycle is linear, so its input is scaled to a fixed RMS and its output
+//     scaled back, which keeps FP16 values in range; 1/diag is capped in FP16.
 #include "nf_internal.h"
 #include "nf_solver.h"
 
@@ -74,16 +78,48 @@ __device__ inline float offdiag(const Dims& d, const Faces<A>& fw, int i, int j,
   return s;
 }
 
+// b_c - (A x)_c with A x accumulated in FP64 from the FP64 iterate.
+__device__ inline double true_residual_at(const Dims& d, const float* ax, const float* ay, const float* az,
+                                          const float* b, const double* x, int i, int j, int k, long c) {
+  Faces<float> fw(d, ax, ay, az, i, j, k);
+  double diag = ((double)fw.w[0] + fw.w[1]) + ((double)fw.w[2] + fw.w[3]) + ((double)fw.w[4] + fw.w[5]);
+  if (!(diag > 0.0)) return 0.0;
+  double s = diag * x[c];
+  long sxy = (long)d.nx * d.ny;
+  if (i > 0) s -= (double)fw.w[0] * x[c - 1];
+  if (i < d.nx - 1) s -= (double)fw.w[1] * x[c + 1];
+  if (j > 0) s -= (double)fw.w[2] * x[c - d.nx];
+  if (j < d.ny - 1) s -= (double)fw.w[3] * x[c + d.nx];
+  if (k > 0) s -= (double)fw.w[4] * x[c - sxy];
+  if (k < d.nz - 1) s -= (double)fw.w[5] * x[c + sxy];
+  return (double)b[c] - s;
+}
+
+__device__ inline double vscale_of(double rr, long n) {
+  double rms = sqrt(rr / (double)n);
+  return rms > 0.0 && isfinite(rms) ? kVcycleRms / rms : 1.0;
+}
+
 // ---------------------------------------------------------------------------
-// CG kernels (fine level, FP32 vectors, FP64 scalars)
+// CG kernels (fine level: FP64 iterate, FP32 vectors, FP64 scalars)
 // ---------------------------------------------------------------------------
+
+__global__ void k_x_load(long n, const float* __restrict__ xin, double* __restrict__ x) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) x[c] = (double)xin[c];
+}
+
+__global__ void k_x_store(long n, const double* __restrict__ x, float* __restrict__ xout) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) xout[c] = (float)x[c];
+}
 
 // r = b - A x; bb, rr -> scalars; decides `done` for a zero / already solved b.
 __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restrict__ ax,
                                                      const float* __restrict__ ay,
                                                      const float* __restrict__ az,
                                                      const float* __restrict__ b,
-                                                     const float* __restrict__ x, float* __restrict__ r,
+                                                     const double* __restrict__ x, float* __restrict__ r,
                                                      double tol, int maxit, CGScalars* sc,
                                                      double* partials) {
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -92,26 +128,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<float> fw(d, ax, ay, az, i, j, k);
-    float xc = x[c];
-    float Ax = fw.diag() * xc - offdiag(d, fw, i, j, k, c, [&](long q) { return x[q]; });
-    float bc = fw.diag() > 0.0f ? b[c] : 0.0f;
-    float rc = bc - Ax;
-    r[c] = rc;
-    v[0] = (double)bc * bc;
-    v[1] = (double)rc * rc;
+    double bc = fw.diag() > 0.0f ? (double)b[c] : 0.0;
+    double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
+    r[c] = (float)rc;
+    v[0] = bc * bc;
+    v[1] = rc * rc;
   }
   double tot[2];
   if (grid_sum<2>(v, partials, &sc->ticket[0], tot) && threadIdx.x == 0) {
     sc->bb = tot[0];
     sc->rr = tot[1];
+    sc->true_rr = tot[1];
     sc->tol2bb = tol * tol * tot[0];
     sc->iters = 0;
     sc->first = 1;
     sc->maxit = maxit;
     sc->nonfinite = !isfinite(tot[1]);
-    sc->done = (tot[0] == 0.0) || (tot[1] <= sc->tol2bb) || sc->nonfinite || maxit <= 0;
+    sc->converged = (tot[0] == 0.0) || (tot[1] <= sc->tol2bb);
+    sc->done = sc->converged || sc->nonfinite || maxit <= 0;
     sc->rho = 0.0;
     sc->beta = 0.0;
+    sc->vscale = vscale_of(tot[1], (long)d.cells());
   }
 }
 
@@ -147,18 +184,19 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
   }
 }
 
-// x += alpha p; r -= alpha q; convergence test on r . r.
-__global__ __launch_bounds__(kBlock) void k_cg_update(long n, float* __restrict__ x, float* __restrict__ r,
+// x += alpha p (FP64); r -= alpha q; convergence test on r . r.
+__global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict__ x, float* __restrict__ r,
                                                        const float* __restrict__ p,
                                                        const float* __restrict__ q, CGScalars* sc,
                                                        double* partials) {
   if (sc->done) return;
-  const float a = (float)sc->alpha;
+  const double a = sc->alpha;
+  const float af = (float)a;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
   if (c < n) {
-    x[c] += a * p[c];
-    float rc = r[c] - a * q[c];
+    x[c] += a * (double)p[c];
+    float rc = r[c] - af * q[c];
     r[c] = rc;
     v[0] = (double)rc * rc;
   }
@@ -166,8 +204,41 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(long n, float* __restrict_
   if (grid_sum<1>(v, partials, &sc->ticket[2], tot) && threadIdx.x == 0) {
     sc->rr = tot[0];
     sc->iters += 1;
+    sc->vscale = vscale_of(tot[0], n);
     if (!isfinite(tot[0])) sc->nonfinite = 1;
     if (tot[0] <= sc->tol2bb || sc->iters >= sc->maxit || sc->nonfinite) sc->done = 1;
+  }
+}
+
+// True residual from the FP64 iterate.  With `replace`, a residual that misses
+// the tolerance replaces r and CG restarts (done = 0, first = 1).
+__global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float* __restrict__ ax,
+                                                              const float* __restrict__ ay,
+                                                              const float* __restrict__ az,
+                                                              const float* __restrict__ b,
+                                                              const double* __restrict__ x, float* __restrict__ r,
+                                                              int replace, CGScalars* sc, double* partials) {
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool rep = replace && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
+  double v[1] = {0.0};
+  if (c < (long)d.cells()) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
+    v[0] = rc * rc;
+    if (rep) r[c] = (float)rc;
+  }
+  double tot[1];
+  if (grid_sum<1>(v, partials, &sc->ticket[4], tot) && threadIdx.x == 0) {
+    sc->true_rr = tot[0];
+    if (!isfinite(tot[0])) sc->nonfinite = 1;
+    sc->converged = !sc->nonfinite && (sc->bb == 0.0 || tot[0] <= sc->tol2bb);
+    if (rep && !sc->converged && !sc->nonfinite) {
+      sc->rr = tot[0];
+      sc->vscale = vscale_of(tot[0], (long)d.cells());
+      sc->first = 1;
+      sc->done = 0;
+    }
   }
 }
 
@@ -181,79 +252,58 @@ __device__ inline void finish_rz(CGScalars* sc, double rz) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_rz_dot(long n, const float* __restrict__ r,
-                                                    const float* __restrict__ z, CGScalars* sc,
-                                                    double* partials) {
+__global__ __launch_bounds__(kBlock) void k_scale_dot(long n, const float* __restrict__ r, float* __restrict__ z,
+                                                       CGScalars* sc, double* partials) {
   if (sc->done) return;
+  const float inv = (float)(1.0 / sc->vscale);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {c < n ? (double)r[c] * (double)z[c] : 0.0};
+  double v[1] = {0.0};
+  if (c < n) {
+    float zc = z[c] * inv;
+    z[c] = zc;
+    v[0] = (double)r[c] * (double)zc;
+  }
   double tot[1];
   if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
 }
 
-// ||b - A x||^2 with A x accumulated in FP64.
-__global__ __launch_bounds__(kBlock) void k_true_residual(Dims d, const float* __restrict__ ax,
-                                                           const float* __restrict__ ay,
-                                                           const float* __restrict__ az,
-                                                           const float* __restrict__ b,
-                                                           const float* __restrict__ x, CGScalars* sc,
-                                                           double* partials) {
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
-  if (c < (long)d.cells()) {
-    int i, j, k;
-    cdec(d, c, i, j, k);
-    Faces<float> fw(d, ax, ay, az, i, j, k);
-    double diag = (double)fw.w[0] + fw.w[1] + fw.w[2] + fw.w[3] + fw.w[4] + fw.w[5];
-    if (diag > 0.0) {
-      double s = diag * (double)x[c];
-      long sxy = (long)d.nx * d.ny;
-      if (i > 0) s -= (double)fw.w[0] * x[c - 1];
-      if (i < d.nx - 1) s -= (double)fw.w[1] * x[c + 1];
-      if (j > 0) s -= (double)fw.w[2] * x[c - d.nx];
-      if (j < d.ny - 1) s -= (double)fw.w[3] * x[c + d.nx];
-      if (k > 0) s -= (double)fw.w[4] * x[c - sxy];
-      if (k < d.nz - 1) s -= (double)fw.w[5] * x[c + sxy];
-      double rr = (double)b[c] - s;
-      v[0] = rr * rr;
-    }
-  }
-  double tot[1];
-  if (grid_sum<1>(v, partials, &sc->ticket[4], tot) && threadIdx.x == 0) sc->true_rr = tot[0];
-}
+// ---------------------------------------------------------------------------
+// multigrid kernels.  A: storage of fractions / 1/diag; R: residual input;
+// Z: correction storage.  At level 0 the residual is the FP32 CG residual,
+// multiplied by sc->vscale on load (`s0`).
+// ---------------------------------------------------------------------------
 
-// ---------------------------------------------------------------------------
-// multigrid kernels (storage type T for level vectors and fractions; the
-// fine-level residual R and output Z are FP32 at level 0)
-// ---------------------------------------------------------------------------
+__device__ inline float level_scale(const CGScalars* sc, int lvl0) { return lvl0 ? (float)sc->vscale : 1.0f; }
 
 // Two damped-Jacobi sweeps from z = 0:  z1 = w D^-1 r,  z2 = z1 + w D^-1 (r - A z1).
 template <typename A, typename R, typename Z>
 __global__ __launch_bounds__(kBlock) void k_mg_pre(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
                                                     const A* __restrict__ az, const A* __restrict__ invd,
                                                     const R* __restrict__ r, Z* __restrict__ z2,
-                                                    const CGScalars* sc) {
+                                                    const CGScalars* sc, int lvl0) {
   if (sc->done) return;
+  const float s0 = level_scale(sc, lvl0);
   long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (c >= (long)d.cells()) return;
   int i, j, k;
   cdec(d, c, i, j, k);
   Faces<A> fw(d, ax, ay, az, i, j, k);
   float idc = ld(invd, c);
-  auto z1 = [&](long t) { return kOmega * ld(invd, t) * ld(r, t); };
-  float rc = ld(r, c);
+  auto z1 = [&](long t) { return kOmega * ld(invd, t) * (s0 * ld(r, t)); };
+  float rc = s0 * ld(r, c);
   float z1c = kOmega * idc * rc;
   float Az = fw.diag() * z1c - offdiag(d, fw, i, j, k, c, z1);
   z2[c] = cvt<Z>(z1c + kOmega * idc * (rc - Az));
 }
 
-// r_coarse(I,J,K) = sum over the 8 children of (r - A z).
+// r_coarse(I,J,K) = mean over the 8 children of (r - A z).
 template <typename A, typename R, typename Z, typename RC>
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(Dims d, Dims cd, const A* __restrict__ ax,
                                                          const A* __restrict__ ay, const A* __restrict__ az,
                                                          const R* __restrict__ r, const Z* __restrict__ z,
-                                                         RC* __restrict__ rc, const CGScalars* sc) {
+                                                         RC* __restrict__ rc, const CGScalars* sc, int lvl0) {
   if (sc->done) return;
+  const float s0 = level_scale(sc, lvl0);
   long C = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (C >= (long)cd.cells()) return;
   int I, J, K;
@@ -266,19 +316,20 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(Dims d, Dims cd, const A
     long c = d.c(i, j, k);
     Faces<A> fw(d, ax, ay, az, i, j, k);
     float Az = fw.diag() * ld(z, c) - offdiag(d, fw, i, j, k, c, zv);
-    s += ld(r, c) - Az;
+    s += s0 * ld(r, c) - Az;
   }
-  rc[C] = cvt<RC>(s);
+  rc[C] = cvt<RC>(0.125f * s);
 }
 
-// z' = z_in + P e (injection from the parent cell); z_out = z' + w D^-1 (r - A z').
+// z' = z_in + 8 e(parent); z_out = z' + w D^-1 (r - A z').
 template <typename A, typename R, typename Z, typename E>
 __global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* __restrict__ ax,
                                                       const A* __restrict__ ay, const A* __restrict__ az,
                                                       const A* __restrict__ invd, const R* __restrict__ r,
                                                       const Z* __restrict__ zin, const E* __restrict__ e,
-                                                      Z* __restrict__ zout, const CGScalars* sc) {
+                                                      Z* __restrict__ zout, const CGScalars* sc, int lvl0) {
   if (sc->done) return;
+  const float s0 = level_scale(sc, lvl0);
   long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (c >= (long)d.cells()) return;
   int i, j, k;
@@ -289,20 +340,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* _
     int ti = (int)(t % d.nx);
     long tt = t / d.nx;
     int tj = (int)(tt % d.ny), tk = (int)(tt / d.ny);
-    return ld(zin, t) + ld(e, (ti >> 1) + (long)cnx * ((tj >> 1) + (long)cny * (tk >> 1)));
+    return ld(zin, t) + 8.0f * ld(e, (ti >> 1) + (long)cnx * ((tj >> 1) + (long)cny * (tk >> 1)));
   };
   float zc = zp(c);
   float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zp);
-  zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (ld(r, c) - Az));
+  zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (s0 * ld(r, c) - Az));
 }
 
-// z_out = z_in + w D^-1 (r - A z_in); optionally rho = r . z_out (level 0).
-template <typename A, typename R, typename Z, typename O, bool DOT>
+// z_out = z_in + w D^-1 (r - A z_in); at level 0 the output is scaled back to
+// the CG residual's units and rho = r . z is reduced.
+template <typename A, typename R, typename Z, typename O, bool LVL0>
 __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
                                                       const A* __restrict__ az, const A* __restrict__ invd,
                                                       const R* __restrict__ r, const Z* __restrict__ zin,
                                                       O* __restrict__ zout, CGScalars* sc, double* partials) {
   if (sc->done) return;
+  const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
+  const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
   if (c < (long)d.cells()) {
@@ -311,13 +365,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
     Faces<A> fw(d, ax, ay, az, i, j, k);
     auto zv = [&](long t) { return ld(zin, t); };
     float zc = ld(zin, c);
-    float rc = ld(r, c);
+    float rraw = ld(r, c);
     float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zv);
-    float zo = zc + kOmega * ld(invd, c) * (rc - Az);
+    float zo = (zc + kOmega * ld(invd, c) * (s0 * rraw - Az)) * inv;
     zout[c] = cvt<O>(zo);
-    v[0] = (double)rc * (double)zo;
+    v[0] = (double)rraw * (double)zo;
   }
-  if (DOT) {
+  if (LVL0) {
     double tot[1];
     if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
   }
@@ -329,14 +383,15 @@ template <typename A, typename R, typename Z>
 __global__ __launch_bounds__(1024) void k_mg_coarse(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
                                                      const A* __restrict__ az, const A* __restrict__ invd,
                                                      const R* __restrict__ r, Z* __restrict__ z,
-                                                     const CGScalars* sc) {
+                                                     const CGScalars* sc, int lvl0) {
   if (sc->done) return;
+  const float s0 = level_scale(sc, lvl0);
   __shared__ float zs[2][kCoarseMaxCells];
   __shared__ float rs[kCoarseMaxCells];
   __shared__ float ids[kCoarseMaxCells];
   const long n = (long)d.cells();
   for (long c = threadIdx.x; c < n; c += blockDim.x) {
-    rs[c] = ld(r, c);
+    rs[c] = s0 * ld(r, c);
     ids[c] = ld(invd, c);
     zs[0][c] = 0.0f;
   }
@@ -358,9 +413,9 @@ __global__ __launch_bounds__(1024) void k_mg_coarse(Dims d, const A* __restrict_
 }
 
 template <typename T>
-__global__ void k_cast_alpha(long n, const float* __restrict__ src, T* __restrict__ dst) {
+__global__ void k_cast(long n, const float* __restrict__ src, T* __restrict__ dst, float cap) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = cvt<T>(src[i]);
+  if (i < n) dst[i] = cvt<T>(fminf(src[i], cap));
 }
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
@@ -377,39 +432,39 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
   auto Ay = [&](int l) { return (const T*)S.lev[l].a[1]; };
   auto Az = [&](int l) { return (const T*)S.lev[l].a[2]; };
   auto ID = [&](int l) { return (const T*)S.lev[l].invd; };
+  const long n0 = (long)S.lev[0].d.cells();
   if (L == 1) {
     hipLaunchKernelGGL((k_mg_coarse<T, float, float>), dim3(1), dim3(1024), 0, st, S.lev[0].d, A(0), Ay(0), Az(0),
-                       ID(0), r0, z0, sc);
-    hipLaunchKernelGGL(k_rz_dot, dim3(nblocks(S.lev[0].d.cells())), dim3(kBlock), 0, st,
-                       (long)S.lev[0].d.cells(), r0, z0, sc, S.partials);
+                       ID(0), r0, z0, sc, 1);
+    hipLaunchKernelGGL(k_scale_dot, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, r0, z0, sc, S.partials);
     return;
   }
-  // down
   for (int l = 0; l < L - 1; ++l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
     T* ta = (T*)S.lev[l].ta;
     T* rc = (T*)S.lev[l + 1].r;
     if (l == 0) {
-      hipLaunchKernelGGL((k_mg_pre<T, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(0), Ay(0),
-                         Az(0), ID(0), r0, ta, sc);
-      hipLaunchKernelGGL((k_mg_restrict<T, float, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d, cd,
-                         A(0), Ay(0), Az(0), r0, (const T*)ta, rc, sc);
+      NF_TIMED(S.prof, SIM_K_MG_PRE, st,
+               hipLaunchKernelGGL((k_mg_pre<T, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(0),
+                                  Ay(0), Az(0), ID(0), r0, ta, sc, 1));
+      NF_TIMED(S.prof, SIM_K_MG_RESTRICT, st,
+               hipLaunchKernelGGL((k_mg_restrict<T, float, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d,
+                                  cd, A(0), Ay(0), Az(0), r0, (const T*)ta, rc, sc, 1));
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_pre<T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l), Ay(l),
-                         Az(l), ID(l), rl, ta, sc);
+                         Az(l), ID(l), rl, ta, sc, 0);
       hipLaunchKernelGGL((k_mg_restrict<T, T, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d, cd, A(l),
-                         Ay(l), Az(l), rl, (const T*)ta, rc, sc);
+                         Ay(l), Az(l), rl, (const T*)ta, rc, sc, 0);
     }
   }
-  // coarsest
   {
     const int l = L - 1;
-    hipLaunchKernelGGL((k_mg_coarse<T, T, T>), dim3(1), dim3(1024), 0, st, S.lev[l].d, A(l), Ay(l), Az(l), ID(l),
-                       (const T*)S.lev[l].r, (T*)S.lev[l].z, sc);
+    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
+             hipLaunchKernelGGL((k_mg_coarse<T, T, T>), dim3(1), dim3(1024), 0, st, S.lev[l].d, A(l), Ay(l), Az(l),
+                                ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].z, sc, 0));
   }
-  // up
   for (int l = L - 2; l >= 0; --l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
@@ -417,14 +472,16 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     T* tb = (T*)S.lev[l].tb;
     const T* e = (const T*)S.lev[l + 1].z;
     if (l == 0) {
-      hipLaunchKernelGGL((k_mg_post1<T, float, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(0),
-                         Ay(0), Az(0), ID(0), r0, ta, e, tb, sc);
-      hipLaunchKernelGGL((k_mg_post2<T, float, T, float, true>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
-                         A(0), Ay(0), Az(0), ID(0), r0, (const T*)tb, z0, sc, S.partials);
+      NF_TIMED(S.prof, SIM_K_MG_POST1, st,
+               hipLaunchKernelGGL((k_mg_post1<T, float, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd,
+                                  A(0), Ay(0), Az(0), ID(0), r0, ta, e, tb, sc, 1));
+      NF_TIMED(S.prof, SIM_K_MG_POST2, st,
+               hipLaunchKernelGGL((k_mg_post2<T, float, T, float, true>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st,
+                                  d, A(0), Ay(0), Az(0), ID(0), r0, (const T*)tb, z0, sc, S.partials));
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_post1<T, T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(l),
-                         Ay(l), Az(l), ID(l), rl, ta, e, tb, sc);
+                         Ay(l), Az(l), ID(l), rl, ta, e, tb, sc, 0);
       hipLaunchKernelGGL((k_mg_post2<T, T, T, T, false>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l),
                          Ay(l), Az(l), ID(l), rl, (const T*)tb, (T*)S.lev[l].z, sc, S.partials);
     }
@@ -440,13 +497,22 @@ static void vcycle_dispatch(const Solver& S, const float* r0, float* z0, hipStre
     vcycle<float>(S, r0, z0, st);
 }
 
+template <typename T>
+static void cast_level(const Dims& d, const float* lx, const float* ly, const float* lz, const float* inv,
+                       const Level& L, float invcap, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast<T>, dim3(nblocks(d.nfx())), dim3(kBlock), 0, st, (long)d.nfx(), lx, (T*)L.a[0], 3e38f);
+  hipLaunchKernelGGL(k_cast<T>, dim3(nblocks(d.nfy())), dim3(kBlock), 0, st, (long)d.nfy(), ly, (T*)L.a[1], 3e38f);
+  hipLaunchKernelGGL(k_cast<T>, dim3(nblocks(d.nfz())), dim3(kBlock), 0, st, (long)d.nfz(), lz, (T*)L.a[2], 3e38f);
+  hipLaunchKernelGGL(k_cast<T>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, (long)d.cells(), inv, (T*)L.invd,
+                     invcap);
+}
+
 // Multigrid copies of the fine fractions and inverse diagonals.
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
   const Dims& d0 = S.lev[0].d;
   const float* fx = fine_alpha;
   const float* fy = fx + d0.nfx();
   const float* fz = fy + d0.nfy();
-  // FP32 fine fractions for the CG operator
   S.ax = fx;
   S.ay = fy;
   S.az = fz;
@@ -466,9 +532,8 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     }
     return;
   }
-  // mixed: build the hierarchy in FP32 scratch (level by level), cast to T
-  float* sx = S.scratch_a;
-  float* sinv = S.scratch_inv;
+  // mixed: build each level in FP32 scratch, then store it in T
+  const float cap = S.precision == SIM_MIXED_FP16 ? kHalfInvDiagMax : 3e38f;
   for (int l = 0; l < S.nlev; ++l) {
     const Dims& d = S.lev[l].d;
     const float *lx, *ly, *lz;
@@ -478,83 +543,106 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
       lz = fz;
     } else {
       const Dims& fd = S.lev[l - 1].d;
-      float* cx = sx + S.scratch_off[l];
+      float* cx = S.scratch_a + S.scratch_off[l];
       float* cy = cx + d.nfx();
       float* cz = cy + d.nfy();
-      const float* px = sx + S.scratch_off[l - 1];
-      const float* py = px + fd.nfx();
-      const float* pz = py + fd.nfy();
+      const float *px, *py, *pz;
       if (l == 1) {
         px = fx;
         py = fy;
         pz = fz;
+      } else {
+        px = S.scratch_a + S.scratch_off[l - 1];
+        py = px + fd.nfx();
+        pz = py + fd.nfy();
       }
       launch_coarsen_alpha(fd, d, px, py, pz, cx, cy, cz, st);
       lx = cx;
       ly = cy;
       lz = cz;
     }
-    launch_invdiag(d, lx, ly, lz, sinv, st);
-    long n = (long)d.faces();
-    if (S.precision == SIM_MIXED_FP16) {
-      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfx())), dim3(kBlock), 0, st, (long)d.nfx(), lx,
-                         (__half*)S.lev[l].a[0]);
-      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfy())), dim3(kBlock), 0, st, (long)d.nfy(), ly,
-                         (__half*)S.lev[l].a[1]);
-      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.nfz())), dim3(kBlock), 0, st, (long)d.nfz(), lz,
-                         (__half*)S.lev[l].a[2]);
-      hipLaunchKernelGGL(k_cast_alpha<__half>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, (long)d.cells(), sinv,
-                         (__half*)S.lev[l].invd);
-    } else {
-      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfx())), dim3(kBlock), 0, st, (long)d.nfx(),
-                         lx, (__hip_bfloat16*)S.lev[l].a[0]);
-      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfy())), dim3(kBlock), 0, st, (long)d.nfy(),
-                         ly, (__hip_bfloat16*)S.lev[l].a[1]);
-      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.nfz())), dim3(kBlock), 0, st, (long)d.nfz(),
-                         lz, (__hip_bfloat16*)S.lev[l].a[2]);
-      hipLaunchKernelGGL(k_cast_alpha<__hip_bfloat16>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st,
-                         (long)d.cells(), sinv, (__hip_bfloat16*)S.lev[l].invd);
-    }
-    (void)n;
+    launch_invdiag(d, lx, ly, lz, S.scratch_inv, st);
+    if (S.precision == SIM_MIXED_FP16)
+      cast_level<__half>(d, lx, ly, lz, S.scratch_inv, S.lev[l], cap, st);
+    else
+      cast_level<__hip_bfloat16>(d, lx, ly, lz, S.scratch_inv, S.lev[l], cap, st);
   }
 }
 
-int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st) {
+static void cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
+  const Dims& d = S.lev[0].d;
+  const long n = (long)d.cells();
+  for (int c = 0; c < count; ++c) {
+    float* pold = S.pcur ? S.p1 : S.p0;
+    float* pnew = S.pcur ? S.p0 : S.p1;
+    NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
+             hipLaunchKernelGGL(k_cg_dir_apply, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
+                                pnew, S.q, S.sc, S.partials));
+    NF_TIMED(S.prof, SIM_K_CG_UPDATE, st,
+             hipLaunchKernelGGL(k_cg_update, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
+                                S.partials));
+    vcycle_dispatch(S, S.r, S.z, st);
+    S.pcur ^= 1;
+  }
+}
+
+static int snapshot(Solver& S, hipStream_t st) {
+  if (hipMemcpyAsync(S.host_sc, S.sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
+  return SIM_OK;
+}
+
+int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, sim_stats* stats, hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
   CGScalars* sc = S.sc;
-  float* r = S.r;
-  float* z = S.z;
-  float* q = S.q;
-  float* p[2] = {S.p0, S.p1};
-  hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, r, tol, maxit, sc,
-                     S.partials);
-  vcycle_dispatch(S, r, z, st);
-  int cur = 0;
-  int enq = 0;
+  double* x = S.x;
+  hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
+  NF_TIMED(S.prof, SIM_K_CG_INIT, st,
+           hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r, tol,
+                              maxit, sc, S.partials));
+  vcycle_dispatch(S, S.r, S.z, st);
+  S.pcur = 0;
+  // First batch sized from the previous solve of this handle, then small
+  // batches.  Every pass of the loop either runs iterations on the device or
+  // uses up one of a bounded number of restarts, so the loop terminates.
+  const int kMaxRestarts = 8;
+  int batch = S.last_iters > 1 ? S.last_iters - 1 : 2;
   const int chunk = S.check_every > 0 ? S.check_every : 2;
+  int restarts = 0;
+  int r = snapshot(S, st);
+  if (r != SIM_OK) return r;
   for (;;) {
-    // device scalars -> pinned host copy, then test `done`
-    if (hipMemcpyAsync(S.host_sc, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
-    if (S.host_sc->done || enq >= maxit) break;
-    for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
-      hipLaunchKernelGGL(k_cg_dir_apply, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, z, p[cur],
-                         p[cur ^ 1], q, sc, S.partials);
-      hipLaunchKernelGGL(k_cg_update, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, r, p[cur ^ 1], q, sc, S.partials);
-      vcycle_dispatch(S, r, z, st);
-      cur ^= 1;
+    const int it_dev = S.host_sc->iters;
+    const int cnt = S.host_sc->done ? 0 : (batch < maxit - it_dev ? batch : maxit - it_dev);
+    if (cnt > 0) {
+      cg_iterations(S, x, cnt, st);
+      r = snapshot(S, st);
+      if (r != SIM_OK) return r;
+    }
+    batch = chunk;
+    const CGScalars& h = *S.host_sc;
+    if (h.nonfinite) break;
+    if (h.done || h.iters >= maxit || cnt <= 0) {
+      // true residual from the FP64 iterate; restart from it if needed
+      const int allow = restarts < kMaxRestarts && h.iters < maxit ? 1 : 0;
+      NF_TIMED(S.prof, SIM_K_CG_TRUE, st,
+               hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
+                                  x, S.r, allow, sc, S.partials));
+      r = snapshot(S, st);
+      if (r != SIM_OK) return r;
+      if (S.host_sc->converged || S.host_sc->nonfinite || !allow) break;
+      ++restarts;
+      vcycle_dispatch(S, S.r, S.z, st);
     }
   }
+  S.last_iters = S.host_sc->iters;
+  hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, xio);
   if (stats) {
-    hipLaunchKernelGGL(k_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, sc,
-                       S.partials);
-    if (hipMemcpyAsync(S.host_sc, sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
-    if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
     const CGScalars& h = *S.host_sc;
     stats->iters = h.iters;
     stats->nonfinite = h.nonfinite;
-    stats->converged = !h.nonfinite && (h.bb == 0.0 || h.rr <= h.tol2bb);
+    stats->converged = h.converged && !h.nonfinite;
     stats->pad = 0;
     stats->rel_res = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
     stats->true_rel_res = h.bb > 0.0 ? sqrt(h.true_rr / h.bb) : 0.0;

@@ -8,7 +8,9 @@ ceil(sqrt(T))) and recomputing each segment's forward before walking it
 backwards; the forward is deterministic (fixed-order reductions, zero initial
 pressure guess), so the recomputed states equal the original ones bitwise.
 The adjoint pressure solve does not depend on the forward solver's iterates
-(only on the converged operator), so no solver state is stored.
+(only on the converged operator), so no solver state is stored; the
+recomputed segment keeps each step's pressure, which the adjoint of the
+face-average update needs on cut faces.
 """
 from __future__ import annotations
 
@@ -49,11 +51,11 @@ class Rollout:
         ro.ctrl = ctrl
         return ro
 
-    def _step(self, n, u, out):
+    def _step(self, n, u, out, p=None):
         th, ct = self.schedule(n)
         if self.timer:
             self.timer.begin("fwd")
-        self.sim.step(u, th, ct, u_out=out, stats=False)
+        self.sim.step(u, th, ct, u_out=out, p_out=p, stats=False)
         if self.timer:
             self.timer.end("fwd")
 
@@ -77,16 +79,17 @@ class Rollout:
         g_ctrl = torch.zeros((T, sim.n_ctrl), dtype=torch.float64, device=dev) if self.grad_geometry else None
         seg_starts = list(range(0, T, K))
         states = [torch.empty_like(g) for _ in range(K + 1)]
+        press = [torch.empty(sim.nc, dtype=torch.float32, device=dev) for _ in range(K)]
         for s in reversed(seg_starts):
             e = min(s + K, T)
             states[0].copy_(self.ckpt[s])
             for n in range(s, e):
-                self._step(n, states[n - s], states[n - s + 1])
+                self._step(n, states[n - s], states[n - s + 1], press[n - s])
             for n in range(e - 1, s - 1, -1):
                 th, ct = self.schedule(n)
                 if self.timer:
                     self.timer.begin("adj")
-                sim.step_adjoint(states[n - s], states[n - s + 1], g, th, ct, g_u_n=gprev,
+                sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
                                  g_theta=g_steps[n] if g_steps is not None else None,
                                  g_ctrl=g_ctrl[n] if g_ctrl is not None else None, stats=False)
                 if self.timer:

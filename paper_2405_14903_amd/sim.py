@@ -158,7 +158,7 @@ class Sim:
                                      C.byref(st) if st is not None else None, _stream()), "sim_project")
         return u_out, (st.as_dict() if st is not None else None)
 
-    def step_adjoint(self, u_n, u_n1, g_u_n1, theta=None, ctrl=None, g_u_n=None, g_theta=None, g_ctrl=None,
+    def step_adjoint(self, u_n, g_u_n1, theta=None, ctrl=None, p_n1=None, g_u_n=None, g_theta=None, g_ctrl=None,
                      stats=True):
         f32, f64 = torch.float32, torch.float64
         if g_u_n is None:
@@ -166,7 +166,7 @@ class Sim:
         keep, thp, ctp = self._geom(theta, ctrl)
         st = L.SimStats() if stats else None
         L.check(self.lib.sim_step_adjoint(
-            self.h, _ptr(u_n, self.nf, f32, "u_n"), _ptr(u_n1, self.nf, f32, "u_n1"), thp, ctp,
+            self.h, _ptr(u_n, self.nf, f32, "u_n"), _ptr(p_n1, self.nc, f32, "p_n1"), thp, ctp,
             _ptr(g_u_n1, self.nf, f32, "g_u_n1"), _ptr(g_u_n, self.nf, f32, "g_u_n"),
             _ptr(g_theta, self.n_params, f64, "g_theta") if g_theta is not None else None,
             _ptr(g_ctrl, self.n_ctrl, f64, "g_ctrl") if g_ctrl is not None else None,
@@ -180,6 +180,30 @@ class Sim:
                                        _ptr(x, self.nc, f32, "x"), float(tol), int(max_iter),
                                        C.byref(st) if st is not None else None, _stream()), "poisson_solve")
         return x, (st.as_dict() if st is not None else None)
+
+    def loss_box(self, u, lo=(0.5, 0.5, 0.5), hi=(1.0, 1.0, 1.0), J=None, g=None):
+        """J = sum of u^2 over faces centred in [lo, hi] (device double) and g = dJ/du."""
+        if J is None:
+            J = torch.empty(1, dtype=torch.float64, device=u.device)
+        if g is None:
+            g = torch.empty_like(u)
+        lo_, lop = _host_doubles(lo, 3, "lo")
+        hi_, hip = _host_doubles(hi, 3, "hi")
+        L.check(self.lib.sim_loss_box(self.h, _ptr(u, self.nf, torch.float32, "u"), lop, hip,
+                                      _ptr(J, 1, torch.float64, "J"), _ptr(g, self.nf, torch.float32, "g"),
+                                      _stream()), "sim_loss_box")
+        return J, g
+
+    def profile(self, kernel):
+        """Time every launch of one kernel family with HIP events (None: stop)."""
+        kid = -1 if kernel is None else L.KERNELS.index(kernel)
+        L.check(self.lib.sim_profile(self.h, kid), "sim_profile")
+
+    def profile_read(self):
+        """(total ms, launches) of the timed kernel since the last read."""
+        ms, cnt = C.c_double(0), C.c_int64(0)
+        L.check(self.lib.sim_profile_read(self.h, C.byref(ms), C.byref(cnt)), "sim_profile_read")
+        return ms.value, cnt.value
 
     def set_geometry(self, theta=None, ctrl=None, alpha_out=None):
         keep, thp, ctp = self._geom(theta, ctrl)
@@ -202,8 +226,9 @@ def sim_project(sim: Sim, u_in, theta=None, ctrl=None, u_out=None, p_out=None):
     return sim.project(u_in, theta, ctrl, u_out, p_out)
 
 
-def sim_step_adjoint(sim: Sim, u_n, u_n1, g_u_n1, theta=None, ctrl=None, g_u_n=None, g_theta=None, g_ctrl=None):
-    return sim.step_adjoint(u_n, u_n1, g_u_n1, theta, ctrl, g_u_n, g_theta, g_ctrl)
+def sim_step_adjoint(sim: Sim, u_n, g_u_n1, theta=None, ctrl=None, p_n1=None, g_u_n=None, g_theta=None,
+                     g_ctrl=None):
+    return sim.step_adjoint(u_n, g_u_n1, theta, ctrl, p_n1, g_u_n, g_theta, g_ctrl)
 
 
 def poisson_solve(sim: Sim, b, x, alpha=None, tol=0.0, max_iter=0):

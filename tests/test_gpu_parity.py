@@ -186,11 +186,18 @@ def test_step_adjoint_parity_32():
     d = geo.vjp(galpha, gus)
     with Sim(ellipsoid_cfg(sc.n, tol=1e-7)) as sim:
         u0 = dev(sc.u0)
-        u1, _ = sim.step(u0, poses[0], sc.ctrl[0])
+        p1 = torch.empty(g.ncells, dtype=torch.float32, device="cuda")
+        sim.step(u0, poses[0], sc.ctrl[0], p_out=p1)
         gth = torch.zeros(15, dtype=torch.float64, device="cuda")
         gct = torch.zeros(6, dtype=torch.float64, device="cuda")
-        gu, st = sim.step_adjoint(u0, u1, dev(gbar), poses[0], sc.ctrl[0], g_theta=gth, g_ctrl=gct)
+        gu, st = sim.step_adjoint(u0, dev(gbar), poses[0], sc.ctrl[0], p_n1=p1, g_theta=gth, g_ctrl=gct)
+        # without the stored pressure the forward system is solved again
+        gth2 = torch.zeros(15, dtype=torch.float64, device="cuda")
+        gct2 = torch.zeros(6, dtype=torch.float64, device="cuda")
+        gu2, _ = sim.step_adjoint(u0, dev(gbar), poses[0], sc.ctrl[0], g_theta=gth2, g_ctrl=gct2)
         torch.cuda.synchronize()
+    assert rel_l2(host(gu2), host(gu)) <= 1e-5
+    assert rel_l2(host(gth2), host(gth)) <= 1e-5 and rel_l2(host(gct2), host(gct)) <= 1e-5
     e = rel_l2(host(gu), gu_o)
     announce(f"  dJ/du rel-L2 {e:.2e}  iters {st['iters']}")
     assert e <= 1e-4, e
@@ -259,4 +266,9 @@ def test_ellipsoid_rollout_gradients_vs_oracle_and_fd():
     announce(f"  J {float(J):.6f} vs {J_o:.6f}; theta rel {e_th:.2e} ctrl rel {e_ct:.2e}")
     assert abs(float(J) - J_o) <= 1e-4 * abs(J_o)
     assert e_th <= 1e-3 and e_ct <= 1e-3, (e_th, e_ct)
-    assert rel_l2(gth[[0, 4, 7]], fd) <= 1e-3, (gth[[0, 4, 7]], fd)
+    # central differences with h = 1e-3 (3% of a cell) straddle the kinks of the
+    # trilinear interpolation and of the marching-squares cases; they agree with
+    # the exact adjoint only to a few percent (the oracle itself: 2.6e-2)
+    e_fd = rel_l2(gth[[0, 4, 7]], fd)
+    announce(f"  vs central differences h=1e-3: rel {e_fd:.2e}")
+    assert e_fd <= 5e-2, (gth[[0, 4, 7]], fd)
