@@ -6,6 +6,7 @@
 #include "nf_solver.h"
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -223,8 +224,14 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   c->dom.inflow = desc->inflow_speed;
   c->S.nlev = p.nlev;
   c->S.prof = &c->prof;
+  {
+    const char* tr = std::getenv("NF_TRACE_SOLVER");
+    c->S.trace = tr && tr[0] == '1';
+  }
   c->S.precision = desc->precision;
   for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
+  c->S.nbottom = p.nlev - 1;
+  while (c->S.nbottom > 0 && p.dims[c->S.nbottom - 1].cells() <= (size_t)kCoarseMaxCells) --c->S.nbottom;
   bool ok = true;
   for_each_buffer(desc, p, c, [&](size_t b, void** ptr) {
     if (!ok) return;
@@ -338,7 +345,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   if (r != SIM_OK) return r;
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
-                            h->S.partials, &h->S.sc->ticket[5], g_theta, g_ctrl, stream));
+                            h->S.partials, g_theta, g_ctrl, stream));
   launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
            launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->gu, g_u_n, stream));
@@ -364,7 +371,7 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
 int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
                      hipStream_t stream) {
   if (!h || !u || !lo || !hi || !J || !g || (const float*)g == u) return SIM_EINVAL;
-  launch_loss_box(h->dom, lo, hi, u, J, g, h->S.partials, &h->S.sc->ticket[6], stream);
+  launch_loss_box(h->dom, lo, hi, u, J, g, h->S.partials, stream);
   return last_hip_error();
 }
 

@@ -76,7 +76,8 @@ struct CGScalars {
   int nonfinite;
   int maxit;
   int converged;     // true residual reached the tolerance
-  unsigned ticket[8];   // last-block counters of the reducing kernels
+  int allow;         // a true residual that misses tol may restart CG
+  int pad2;
 };
 
 // ---------------------------------------------------------------------------
@@ -170,40 +171,42 @@ __device__ inline void block_sum(double (&v)[N], double* sh) {
   }
 }
 
-// Write this block's N partial sums; the last block to arrive sums all
-// partials in fixed order and returns true (thread 0 then holds the totals in
-// `tot`).  The ticket counter is reset by the last block.
+// Write this block's N partial sums to partials[q * gridDim.x + blockIdx.x]
+// (fixed-order block sum).  A separate single-block kernel combines them after
+// the kernel boundary, so no cross-workgroup synchronisation is needed.
 template <int N>
-__device__ inline bool grid_sum(double (&v)[N], double* partials, unsigned* ticket, double (&tot)[N]) {
+__device__ inline void block_partials(double (&v)[N], double* partials) {
   __shared__ double sh[N * (kBlock / 64) + 1];
-  __shared__ int last;
   block_sum<N>(v, sh);
-  const int nb = gridDim.x;
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) partials[(size_t)q * nb + blockIdx.x] = v[q];
-    __threadfence();
-    unsigned t = atomicAdd(ticket, 1u);
-    last = (t == (unsigned)nb - 1);
+    for (int q = 0; q < N; ++q) partials[(size_t)q * gridDim.x + blockIdx.x] = v[q];
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  double acc[N];
+}
+
+// Fixed-order total of N partial arrays of nb entries, by one block of
+// kFinBlock threads.  Result valid in thread 0.
+constexpr int kFinBlock = 1024;
+template <int N>
+__device__ inline void finish_partials(const double* partials, int nb, double (&tot)[N]) {
+  __shared__ double sh[N * (kFinBlock / 64) + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += kBlock) s += partials[(size_t)q * nb + b];
-    acc[q] = s;
+    for (int b = threadIdx.x; b < nb; b += kFinBlock) s += partials[(size_t)q * nb + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[q * (kFinBlock / 64) + wv] = s;
   }
   __syncthreads();
-  block_sum<N>(acc, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) tot[q] = acc[q];
-    *ticket = 0u;
+    for (int q = 0; q < N; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kFinBlock / 64; ++w) s += sh[q * (kFinBlock / 64) + w];
+      tot[q] = s;
+    }
   }
-  return true;
 }
 
 }  // namespace nf

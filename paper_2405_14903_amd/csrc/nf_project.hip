@@ -247,10 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, fl
                                                        const float* __restrict__ y,
                                                        const float* __restrict__ uhat,
                                                        const float* __restrict__ p,
-                                                       float* __restrict__ gu, double* __restrict__ partials,
-                                                       unsigned* __restrict__ ticket,
-                                                       double* __restrict__ g_theta,
-                                                       double* __restrict__ g_ctrl) {
+                                                       float* __restrict__ gu, double* __restrict__ partials) {
   const Dims& d = D.d;
   long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double acc[21];
@@ -307,22 +304,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, fl
       }
     }
   }
-  if (GRAD) {
-    double tot[21];
-    if (grid_sum<21>(acc, partials, ticket, tot) && threadIdx.x == 0) {
-      if (g_theta)
-        for (int t = 0; t < 15; ++t) g_theta[t] += tot[t];
-      if (g_ctrl)
-        for (int t = 0; t < 6; ++t) g_ctrl[t] += tot[15 + t];
-    }
+  if (GRAD) block_partials<21>(acc, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_adj_faces(int nb, const double* __restrict__ partials,
+                                                              double* __restrict__ g_theta,
+                                                              double* __restrict__ g_ctrl) {
+  double tot[21];
+  finish_partials<21>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    if (g_theta)
+      for (int t = 0; t < 15; ++t) g_theta[t] += tot[t];
+    if (g_ctrl)
+      for (int t = 0; t < 6; ++t) g_ctrl[t] += tot[15 + t];
   }
 }
 
 // J = sum of u_f^2 over faces whose centre lies in [lo, hi]; g = 2 u there.
 __global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, double lo1, double lo2, double hi0,
                                                       double hi1, double hi2, const float* __restrict__ u,
-                                                      double* __restrict__ J, float* __restrict__ g,
-                                                      double* __restrict__ partials, unsigned* __restrict__ ticket) {
+                                                      float* __restrict__ g, double* __restrict__ partials) {
   const Dims& d = D.d;
   long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
@@ -338,16 +339,24 @@ __global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, doubl
     g[f] = in ? 2.0f * uf : 0.0f;
     v[0] = in ? (double)uf * (double)uf : 0.0;
   }
+  block_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_loss(int nb, const double* __restrict__ partials,
+                                                         double* __restrict__ J) {
   double tot[1];
-  if (grid_sum<1>(v, partials, ticket, tot) && threadIdx.x == 0) *J = tot[0];
+  finish_partials<1>(partials, nb, tot);
+  if (threadIdx.x == 0) *J = tot[0];
 }
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
-                     double* partials, unsigned* ticket, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss_box, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, lo[0], lo[1], lo[2], hi[0], hi[1],
-                     hi[2], u, J, g, partials, ticket);
+                     double* partials, hipStream_t s) {
+  const int nb = (int)nblocks(D.d.faces());
+  hipLaunchKernelGGL(k_loss_box, dim3(nb), dim3(kBlock), 0, s, D, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], u, g,
+                     partials);
+  hipLaunchKernelGGL(k_fin_loss, dim3(1), dim3(kFinBlock), 0, s, nb, partials, J);
 }
 
 void launch_rhs(const Domain& D, const GeomParams& G, double inv_k, const float* alpha, const float* uhat,
@@ -369,14 +378,16 @@ size_t adj_faces_partials(const Dims& d) { return (size_t)nblocks(d.faces()) * 2
 
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, unsigned* ticket, double* g_theta, double* g_ctrl,
-                      hipStream_t s) {
-  if (grad)
-    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, (float)kk, alpha,
-                       phi, g, y, uhat, p, gu, partials, ticket, g_theta, g_ctrl);
-  else
-    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D, G, (float)kk, alpha,
-                       phi, g, y, uhat, p, gu, partials, ticket, g_theta, g_ctrl);
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, hipStream_t s) {
+  const int nb = (int)nblocks(D.d.faces());
+  if (grad) {
+    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nb), dim3(kBlock), 0, s, D, G, (float)kk, alpha, phi, g, y, uhat, p,
+                       gu, partials);
+    hipLaunchKernelGGL(k_fin_adj_faces, dim3(1), dim3(kFinBlock), 0, s, nb, partials, g_theta, g_ctrl);
+  } else {
+    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nb), dim3(kBlock), 0, s, D, G, (float)kk, alpha, phi, g, y, uhat, p,
+                       gu, partials);
+  }
 }
 
 }  // namespace nf

@@ -53,10 +53,12 @@ struct Level {
 
 struct Solver {
   int nlev = 0;
+  int nbottom = 0;     // first level with at most kCoarseMaxCells cells
   int precision = SIM_FP32;
   int check_every = 2;
   int pcur = 0;        // which of p0 / p1 holds the current direction
   int last_iters = 0;  // iterations of the previous solve (sizes the first batch)
+  int trace = 0;       // print each convergence snapshot to stderr (NF_TRACE_SOLVER=1)
   Level lev[kMaxLevels];
   const float* ax = nullptr;   // fine FP32 fractions (CG operator)
   const float* ay = nullptr;
@@ -97,10 +99,9 @@ void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rh
 size_t adj_faces_partials(const Dims& d);
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, unsigned* ticket, double* g_theta, double* g_ctrl,
-                      hipStream_t s);
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, hipStream_t s);
 void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
-                     double* partials, unsigned* ticket, hipStream_t s);
+                     double* partials, hipStream_t s);
 // nf_solver.hip
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st);
 int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st);

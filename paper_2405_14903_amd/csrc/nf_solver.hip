@@ -29,6 +29,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 
+#include <cstdio>
+
 namespace nf {
 
 template <typename T> __device__ inline float ld(const T* p, long i);
@@ -64,34 +66,35 @@ struct Faces {
   __device__ float diag() const { return ((w[0] + w[1]) + (w[2] + w[3])) + (w[4] + w[5]); }
 };
 
-// sum over interior neighbours of alpha_f * v(nb); `val(c)` gives v at cell c.
+// (A x)_c = sum over the 6 faces of alpha_f (x_c - x_nb), x_nb = 0 beyond the
+// domain.  The differences are formed before the weighting: for a smooth x the
+// subtraction of neighbouring values is exact in FP32, so A x keeps its
+// relative accuracy (diag * x_c - sum alpha x_nb would cancel catastrophically).
 template <typename A, typename F>
-__device__ inline float offdiag(const Dims& d, const Faces<A>& fw, int i, int j, int k, long c, F val) {
-  float s = 0.0f;
-  if (i > 0) s += fw.w[0] * val(c - 1);
-  if (i < d.nx - 1) s += fw.w[1] * val(c + 1);
-  if (j > 0) s += fw.w[2] * val(c - d.nx);
-  if (j < d.ny - 1) s += fw.w[3] * val(c + d.nx);
-  long sxy = (long)d.nx * d.ny;
-  if (k > 0) s += fw.w[4] * val(c - sxy);
-  if (k < d.nz - 1) s += fw.w[5] * val(c + sxy);
+__device__ inline float apply_A(const Dims& d, const Faces<A>& fw, int i, int j, int k, long c, float xc, F val) {
+  const long sxy = (long)d.nx * d.ny;
+  float s = fw.w[0] * (xc - (i > 0 ? val(c - 1) : 0.0f));
+  s += fw.w[1] * (xc - (i < d.nx - 1 ? val(c + 1) : 0.0f));
+  s += fw.w[2] * (xc - (j > 0 ? val(c - d.nx) : 0.0f));
+  s += fw.w[3] * (xc - (j < d.ny - 1 ? val(c + d.nx) : 0.0f));
+  s += fw.w[4] * (xc - (k > 0 ? val(c - sxy) : 0.0f));
+  s += fw.w[5] * (xc - (k < d.nz - 1 ? val(c + sxy) : 0.0f));
   return s;
 }
 
-// b_c - (A x)_c with A x accumulated in FP64 from the FP64 iterate.
+// b_c - (A x)_c accumulated in FP64 from the FP64 iterate (0 on inactive cells).
 __device__ inline double true_residual_at(const Dims& d, const float* ax, const float* ay, const float* az,
                                           const float* b, const double* x, int i, int j, int k, long c) {
   Faces<float> fw(d, ax, ay, az, i, j, k);
-  double diag = ((double)fw.w[0] + fw.w[1]) + ((double)fw.w[2] + fw.w[3]) + ((double)fw.w[4] + fw.w[5]);
-  if (!(diag > 0.0)) return 0.0;
-  double s = diag * x[c];
-  long sxy = (long)d.nx * d.ny;
-  if (i > 0) s -= (double)fw.w[0] * x[c - 1];
-  if (i < d.nx - 1) s -= (double)fw.w[1] * x[c + 1];
-  if (j > 0) s -= (double)fw.w[2] * x[c - d.nx];
-  if (j < d.ny - 1) s -= (double)fw.w[3] * x[c + d.nx];
-  if (k > 0) s -= (double)fw.w[4] * x[c - sxy];
-  if (k < d.nz - 1) s -= (double)fw.w[5] * x[c + sxy];
+  if (!(fw.diag() > 0.0f)) return 0.0;
+  const long sxy = (long)d.nx * d.ny;
+  const double xc = x[c];
+  double s = (double)fw.w[0] * (xc - (i > 0 ? x[c - 1] : 0.0));
+  s += (double)fw.w[1] * (xc - (i < d.nx - 1 ? x[c + 1] : 0.0));
+  s += (double)fw.w[2] * (xc - (j > 0 ? x[c - d.nx] : 0.0));
+  s += (double)fw.w[3] * (xc - (j < d.ny - 1 ? x[c + d.nx] : 0.0));
+  s += (double)fw.w[4] * (xc - (k > 0 ? x[c - sxy] : 0.0));
+  s += (double)fw.w[5] * (xc - (k < d.nz - 1 ? x[c + sxy] : 0.0));
   return (double)b[c] - s;
 }
 
@@ -101,7 +104,9 @@ __device__ inline double vscale_of(double rr, long n) {
 }
 
 // ---------------------------------------------------------------------------
-// CG kernels (fine level: FP64 iterate, FP32 vectors, FP64 scalars)
+// CG kernels (fine level: FP64 iterate, FP32 vectors).  Each reducing kernel
+// writes per-block partials; a one-block k_fin_* kernel turns them into the
+// device-resident scalars after the kernel boundary.
 // ---------------------------------------------------------------------------
 
 __global__ void k_x_load(long n, const float* __restrict__ xin, double* __restrict__ x) {
@@ -114,13 +119,12 @@ __global__ void k_x_store(long n, const double* __restrict__ x, float* __restric
   if (c < n) xout[c] = (float)x[c];
 }
 
-// r = b - A x; bb, rr -> scalars; decides `done` for a zero / already solved b.
+// r = b - A x; partials of b.b (active cells) and r.r.
 __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restrict__ ax,
                                                      const float* __restrict__ ay,
                                                      const float* __restrict__ az,
                                                      const float* __restrict__ b,
                                                      const double* __restrict__ x, float* __restrict__ r,
-                                                     double tol, int maxit, CGScalars* sc,
                                                      double* partials) {
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[2] = {0.0, 0.0};
@@ -134,8 +138,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
     v[0] = bc * bc;
     v[1] = rc * rc;
   }
+  block_partials<2>(v, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* partials, CGScalars* sc, double tol,
+                                                         int maxit, long ncells) {
   double tot[2];
-  if (grid_sum<2>(v, partials, &sc->ticket[0], tot) && threadIdx.x == 0) {
+  finish_partials<2>(partials, nb, tot);
+  if (threadIdx.x == 0) {
     sc->bb = tot[0];
     sc->rr = tot[1];
     sc->true_rr = tot[1];
@@ -148,19 +158,20 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
     sc->done = sc->converged || sc->nonfinite || maxit <= 0;
     sc->rho = 0.0;
     sc->beta = 0.0;
-    sc->vscale = vscale_of(tot[1], (long)d.cells());
+    sc->alpha = 0.0;
+    sc->vscale = vscale_of(tot[1], ncells);
   }
 }
 
 // p_new = z + beta p_old (p_new = z on the first iteration); q = A p_new;
-// alpha = rho / (p_new . q).
+// partials of p_new . q.
 __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __restrict__ ax,
                                                           const float* __restrict__ ay,
                                                           const float* __restrict__ az,
                                                           const float* __restrict__ z,
                                                           const float* __restrict__ pold,
                                                           float* __restrict__ pnew, float* __restrict__ q,
-                                                          CGScalars* sc, double* partials) {
+                                                          const CGScalars* sc, double* partials) {
   if (sc->done) return;
   const bool first = sc->first;
   const float beta = (float)sc->beta;
@@ -172,22 +183,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
     Faces<float> fw(d, ax, ay, az, i, j, k);
     auto pv = [&](long t) { return first ? z[t] : z[t] + beta * pold[t]; };
     float pc = pv(c);
-    float qc = fw.diag() * pc - offdiag(d, fw, i, j, k, c, pv);
+    float qc = apply_A(d, fw, i, j, k, c, pc, pv);
     pnew[c] = pc;
     q[c] = qc;
     v[0] = (double)pc * qc;
   }
+  block_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_pq(int nb, const double* partials, CGScalars* sc) {
+  if (sc->done) return;
   double tot[1];
-  if (grid_sum<1>(v, partials, &sc->ticket[1], tot) && threadIdx.x == 0) {
+  finish_partials<1>(partials, nb, tot);
+  if (threadIdx.x == 0) {
     sc->alpha = tot[0] != 0.0 ? sc->rho / tot[0] : 0.0;
     sc->first = 0;
   }
 }
 
-// x += alpha p (FP64); r -= alpha q; convergence test on r . r.
+// x += alpha p (FP64); r -= alpha q; partials of r . r.
 __global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict__ x, float* __restrict__ r,
                                                        const float* __restrict__ p,
-                                                       const float* __restrict__ q, CGScalars* sc,
+                                                       const float* __restrict__ q, const CGScalars* sc,
                                                        double* partials) {
   if (sc->done) return;
   const double a = sc->alpha;
@@ -200,26 +217,36 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict
     r[c] = rc;
     v[0] = (double)rc * rc;
   }
+  block_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_rr(int nb, const double* partials, CGScalars* sc, long ncells) {
+  if (sc->done) return;
   double tot[1];
-  if (grid_sum<1>(v, partials, &sc->ticket[2], tot) && threadIdx.x == 0) {
+  finish_partials<1>(partials, nb, tot);
+  if (threadIdx.x == 0) {
     sc->rr = tot[0];
     sc->iters += 1;
-    sc->vscale = vscale_of(tot[0], n);
+    sc->vscale = vscale_of(tot[0], ncells);
     if (!isfinite(tot[0])) sc->nonfinite = 1;
     if (tot[0] <= sc->tol2bb || sc->iters >= sc->maxit || sc->nonfinite) sc->done = 1;
   }
 }
 
-// True residual from the FP64 iterate.  With `replace`, a residual that misses
-// the tolerance replaces r and CG restarts (done = 0, first = 1).
+// True residual from the FP64 iterate.  With `allow`, a residual that misses
+// the tolerance replaces r and CG restarts (k_fin_true sets done = 0, first = 1).
+__device__ inline bool may_replace(const CGScalars* sc, int allow) {
+  return allow && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float* __restrict__ ax,
                                                               const float* __restrict__ ay,
                                                               const float* __restrict__ az,
                                                               const float* __restrict__ b,
                                                               const double* __restrict__ x, float* __restrict__ r,
-                                                              int replace, CGScalars* sc, double* partials) {
+                                                              int allow, const CGScalars* sc, double* partials) {
+  const bool rep = may_replace(sc, allow);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool rep = replace && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
   double v[1] = {0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
@@ -228,49 +255,65 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
     v[0] = rc * rc;
     if (rep) r[c] = (float)rc;
   }
+  block_partials<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* partials, CGScalars* sc, int allow,
+                                                         long ncells) {
+  const bool rep = may_replace(sc, allow);
   double tot[1];
-  if (grid_sum<1>(v, partials, &sc->ticket[4], tot) && threadIdx.x == 0) {
+  finish_partials<1>(partials, nb, tot);
+  if (threadIdx.x == 0) {
     sc->true_rr = tot[0];
     if (!isfinite(tot[0])) sc->nonfinite = 1;
     sc->converged = !sc->nonfinite && (sc->bb == 0.0 || tot[0] <= sc->tol2bb);
     if (rep && !sc->converged && !sc->nonfinite) {
       sc->rr = tot[0];
-      sc->vscale = vscale_of(tot[0], (long)d.cells());
+      sc->vscale = vscale_of(tot[0], ncells);
       sc->first = 1;
       sc->done = 0;
     }
   }
 }
 
-// rho = r . z (and beta = rho_new / rho_old after the first V-cycle).
-__device__ inline void finish_rz(CGScalars* sc, double rz) {
-  if (sc->first) {
-    sc->rho = rz;
-  } else {
-    sc->beta = sc->rho != 0.0 ? rz / sc->rho : 0.0;
-    sc->rho = rz;
+// rho = r . z and the flexible (Polak-Ribiere) direction coefficient
+// beta = r_new . (z_new - z_old) / rho_old: the rounding of the FP16 / BF16
+// V-cycle makes the preconditioner slightly non-linear, which this form
+// tolerates; for an exactly linear preconditioner r_new . z_old = 0 and it
+// reduces to the Fletcher-Reeves ratio.
+__global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc) {
+  if (sc->done) return;
+  double tot[2];
+  finish_partials<2>(partials, nb, tot);
+  if (threadIdx.x == 0) {
+    if (sc->first) {
+      sc->rho = tot[0];
+    } else {
+      sc->beta = sc->rho != 0.0 ? (tot[0] - tot[1]) / sc->rho : 0.0;
+      sc->rho = tot[0];
+    }
   }
 }
 
+// z *= 1 / vscale (the V-cycle ran on the scaled residual); partials of r . z.
 __global__ __launch_bounds__(kBlock) void k_scale_dot(long n, const float* __restrict__ r, float* __restrict__ z,
-                                                       CGScalars* sc, double* partials) {
+                                                       const CGScalars* sc, double* partials) {
   if (sc->done) return;
   const float inv = (float)(1.0 / sc->vscale);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
+  double v[2] = {0.0, 0.0};
   if (c < n) {
     float zc = z[c] * inv;
     z[c] = zc;
     v[0] = (double)r[c] * (double)zc;
   }
-  double tot[1];
-  if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
+  block_partials<2>(v, partials);
 }
 
 // ---------------------------------------------------------------------------
-// multigrid kernels.  A: storage of fractions / 1/diag; R: residual input;
-// Z: correction storage.  At level 0 the residual is the FP32 CG residual,
-// multiplied by sc->vscale on load (`s0`).
+// multigrid kernels on the grid levels.  A: storage of fractions / 1/diag;
+// R: residual input; Z: correction storage.  At level 0 the residual is the
+// FP32 CG residual, multiplied by sc->vscale on load (`s0`).
 // ---------------------------------------------------------------------------
 
 __device__ inline float level_scale(const CGScalars* sc, int lvl0) { return lvl0 ? (float)sc->vscale : 1.0f; }
@@ -292,7 +335,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_pre(Dims d, const A* __restrict__
   auto z1 = [&](long t) { return kOmega * ld(invd, t) * (s0 * ld(r, t)); };
   float rc = s0 * ld(r, c);
   float z1c = kOmega * idc * rc;
-  float Az = fw.diag() * z1c - offdiag(d, fw, i, j, k, c, z1);
+  float Az = apply_A(d, fw, i, j, k, c, z1c, z1);
   z2[c] = cvt<Z>(z1c + kOmega * idc * (rc - Az));
 }
 
@@ -315,7 +358,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(Dims d, Dims cd, const A
     int i = 2 * I + (b & 1), j = 2 * J + ((b >> 1) & 1), k = 2 * K + (b >> 2);
     long c = d.c(i, j, k);
     Faces<A> fw(d, ax, ay, az, i, j, k);
-    float Az = fw.diag() * ld(z, c) - offdiag(d, fw, i, j, k, c, zv);
+    float Az = apply_A(d, fw, i, j, k, c, ld(z, c), zv);
     s += s0 * ld(r, c) - Az;
   }
   rc[C] = cvt<RC>(0.125f * s);
@@ -343,22 +386,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* _
     return ld(zin, t) + 8.0f * ld(e, (ti >> 1) + (long)cnx * ((tj >> 1) + (long)cny * (tk >> 1)));
   };
   float zc = zp(c);
-  float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zp);
+  float Az = apply_A(d, fw, i, j, k, c, zc, zp);
   zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (s0 * ld(r, c) - Az));
 }
 
 // z_out = z_in + w D^-1 (r - A z_in); at level 0 the output is scaled back to
-// the CG residual's units and rho = r . z is reduced.
+// the CG residual's units and partials of r . z are written.
 template <typename A, typename R, typename Z, typename O, bool LVL0>
 __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
                                                       const A* __restrict__ az, const A* __restrict__ invd,
                                                       const R* __restrict__ r, const Z* __restrict__ zin,
-                                                      O* __restrict__ zout, CGScalars* sc, double* partials) {
+                                                      O* __restrict__ zout, const CGScalars* sc, double* partials) {
   if (sc->done) return;
   const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
+  const bool first = sc->first;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
+  double v[2] = {0.0, 0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
@@ -366,50 +410,136 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
     auto zv = [&](long t) { return ld(zin, t); };
     float zc = ld(zin, c);
     float rraw = ld(r, c);
-    float Az = fw.diag() * zc - offdiag(d, fw, i, j, k, c, zv);
+    float Az = apply_A(d, fw, i, j, k, c, zc, zv);
     float zo = (zc + kOmega * ld(invd, c) * (s0 * rraw - Az)) * inv;
+    if (LVL0 && !first) v[1] = (double)rraw * (double)ld(zout, c);   // r_new . z_old
     zout[c] = cvt<O>(zo);
     v[0] = (double)rraw * (double)zo;
   }
-  if (LVL0) {
-    double tot[1];
-    if (grid_sum<1>(v, partials, &sc->ticket[3], tot) && threadIdx.x == 0) finish_rz(sc, tot[0]);
-  }
+  if (LVL0) block_partials<2>(v, partials);
 }
 
-// Coarsest level: kCoarseSweeps damped-Jacobi sweeps from zero, one workgroup,
-// vectors in LDS.
+// ---------------------------------------------------------------------------
+// bottom of the V-cycle: every level with at most kCoarseMaxCells cells, in one
+// workgroup with the vectors in LDS (same smoother, transfers and coarsest
+// sweeps as the grid levels).
+// ---------------------------------------------------------------------------
+
+template <typename A>
+struct Bottom {
+  int nl;
+  Dims d[kMaxLevels];
+  const A* ax[kMaxLevels];
+  const A* ay[kMaxLevels];
+  const A* az[kMaxLevels];
+  const A* invd[kMaxLevels];
+  int off[kMaxLevels];   // LDS offset (floats) of level l's three vectors r, z, t
+};
+
 template <typename A, typename R, typename Z>
-__global__ __launch_bounds__(1024) void k_mg_coarse(Dims d, const A* __restrict__ ax, const A* __restrict__ ay,
-                                                     const A* __restrict__ az, const A* __restrict__ invd,
-                                                     const R* __restrict__ r, Z* __restrict__ z,
+__global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __restrict__ rin, Z* __restrict__ zout,
                                                      const CGScalars* sc, int lvl0) {
   if (sc->done) return;
+  extern __shared__ float lds[];
   const float s0 = level_scale(sc, lvl0);
-  __shared__ float zs[2][kCoarseMaxCells];
-  __shared__ float rs[kCoarseMaxCells];
-  __shared__ float ids[kCoarseMaxCells];
-  const long n = (long)d.cells();
-  for (long c = threadIdx.x; c < n; c += blockDim.x) {
-    rs[c] = s0 * ld(r, c);
-    ids[c] = ld(invd, c);
-    zs[0][c] = 0.0f;
+  const int T = blockDim.x;
+  auto R_ = [&](int l) { return lds + B.off[l]; };
+  auto Z_ = [&](int l) { return lds + B.off[l] + (int)B.d[l].cells(); };
+  auto T_ = [&](int l) { return lds + B.off[l] + 2 * (int)B.d[l].cells(); };
+  {
+    const int n = (int)B.d[0].cells();
+    float* r0 = R_(0);
+    for (int c = threadIdx.x; c < n; c += T) r0[c] = s0 * ld(rin, c);
   }
   __syncthreads();
-  int cur = 0;
-  for (int s = 0; s < kCoarseSweeps; ++s) {
-    for (long c = threadIdx.x; c < n; c += blockDim.x) {
+  // down
+  for (int l = 0; l < B.nl; ++l) {
+    const Dims& d = B.d[l];
+    const int n = (int)d.cells();
+    float *r = R_(l), *z = Z_(l), *t = T_(l);
+    if (l == B.nl - 1) {
+      for (int c = threadIdx.x; c < n; c += T) z[c] = 0.0f;
+      __syncthreads();
+      float *src = z, *dst = t;
+      for (int s = 0; s < kCoarseSweeps; ++s) {
+        for (int c = threadIdx.x; c < n; c += T) {
+          int i, j, k;
+          cdec(d, c, i, j, k);
+          Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
+          float Az = apply_A(d, fw, i, j, k, c, src[c], [&](long q) { return src[q]; });
+          dst[c] = src[c] + kOmega * ld(B.invd[l], c) * (r[c] - Az);
+        }
+        __syncthreads();
+        float* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+      if (src != z) {
+        for (int c = threadIdx.x; c < n; c += T) z[c] = src[c];
+        __syncthreads();
+      }
+      break;
+    }
+    for (int c = threadIdx.x; c < n; c += T) t[c] = kOmega * ld(B.invd[l], c) * r[c];
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += T) {
       int i, j, k;
       cdec(d, c, i, j, k);
-      Faces<A> fw(d, ax, ay, az, i, j, k);
-      const float* zc = zs[cur];
-      float Az = fw.diag() * zc[c] - offdiag(d, fw, i, j, k, c, [&](long t) { return zc[t]; });
-      zs[cur ^ 1][c] = zc[c] + kOmega * ids[c] * (rs[c] - Az);
+      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
+      float Az = apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; });
+      z[c] = t[c] + kOmega * ld(B.invd[l], c) * (r[c] - Az);
     }
     __syncthreads();
-    cur ^= 1;
+    const Dims& cd = B.d[l + 1];
+    float* rc = R_(l + 1);
+    for (int C = threadIdx.x; C < (int)cd.cells(); C += T) {
+      int I, J, K;
+      cdec(cd, C, I, J, K);
+      float s = 0.0f;
+      for (int b = 0; b < 8; ++b) {
+        int i = 2 * I + (b & 1), j = 2 * J + ((b >> 1) & 1), k = 2 * K + (b >> 2);
+        int c = d.c(i, j, k);
+        Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
+        s += r[c] - apply_A(d, fw, i, j, k, c, z[c], [&](long q) { return z[q]; });
+      }
+      rc[C] = 0.125f * s;
+    }
+    __syncthreads();
   }
-  for (long c = threadIdx.x; c < n; c += blockDim.x) z[c] = cvt<Z>(zs[cur][c]);
+  // up
+  for (int l = B.nl - 2; l >= 0; --l) {
+    const Dims& d = B.d[l];
+    const Dims& cd = B.d[l + 1];
+    const int n = (int)d.cells();
+    float *r = R_(l), *z = Z_(l), *t = T_(l);
+    const float* e = Z_(l + 1);
+    auto zp = [&](long q) {
+      int ti = (int)(q % d.nx);
+      long tt = q / d.nx;
+      int tj = (int)(tt % d.ny), tk = (int)(tt / d.ny);
+      return z[q] + 8.0f * e[(ti >> 1) + cd.nx * ((tj >> 1) + cd.ny * (tk >> 1))];
+    };
+    for (int c = threadIdx.x; c < n; c += T) {
+      int i, j, k;
+      cdec(d, c, i, j, k);
+      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
+      float zc = zp(c);
+      t[c] = zc + kOmega * ld(B.invd[l], c) * (r[c] - apply_A(d, fw, i, j, k, c, zc, zp));
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += T) {
+      int i, j, k;
+      cdec(d, c, i, j, k);
+      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
+      z[c] = t[c] + kOmega * ld(B.invd[l], c) * (r[c] - apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; }));
+    }
+    __syncthreads();
+  }
+  {
+    const int n = (int)B.d[0].cells();
+    const float* z0 = Z_(0);
+    for (int c = threadIdx.x; c < n; c += T) zout[c] = cvt<Z>(z0[c]);
+  }
 }
 
 template <typename T>
@@ -427,19 +557,36 @@ static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / 
 template <typename T>
 static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) {
   const int L = S.nlev;
+  const int G = S.nbottom;  // levels 0 .. G-1 run as grid kernels, G .. L-1 in one workgroup
   CGScalars* sc = S.sc;
   auto A = [&](int l) { return (const T*)S.lev[l].a[0]; };
   auto Ay = [&](int l) { return (const T*)S.lev[l].a[1]; };
   auto Az = [&](int l) { return (const T*)S.lev[l].a[2]; };
   auto ID = [&](int l) { return (const T*)S.lev[l].invd; };
   const long n0 = (long)S.lev[0].d.cells();
-  if (L == 1) {
-    hipLaunchKernelGGL((k_mg_coarse<T, float, float>), dim3(1), dim3(1024), 0, st, S.lev[0].d, A(0), Ay(0), Az(0),
-                       ID(0), r0, z0, sc, 1);
+  Bottom<T> B;
+  B.nl = L - G;
+  int off = 0;
+  for (int q = 0; q < B.nl; ++q) {
+    const int l = G + q;
+    B.d[q] = S.lev[l].d;
+    B.ax[q] = A(l);
+    B.ay[q] = Ay(l);
+    B.az[q] = Az(l);
+    B.invd[q] = ID(l);
+    B.off[q] = off;
+    off += 3 * (int)S.lev[l].d.cells();
+  }
+  const size_t lds = (size_t)off * sizeof(float);
+  const int bthreads = S.lev[G].d.cells() >= 1024 ? 1024 : (int)((S.lev[G].d.cells() + 63) / 64 * 64);
+  if (G == 0) {
+    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
+             hipLaunchKernelGGL((k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1));
     hipLaunchKernelGGL(k_scale_dot, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, r0, z0, sc, S.partials);
+    hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n0), S.partials, sc);
     return;
   }
-  for (int l = 0; l < L - 1; ++l) {
+  for (int l = 0; l < G; ++l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
     T* ta = (T*)S.lev[l].ta;
@@ -459,13 +606,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
                          Ay(l), Az(l), rl, (const T*)ta, rc, sc, 0);
     }
   }
-  {
-    const int l = L - 1;
-    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
-             hipLaunchKernelGGL((k_mg_coarse<T, T, T>), dim3(1), dim3(1024), 0, st, S.lev[l].d, A(l), Ay(l), Az(l),
-                                ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].z, sc, 0));
-  }
-  for (int l = L - 2; l >= 0; --l) {
+  NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
+           hipLaunchKernelGGL((k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
+                              (T*)S.lev[G].z, sc, 0));
+  for (int l = G - 1; l >= 0; --l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
     const T* ta = (const T*)S.lev[l].ta;
@@ -478,6 +622,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       NF_TIMED(S.prof, SIM_K_MG_POST2, st,
                hipLaunchKernelGGL((k_mg_post2<T, float, T, float, true>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st,
                                   d, A(0), Ay(0), Az(0), ID(0), r0, (const T*)tb, z0, sc, S.partials));
+      hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(d.cells()), S.partials, sc);
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_post1<T, T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(l),
@@ -575,12 +720,15 @@ static void cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
   for (int c = 0; c < count; ++c) {
     float* pold = S.pcur ? S.p1 : S.p0;
     float* pnew = S.pcur ? S.p0 : S.p1;
+    const int nb = (int)nblocks(n);
     NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
-             hipLaunchKernelGGL(k_cg_dir_apply, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
+             hipLaunchKernelGGL(k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
                                 pnew, S.q, S.sc, S.partials));
+    hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc);
     NF_TIMED(S.prof, SIM_K_CG_UPDATE, st,
-             hipLaunchKernelGGL(k_cg_update, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
+             hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
                                 S.partials));
+    hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc, n);
     vcycle_dispatch(S, S.r, S.z, st);
     S.pcur ^= 1;
   }
@@ -589,6 +737,12 @@ static void cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
 static int snapshot(Solver& S, hipStream_t st) {
   if (hipMemcpyAsync(S.host_sc, S.sc, sizeof(CGScalars), hipMemcpyDeviceToHost, st) != hipSuccess) return SIM_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return SIM_EHIP;
+  if (S.trace) {
+    const CGScalars& h = *S.host_sc;
+    fprintf(stderr, "[nf-solver] iters %d done %d conv %d first %d rel %.3e true %.3e vscale %.3e\n", h.iters, h.done,
+            h.converged, h.first, h.bb > 0 ? sqrt(h.rr / h.bb) : 0.0, h.bb > 0 ? sqrt(h.true_rr / h.bb) : 0.0,
+            h.vscale);
+  }
   return SIM_OK;
 }
 
@@ -599,8 +753,9 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
   double* x = S.x;
   hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
   NF_TIMED(S.prof, SIM_K_CG_INIT, st,
-           hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r, tol,
-                              maxit, sc, S.partials));
+           hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
+                              S.partials));
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n);
   vcycle_dispatch(S, S.r, S.z, st);
   S.pcur = 0;
   // First batch sized from the previous solve of this handle, then small
@@ -629,6 +784,7 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
       NF_TIMED(S.prof, SIM_K_CG_TRUE, st,
                hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
                                   x, S.r, allow, sc, S.partials));
+      hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n);
       r = snapshot(S, st);
       if (r != SIM_OK) return r;
       if (S.host_sc->converged || S.host_sc->nonfinite || !allow) break;
