@@ -32,7 +32,7 @@ N = 128
 T = 64
 EVERY = 8
 HBM_PEAK_GBS = 8000.0
-ROOFLINE_KERNEL = "mg_post2"
+ROOFLINE_KERNEL = "mg_up"
 
 
 def parse():
@@ -44,7 +44,21 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 launches): the reference kernel that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiling run")
     return ap.parse_args()
+
+
+def copy_probe(mib, torch):
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 3}), flush=True)
 
 
 class StepTimer:
@@ -130,14 +144,16 @@ def pct(v, q):
 
 
 def roofline(prof, precision):
-    """Algorithmic bytes per launch of the finest-level post-smoother
-    z_out = z_in + w D^-1 (r - A z_in), plus the r.z reduction: it reads z_in
-    (storage type), r (FP32), 1/diag (storage type) and the three face-fraction
-    arrays (storage type; each face read once), and writes z_out (FP32)."""
+    """Algorithmic bytes per launch of the finest-level up kernel of the
+    V-cycle (coarse correction z' = z2 + 8 e(parent), two damped-Jacobi sweeps,
+    r.z partials): it reads z2 (FP32), the coarse correction e (storage type,
+    C/8 values), r (FP32), 1/diag (storage type), the three face-fraction
+    arrays (storage type; each face once) and the previous z (FP32, for the
+    flexible direction coefficient), and writes z (FP32)."""
     es = 4 if precision == "fp32" else 2
     C = N ** 3
     F = (N + 1) * N * N * 3
-    bytes_per_launch = C * es + C * 4 + C * es + F * es + C * 4
+    bytes_per_launch = C * 4 + (C // 8) * es + C * 4 + C * es + F * es + C * 4 + C * 4
     ms, cnt = prof
     if not cnt:
         return None
@@ -145,7 +161,7 @@ def roofline(prof, precision):
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_mg_post2 (finest level, " + precision + ")", "launches": cnt,
+            "kernel": "k_mg_up (finest level, " + precision + ")", "launches": cnt,
             "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch}
 
 
@@ -183,6 +199,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, torch)
+        return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
     main_form, prof, _ = run_form(args.precision, args.steps, args.warmup, scene, torch,
                                   profile_kernel=ROOFLINE_KERNEL)

@@ -182,11 +182,17 @@ int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const doubl
  * the launch stream around every launch of one kernel family (multigrid
  * kernels: finest level only).  sim_profile_read synchronises those events and
  * returns the summed duration (ms) and the number of launches timed, then
- * clears them.  kernel: one of sim_kernel, or -1 to disable. */
+ * clears them.  kernel: one of sim_kernel, or -1 to disable.
+ * SIM_K_MG_DOWN: finest-level pre-smoothing + restriction (one fused launch,
+ * or the first of two when the fused kernels are disabled); SIM_K_MG_DOWN2:
+ * the restriction launch of the unfused form; SIM_K_MG_UP: finest-level
+ * correction + post-smoothing (fused) or the last post-smoothing launch
+ * (unfused); SIM_K_MG_UP1: the first post-smoothing launch (unfused);
+ * SIM_K_MG_COARSE: the one-workgroup bottom solve. */
 typedef enum {
   SIM_K_GEOM_PHI = 0, SIM_K_GEOM_ALPHA, SIM_K_ADVECT, SIM_K_RHS, SIM_K_UPDATE, SIM_K_ADJ_DIV,
   SIM_K_ADJ_FACES, SIM_K_ADVECT_ADJ, SIM_K_CG_INIT, SIM_K_CG_APPLY, SIM_K_CG_UPDATE, SIM_K_CG_TRUE,
-  SIM_K_MG_PRE, SIM_K_MG_RESTRICT, SIM_K_MG_POST1, SIM_K_MG_POST2, SIM_K_MG_COARSE, SIM_K_COUNT
+  SIM_K_MG_DOWN, SIM_K_MG_DOWN2, SIM_K_MG_UP1, SIM_K_MG_UP, SIM_K_MG_COARSE, SIM_K_COUNT
 } sim_kernel;
 int32_t sim_profile(sim_handle h, int32_t kernel);
 int32_t sim_profile_read(sim_handle h, double* total_ms, int64_t* count);

@@ -26,7 +26,7 @@ EXPORTS = [
 
 #: sim_kernel ids (include/neuralfluid.h)
 KERNELS = ["geom_phi", "geom_alpha", "advect", "rhs", "update", "adj_div", "adj_faces", "advect_adj", "cg_init",
-           "cg_apply", "cg_update", "cg_true", "mg_pre", "mg_restrict", "mg_post1", "mg_post2", "mg_coarse"]
+           "cg_apply", "cg_update", "cg_true", "mg_down", "mg_down2", "mg_up1", "mg_up", "mg_coarse"]
 
 
 class SimDesc(C.Structure):

@@ -108,7 +108,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(C * 4, (void**)&t->S.p0);
   alloc(C * 4, (void**)&t->S.p1);
   size_t nb_faces = (F_ + kBlock - 1) / kBlock, nb_cells = (C + kBlock - 1) / kBlock;
-  size_t npart = nb_faces * 21 > nb_cells * 2 ? nb_faces * 21 : nb_cells * 2;
+  size_t npart = nb_faces * 21 > nb_cells * 4 ? nb_faces * 21 : nb_cells * 4;
   alloc(npart * 8, (void**)&t->S.partials);
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
   for (int l = 0; l < p.nlev; ++l) {
@@ -124,8 +124,10 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
       alloc(dl.cells() * es, &L.r);
       alloc(dl.cells() * es, &L.z);
     }
-    alloc(dl.cells() * es, &L.ta);
-    alloc(dl.cells() * es, &L.tb);
+    // the finest level's smoother iterates stay FP32 in every precision
+    const size_t ts = l == 0 ? 4 : es;
+    alloc(dl.cells() * ts, &L.ta);
+    alloc(dl.cells() * ts, &L.tb);
   }
   if (d->precision != SIM_FP32) {
     size_t tot = 0;
@@ -227,9 +229,17 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   {
     const char* tr = std::getenv("NF_TRACE_SOLVER");
     c->S.trace = tr && tr[0] == '1';
+    const char* gr = std::getenv("NF_SOLVER_GRAPHS");
+    c->S.use_graph = !(gr && gr[0] == '0');
+    const char* fu = std::getenv("NF_MG_FUSED");
+    c->S.fused = !(fu && fu[0] == '0');
   }
   c->S.precision = desc->precision;
   for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
+  solver_init_device(c->S);
+  c->S.project = 1;
+  for (int s = 0; s < 6; ++s)
+    if (desc->bc[s] == SIM_BC_OUTFLOW) c->S.project = 0;
   c->S.nbottom = p.nlev - 1;
   while (c->S.nbottom > 0 && p.dims[c->S.nbottom - 1].cells() <= (size_t)kCoarseMaxCells) --c->S.nbottom;
   bool ok = true;
@@ -256,6 +266,7 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
 
 int32_t sim_destroy(sim_handle h) {
   if (!h) return SIM_EINVAL;
+  solver_release(h->S);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->S.host_sc) (void)hipHostFree(h->S.host_sc);
   delete h;

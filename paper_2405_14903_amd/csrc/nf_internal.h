@@ -16,10 +16,11 @@ constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 4096;
 constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coarse correction
 constexpr float kOmega = 0.8f;
-constexpr int kCoarseSweeps = 40;
+constexpr int kCoarseSweepsMax = 40;   // coarsest level: min(40, 2 * (largest extent)^2) sweeps
 constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces
 constexpr double kVcycleRms = 1.0 / 64.0;   // RMS of the (scaled) residual entering the V-cycle
 constexpr float kHalfInvDiagMax = 1024.0f;  // cap of 1/diag in FP16 storage
+constexpr float kHalfMax = 65504.0f;         // largest finite FP16 value
 
 struct Dims {
   int nx, ny, nz;
@@ -70,6 +71,9 @@ struct CGScalars {
   double tol2bb;     // tol^2 * b . b
   double true_rr;    // ||b - A x||^2 recomputed in FP64
   double vscale;     // scale applied to the fine residual before the V-cycle
+  double mu;         // mean of the residual over active cells (removed when the system is singular)
+  double zmu;        // mean of the preconditioned residual over active cells (singular systems)
+  double nact;       // number of active cells
   int iters;
   int done;
   int first;
@@ -118,31 +122,30 @@ __device__ inline double face_solid_velocity(const Domain& D, const GeomParams& 
   return G.v[2] + G.w[0] * r1 - G.w[1] * r0;
 }
 
-// Decode a flat velocity index into (component, i, j, k).
+// Decode a flat velocity index into (component, i, j, k) (32-bit arithmetic:
+// grids are limited to 2^30 cells).
 __device__ inline void face_decode(const Dims& d, long f, int& comp, int& i, int& j, int& k) {
-  long nfx = (long)d.nfx(), nfy = (long)d.nfy();
-  if (f < nfx) {
+  const unsigned nfx = (unsigned)d.nfx(), nfy = (unsigned)d.nfy();
+  unsigned fu = (unsigned)f, sx, sy;
+  if (fu < nfx) {
     comp = 0;
-    int sx = d.nx + 1;
-    i = (int)(f % sx);
-    long t = f / sx;
-    j = (int)(t % d.ny);
-    k = (int)(t / d.ny);
-  } else if (f < nfx + nfy) {
+    sx = d.nx + 1;
+    sy = d.ny;
+  } else if (fu < nfx + nfy) {
     comp = 1;
-    f -= nfx;
-    i = (int)(f % d.nx);
-    long t = f / d.nx;
-    j = (int)(t % (d.ny + 1));
-    k = (int)(t / (d.ny + 1));
+    fu -= nfx;
+    sx = d.nx;
+    sy = d.ny + 1;
   } else {
     comp = 2;
-    f -= nfx + nfy;
-    i = (int)(f % d.nx);
-    long t = f / d.nx;
-    j = (int)(t % d.ny);
-    k = (int)(t / d.ny);
+    fu -= nfx + nfy;
+    sx = d.nx;
+    sy = d.ny;
   }
+  const unsigned t = fu / sx;
+  i = (int)(fu - t * sx);
+  k = (int)(t / sy);
+  j = (int)(t - (unsigned)k * sy);
 }
 
 __device__ inline double wave_sum(double v) {

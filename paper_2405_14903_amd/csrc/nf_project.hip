@@ -19,6 +19,9 @@
 //   dJ/dU^ = S h,  dJ/dU_s = (I - S) h,  dJ/dalpha_f = h_f (W_f - U_s,f)
 // and dJ/dalpha, dJ/dU_s are carried to the ellipsoid's pose and controls
 // through the marching-squares fraction and the rigid velocity field.
+#include <algorithm>
+#include <cmath>
+
 #include "nf_internal.h"
 
 namespace nf {
@@ -236,87 +239,116 @@ __device__ inline int corner_node(const Dims& d, int comp, int i, int j, int k, 
   return d.node(n[0], n[1], n[2]);
 }
 
-// Per face: dJ/dU^ into gu; with GRAD, the ellipsoid's pose (15) and control
-// (6) partials are reduced (fixed order, FP64) and added to g_theta / g_ctrl.
-// uhat and p are the step's advected field and pressure (for W on cut faces).
-template <bool GRAD>
-__global__ __launch_bounds__(kBlock) void k_adj_faces(Domain D, GeomParams G, float kk,
-                                                       const float* __restrict__ alpha,
-                                                       const double* __restrict__ phi,
-                                                       const float* __restrict__ g,
-                                                       const float* __restrict__ y,
-                                                       const float* __restrict__ uhat,
-                                                       const float* __restrict__ p,
-                                                       float* __restrict__ gu, double* __restrict__ partials) {
+// Lattice index box per face component: faces lo[c][m] .. lo[c][m] + ext[c][m] - 1
+// along axis m; start[c] = first flat thread index of component c.
+struct FaceBox {
+  int lo[3][3];
+  int ext[3][3];
+  long start[4];
+};
+
+// Per face: dJ/dU^ = alpha h, h = g + G y.
+__global__ __launch_bounds__(kBlock) void k_adj_faces(Dims d, const float* __restrict__ alpha,
+                                                       const float* __restrict__ g, const float* __restrict__ y,
+                                                       float* __restrict__ gu) {
+  const long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (f >= (long)d.faces()) return;
+  int comp, i, j, k;
+  face_decode(d, f, comp, i, j, k);
+  float yp, ym;
+  face_cells(d, y, comp, i, j, k, yp, ym);
+  gu[f] = alpha[f] * (g[f] + (yp - ym));
+}
+
+// The ellipsoid's pose (15) and control (6) partials, reduced in a fixed
+// order in FP64.  Only faces with alpha < 1 contribute, and those have a
+// corner node inside the closed ellipsoid, so the kernel walks the faces of
+// the ellipsoid's bounding box (FaceBox) only.  uhat and p are the step's
+// advected field and pressure (for W on cut faces).
+__global__ __launch_bounds__(kBlock) void k_adj_geom(Domain D, GeomParams G, FaceBox B, float kk,
+                                                      const float* __restrict__ alpha,
+                                                      const double* __restrict__ phi,
+                                                      const float* __restrict__ g,
+                                                      const float* __restrict__ y,
+                                                      const float* __restrict__ uhat,
+                                                      const float* __restrict__ p, double* __restrict__ partials) {
   const Dims& d = D.d;
-  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double acc[21];
 #pragma unroll
   for (int t = 0; t < 21; ++t) acc[t] = 0.0;
-  if (f < (long)d.faces()) {
-    int comp, i, j, k;
-    face_decode(d, f, comp, i, j, k);
+  const long oy = (long)d.nfx(), oz = oy + (long)d.nfy();
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < B.start[3]; t += (long)gridDim.x * blockDim.x) {
+    const int comp = t < B.start[1] ? 0 : (t < B.start[2] ? 1 : 2);
+    const long lt = t - B.start[comp];
+    const int ex = B.ext[comp][0], ey = B.ext[comp][1];
+    const int i = B.lo[comp][0] + (int)(lt % ex);
+    const int j = B.lo[comp][1] + (int)((lt / ex) % ey);
+    const int k = B.lo[comp][2] + (int)(lt / ((long)ex * ey));
+    const long f = comp == 0 ? (long)d.fx(i, j, k) : (comp == 1 ? oy + d.fy(i, j, k) : oz + d.fz(i, j, k));
     const float a = alpha[f];
+    if (!(a < 1.0f)) continue;
+    const int own = comp == 0 ? i : (comp == 1 ? j : k);
+    const int sk = side_kind(D, comp, own);
+    if (sk == SIM_BC_WALL || sk == SIM_BC_INFLOW) continue;
     float yp, ym;
     face_cells(d, y, comp, i, j, k, yp, ym);
     const float hf = g[f] + (yp - ym);
-    gu[f] = a * hf;
-    if (GRAD && hf != 0.0f && a < 1.0f) {
-      int own = comp == 0 ? i : (comp == 1 ? j : k);
-      int sk = side_kind(D, comp, own);
-      bool fixed = sk == SIM_BC_WALL || sk == SIM_BC_INFLOW;
-      if (!fixed) {
-        double us = face_solid_velocity(D, G, comp, i, j, k);
-        if (a > 0.0f) {
-          // dJ/dalpha = h (W - U_s), W = U^ - k G P
-          float pp, pm;
-          face_cells(d, p, comp, i, j, k, pp, pm);
-          double W = (double)uhat[f] - (double)kk * ((double)pp - (double)pm);
-          double galpha = (double)hf * (W - us);
-          double ph[4], dg[4];
-          for (int q = 0; q < 4; ++q) ph[q] = phi[corner_node(d, comp, i, j, k, q)];
-          fraction_grad(ph, dg);
-          for (int q = 0; q < 4; ++q) {
-            if (dg[q] == 0.0) continue;
-            double xyz[3], gp[15];
-            node_xyz(d, D.dx, comp, i, j, k, q, xyz);
-            ellipsoid_phi_grad(G, xyz[0], xyz[1], xyz[2], gp);
-            double w = galpha * dg[q];
-            for (int t = 0; t < 15; ++t) acc[t] += w * gp[t];
-          }
-        }
-        // dJ/dU_s = (1 - alpha) h, through u_s = v + w x (x - c)
-        double gus = (1.0 - (double)a) * (double)hf;
-        double x[3] = {(i + (comp == 0 ? 0.0 : 0.5)) * D.dx, (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
-                       (k + (comp == 2 ? 0.0 : 0.5)) * D.dx};
-        double r0 = x[0] - G.c[0], r1 = x[1] - G.c[1], r2 = x[2] - G.c[2];
-        acc[15 + comp] += gus;
-        if (comp == 0) {
-          acc[19] += gus * r2;  acc[20] -= gus * r1;       // d/dw
-          acc[1] += gus * G.w[2]; acc[2] -= gus * G.w[1];  // d/dc = -d/dr
-        } else if (comp == 1) {
-          acc[18] -= gus * r2;  acc[20] += gus * r0;
-          acc[0] -= gus * G.w[2]; acc[2] += gus * G.w[0];
-        } else {
-          acc[18] += gus * r1;  acc[19] -= gus * r0;
-          acc[0] += gus * G.w[1]; acc[1] -= gus * G.w[0];
-        }
+    if (hf == 0.0f) continue;
+    const double us = face_solid_velocity(D, G, comp, i, j, k);
+    if (a > 0.0f) {
+      // dJ/dalpha = h (W - U_s), W = U^ - k G P
+      float pp, pm;
+      face_cells(d, p, comp, i, j, k, pp, pm);
+      const double W = (double)uhat[f] - (double)kk * ((double)pp - (double)pm);
+      const double galpha = (double)hf * (W - us);
+      double ph[4], dg[4];
+      for (int q = 0; q < 4; ++q) ph[q] = phi[corner_node(d, comp, i, j, k, q)];
+      fraction_grad(ph, dg);
+      for (int q = 0; q < 4; ++q) {
+        if (dg[q] == 0.0) continue;
+        double xyz[3], gp[15];
+        node_xyz(d, D.dx, comp, i, j, k, q, xyz);
+        ellipsoid_phi_grad(G, xyz[0], xyz[1], xyz[2], gp);
+        const double w = galpha * dg[q];
+#pragma unroll
+        for (int s = 0; s < 15; ++s) acc[s] += w * gp[s];
       }
     }
+    // dJ/dU_s = (1 - alpha) h, through u_s = v + w x (x - c)
+    const double gus = (1.0 - (double)a) * (double)hf;
+    const double x0 = (i + (comp == 0 ? 0.0 : 0.5)) * D.dx, x1 = (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
+                 x2 = (k + (comp == 2 ? 0.0 : 0.5)) * D.dx;
+    const double r0 = x0 - G.c[0], r1 = x1 - G.c[1], r2 = x2 - G.c[2];
+    if (comp == 0) {
+      acc[15] += gus;
+      acc[19] += gus * r2;  acc[20] -= gus * r1;       // d/dw
+      acc[1] += gus * G.w[2]; acc[2] -= gus * G.w[1];  // d/dc = -d/dr
+    } else if (comp == 1) {
+      acc[16] += gus;
+      acc[18] -= gus * r2;  acc[20] += gus * r0;
+      acc[0] -= gus * G.w[2]; acc[2] += gus * G.w[0];
+    } else {
+      acc[17] += gus;
+      acc[18] += gus * r1;  acc[19] -= gus * r0;
+      acc[0] += gus * G.w[1]; acc[1] -= gus * G.w[0];
+    }
   }
-  if (GRAD) block_partials<21>(acc, partials);
+  block_partials<21>(acc, partials);
 }
 
-__global__ __launch_bounds__(kFinBlock) void k_fin_adj_faces(int nb, const double* __restrict__ partials,
-                                                              double* __restrict__ g_theta,
-                                                              double* __restrict__ g_ctrl) {
-  double tot[21];
-  finish_partials<21>(partials, nb, tot);
+// One block per partial: fixed-order total, added to g_theta (0..14) or g_ctrl (15..20).
+__global__ __launch_bounds__(kFinBlock) void k_fin_adj_geom(int nb, const double* __restrict__ partials,
+                                                             double* __restrict__ g_theta,
+                                                             double* __restrict__ g_ctrl) {
+  const int q = blockIdx.x;
+  double tot[1];
+  finish_partials<1>(partials + (size_t)q * nb, nb, tot);
   if (threadIdx.x == 0) {
-    if (g_theta)
-      for (int t = 0; t < 15; ++t) g_theta[t] += tot[t];
-    if (g_ctrl)
-      for (int t = 0; t < 6; ++t) g_ctrl[t] += tot[15 + t];
+    if (q < 15) {
+      if (g_theta) g_theta[q] += tot[0];
+    } else if (g_ctrl) {
+      g_ctrl[q - 15] += tot[0];
+    }
   }
 }
 
@@ -376,18 +408,50 @@ void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rh
 
 size_t adj_faces_partials(const Dims& d) { return (size_t)nblocks(d.faces()) * 21; }
 
+// Faces that can have alpha < 1: a corner node inside the closed ellipsoid
+// x = c + R diag(a) u, |u| <= 1, whose extent along world axis m is
+// sqrt(sum_j (R_mj a_j)^2); two cells of margin on each side.
+FaceBox ellipsoid_face_box(const Dims& d, double dx, const GeomParams& G) {
+  FaceBox B;
+  const int n[3] = {d.nx, d.ny, d.nz};
+  int lo[3], hi[3];
+  for (int m = 0; m < 3; ++m) {
+    double e2 = 0.0;
+    for (int j = 0; j < 3; ++j) e2 += (G.R[3 * m + j] * G.a[j]) * (G.R[3 * m + j] * G.a[j]);
+    const double e = std::sqrt(e2);
+    const double l = std::floor((G.c[m] - e) / dx) - 2.0, h = std::ceil((G.c[m] + e) / dx) + 2.0;
+    lo[m] = (int)std::max(0.0, std::min((double)n[m] + 1.0, l));
+    hi[m] = (int)std::max(0.0, std::min((double)n[m] + 1.0, h + 1.0));
+  }
+  long tot = 0;
+  for (int c = 0; c < 3; ++c) {
+    B.start[c] = tot;
+    long cnt = 1;
+    for (int m = 0; m < 3; ++m) {
+      const int size = n[m] + (m == c ? 1 : 0);
+      const int l = std::min(lo[m], size), h = std::min(hi[m], size);
+      B.lo[c][m] = l;
+      B.ext[c][m] = std::max(0, h - l);
+      cnt *= B.ext[c][m];
+    }
+    tot += cnt;
+  }
+  B.start[3] = tot;
+  return B;
+}
+
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
                       float* gu, double* partials, double* g_theta, double* g_ctrl, hipStream_t s) {
-  const int nb = (int)nblocks(D.d.faces());
-  if (grad) {
-    hipLaunchKernelGGL(k_adj_faces<true>, dim3(nb), dim3(kBlock), 0, s, D, G, (float)kk, alpha, phi, g, y, uhat, p,
-                       gu, partials);
-    hipLaunchKernelGGL(k_fin_adj_faces, dim3(1), dim3(kFinBlock), 0, s, nb, partials, g_theta, g_ctrl);
-  } else {
-    hipLaunchKernelGGL(k_adj_faces<false>, dim3(nb), dim3(kBlock), 0, s, D, G, (float)kk, alpha, phi, g, y, uhat, p,
-                       gu, partials);
-  }
+  hipLaunchKernelGGL(k_adj_faces, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D.d, alpha, g, y, gu);
+  if (!grad) return;
+  const FaceBox B = ellipsoid_face_box(D.d, D.dx, G);
+  if (B.start[3] == 0) return;
+  // a bounded grid with a grid-stride loop keeps the partial count small
+  const int nb = (int)std::min<size_t>(nblocks((size_t)B.start[3]), 1024);
+  hipLaunchKernelGGL(k_adj_geom, dim3(nb), dim3(kBlock), 0, s, D, G, B, (float)kk, alpha, phi, g, y, uhat, p,
+                     partials);
+  hipLaunchKernelGGL(k_fin_adj_geom, dim3(21), dim3(kFinBlock), 0, s, nb, partials, g_theta, g_ctrl);
 }
 
 }  // namespace nf

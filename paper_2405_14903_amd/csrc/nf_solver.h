@@ -59,6 +59,12 @@ struct Solver {
   int pcur = 0;        // which of p0 / p1 holds the current direction
   int last_iters = 0;  // iterations of the previous solve (sizes the first batch)
   int trace = 0;       // print each convergence snapshot to stderr (NF_TRACE_SOLVER=1)
+  size_t lds_bytes = 65536;  // dynamic LDS the one-workgroup bottom solve may use
+  // No Dirichlet side: the operator's null space holds the constants, and the
+  // residual's mean over active cells (rounding of a compatible right-hand
+  // side) is removed at the start and at every restart.
+  int project = 0;
+  int fused = 1;       // fused tile kernels per grid level (NF_MG_FUSED=0: four passes per level)
   Level lev[kMaxLevels];
   const float* ax = nullptr;   // fine FP32 fractions (CG operator)
   const float* ay = nullptr;
@@ -76,6 +82,12 @@ struct Solver {
   float* scratch_inv = nullptr;
   size_t scratch_off[kMaxLevels] = {};
   Profiler* prof = nullptr;
+  // CUDA-graph style replay of two CG iterations (captured once per handle on
+  // an internal stream, launched on the caller's stream)
+  int use_graph = 1;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t iter_graph = nullptr;
+  hipGraphExec_t iter_exec = nullptr;
 };
 
 // nf_geom.hip
@@ -105,5 +117,7 @@ void launch_loss_box(const Domain& D, const double* lo, const double* hi, const 
 // nf_solver.hip
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st);
 int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st);
+void solver_init_device(Solver& S);
+void solver_release(Solver& S);
 
 }  // namespace nf

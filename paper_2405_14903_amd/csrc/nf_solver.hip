@@ -5,24 +5,29 @@
 // Profiling: MGPCG with custom prolongation / restriction between a
 // hierarchy of grids).  This solver:
 //   * applies A x = sum over faces of alpha_f (x_c - x_nb) as a 7-point
-//     stencil read straight from the face fractions (no stored matrix);
+//     stencil read straight from the face fractions (no stored matrix), in
+//     difference form so that FP32 A p keeps its relative accuracy;
 //   * keeps the iterate x in FP64 and the other CG vectors in FP32; every CG
 //     scalar stays on the device, with FP64 dot products reduced in a fixed
-//     order (per-block partials summed by the last block to finish), so a
+//     order (per-block partials, then a one-block finishing kernel), so a
 //     solve is bitwise reproducible;
 //   * stops on the recursive residual, then recomputes b - A x from the FP64
-//     iterate; if that true residual misses the tolerance, the true residual
-//     replaces the recursive one and CG restarts (iterative refinement);
+//     iterate; if that true residual misses the tolerance, it replaces the
+//     recursive one and CG restarts (iterative refinement, bounded);
+//   * on singular systems (no Dirichlet side) removes the residual's mean over
+//     active cells at the start and at every restart;
 //   * preconditions with one V-cycle: level l+1 halves each axis, coarse face
 //     weight = 1/2 * sum of the 2x2 fine faces it covers, restriction = mean
-//     of the 8 child residuals with prolongation = 8 x injection (together the
-//     transpose pair), two damped-Jacobi sweeps (omega = 0.8) before and after
-//     the correction, and 40 Jacobi sweeps on the coarsest level (<= 4096
-//     cells) in one workgroup.  Every piece is a fixed linear symmetric map,
-//     so the preconditioner is symmetric and plain CG applies;
-//   * stores the multigrid arrays in FP32, FP16 or BF16 (template T).  The
+//     of the 8 child residuals with prolongation = 8 x injection, two
+//     damped-Jacobi sweeps (omega = 0.8) before and after the correction, and
+//     the levels of at most 4096 cells in one workgroup with the coarsest
+//     level relaxed by up to 40 sweeps;
+//   * uses the flexible (Polak-Ribiere) direction coefficient, since FP16 /
+//     BF16 rounding makes the preconditioner slightly non-linear;
+//   * stores the multigrid fractions, 1/diag and coarse vectors in FP32, FP16
+//     or BF16 (template T); level 0's smoother iterates stay FP32.  The
 //     V-cycle is linear, so its input is scaled to a fixed RMS and its output
-//     scaled back, which keeps FP16 values in range; 1/diag is capped in FP16.
+//     scaled back, which keeps FP16 values in range.
 #include "nf_internal.h"
 #include "nf_solver.h"
 
@@ -45,10 +50,11 @@ template <> __device__ inline __half cvt<__half>(float v) { return __float2half(
 template <> __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
 __device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) {
-  i = (int)(c % d.nx);
-  long t = c / d.nx;
-  j = (int)(t % d.ny);
-  k = (int)(t / d.ny);
+  const unsigned cu = (unsigned)c, nx = (unsigned)d.nx, ny = (unsigned)d.ny;
+  const unsigned t = cu / nx;
+  i = (int)(cu - t * nx);
+  k = (int)(t / ny);
+  j = (int)(t - (unsigned)k * ny);
 }
 
 // The 6 face weights of cell (i,j,k): lower / upper along x, y, z.
@@ -114,12 +120,21 @@ __global__ void k_x_load(long n, const float* __restrict__ xin, double* __restri
   if (c < n) x[c] = (double)xin[c];
 }
 
-__global__ void k_x_store(long n, const double* __restrict__ x, float* __restrict__ xout) {
+// Output of a solve: the iterate on active cells, 0 on inactive (fully solid)
+// cells, which carry no unknown (the preconditioner's prolongation may leave
+// values there that are never coupled to anything).
+__global__ void k_x_store(Dims d, const float* __restrict__ ax, const float* __restrict__ ay,
+                          const float* __restrict__ az, const double* __restrict__ x, float* __restrict__ xout) {
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n) xout[c] = (float)x[c];
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cdec(d, c, i, j, k);
+  Faces<float> fw(d, ax, ay, az, i, j, k);
+  xout[c] = fw.diag() > 0.0f ? (float)x[c] : 0.0f;
 }
 
-// r = b - A x; partials of b.b (active cells) and r.r.
+// r = b - A x; partials of b.b (active cells), r.r, sum of r and the number
+// of active cells.
 __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restrict__ ax,
                                                      const float* __restrict__ ay,
                                                      const float* __restrict__ az,
@@ -127,25 +142,41 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
                                                      const double* __restrict__ x, float* __restrict__ r,
                                                      double* partials) {
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[2] = {0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<float> fw(d, ax, ay, az, i, j, k);
-    double bc = fw.diag() > 0.0f ? (double)b[c] : 0.0;
+    const bool act = fw.diag() > 0.0f;
+    double bc = act ? (double)b[c] : 0.0;
     double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
     r[c] = (float)rc;
     v[0] = bc * bc;
     v[1] = rc * rc;
+    v[2] = rc;
+    v[3] = act ? 1.0 : 0.0;
   }
-  block_partials<2>(v, partials);
+  block_partials<4>(v, partials);
+}
+
+// ||r - mean||^2 over active cells from r.r, sum(r) and the active count
+// (or r.r when the system has a Dirichlet side).
+__device__ inline double projected_rr(double rr, double sr, double na, int project) {
+  if (!project || !(na > 0.0)) return rr;
+  double v = rr - sr * sr / na;
+  return v > 0.0 ? v : 0.0;
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* partials, CGScalars* sc, double tol,
-                                                         int maxit, long ncells) {
-  double tot[2];
-  finish_partials<2>(partials, nb, tot);
+                                                         int maxit, long ncells, int project) {
+  double tot[4];
+  finish_partials<4>(partials, nb, tot);
   if (threadIdx.x == 0) {
+    const double rr = projected_rr(tot[1], tot[2], tot[3], project);
+    sc->mu = project && tot[3] > 0.0 ? tot[2] / tot[3] : 0.0;
+    sc->nact = tot[3];
+    sc->zmu = 0.0;
+    tot[1] = rr;
     sc->bb = tot[0];
     sc->rr = tot[1];
     sc->true_rr = tot[1];
@@ -175,13 +206,18 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
   if (sc->done) return;
   const bool first = sc->first;
   const float beta = (float)sc->beta;
+  // z minus its mean over active cells (0 unless the system is singular): the
+  // V-cycle maps the constants to a large multiple of themselves, and a
+  // rounding-level constant left in r would otherwise grow in p.  Values on
+  // inactive cells never couple (all their faces are closed).
+  const float zmu = (float)sc->zmu;
   long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<float> fw(d, ax, ay, az, i, j, k);
-    auto pv = [&](long t) { return first ? z[t] : z[t] + beta * pold[t]; };
+    auto pv = [&](long t) { return first ? z[t] - zmu : (z[t] - zmu) + beta * pold[t]; };
     float pc = pv(c);
     float qc = apply_A(d, fw, i, j, k, c, pc, pv);
     pnew[c] = pc;
@@ -247,23 +283,28 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
                                                               int allow, const CGScalars* sc, double* partials) {
   const bool rep = may_replace(sc, allow);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
+  double v[3] = {0.0, 0.0, 0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
+    Faces<float> fw(d, ax, ay, az, i, j, k);
     double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
     v[0] = rc * rc;
+    v[1] = rc;
+    v[2] = fw.diag() > 0.0f ? 1.0 : 0.0;
     if (rep) r[c] = (float)rc;
   }
-  block_partials<1>(v, partials);
+  block_partials<3>(v, partials);
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* partials, CGScalars* sc, int allow,
-                                                         long ncells) {
+                                                         long ncells, int project) {
   const bool rep = may_replace(sc, allow);
-  double tot[1];
-  finish_partials<1>(partials, nb, tot);
+  double tot[3];
+  finish_partials<3>(partials, nb, tot);
   if (threadIdx.x == 0) {
+    tot[0] = projected_rr(tot[0], tot[1], tot[2], project);
+    sc->mu = project && tot[2] > 0.0 ? tot[1] / tot[2] : 0.0;
     sc->true_rr = tot[0];
     if (!isfinite(tot[0])) sc->nonfinite = 1;
     sc->converged = !sc->nonfinite && (sc->bb == 0.0 || tot[0] <= sc->tol2bb);
@@ -276,16 +317,31 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* pa
   }
 }
 
+// r -= mean on active cells (singular systems, after k_fin_init / a restart).
+__global__ __launch_bounds__(kBlock) void k_sub_mean(Dims d, const float* __restrict__ ax,
+                                                      const float* __restrict__ ay, const float* __restrict__ az,
+                                                      float* __restrict__ r, const CGScalars* sc) {
+  if (sc->done) return;
+  const double mu = sc->mu;
+  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cdec(d, c, i, j, k);
+  Faces<float> fw(d, ax, ay, az, i, j, k);
+  if (fw.diag() > 0.0f) r[c] = (float)((double)r[c] - mu);
+}
+
 // rho = r . z and the flexible (Polak-Ribiere) direction coefficient
 // beta = r_new . (z_new - z_old) / rho_old: the rounding of the FP16 / BF16
 // V-cycle makes the preconditioner slightly non-linear, which this form
 // tolerates; for an exactly linear preconditioner r_new . z_old = 0 and it
 // reduces to the Fletcher-Reeves ratio.
-__global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc) {
+__global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc, int project) {
   if (sc->done) return;
-  double tot[2];
-  finish_partials<2>(partials, nb, tot);
+  double tot[3];
+  finish_partials<3>(partials, nb, tot);
   if (threadIdx.x == 0) {
+    sc->zmu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
     if (sc->first) {
       sc->rho = tot[0];
     } else {
@@ -295,19 +351,23 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* part
   }
 }
 
-// z *= 1 / vscale (the V-cycle ran on the scaled residual); partials of r . z.
-__global__ __launch_bounds__(kBlock) void k_scale_dot(long n, const float* __restrict__ r, float* __restrict__ z,
-                                                       const CGScalars* sc, double* partials) {
+// z *= 1 / vscale (the V-cycle ran on the scaled residual), 0 on inactive
+// cells; partials of r . z, r . z_old (always 0 here: the whole V-cycle ran in
+// one workgroup and overwrote z) and sum(z).
+template <typename A>
+__global__ __launch_bounds__(kBlock) void k_scale_dot(long n, const A* __restrict__ invd, const float* __restrict__ r,
+                                                       float* __restrict__ z, const CGScalars* sc, double* partials) {
   if (sc->done) return;
   const float inv = (float)(1.0 / sc->vscale);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[2] = {0.0, 0.0};
+  double v[3] = {0.0, 0.0, 0.0};
   if (c < n) {
-    float zc = z[c] * inv;
+    float zc = ld(invd, c) > 0.0f ? z[c] * inv : 0.0f;
     z[c] = zc;
     v[0] = (double)r[c] * (double)zc;
+    v[2] = zc;
   }
-  block_partials<2>(v, partials);
+  block_partials<3>(v, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,15 +438,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* _
   int i, j, k;
   cdec(d, c, i, j, k);
   Faces<A> fw(d, ax, ay, az, i, j, k);
+  // z' at the cell and its 6 neighbours; the parent of a neighbour differs
+  // from the cell's parent only across an even-odd boundary
   const int cnx = cd.nx, cny = cd.ny;
-  auto zp = [&](long t) {
-    int ti = (int)(t % d.nx);
-    long tt = t / d.nx;
-    int tj = (int)(tt % d.ny), tk = (int)(tt / d.ny);
-    return ld(zin, t) + 8.0f * ld(e, (ti >> 1) + (long)cnx * ((tj >> 1) + (long)cny * (tk >> 1)));
+  const long pc = (i >> 1) + (long)cnx * ((j >> 1) + (long)cny * (k >> 1));
+  const long psx = 1, psy = cnx, psz = (long)cnx * cny;
+  const float ec = ld(e, pc);
+  const float zc = ld(zin, c) + 8.0f * ec;
+  const long sxy = (long)d.nx * d.ny;
+  auto nb = [&](bool ok, long q, bool same, long pq) {
+    return ok ? ld(zin, q) + 8.0f * (same ? ec : ld(e, pq)) : 0.0f;
   };
-  float zc = zp(c);
-  float Az = apply_A(d, fw, i, j, k, c, zc, zp);
+  float Az = fw.w[0] * (zc - nb(i > 0, c - 1, (i & 1), pc - psx));
+  Az += fw.w[1] * (zc - nb(i < d.nx - 1, c + 1, !(i & 1), pc + psx));
+  Az += fw.w[2] * (zc - nb(j > 0, c - d.nx, (j & 1), pc - psy));
+  Az += fw.w[3] * (zc - nb(j < d.ny - 1, c + d.nx, !(j & 1), pc + psy));
+  Az += fw.w[4] * (zc - nb(k > 0, c - sxy, (k & 1), pc - psz));
+  Az += fw.w[5] * (zc - nb(k < d.nz - 1, c + sxy, !(k & 1), pc + psz));
   zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (s0 * ld(r, c) - Az));
 }
 
@@ -402,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[2] = {0.0, 0.0};
+  double v[3] = {0.0, 0.0, 0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
@@ -411,12 +479,188 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
     float zc = ld(zin, c);
     float rraw = ld(r, c);
     float Az = apply_A(d, fw, i, j, k, c, zc, zv);
-    float zo = (zc + kOmega * ld(invd, c) * (s0 * rraw - Az)) * inv;
+    const float idc = ld(invd, c);
+    float zo = (zc + kOmega * idc * (s0 * rraw - Az)) * inv;
+    if (LVL0 && !(idc > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
     if (LVL0 && !first) v[1] = (double)rraw * (double)ld(zout, c);   // r_new . z_old
     zout[c] = cvt<O>(zo);
     v[0] = (double)rraw * (double)zo;
+    v[2] = zo;
   }
-  if (LVL0) block_partials<2>(v, partials);
+  if (LVL0) block_partials<3>(v, partials);
+}
+
+// ---------------------------------------------------------------------------
+// Fused grid-level kernels.  One workgroup owns a kTX x kTY x kTZ tile of a
+// level and recomputes what its neighbours own on a halo instead of waiting
+// for them, so the four smoother / transfer passes of a level become two
+// launches and each array is read from memory once per launch:
+//   down: z1 = w D^-1 r on the tile + 2 cells, z2 = z1 + w D^-1 (r - A z1)
+//         on the tile + 1 cell (stored for the way up), and the restricted
+//         residual mean(r - A z2) of the tile's coarse cells;
+//   up:   z' = z2 + 8 e(parent) on the tile + 2 cells, z3 = z' + w D^-1 (r - A z')
+//         on the tile + 1 cell, z4 = z3 + w D^-1 (r - A z3) on the tile.
+// Values beyond the domain are 0, as in apply_A.
+// ---------------------------------------------------------------------------
+
+constexpr int kTX = 32, kTY = 8, kTZ = 8;
+template <int H>
+struct Halo {
+  static constexpr int X = kTX + 2 * H, Y = kTY + 2 * H, Z = kTZ + 2 * H, N = X * Y * Z;
+};
+
+__device__ inline int tiles_of(const Dims& d) {
+  return ((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
+}
+
+__device__ inline void tile_origin(const Dims& d, int& i0, int& j0, int& k0) {
+  const int tx = (d.nx + kTX - 1) / kTX, ty = (d.ny + kTY - 1) / kTY;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
+  i0 = (b % tx) * kTX;
+  j0 = ((b / tx) % ty) * kTY;
+  k0 = (b / (tx * ty)) * kTZ;
+}
+
+__device__ inline bool in_dom(const Dims& d, int i, int j, int k) {
+  return i >= 0 && j >= 0 && k >= 0 && i < d.nx && j < d.ny && k < d.nz;
+}
+
+// sum over the 6 faces of w_f (v[q] - v[nb]) for a cell at local index q of a
+// halo region with row length X and plane size XY (neighbours beyond the
+// domain hold 0 in v, the Dirichlet / closed convention of apply_A)
+template <typename A>
+__device__ inline float apply_local(const Faces<A>& fw, const float* v, int q, int X, int XY) {
+  const float c = v[q];
+  float s = fw.w[0] * (c - v[q - 1]);
+  s += fw.w[1] * (c - v[q + 1]);
+  s += fw.w[2] * (c - v[q - X]);
+  s += fw.w[3] * (c - v[q + X]);
+  s += fw.w[4] * (c - v[q - XY]);
+  s += fw.w[5] * (c - v[q + XY]);
+  return s;
+}
+
+template <typename A, typename R, typename Z, typename RC>
+__global__ __launch_bounds__(kBlock) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
+                                                     const A* __restrict__ ay, const A* __restrict__ az,
+                                                     const A* __restrict__ invd, const R* __restrict__ r,
+                                                     Z* __restrict__ z2out, RC* __restrict__ rc, const CGScalars* sc,
+                                                     int lvl0) {
+  if (sc->done) return;
+  using H2 = Halo<2>;
+  using H1 = Halo<1>;
+  __shared__ float z1s[H2::N];
+  __shared__ float rs[H1::N];
+  __shared__ float z2s[H1::N];
+  const float s0 = level_scale(sc, lvl0);
+  int i0, j0, k0;
+  tile_origin(d, i0, j0, k0);
+  for (int q = threadIdx.x; q < H2::N; q += kBlock) {
+    const int li = q % H2::X, lj = (q / H2::X) % H2::Y, lk = q / (H2::X * H2::Y);
+    const int i = i0 + li - 2, j = j0 + lj - 2, k = k0 + lk - 2;
+    float v = 0.0f;
+    if (in_dom(d, i, j, k)) {
+      const long c = d.c(i, j, k);
+      v = kOmega * ld(invd, c) * (s0 * ld(r, c));
+    }
+    z1s[q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < H1::N; q += kBlock) {
+    const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
+    const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
+    float z2 = 0.0f, rv = 0.0f;
+    if (in_dom(d, i, j, k)) {
+      const long c = d.c(i, j, k);
+      Faces<A> fw(d, ax, ay, az, i, j, k);
+      const int q2 = (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
+      rv = s0 * ld(r, c);
+      const float Az = apply_local(fw, z1s, q2, H2::X, H2::X * H2::Y);
+      const Z zs = cvt<Z>(z1s[q2] + kOmega * ld(invd, c) * (rv - Az));
+      z2 = ld(&zs, 0);
+      if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ) z2out[c] = zs;
+    }
+    z2s[q] = z2;
+    rs[q] = rv;
+  }
+  __syncthreads();
+  {
+    // the tile's (kTX/2) x (kTY/2) x (kTZ/2) = kBlock coarse cells, one per thread
+    const int t = threadIdx.x;
+    const int ci = t % (kTX / 2), cj = (t / (kTX / 2)) % (kTY / 2), ck = t / ((kTX / 2) * (kTY / 2));
+    const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
+    if (I < cd.nx && J < cd.ny && K < cd.nz) {
+      float s = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
+        const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+        Faces<A> fw(d, ax, ay, az, i, j, k);
+        const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+        s += rs[q1] - apply_local(fw, z2s, q1, H1::X, H1::X * H1::Y);
+      }
+      rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
+    }
+  }
+}
+
+template <typename A, typename R, typename Z, typename E, typename O, bool LVL0>
+__global__ __launch_bounds__(kBlock) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
+                                                   const A* __restrict__ ay, const A* __restrict__ az,
+                                                   const A* __restrict__ invd, const R* __restrict__ r,
+                                                   const Z* __restrict__ z2, const E* __restrict__ e,
+                                                   O* __restrict__ zout, const CGScalars* sc, double* partials) {
+  if (sc->done) return;
+  using H2 = Halo<2>;
+  using H1 = Halo<1>;
+  __shared__ float zp[H2::N];
+  __shared__ float z3s[H1::N];
+  const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
+  const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
+  const bool first = sc->first;
+  int i0, j0, k0;
+  tile_origin(d, i0, j0, k0);
+  for (int q = threadIdx.x; q < H2::N; q += kBlock) {
+    const int li = q % H2::X, lj = (q / H2::X) % H2::Y, lk = q / (H2::X * H2::Y);
+    const int i = i0 + li - 2, j = j0 + lj - 2, k = k0 + lk - 2;
+    float v = 0.0f;
+    if (in_dom(d, i, j, k)) v = ld(z2, d.c(i, j, k)) + 8.0f * ld(e, cd.c(i >> 1, j >> 1, k >> 1));
+    zp[q] = v;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < H1::N; q += kBlock) {
+    const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
+    const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
+    float v = 0.0f;
+    if (in_dom(d, i, j, k)) {
+      const long c = d.c(i, j, k);
+      Faces<A> fw(d, ax, ay, az, i, j, k);
+      const int q2 = (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
+      v = zp[q2] + kOmega * ld(invd, c) * (s0 * ld(r, c) - apply_local(fw, zp, q2, H2::X, H2::X * H2::Y));
+    }
+    z3s[q] = v;
+  }
+  __syncthreads();
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < kTX * kTY * kTZ; q += kBlock) {
+    const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    if (!in_dom(d, i, j, k)) continue;
+    const long c = d.c(i, j, k);
+    Faces<A> fw(d, ax, ay, az, i, j, k);
+    const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+    const float rraw = ld(r, c);
+    const float idc = ld(invd, c);
+    float zo = (z3s[q1] + kOmega * idc * (s0 * rraw - apply_local(fw, z3s, q1, H1::X, H1::X * H1::Y))) * inv;
+    if (LVL0 && !(idc > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
+    if (LVL0 && !first) acc[1] += (double)rraw * (double)ld(zout, c);   // r_new . z_old
+    zout[c] = cvt<O>(zo);
+    if (LVL0) {
+      acc[0] += (double)rraw * (double)zo;
+      acc[2] += (double)zo;
+    }
+  }
+  if (LVL0) block_partials<3>(acc, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -433,8 +677,128 @@ struct Bottom {
   const A* ay[kMaxLevels];
   const A* az[kMaxLevels];
   const A* invd[kMaxLevels];
-  int off[kMaxLevels];   // LDS offset (floats) of level l's three vectors r, z, t
+  int off[kMaxLevels];    // LDS offset (floats) of level l's three vectors r, z, t
+  int coff[kMaxLevels];   // LDS offset of the level's staged fractions and 1/diag (FP32), -1: read from memory
 };
+
+// Coefficients of one level, from LDS (P = float) or from memory (P = storage type).
+template <typename P>
+struct Coef {
+  const P* ax;
+  const P* ay;
+  const P* az;
+  const P* invd;
+};
+
+// z = two damped-Jacobi sweeps from 0 (t holds the first); then the restricted
+// residual mean over the 8 children of (r - A z) into rc.
+template <typename P>
+__device__ inline void bottom_down(const Dims& d, const Dims& cd, const Coef<P>& K, const float* r, float* z, float* t,
+                                   float* rc) {
+  const int n = (int)d.cells(), T = blockDim.x;
+  for (int c = threadIdx.x; c < n; c += T) t[c] = kOmega * ld(K.invd, c) * r[c];
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += T) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+    float Az = apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; });
+    z[c] = t[c] + kOmega * ld(K.invd, c) * (r[c] - Az);
+  }
+  __syncthreads();
+  for (int C = threadIdx.x; C < (int)cd.cells(); C += T) {
+    int I, J, K_;
+    cdec(cd, C, I, J, K_);
+    float s = 0.0f;
+    for (int b = 0; b < 8; ++b) {
+      int i = 2 * I + (b & 1), j = 2 * J + ((b >> 1) & 1), k = 2 * K_ + (b >> 2);
+      int c = d.c(i, j, k);
+      Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+      s += r[c] - apply_A(d, fw, i, j, k, c, z[c], [&](long q) { return z[q]; });
+    }
+    rc[C] = 0.125f * s;
+  }
+  __syncthreads();
+}
+
+// Coarsest level: min(kCoarseSweepsMax, 2 * extent^2) damped-Jacobi sweeps
+// from 0.  When every cell has its own thread, the cell's coefficients stay in
+// registers across the sweeps.
+template <typename P>
+__device__ inline void bottom_coarsest(const Dims& d, const Coef<P>& K, const float* r, float* z, float* t) {
+  const int n = (int)d.cells(), T = blockDim.x;
+  const int ext = max(d.nx, max(d.ny, d.nz));
+  const int sweeps = min(kCoarseSweepsMax, 2 * ext * ext);
+  for (int c = threadIdx.x; c < n; c += T) z[c] = 0.0f;
+  __syncthreads();
+  float *src = z, *dst = t;
+  if (n <= T) {
+    const int c = threadIdx.x;
+    const bool on = c < n;
+    int i = 0, j = 0, k = 0;
+    if (on) cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, on ? i : 0, on ? j : 0, on ? k : 0);
+    const float idc = on ? ld(K.invd, c) : 0.0f;
+    const float rc = on ? r[c] : 0.0f;
+    for (int s = 0; s < sweeps; ++s) {
+      if (on) {
+        const float* sp = src;
+        float Az = apply_A(d, fw, i, j, k, c, sp[c], [&](long q) { return sp[q]; });
+        dst[c] = sp[c] + kOmega * idc * (rc - Az);
+      }
+      __syncthreads();
+      float* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+  } else {
+    for (int s = 0; s < sweeps; ++s) {
+      for (int c = threadIdx.x; c < n; c += T) {
+        int i, j, k;
+        cdec(d, c, i, j, k);
+        Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+        const float* sp = src;
+        float Az = apply_A(d, fw, i, j, k, c, sp[c], [&](long q) { return sp[q]; });
+        dst[c] = sp[c] + kOmega * ld(K.invd, c) * (r[c] - Az);
+      }
+      __syncthreads();
+      float* tmp = src;
+      src = dst;
+      dst = tmp;
+    }
+  }
+  if (src != z) {
+    for (int c = threadIdx.x; c < n; c += T) z[c] = src[c];
+    __syncthreads();
+  }
+}
+
+// z' = z + 8 e(parent); t = z' + w D^-1 (r - A z'); z = t + w D^-1 (r - A t).
+template <typename P>
+__device__ inline void bottom_up(const Dims& d, const Dims& cd, const Coef<P>& K, const float* r, float* z, float* t,
+                                 const float* e) {
+  const int n = (int)d.cells(), T = blockDim.x;
+  auto zp = [&](long q) {
+    int ti, tj, tk;
+    cdec(d, q, ti, tj, tk);
+    return z[q] + 8.0f * e[(ti >> 1) + cd.nx * ((tj >> 1) + cd.ny * (tk >> 1))];
+  };
+  for (int c = threadIdx.x; c < n; c += T) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+    float zc = zp(c);
+    t[c] = zc + kOmega * ld(K.invd, c) * (r[c] - apply_A(d, fw, i, j, k, c, zc, zp));
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += T) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+    z[c] = t[c] + kOmega * ld(K.invd, c) * (r[c] - apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; }));
+  }
+  __syncthreads();
+}
 
 template <typename A, typename R, typename Z>
 __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __restrict__ rin, Z* __restrict__ zout,
@@ -446,94 +810,44 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __rest
   auto R_ = [&](int l) { return lds + B.off[l]; };
   auto Z_ = [&](int l) { return lds + B.off[l] + (int)B.d[l].cells(); };
   auto T_ = [&](int l) { return lds + B.off[l] + 2 * (int)B.d[l].cells(); };
+  auto staged = [&](int l) {
+    const float* p = lds + B.coff[l];
+    const int fx = (int)B.d[l].nfx(), fy = (int)B.d[l].nfy(), fz = (int)B.d[l].nfz();
+    return Coef<float>{p, p + fx, p + fx + fy, p + fx + fy + fz};
+  };
+  auto global = [&](int l) { return Coef<A>{B.ax[l], B.ay[l], B.az[l], B.invd[l]}; };
+  // stage the coefficients that fit, converted to FP32
+  for (int l = 0; l < B.nl; ++l) {
+    if (B.coff[l] < 0) continue;
+    float* dst = lds + B.coff[l];
+    const int fx = (int)B.d[l].nfx(), fy = (int)B.d[l].nfy(), fz = (int)B.d[l].nfz(), n = (int)B.d[l].cells();
+    for (int q = threadIdx.x; q < fx; q += T) dst[q] = ld(B.ax[l], q);
+    for (int q = threadIdx.x; q < fy; q += T) dst[fx + q] = ld(B.ay[l], q);
+    for (int q = threadIdx.x; q < fz; q += T) dst[fx + fy + q] = ld(B.az[l], q);
+    for (int q = threadIdx.x; q < n; q += T) dst[fx + fy + fz + q] = ld(B.invd[l], q);
+  }
   {
     const int n = (int)B.d[0].cells();
     float* r0 = R_(0);
     for (int c = threadIdx.x; c < n; c += T) r0[c] = s0 * ld(rin, c);
   }
   __syncthreads();
-  // down
-  for (int l = 0; l < B.nl; ++l) {
-    const Dims& d = B.d[l];
-    const int n = (int)d.cells();
-    float *r = R_(l), *z = Z_(l), *t = T_(l);
-    if (l == B.nl - 1) {
-      for (int c = threadIdx.x; c < n; c += T) z[c] = 0.0f;
-      __syncthreads();
-      float *src = z, *dst = t;
-      for (int s = 0; s < kCoarseSweeps; ++s) {
-        for (int c = threadIdx.x; c < n; c += T) {
-          int i, j, k;
-          cdec(d, c, i, j, k);
-          Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
-          float Az = apply_A(d, fw, i, j, k, c, src[c], [&](long q) { return src[q]; });
-          dst[c] = src[c] + kOmega * ld(B.invd[l], c) * (r[c] - Az);
-        }
-        __syncthreads();
-        float* tmp = src;
-        src = dst;
-        dst = tmp;
-      }
-      if (src != z) {
-        for (int c = threadIdx.x; c < n; c += T) z[c] = src[c];
-        __syncthreads();
-      }
-      break;
-    }
-    for (int c = threadIdx.x; c < n; c += T) t[c] = kOmega * ld(B.invd[l], c) * r[c];
-    __syncthreads();
-    for (int c = threadIdx.x; c < n; c += T) {
-      int i, j, k;
-      cdec(d, c, i, j, k);
-      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
-      float Az = apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; });
-      z[c] = t[c] + kOmega * ld(B.invd[l], c) * (r[c] - Az);
-    }
-    __syncthreads();
-    const Dims& cd = B.d[l + 1];
-    float* rc = R_(l + 1);
-    for (int C = threadIdx.x; C < (int)cd.cells(); C += T) {
-      int I, J, K;
-      cdec(cd, C, I, J, K);
-      float s = 0.0f;
-      for (int b = 0; b < 8; ++b) {
-        int i = 2 * I + (b & 1), j = 2 * J + ((b >> 1) & 1), k = 2 * K + (b >> 2);
-        int c = d.c(i, j, k);
-        Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
-        s += r[c] - apply_A(d, fw, i, j, k, c, z[c], [&](long q) { return z[q]; });
-      }
-      rc[C] = 0.125f * s;
-    }
-    __syncthreads();
+  const int L = B.nl;
+  for (int l = 0; l < L - 1; ++l) {
+    if (B.coff[l] >= 0)
+      bottom_down(B.d[l], B.d[l + 1], staged(l), R_(l), Z_(l), T_(l), R_(l + 1));
+    else
+      bottom_down(B.d[l], B.d[l + 1], global(l), R_(l), Z_(l), T_(l), R_(l + 1));
   }
-  // up
-  for (int l = B.nl - 2; l >= 0; --l) {
-    const Dims& d = B.d[l];
-    const Dims& cd = B.d[l + 1];
-    const int n = (int)d.cells();
-    float *r = R_(l), *z = Z_(l), *t = T_(l);
-    const float* e = Z_(l + 1);
-    auto zp = [&](long q) {
-      int ti = (int)(q % d.nx);
-      long tt = q / d.nx;
-      int tj = (int)(tt % d.ny), tk = (int)(tt / d.ny);
-      return z[q] + 8.0f * e[(ti >> 1) + cd.nx * ((tj >> 1) + cd.ny * (tk >> 1))];
-    };
-    for (int c = threadIdx.x; c < n; c += T) {
-      int i, j, k;
-      cdec(d, c, i, j, k);
-      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
-      float zc = zp(c);
-      t[c] = zc + kOmega * ld(B.invd[l], c) * (r[c] - apply_A(d, fw, i, j, k, c, zc, zp));
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < n; c += T) {
-      int i, j, k;
-      cdec(d, c, i, j, k);
-      Faces<A> fw(d, B.ax[l], B.ay[l], B.az[l], i, j, k);
-      z[c] = t[c] + kOmega * ld(B.invd[l], c) * (r[c] - apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; }));
-    }
-    __syncthreads();
+  if (B.coff[L - 1] >= 0)
+    bottom_coarsest(B.d[L - 1], staged(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1));
+  else
+    bottom_coarsest(B.d[L - 1], global(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1));
+  for (int l = L - 2; l >= 0; --l) {
+    if (B.coff[l] >= 0)
+      bottom_up(B.d[l], B.d[l + 1], staged(l), R_(l), Z_(l), T_(l), Z_(l + 1));
+    else
+      bottom_up(B.d[l], B.d[l + 1], global(l), R_(l), Z_(l), T_(l), Z_(l + 1));
   }
   {
     const int n = (int)B.d[0].cells();
@@ -575,15 +889,62 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     B.az[q] = Az(l);
     B.invd[q] = ID(l);
     B.off[q] = off;
+    B.coff[q] = -1;
     off += 3 * (int)S.lev[l].d.cells();
+  }
+  // stage coefficients in LDS from the coarsest level up, while they fit
+  for (int q = B.nl - 1; q >= 0; --q) {
+    const Dims& d = S.lev[G + q].d;
+    const int need = (int)(d.nfx() + d.nfy() + d.nfz() + d.cells());
+    if ((size_t)(off + need) * sizeof(float) > S.lds_bytes) break;
+    B.coff[q] = off;
+    off += need;
   }
   const size_t lds = (size_t)off * sizeof(float);
   const int bthreads = S.lev[G].d.cells() >= 1024 ? 1024 : (int)((S.lev[G].d.cells() + 63) / 64 * 64);
   if (G == 0) {
     NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
              hipLaunchKernelGGL((k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1));
-    hipLaunchKernelGGL(k_scale_dot, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, r0, z0, sc, S.partials);
-    hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n0), S.partials, sc);
+    hipLaunchKernelGGL(k_scale_dot<T>, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, ID(0), r0, z0, sc, S.partials);
+    hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n0), S.partials, sc, S.project);
+    return;
+  }
+  if (S.fused) {
+    auto tiles = [](const Dims& d) {
+      return (unsigned)(((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ));
+    };
+    for (int l = 0; l < G; ++l) {
+      const Dims& d = S.lev[l].d;
+      const Dims& cd = S.lev[l + 1].d;
+      T* rc = (T*)S.lev[l + 1].r;
+      if (l == 0) {
+        NF_TIMED(S.prof, SIM_K_MG_DOWN, st,
+                 hipLaunchKernelGGL((k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(0),
+                                    Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1));
+      } else {
+        hipLaunchKernelGGL((k_mg_down<T, T, T, T>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(l), Ay(l), Az(l),
+                           ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0);
+      }
+    }
+    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
+             hipLaunchKernelGGL((k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
+                                (T*)S.lev[G].z, sc, 0));
+    for (int l = G - 1; l >= 0; --l) {
+      const Dims& d = S.lev[l].d;
+      const Dims& cd = S.lev[l + 1].d;
+      const T* e = (const T*)S.lev[l + 1].z;
+      if (l == 0) {
+        NF_TIMED(S.prof, SIM_K_MG_UP, st,
+                 hipLaunchKernelGGL((k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kBlock), 0, st,
+                                    d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
+                                    S.partials));
+        hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d), S.partials, sc, S.project);
+      } else {
+        hipLaunchKernelGGL((k_mg_up<T, T, T, T, T, false>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(l), Ay(l),
+                           Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
+                           S.partials);
+      }
+    }
     return;
   }
   for (int l = 0; l < G; ++l) {
@@ -592,12 +953,13 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     T* ta = (T*)S.lev[l].ta;
     T* rc = (T*)S.lev[l + 1].r;
     if (l == 0) {
-      NF_TIMED(S.prof, SIM_K_MG_PRE, st,
-               hipLaunchKernelGGL((k_mg_pre<T, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(0),
-                                  Ay(0), Az(0), ID(0), r0, ta, sc, 1));
-      NF_TIMED(S.prof, SIM_K_MG_RESTRICT, st,
-               hipLaunchKernelGGL((k_mg_restrict<T, float, T, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, d,
-                                  cd, A(0), Ay(0), Az(0), r0, (const T*)ta, rc, sc, 1));
+      float* ta0 = (float*)S.lev[0].ta;
+      NF_TIMED(S.prof, SIM_K_MG_DOWN, st,
+               hipLaunchKernelGGL((k_mg_pre<T, float, float>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
+                                  A(0), Ay(0), Az(0), ID(0), r0, ta0, sc, 1));
+      NF_TIMED(S.prof, SIM_K_MG_DOWN2, st,
+               hipLaunchKernelGGL((k_mg_restrict<T, float, float, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0,
+                                  st, d, cd, A(0), Ay(0), Az(0), r0, (const float*)ta0, rc, sc, 1));
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_pre<T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l), Ay(l),
@@ -616,13 +978,16 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     T* tb = (T*)S.lev[l].tb;
     const T* e = (const T*)S.lev[l + 1].z;
     if (l == 0) {
-      NF_TIMED(S.prof, SIM_K_MG_POST1, st,
-               hipLaunchKernelGGL((k_mg_post1<T, float, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd,
-                                  A(0), Ay(0), Az(0), ID(0), r0, ta, e, tb, sc, 1));
-      NF_TIMED(S.prof, SIM_K_MG_POST2, st,
-               hipLaunchKernelGGL((k_mg_post2<T, float, T, float, true>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st,
-                                  d, A(0), Ay(0), Az(0), ID(0), r0, (const T*)tb, z0, sc, S.partials));
-      hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(d.cells()), S.partials, sc);
+      const float* ta0 = (const float*)S.lev[0].ta;
+      float* tb0 = (float*)S.lev[0].tb;
+      NF_TIMED(S.prof, SIM_K_MG_UP1, st,
+               hipLaunchKernelGGL((k_mg_post1<T, float, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
+                                  cd, A(0), Ay(0), Az(0), ID(0), r0, ta0, e, tb0, sc, 1));
+      NF_TIMED(S.prof, SIM_K_MG_UP, st,
+               hipLaunchKernelGGL((k_mg_post2<T, float, float, float, true>), dim3(nblocks(d.cells())), dim3(kBlock),
+                                  0, st, d, A(0), Ay(0), Az(0), ID(0), r0, (const float*)tb0, z0, sc, S.partials));
+      hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(d.cells()), S.partials, sc,
+                         S.project);
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_post1<T, T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cd, A(l),
@@ -678,8 +1043,10 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     return;
   }
   // mixed: build each level in FP32 scratch, then store it in T
-  const float cap = S.precision == SIM_MIXED_FP16 ? kHalfInvDiagMax : 3e38f;
   for (int l = 0; l < S.nlev; ++l) {
+    // FP16: level 0 only needs 1/diag to stay finite (its iterates are FP32);
+    // coarser levels store their iterates in FP16 and keep the tighter cap
+    const float cap = S.precision != SIM_MIXED_FP16 ? 3e38f : (l == 0 ? kHalfMax : kHalfInvDiagMax);
     const Dims& d = S.lev[l].d;
     const float *lx, *ly, *lz;
     if (l == 0) {
@@ -714,7 +1081,7 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
   }
 }
 
-static void cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
+static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
   for (int c = 0; c < count; ++c) {
@@ -732,6 +1099,67 @@ static void cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
     vcycle_dispatch(S, S.r, S.z, st);
     S.pcur ^= 1;
   }
+}
+
+// Capture two iterations (starting with p0 as the current direction) into a
+// graph; replaying it leaves the direction parity unchanged.
+static bool capture_pair(Solver& S, double* x) {
+  if (S.iter_exec) return true;
+  if (!S.cap_stream && hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
+  const int saved = S.pcur;
+  S.pcur = 0;
+  Profiler* prof = S.prof;
+  S.prof = nullptr;
+  enqueue_iterations(S, x, 2, S.cap_stream);
+  S.prof = prof;
+  S.pcur = saved;
+  if (hipStreamEndCapture(S.cap_stream, &S.iter_graph) != hipSuccess) return false;
+  if (hipGraphInstantiate(&S.iter_exec, S.iter_graph, nullptr, nullptr, 0) != hipSuccess) {
+    S.iter_exec = nullptr;
+    return false;
+  }
+  return true;
+}
+
+// Run `count` CG iterations (count is rounded up to an even number when the
+// captured pair is replayed; surplus iterations after convergence are skipped
+// on the device).  Returns the number enqueued.
+static int cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
+  const bool timing = S.prof && S.prof->active >= 0;
+  if (S.use_graph && !timing && S.pcur == 0 && capture_pair(S, x)) {
+    const int pairs = (count + 1) / 2;
+    for (int q = 0; q < pairs; ++q) (void)hipGraphLaunch(S.iter_exec, st);
+    return 2 * pairs;
+  }
+  enqueue_iterations(S, x, count, st);
+  return count;
+}
+
+// Dynamic LDS available to the one-workgroup bottom solve on the current device.
+void solver_init_device(Solver& S) {
+  int dev = 0, v = 0;
+  S.lds_bytes = 65536;
+  if (hipGetDevice(&dev) != hipSuccess) return;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) return;
+  const void* fns[6] = {(const void*)k_mg_bottom<float, float, float>,
+                        (const void*)k_mg_bottom<__half, float, float>,
+                        (const void*)k_mg_bottom<__hip_bfloat16, float, float>,
+                        (const void*)k_mg_bottom<float, float, float>,
+                        (const void*)k_mg_bottom<__half, __half, __half>,
+                        (const void*)k_mg_bottom<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>};
+  for (const void* f : fns)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) return;
+  S.lds_bytes = (size_t)v;
+}
+
+void solver_release(Solver& S) {
+  if (S.iter_exec) (void)hipGraphExecDestroy(S.iter_exec);
+  if (S.iter_graph) (void)hipGraphDestroy(S.iter_graph);
+  if (S.cap_stream) (void)hipStreamDestroy(S.cap_stream);
+  S.iter_exec = nullptr;
+  S.iter_graph = nullptr;
+  S.cap_stream = nullptr;
 }
 
 static int snapshot(Solver& S, hipStream_t st) {
@@ -755,7 +1183,10 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
   NF_TIMED(S.prof, SIM_K_CG_INIT, st,
            hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
                               S.partials));
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n);
+  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
+                     S.project);
+  if (S.project)
+    hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
   vcycle_dispatch(S, S.r, S.z, st);
   S.pcur = 0;
   // First batch sized from the previous solve of this handle, then small
@@ -771,7 +1202,7 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
     const int it_dev = S.host_sc->iters;
     const int cnt = S.host_sc->done ? 0 : (batch < maxit - it_dev ? batch : maxit - it_dev);
     if (cnt > 0) {
-      cg_iterations(S, x, cnt, st);
+      (void)cg_iterations(S, x, cnt, st);
       r = snapshot(S, st);
       if (r != SIM_OK) return r;
     }
@@ -784,16 +1215,19 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
       NF_TIMED(S.prof, SIM_K_CG_TRUE, st,
                hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
                                   x, S.r, allow, sc, S.partials));
-      hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n);
+      hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n,
+                         S.project);
       r = snapshot(S, st);
       if (r != SIM_OK) return r;
       if (S.host_sc->converged || S.host_sc->nonfinite || !allow) break;
       ++restarts;
+      if (S.project)
+        hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
       vcycle_dispatch(S, S.r, S.z, st);
     }
   }
   S.last_iters = S.host_sc->iters;
-  hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, n, x, xio);
+  hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
   if (stats) {
     const CGScalars& h = *S.host_sc;
     stats->iters = h.iters;

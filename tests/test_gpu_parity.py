@@ -79,6 +79,36 @@ def test_poisson_zero_rhs_and_iteration_cap():
         assert st["iters"] == 1 and not st["converged"] and 0 < st["rel_res"] < 1
 
 
+def test_poisson_closed_box_incompatible_rhs():
+    """A closed box makes G^T S G singular (constants).  A right-hand side with
+    a component along the constants (here added on purpose; in a step it is the
+    FP32 rounding of a compatible one) has no solution; the solver must still
+    converge on the compatible part and return the least-squares solution,
+    whose pressure gradient is the oracle's for the projected right-hand side.
+    Restarting CG from a true residual that keeps the constant component made
+    the iteration diverge."""
+    announce("poisson closed box, rhs with a null-space component")
+    n = (32, 32, 32)
+    g = Grid(n, 1 / 32)
+    sph = np.array([[0.45, 0.55, 0.5, 0.2]])
+    geo = sphere_geometry(g, sph)
+    ops = Operators(g, geo.alpha)
+    rng = np.random.default_rng(5)
+    b0 = ops.remove_null(np.where(ops.active, ops.GT @ (geo.alpha * rng.uniform(-1, 1, g.nfaces)), 0.0))
+    from oracle.projection import solve
+    P, _ = solve(ops, b0, tol=1e-12)
+    for c in (1e-9, 1e-6, 1e-3):
+        b = b0 + np.where(ops.active, c * np.linalg.norm(b0) / np.sqrt(ops.active.sum()), 0.0)
+        with Sim(sphere_cfg(n, sph)) as sim:
+            x = torch.zeros(g.ncells, dtype=torch.float32, device="cuda")
+            _, st = sim.poisson_solve(dev(b), x, alpha=dev(geo.alpha), tol=1e-7, max_iter=200)
+            torch.cuda.synchronize()
+        announce(f"  constant part {c:.0e}: {st}")
+        assert st["converged"] and st["iters"] <= 40, (c, st)
+        xg = remove_floating_means(ops, host(x))
+        assert rel_l2(ops.G @ xg, ops.G @ P, mask=geo.alpha > 0) <= 1e-5, c
+
+
 # ---------------------------------------------------------------------------
 # forward step (teacher forced)
 # ---------------------------------------------------------------------------
