@@ -98,11 +98,29 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * q + (x < r ? x : r) + s;
 }
 
+// A wave-uniform value as an opaque register value.  Selecting between struct
+// fields by a run-time index otherwise becomes one load from a run-time
+// address, which moves the kernel-argument struct to scratch memory.
+__device__ inline int uniform_value(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Extent of the domain along axis a.
+__device__ inline int extent(const Dims& d, int a) {
+  const int nx = uniform_value(d.nx), ny = uniform_value(d.ny), nz = uniform_value(d.nz);
+  return a == 0 ? nx : (a == 1 ? ny : nz);
+}
+
+// Boundary kind of the domain side a face lies on (-1: interior face).
 __device__ inline int side_kind(const Domain& D, int d, int own) {
-  int nd = d == 0 ? D.d.nx : (d == 1 ? D.d.ny : D.d.nz);
-  if (own == 0) return D.bc[2 * d];
-  if (own == nd) return D.bc[2 * d + 1];
-  return -1;
+  const int nd = extent(D.d, d);
+  if (own != 0 && own != nd) return -1;
+  const int s = 2 * d + (own == 0 ? 0 : 1);
+  int v = uniform_value(D.bc[0]);
+  v = s == 1 ? uniform_value(D.bc[1]) : v;
+  v = s == 2 ? uniform_value(D.bc[2]) : v;
+  v = s == 3 ? uniform_value(D.bc[3]) : v;
+  v = s == 4 ? uniform_value(D.bc[4]) : v;
+  v = s == 5 ? uniform_value(D.bc[5]) : v;
+  return v;
 }
 
 // Normal component of the solid velocity at face (d, i, j, k), with the

@@ -279,11 +279,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_geom(Domain D, GeomParams G, Fac
   const long oy = (long)d.nfx(), oz = oy + (long)d.nfy();
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < B.start[3]; t += (long)gridDim.x * blockDim.x) {
     const int comp = t < B.start[1] ? 0 : (t < B.start[2] ? 1 : 2);
-    const long lt = t - B.start[comp];
-    const int ex = B.ext[comp][0], ey = B.ext[comp][1];
-    const int i = B.lo[comp][0] + (int)(lt % ex);
-    const int j = B.lo[comp][1] + (int)((lt / ex) % ey);
-    const int k = B.lo[comp][2] + (int)(lt / ((long)ex * ey));
+    // per-component box values, selected as registers (see uniform_value)
+    auto pick = [&](int v0, int v1, int v2) {
+      const int a = uniform_value(v0), b = uniform_value(v1), c = uniform_value(v2);
+      return comp == 0 ? a : (comp == 1 ? b : c);
+    };
+    const long lt = t - (comp == 0 ? 0 : (comp == 1 ? B.start[1] : B.start[2]));
+    const int ex = pick(B.ext[0][0], B.ext[1][0], B.ext[2][0]), ey = pick(B.ext[0][1], B.ext[1][1], B.ext[2][1]);
+    const int i = pick(B.lo[0][0], B.lo[1][0], B.lo[2][0]) + (int)(lt % ex);
+    const int j = pick(B.lo[0][1], B.lo[1][1], B.lo[2][1]) + (int)((lt / ex) % ey);
+    const int k = pick(B.lo[0][2], B.lo[1][2], B.lo[2][2]) + (int)(lt / ((long)ex * ey));
     const long f = comp == 0 ? (long)d.fx(i, j, k) : (comp == 1 ? oy + d.fy(i, j, k) : oz + d.fz(i, j, k));
     const float a = alpha[f];
     if (!(a < 1.0f)) continue;

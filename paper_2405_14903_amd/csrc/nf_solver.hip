@@ -208,8 +208,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
   const float beta = (float)sc->beta;
   // z minus its mean over active cells (0 unless the system is singular): the
   // V-cycle maps the constants to a large multiple of themselves, and a
-  // rounding-level constant left in r would otherwise grow in p.  Values on
-  // inactive cells never couple (all their faces are closed).
+  // rounding-level constant left in r would otherwise grow in p (k_fin_rz
+  // forms the dots of the same projected z).  Values on inactive cells never
+  // couple (all their faces are closed).
   const float zmu = (float)sc->zmu;
   long c = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
@@ -335,39 +336,46 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(Dims d, const float* __rest
 // beta = r_new . (z_new - z_old) / rho_old: the rounding of the FP16 / BF16
 // V-cycle makes the preconditioner slightly non-linear, which this form
 // tolerates; for an exactly linear preconditioner r_new . z_old = 0 and it
-// reduces to the Fletcher-Reeves ratio.
+// reduces to the Fletcher-Reeves ratio.  On singular systems z is used minus
+// its mean over active cells (k_cg_dir_apply subtracts zmu), and the dots are
+// those of the projected vectors: r . (z - mu) = r . z - mu sum(r).
+// Partials: r.z_new, r.z_old, sum(z_new), sum(r).
 __global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc, int project) {
   if (sc->done) return;
-  double tot[3];
-  finish_partials<3>(partials, nb, tot);
+  double tot[4];
+  finish_partials<4>(partials, nb, tot);
   if (threadIdx.x == 0) {
-    sc->zmu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
+    const double mu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
+    const double rz = tot[0] - mu * tot[3];
     if (sc->first) {
-      sc->rho = tot[0];
+      sc->rho = rz;
     } else {
-      sc->beta = sc->rho != 0.0 ? (tot[0] - tot[1]) / sc->rho : 0.0;
-      sc->rho = tot[0];
+      const double rzo = tot[1] - sc->zmu * tot[3];
+      sc->beta = sc->rho != 0.0 ? (rz - rzo) / sc->rho : 0.0;
+      sc->rho = rz;
     }
+    sc->zmu = mu;
   }
 }
 
 // z *= 1 / vscale (the V-cycle ran on the scaled residual), 0 on inactive
 // cells; partials of r . z, r . z_old (always 0 here: the whole V-cycle ran in
-// one workgroup and overwrote z) and sum(z).
+// one workgroup and overwrote z), sum(z) and sum(r).
 template <typename A>
 __global__ __launch_bounds__(kBlock) void k_scale_dot(long n, const A* __restrict__ invd, const float* __restrict__ r,
                                                        float* __restrict__ z, const CGScalars* sc, double* partials) {
   if (sc->done) return;
   const float inv = (float)(1.0 / sc->vscale);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < n) {
     float zc = ld(invd, c) > 0.0f ? z[c] * inv : 0.0f;
     z[c] = zc;
     v[0] = (double)r[c] * (double)zc;
     v[2] = zc;
+    v[3] = r[c];
   }
-  block_partials<3>(v, partials);
+  block_partials<4>(v, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -470,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (c < (long)d.cells()) {
     int i, j, k;
     cdec(d, c, i, j, k);
@@ -486,8 +494,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
     zout[c] = cvt<O>(zo);
     v[0] = (double)rraw * (double)zo;
     v[2] = zo;
+    v[3] = rraw;
   }
-  if (LVL0) block_partials<3>(v, partials);
+  if (LVL0) block_partials<4>(v, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -641,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(Dims d, Dims cd, const A* __re
     z3s[q] = v;
   }
   __syncthreads();
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int q = threadIdx.x; q < kTX * kTY * kTZ; q += kBlock) {
     const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
     const int i = i0 + li, j = j0 + lj, k = k0 + lk;
@@ -658,9 +667,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(Dims d, Dims cd, const A* __re
     if (LVL0) {
       acc[0] += (double)rraw * (double)zo;
       acc[2] += (double)zo;
+      acc[3] += (double)rraw;
     }
   }
-  if (LVL0) block_partials<3>(acc, partials);
+  if (LVL0) block_partials<4>(acc, partials);
 }
 
 // ---------------------------------------------------------------------------
