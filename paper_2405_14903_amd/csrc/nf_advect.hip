@@ -26,6 +26,7 @@ namespace nf {
 struct Tap {
   int base;       // flat index of the (i0, j0, k0) corner
   int sx, sxy;    // strides of the component lattice
+  int i0[3];      // lattice coordinates of that corner
   double f[3];    // fractions
   int inside;     // bit a: coordinate a lies inside the lattice (d clamped / dX = 1), else clamped (0)
 };
@@ -57,6 +58,9 @@ __device__ inline Tap make_tap(const Dims& d, int e, const double X[3]) {
   t.sx = m[0];
   t.sxy = m[0] * m[1];
   t.base = i0[0] + t.sx * (i0[1] + m[1] * i0[2]);
+  t.i0[0] = i0[0];
+  t.i0[1] = i0[1];
+  t.i0[2] = i0[2];
   return t;
 }
 
@@ -119,8 +123,12 @@ __device__ inline void face_pos(int comp, int i, int j, int k, double X[3]) {
   X[2] = (double)k + (comp == 2 ? 0.0 : 0.5);
 }
 
+// trace (optional): the back-traced positions X_mid and X_src of every face,
+// as six FP64 arrays of d.faces() entries (X_mid x, y, z, X_src x, y, z), for
+// the adjoint of the same step.
 __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0, float g1, float g2, float dt,
-                                                    const float* __restrict__ u, float* __restrict__ out) {
+                                                    const float* __restrict__ u, float* __restrict__ out,
+                                                    double* __restrict__ trace) {
   long nf = (long)d.faces();
   long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (f >= nf) return;
@@ -137,6 +145,13 @@ __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0,
   for (int e = 0; e < 3; ++e) v1[e] = tap_value(uc[e], make_tap(d, e, Xm));
 #pragma unroll
   for (int a = 0; a < 3; ++a) Xs[a] = Xf[a] - cfl * v1[a];
+  if (trace) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      trace[(size_t)a * nf + f] = Xm[a];
+      trace[(size_t)(3 + a) * nf + f] = Xs[a];
+    }
+  }
   double val = tap_value(uc[comp], make_tap(d, comp, Xs));
   float gcomp = comp == 0 ? g0 : (comp == 1 ? g1 : g2);
   out[f] = (float)val + dt * gcomp;
@@ -147,21 +162,23 @@ __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0,
 // accumulated there; others go straight to global memory.
 struct Window {
   int o[3];                 // lattice coordinate of the window origin (same for all components)
-  float* lds;               // 3 windows of kWin^3 floats
+  float* lds;               // 3 windows of kWinX * kWinY * kWinZ floats
 };
-constexpr int kBrick = 8;
+// Brick of cells owned by one workgroup (one face per thread: at most
+// 9*8*4 + 8*9*4 + 8*8*5 = 896 faces) and the halo of its scatter windows.
+constexpr int kBX = 8, kBY = 8, kBZ = 4;
+constexpr int kAdjThreads = 1024;
 constexpr int kHalo = 2;
-constexpr int kWin = kBrick + 1 + 2 * kHalo;
+constexpr int kWinX = kBX + 1 + 2 * kHalo, kWinY = kBY + 1 + 2 * kHalo, kWinZ = kBZ + 1 + 2 * kHalo;
+constexpr int kWin3 = kWinX * kWinY * kWinZ;
 
 __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, const Tap& t, double w) {
   if (w == 0.0) return;
   const double fx = t.f[0], fy = t.f[1], fz = t.f[2];
   const double wz[2] = {1.0 - fz, fz}, wy[2] = {1.0 - fy, fy}, wx[2] = {1.0 - fx, fx};
-  // lattice coordinates of the base corner
-  const int a0 = t.base % t.sx, b0 = (t.base / t.sx) % (t.sxy / t.sx), c0 = t.base / t.sxy;
-  const int la = a0 - W.o[0], lb = b0 - W.o[1], lc = c0 - W.o[2];
-  const bool inside = la >= 0 && lb >= 0 && lc >= 0 && la + 1 < kWin && lb + 1 < kWin && lc + 1 < kWin;
-  float* win = W.lds + e * kWin * kWin * kWin;
+  const int la = t.i0[0] - W.o[0], lb = t.i0[1] - W.o[1], lc = t.i0[2] - W.o[2];
+  const bool inside = la >= 0 && lb >= 0 && lc >= 0 && la + 1 < kWinX && lb + 1 < kWinY && lc + 1 < kWinZ;
+  float* win = W.lds + e * kWin3;
 #pragma unroll
   for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
@@ -170,39 +187,47 @@ __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, 
       for (int bx = 0; bx < 2; ++bx) {
         double ww = w * wz[bz] * wy[by] * wx[bx];
         if (ww == 0.0) continue;
+        // distinct scopes keep the two adds apart (merged, they would become
+        // one generic-address atomic instead of an LDS atomic)
         if (inside)
-          atomicAdd(win + (la + bx) + kWin * ((lb + by) + kWin * (lc + bz)), (float)ww);
+          __hip_atomic_fetch_add(win + (la + bx) + kWinX * ((lb + by) + kWinY * (lc + bz)), (float)ww,
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         else
-          unsafeAtomicAdd(g + t.base + bx + by * t.sx + bz * t.sxy, (float)ww);
+          __hip_atomic_fetch_add(g + t.base + bx + by * t.sx + bz * t.sxy, (float)ww, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
       }
 }
 
-// One workgroup per 8^3 brick of cells; it handles the faces owned by the
-// brick (a face belongs to the cell on its + side, the upper domain faces to
-// the last cell) and accumulates their scatters in LDS windows that cover the
-// brick plus a 2-cell halo, then adds each touched window entry to global
-// memory once.
-__global__ __launch_bounds__(kBlock) void k_advect_adjoint(Dims d, double cfl, const float* __restrict__ u,
-                                                            const float* __restrict__ gout,
-                                                            float* __restrict__ gin) {
-  __shared__ float lds[3 * kWin * kWin * kWin];
-  const int nbx = (d.nx + kBrick - 1) / kBrick, nby = (d.ny + kBrick - 1) / kBrick;
+// One workgroup per brick of kBX x kBY x kBZ cells; one thread per face owned
+// by the brick (a face belongs to the cell on its + side, the upper domain
+// faces to the last cell).  The scatters accumulate in LDS windows that cover
+// the brick plus a kHalo-cell halo.  The windows are then stored whole to a
+// staging area (coalesced, no atomics); k_advect_adjoint_gather adds, for
+// every face, the entries of the windows that cover it.  Taps outside the
+// window (more than about one cell of motion per step) are added to gin
+// directly with float atomics.
+__global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double cfl, const float* __restrict__ u,
+                                                                 const double* __restrict__ trace,
+                                                                 const float* __restrict__ gout,
+                                                                 float* __restrict__ gin, float* __restrict__ stage) {
+  __shared__ float lds[3 * kWin3];
+  const int nbx = (d.nx + kBX - 1) / kBX, nby = (d.ny + kBY - 1) / kBY;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int bxi = bid % nbx, byi = (bid / nbx) % nby, bzi = bid / (nbx * nby);
-  const int i0 = bxi * kBrick, j0 = byi * kBrick, k0 = bzi * kBrick;
+  const int i0 = bxi * kBX, j0 = byi * kBY, k0 = bzi * kBZ;
   Window W;
   W.o[0] = i0 - kHalo;
   W.o[1] = j0 - kHalo;
   W.o[2] = k0 - kHalo;
   W.lds = lds;
-  for (int q = threadIdx.x; q < 3 * kWin * kWin * kWin; q += blockDim.x) lds[q] = 0.0f;
+  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) lds[q] = 0.0f;
   __syncthreads();
   const float* uc[3] = {u, u + d.nfx(), u + d.nfx() + d.nfy()};
   float* gc[3] = {gin, gin + d.nfx(), gin + d.nfx() + d.nfy()};
   // faces of the brick, per component: extents along each axis
   int ext[3][3];
-  const int bn[3] = {min(kBrick, d.nx - i0), min(kBrick, d.ny - j0), min(kBrick, d.nz - k0)};
-  const bool last[3] = {i0 + kBrick >= d.nx, j0 + kBrick >= d.ny, k0 + kBrick >= d.nz};
+  const int bn[3] = {min(kBX, d.nx - i0), min(kBY, d.ny - j0), min(kBZ, d.nz - k0)};
+  const bool last[3] = {i0 + kBX >= d.nx, j0 + kBY >= d.ny, k0 + kBZ >= d.nz};
   int total = 0, start[4];
   for (int e = 0; e < 3; ++e) {
     start[e] = total;
@@ -219,34 +244,31 @@ __global__ __launch_bounds__(kBlock) void k_advect_adjoint(Dims d, double cfl, c
                              : (comp == 1 ? (long)d.nfx() + d.fy(i, j, k) : (long)d.nfx() + d.nfy() + d.fz(i, j, k));
     const double g = gout[f];
     if (g == 0.0) continue;
-    // recompute the back-trace (the taps of X_f and the corners of X_mid are
-    // re-derived / re-loaded where they are needed, to keep registers low)
-    double Xf[3], v0[3], Xm[3], v1[3], Xs[3];
+    // the step's back-traced positions (k_advect of the same u); taps are
+    // re-derived from them where they are needed instead of being kept
+    double Xf[3], Xm[3], Xs[3];
     face_pos(comp, i, j, k, Xf);
+    const size_t nf = d.faces();
 #pragma unroll
-    for (int e = 0; e < 3; ++e) v0[e] = tap_value(uc[e], make_tap(d, e, Xf));
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Xm[a] = Xf[a] - 0.5 * cfl * v0[a];
-    Tap t1[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      t1[e] = make_tap(d, e, Xm);
-      v1[e] = tap_value(uc[e], t1[e]);
+    for (int a = 0; a < 3; ++a) {
+      Xm[a] = trace[(size_t)a * nf + f];
+      Xs[a] = trace[(size_t)(3 + a) * nf + f];
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Xs[a] = Xf[a] - cfl * v1[a];
-    const Tap ts = make_tap(d, comp, Xs);
-    // U~_f = I_comp(u; X_src)
-    scatter_w(W, gc[comp], comp, ts, g);
     double gs[3];
-    corner_grad(load_corners(uc[comp], ts), ts, gs);
+    {
+      // U~_f = I_comp(u; X_src)
+      const Tap ts = make_tap(d, comp, Xs);
+      scatter_w(W, gc[comp], comp, ts, g);
+      corner_grad(load_corners(uc[comp], ts), ts, gs);
+    }
     double gXm[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
+      const Tap t1 = make_tap(d, e, Xm);
       const double gv1 = -cfl * g * gs[e];
-      scatter_w(W, gc[e], e, t1[e], gv1);
+      scatter_w(W, gc[e], e, t1, gv1);
       double ge[3];
-      corner_grad(load_corners(uc[e], t1[e]), t1[e], ge);
+      corner_grad(load_corners(uc[e], t1), t1, ge);
 #pragma unroll
       for (int a = 0; a < 3; ++a) gXm[a] += gv1 * ge[a];
     }
@@ -254,18 +276,43 @@ __global__ __launch_bounds__(kBlock) void k_advect_adjoint(Dims d, double cfl, c
     for (int e = 0; e < 3; ++e) scatter_w(W, gc[e], e, make_tap(d, e, Xf), -0.5 * cfl * gXm[e]);
   }
   __syncthreads();
-  // flush the windows
-  for (int q = threadIdx.x; q < 3 * kWin * kWin * kWin; q += blockDim.x) {
-    const float v = lds[q];
-    if (v == 0.0f) continue;
-    const int e = q / (kWin * kWin * kWin);
-    const int r = q % (kWin * kWin * kWin);
-    const int a = W.o[0] + r % kWin, b = W.o[1] + (r / kWin) % kWin, c = W.o[2] + r / (kWin * kWin);
-    int m[3];
-    lattice(d, e, m);
-    if (a < 0 || b < 0 || c < 0 || a >= m[0] || b >= m[1] || c >= m[2]) continue;
-    unsafeAtomicAdd(gc[e] + a + m[0] * (b + m[1] * c), v);
-  }
+  // store the three windows of this brick
+  float* dst = stage + (size_t)bid * (3 * kWin3);
+  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) dst[q] = lds[q];
+}
+
+// gin_f += sum of the staged window entries of face f over the bricks whose
+// window covers it (brick b along an axis with brick size B covers lattice
+// coordinates B b - kHalo .. B b - kHalo + (window size) - 1).
+__device__ inline int cover_lo(int v, int B, int W) {
+  // ceil((v + kHalo - W + 1) / B), clamped at 0 (the offset keeps the division non-negative)
+  return max(0, (v + kHalo - W + 1 + B - 1 + 64 * B) / B - 64);
+}
+
+__global__ __launch_bounds__(kBlock) void k_advect_adjoint_gather(Dims d, const float* __restrict__ stage,
+                                                                   float* __restrict__ gin) {
+  const long f = (long)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (f >= (long)d.faces()) return;
+  int comp, a, b, c;
+  face_decode(d, f, comp, a, b, c);
+  const int nbx = (d.nx + kBX - 1) / kBX, nby = (d.ny + kBY - 1) / kBY, nbz = (d.nz + kBZ - 1) / kBZ;
+  const int x0 = cover_lo(a, kBX, kWinX), x1 = min(nbx - 1, (a + kHalo) / kBX);
+  const int y0 = cover_lo(b, kBY, kWinY), y1 = min(nby - 1, (b + kHalo) / kBY);
+  const int z0 = cover_lo(c, kBZ, kWinZ), z1 = min(nbz - 1, (c + kHalo) / kBZ);
+  float s = 0.0f;
+  for (int bz = z0; bz <= z1; ++bz)
+    for (int by = y0; by <= y1; ++by)
+      for (int bx = x0; bx <= x1; ++bx) {
+        const int la = a - (kBX * bx - kHalo), lb = b - (kBY * by - kHalo), lc = c - (kBZ * bz - kHalo);
+        const size_t brick = (size_t)bx + nbx * ((size_t)by + (size_t)nby * bz);
+        s += stage[brick * 3 * kWin3 + comp * kWin3 + la + kWinX * (lb + kWinY * lc)];
+      }
+  gin[f] += s;
+}
+
+size_t advect_stage_floats(const Dims& d) {
+  const size_t nb = (size_t)((d.nx + kBX - 1) / kBX) * ((d.ny + kBY - 1) / kBY) * ((d.nz + kBZ - 1) / kBZ);
+  return nb * 3 * kWin3;
 }
 
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
@@ -281,16 +328,18 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 }
 
 void launch_advect(const Dims& d, double dx, double dt, const double* grav, const float* u, float* out,
-                   hipStream_t s) {
+                   double* trace, hipStream_t s) {
   hipLaunchKernelGGL(k_advect, dim3(nblocks(d.faces())), dim3(kBlock), 0, s, d, dt / dx, (float)grav[0],
-                     (float)grav[1], (float)grav[2], (float)dt, u, out);
+                     (float)grav[1], (float)grav[2], (float)dt, u, out, trace);
 }
 
-void launch_advect_adjoint(const Dims& d, double dx, double dt, const float* u, const float* gout,
-                           float* gin, hipStream_t s) {
-  const unsigned nb = (unsigned)(((d.nx + kBrick - 1) / kBrick) * ((d.ny + kBrick - 1) / kBrick) *
-                                 ((d.nz + kBrick - 1) / kBrick));
-  hipLaunchKernelGGL(k_advect_adjoint, dim3(nb), dim3(kBlock), 0, s, d, dt / dx, u, gout, gin);
+// gin must hold zeros (the out-of-window taps are added to it first); trace
+// holds the positions written by launch_advect for the same u.
+void launch_advect_adjoint(const Dims& d, double dx, double dt, const float* u, const double* trace,
+                           const float* gout, float* gin, float* stage, hipStream_t s) {
+  const unsigned nb = (unsigned)(((d.nx + kBX - 1) / kBX) * ((d.ny + kBY - 1) / kBY) * ((d.nz + kBZ - 1) / kBZ));
+  hipLaunchKernelGGL(k_advect_adjoint, dim3(nb), dim3(kAdjThreads), 0, s, d, dt / dx, u, trace, gout, gin, stage);
+  hipLaunchKernelGGL(k_advect_adjoint_gather, dim3(nblocks(d.faces())), dim3(kBlock), 0, s, d, stage, gin);
 }
 
 }  // namespace nf

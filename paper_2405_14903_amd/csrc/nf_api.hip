@@ -26,6 +26,8 @@ struct sim_ctx {
   float* b = nullptr;       // right-hand side
   float* P = nullptr;       // pressure (when the caller passes none)
   float* y = nullptr;       // adjoint pressure
+  float* stage = nullptr;   // per-brick LDS windows of the advection adjoint
+  double* trace = nullptr;  // back-traced positions (6 FP64 per face) for the advection adjoint
   std::vector<void*> allocs;
   GeomParams last_geom;
   bool have_geom = false;
@@ -101,6 +103,8 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(C * 4, (void**)&t->b);
   alloc(C * 4, (void**)&t->P);
   alloc(C * 4, (void**)&t->y);
+  alloc(advect_stage_floats(d0) * 4, (void**)&t->stage);
+  alloc(F_ * 6 * 8, (void**)&t->trace);
   alloc(C * 8, (void**)&t->S.x);
   alloc(C * 4, (void**)&t->S.r);
   alloc(C * 4, (void**)&t->S.z);
@@ -241,7 +245,12 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   for (int s = 0; s < 6; ++s)
     if (desc->bc[s] == SIM_BC_OUTFLOW) c->S.project = 0;
   c->S.nbottom = p.nlev - 1;
-  while (c->S.nbottom > 0 && p.dims[c->S.nbottom - 1].cells() <= (size_t)kCoarseMaxCells) --c->S.nbottom;
+  size_t bottom_cells = kBottomCells;
+  if (const char* bc = std::getenv("NF_MG_BOTTOM_CELLS")) {
+    const long v = std::atol(bc);
+    if (v > 0 && v <= kCoarseMaxCells) bottom_cells = (size_t)v;
+  }
+  while (c->S.nbottom > 0 && p.dims[c->S.nbottom - 1].cells() <= bottom_cells) --c->S.nbottom;
   bool ok = true;
   for_each_buffer(desc, p, c, [&](size_t b, void** ptr) {
     if (!ok) return;
@@ -313,7 +322,7 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
-           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream));
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, nullptr, stream));
   return project_common(h, h->uhat, g, u_n1, p_n1, st, stream);
 }
 
@@ -339,7 +348,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   eval_geometry(h, g, stream);
   // the step's advected field (the fluid velocity W on cut faces needs it)
   NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
-           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, stream));
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, h->trace, stream));
   const float* P = p_n1;
   if (!P && grad) {
     // no stored pressure: solve the forward system again
@@ -359,7 +368,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
                             h->S.partials, g_theta, g_ctrl, stream));
   launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
-           launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->gu, g_u_n, stream));
+           launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->trace, h->gu, g_u_n, h->stage, stream));
   return last_hip_error();
 }
 

@@ -13,7 +13,8 @@ namespace nf {
 
 constexpr int kBlock = 256;          // 4 waves of 64 lanes
 constexpr int kMaxLevels = 12;
-constexpr int kCoarseMaxCells = 4096;
+constexpr int kCoarseMaxCells = 4096;   // largest coarsest level (it must fit one workgroup's LDS)
+constexpr int kBottomCells = 512;       // levels of at most this many cells run in the one-workgroup bottom solve
 constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coarse correction
 constexpr float kOmega = 0.8f;
 constexpr int kCoarseSweepsMax = 40;   // coarsest level: min(40, 2 * (largest extent)^2) sweeps
@@ -171,34 +172,36 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Fixed-order block sum of N doubles per thread (deterministic).  Result valid
-// in thread 0.  `sh` must hold N * (kBlock / 64) doubles.
-template <int N>
+// Fixed-order block sum of N doubles per thread (deterministic) for a block
+// of BS threads.  Result valid in thread 0.  `sh` must hold N * (BS / 64)
+// doubles.
+template <int N, int BS = kBlock>
 __device__ inline void block_sum(double (&v)[N], double* sh) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q < N; ++q) {
     double s = wave_sum(v[q]);
-    if (lane == 0) sh[q * (kBlock / 64) + wv] = s;
+    if (lane == 0) sh[q * (BS / 64) + wv] = s;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < N; ++q) {
       double s = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) s += sh[q * (kBlock / 64) + w];
+      for (int w = 0; w < BS / 64; ++w) s += sh[q * (BS / 64) + w];
       v[q] = s;
     }
   }
 }
 
 // Write this block's N partial sums to partials[q * gridDim.x + blockIdx.x]
-// (fixed-order block sum).  A separate single-block kernel combines them after
-// the kernel boundary, so no cross-workgroup synchronisation is needed.
-template <int N>
+// (fixed-order block sum of a BS-thread block).  A separate single-block
+// kernel combines them after the kernel boundary, so no cross-workgroup
+// synchronisation is needed.
+template <int N, int BS = kBlock>
 __device__ inline void block_partials(double (&v)[N], double* partials) {
-  __shared__ double sh[N * (kBlock / 64) + 1];
-  block_sum<N>(v, sh);
+  __shared__ double sh[N * (BS / 64) + 1];
+  block_sum<N, BS>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int q = 0; q < N; ++q) partials[(size_t)q * gridDim.x + blockIdx.x] = v[q];

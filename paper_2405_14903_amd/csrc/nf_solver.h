@@ -53,7 +53,7 @@ struct Level {
 
 struct Solver {
   int nlev = 0;
-  int nbottom = 0;     // first level with at most kCoarseMaxCells cells
+  int nbottom = 0;     // first level run in the one-workgroup bottom solve (at most kBottomCells cells)
   int precision = SIM_FP32;
   int check_every = 2;
   int pcur = 0;        // which of p0 / p1 holds the current direction
@@ -99,9 +99,10 @@ void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, cons
 // nf_advect.hip
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
 void launch_advect(const Dims& d, double dx, double dt, const double* grav, const float* u, float* out,
-                   hipStream_t s);
-void launch_advect_adjoint(const Dims& d, double dx, double dt, const float* u, const float* gout, float* gin,
-                           hipStream_t s);
+                   double* trace, hipStream_t s);
+void launch_advect_adjoint(const Dims& d, double dx, double dt, const float* u, const double* trace,
+                           const float* gout, float* gin, float* stage, hipStream_t s);
+size_t advect_stage_floats(const Dims& d);
 // nf_project.hip
 void launch_rhs(const Domain& D, const GeomParams& G, double inv_k, const float* alpha, const float* uhat,
                 float* b, hipStream_t s);

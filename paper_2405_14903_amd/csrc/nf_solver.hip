@@ -61,6 +61,7 @@ __device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) {
 template <typename A>
 struct Faces {
   float w[6];
+  __device__ Faces() {}
   __device__ Faces(const Dims& d, const A* ax, const A* ay, const A* az, int i, int j, int k) {
     w[0] = ld(ax, d.fx(i, j, k));
     w[1] = ld(ax, d.fx(i + 1, j, k));
@@ -513,6 +514,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
 // ---------------------------------------------------------------------------
 
 constexpr int kTX = 32, kTY = 8, kTZ = 8;
+constexpr int kTileThreads = 512;   // 8 waves per tile: more loads in flight per CU
+// Loops over a region have a compile-time trip count, so they unroll fully
+// and every thread issues all of its loads before the first one is used.
+constexpr int trips(int n) { return (n + kTileThreads - 1) / kTileThreads; }
 template <int H>
 struct Halo {
   static constexpr int X = kTX + 2 * H, Y = kTY + 2 * H, Z = kTZ + 2 * H, N = X * Y * Z;
@@ -549,12 +554,43 @@ __device__ inline float apply_local(const Faces<A>& fw, const float* v, int q, i
   return s;
 }
 
+// Each phase first issues every load of the thread's cells (out-of-domain
+// cells load element 0, which always exists, and are masked afterwards), then
+// computes: a thread keeps all its loads in flight at once.
+struct RegionCell {
+  int q, i, j, k;
+  bool ok;   // q inside the region and (i, j, k) inside the domain
+};
+
+template <int H>
+__device__ inline RegionCell region_cell(const Dims& d, int i0, int j0, int k0, int u) {
+  using R = Halo<H>;
+  RegionCell rc;
+  rc.q = threadIdx.x + u * kTileThreads;
+  const int q = rc.q < R::N ? rc.q : 0;
+  const int li = q % R::X, lj = (q / R::X) % R::Y, lk = q / (R::X * R::Y);
+  rc.i = i0 + li - H;
+  rc.j = j0 + lj - H;
+  rc.k = k0 + lk - H;
+  rc.ok = rc.q < R::N && in_dom(d, rc.i, rc.j, rc.k);
+  if (!rc.ok) rc.i = rc.j = rc.k = 0;
+  return rc;
+}
+
+// local index in the +2 region of a cell at local index q of the +1 region
+__device__ inline int up1to2(int q) {
+  using H1 = Halo<1>;
+  using H2 = Halo<2>;
+  const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
+  return (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
+}
+
 template <typename A, typename R, typename Z, typename RC>
-__global__ __launch_bounds__(kBlock) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
-                                                     const A* __restrict__ ay, const A* __restrict__ az,
-                                                     const A* __restrict__ invd, const R* __restrict__ r,
-                                                     Z* __restrict__ z2out, RC* __restrict__ rc, const CGScalars* sc,
-                                                     int lvl0) {
+__global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
+                                                          const A* __restrict__ ay, const A* __restrict__ az,
+                                                          const A* __restrict__ invd, const R* __restrict__ r,
+                                                          Z* __restrict__ z2out, RC* __restrict__ rc,
+                                                          const CGScalars* sc, int lvl0) {
   if (sc->done) return;
   using H2 = Halo<2>;
   using H1 = Halo<1>;
@@ -564,49 +600,73 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(Dims d, Dims cd, const A* __
   const float s0 = level_scale(sc, lvl0);
   int i0, j0, k0;
   tile_origin(d, i0, j0, k0);
-  for (int q = threadIdx.x; q < H2::N; q += kBlock) {
-    const int li = q % H2::X, lj = (q / H2::X) % H2::Y, lk = q / (H2::X * H2::Y);
-    const int i = i0 + li - 2, j = j0 + lj - 2, k = k0 + lk - 2;
-    float v = 0.0f;
-    if (in_dom(d, i, j, k)) {
-      const long c = d.c(i, j, k);
-      v = kOmega * ld(invd, c) * (s0 * ld(r, c));
+  {
+    constexpr int T = trips(H2::N);
+    RegionCell cell[T];
+    float id[T], rv[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      cell[u] = region_cell<2>(d, i0, j0, k0, u);
+      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
+      id[u] = ld(invd, c);
+      rv[u] = ld(r, c);
     }
-    z1s[q] = v;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < H1::N; q += kBlock) {
-    const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
-    const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
-    float z2 = 0.0f, rv = 0.0f;
-    if (in_dom(d, i, j, k)) {
-      const long c = d.c(i, j, k);
-      Faces<A> fw(d, ax, ay, az, i, j, k);
-      const int q2 = (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
-      rv = s0 * ld(r, c);
-      const float Az = apply_local(fw, z1s, q2, H2::X, H2::X * H2::Y);
-      const Z zs = cvt<Z>(z1s[q2] + kOmega * ld(invd, c) * (rv - Az));
-      z2 = ld(&zs, 0);
-      if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ) z2out[c] = zs;
-    }
-    z2s[q] = z2;
-    rs[q] = rv;
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+      if (cell[u].q < H2::N) z1s[cell[u].q] = cell[u].ok ? kOmega * id[u] * (s0 * rv[u]) : 0.0f;
   }
   __syncthreads();
   {
-    // the tile's (kTX/2) x (kTY/2) x (kTZ/2) = kBlock coarse cells, one per thread
+    constexpr int T = trips(H1::N);
+    RegionCell cell[T];
+    Faces<A> fw[T];
+    float id[T], rv[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      cell[u] = region_cell<1>(d, i0, j0, k0, u);
+      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
+      fw[u] = Faces<A>(d, ax, ay, az, cell[u].i, cell[u].j, cell[u].k);
+      id[u] = ld(invd, c);
+      rv[u] = ld(r, c);
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int q = cell[u].q;
+      if (q >= H1::N) continue;
+      float z2 = 0.0f, rr = 0.0f;
+      if (cell[u].ok) {
+        const int q2 = up1to2(q);
+        rr = s0 * rv[u];
+        const Z zs = cvt<Z>(z1s[q2] + kOmega * id[u] * (rr - apply_local(fw[u], z1s, q2, H2::X, H2::X * H2::Y)));
+        z2 = ld(&zs, 0);
+        const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
+        if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ)
+          z2out[d.c(cell[u].i, cell[u].j, cell[u].k)] = zs;
+      }
+      z2s[q] = z2;
+      rs[q] = rr;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < (kTX / 2) * (kTY / 2) * (kTZ / 2)) {
+    // the tile's (kTX/2) x (kTY/2) x (kTZ/2) = 256 coarse cells, one per thread
     const int t = threadIdx.x;
     const int ci = t % (kTX / 2), cj = (t / (kTX / 2)) % (kTY / 2), ck = t / ((kTX / 2) * (kTY / 2));
     const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
-    if (I < cd.nx && J < cd.ny && K < cd.nz) {
+    const bool ok = I < cd.nx && J < cd.ny && K < cd.nz;
+    Faces<A> fw[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int i = ok ? 2 * I + (b & 1) : 0, j = ok ? 2 * J + ((b >> 1) & 1) : 0, k = ok ? 2 * K + (b >> 2) : 0;
+      fw[b] = Faces<A>(d, ax, ay, az, i, j, k);
+    }
+    if (ok) {
       float s = 0.0f;
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
         const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
-        const int i = i0 + li, j = j0 + lj, k = k0 + lk;
-        Faces<A> fw(d, ax, ay, az, i, j, k);
         const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-        s += rs[q1] - apply_local(fw, z2s, q1, H1::X, H1::X * H1::Y);
+        s += rs[q1] - apply_local(fw[b], z2s, q1, H1::X, H1::X * H1::Y);
       }
       rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
     }
@@ -614,11 +674,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_down(Dims d, Dims cd, const A* __
 }
 
 template <typename A, typename R, typename Z, typename E, typename O, bool LVL0>
-__global__ __launch_bounds__(kBlock) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
-                                                   const A* __restrict__ ay, const A* __restrict__ az,
-                                                   const A* __restrict__ invd, const R* __restrict__ r,
-                                                   const Z* __restrict__ z2, const E* __restrict__ e,
-                                                   O* __restrict__ zout, const CGScalars* sc, double* partials) {
+__global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
+                                                        const A* __restrict__ ay, const A* __restrict__ az,
+                                                        const A* __restrict__ invd, const R* __restrict__ r,
+                                                        const Z* __restrict__ z2, const E* __restrict__ e,
+                                                        O* __restrict__ zout, const CGScalars* sc, double* partials) {
   if (sc->done) return;
   using H2 = Halo<2>;
   using H1 = Halo<1>;
@@ -629,48 +689,161 @@ __global__ __launch_bounds__(kBlock) void k_mg_up(Dims d, Dims cd, const A* __re
   const bool first = sc->first;
   int i0, j0, k0;
   tile_origin(d, i0, j0, k0);
-  for (int q = threadIdx.x; q < H2::N; q += kBlock) {
-    const int li = q % H2::X, lj = (q / H2::X) % H2::Y, lk = q / (H2::X * H2::Y);
-    const int i = i0 + li - 2, j = j0 + lj - 2, k = k0 + lk - 2;
-    float v = 0.0f;
-    if (in_dom(d, i, j, k)) v = ld(z2, d.c(i, j, k)) + 8.0f * ld(e, cd.c(i >> 1, j >> 1, k >> 1));
-    zp[q] = v;
+  {
+    constexpr int T = trips(H2::N);
+    RegionCell cell[T];
+    float zv[T], ev[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      cell[u] = region_cell<2>(d, i0, j0, k0, u);
+      zv[u] = ld(z2, d.c(cell[u].i, cell[u].j, cell[u].k));
+      ev[u] = ld(e, cd.c(cell[u].i >> 1, cell[u].j >> 1, cell[u].k >> 1));
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u)
+      if (cell[u].q < H2::N) zp[cell[u].q] = cell[u].ok ? zv[u] + 8.0f * ev[u] : 0.0f;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < H1::N; q += kBlock) {
-    const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
-    const int i = i0 + li - 1, j = j0 + lj - 1, k = k0 + lk - 1;
-    float v = 0.0f;
-    if (in_dom(d, i, j, k)) {
-      const long c = d.c(i, j, k);
-      Faces<A> fw(d, ax, ay, az, i, j, k);
-      const int q2 = (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
-      v = zp[q2] + kOmega * ld(invd, c) * (s0 * ld(r, c) - apply_local(fw, zp, q2, H2::X, H2::X * H2::Y));
+  {
+    constexpr int T = trips(H1::N);
+    RegionCell cell[T];
+    Faces<A> fw[T];
+    float id[T], rv[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      cell[u] = region_cell<1>(d, i0, j0, k0, u);
+      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
+      fw[u] = Faces<A>(d, ax, ay, az, cell[u].i, cell[u].j, cell[u].k);
+      id[u] = ld(invd, c);
+      rv[u] = ld(r, c);
     }
-    z3s[q] = v;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int q = cell[u].q;
+      if (q >= H1::N) continue;
+      float v = 0.0f;
+      if (cell[u].ok) {
+        const int q2 = up1to2(q);
+        v = zp[q2] + kOmega * id[u] * (s0 * rv[u] - apply_local(fw[u], zp, q2, H2::X, H2::X * H2::Y));
+      }
+      z3s[q] = v;
+    }
   }
   __syncthreads();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int q = threadIdx.x; q < kTX * kTY * kTZ; q += kBlock) {
-    const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
-    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
-    if (!in_dom(d, i, j, k)) continue;
-    const long c = d.c(i, j, k);
-    Faces<A> fw(d, ax, ay, az, i, j, k);
-    const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-    const float rraw = ld(r, c);
-    const float idc = ld(invd, c);
-    float zo = (z3s[q1] + kOmega * idc * (s0 * rraw - apply_local(fw, z3s, q1, H1::X, H1::X * H1::Y))) * inv;
-    if (LVL0 && !(idc > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
-    if (LVL0 && !first) acc[1] += (double)rraw * (double)ld(zout, c);   // r_new . z_old
-    zout[c] = cvt<O>(zo);
-    if (LVL0) {
-      acc[0] += (double)rraw * (double)zo;
-      acc[2] += (double)zo;
-      acc[3] += (double)rraw;
+  {
+    constexpr int T = trips(kTX * kTY * kTZ);
+    int cl[T];
+    bool ok[T];
+    Faces<A> fw[T];
+    float id[T], rv[T], zold[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int q = threadIdx.x + u * kTileThreads;
+      const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
+      int i = i0 + li, j = j0 + lj, k = k0 + lk;
+      ok[u] = in_dom(d, i, j, k);
+      if (!ok[u]) i = j = k = 0;
+      cl[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+      const long c = d.c(i, j, k);
+      fw[u] = Faces<A>(d, ax, ay, az, i, j, k);
+      id[u] = ld(invd, c);
+      rv[u] = ld(r, c);
+      zold[u] = (LVL0 && !first) ? ld(zout, c) : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      if (!ok[u]) continue;
+      const int q = threadIdx.x + u * kTileThreads;
+      const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
+      const long c = d.c(i0 + li, j0 + lj, k0 + lk);
+      const int q1 = cl[u];
+      float zo = (z3s[q1] + kOmega * id[u] * (s0 * rv[u] - apply_local(fw[u], z3s, q1, H1::X, H1::X * H1::Y))) * inv;
+      if (LVL0 && !(id[u] > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
+      if (LVL0 && !first) acc[1] += (double)rv[u] * (double)zold[u];   // r_new . z_old
+      zout[c] = cvt<O>(zo);
+      if (LVL0) {
+        acc[0] += (double)rv[u] * (double)zo;
+        acc[2] += (double)zo;
+        acc[3] += (double)rv[u];
+      }
     }
   }
-  if (LVL0) block_partials<4>(acc, partials);
+  if (LVL0) block_partials<4, kTileThreads>(acc, partials);
+}
+
+// CG direction and operator on a tile: p = (z - zmu) + beta p_old on the tile
+// + 1 cell (in LDS; written out on the tile), q = A p and p.q partials on the
+// tile.  Same arithmetic as k_cg_dir_apply with one load of z and p_old per
+// cell and halo.
+__global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, const float* __restrict__ ax,
+                                                                    const float* __restrict__ ay,
+                                                                    const float* __restrict__ az,
+                                                                    const float* __restrict__ z,
+                                                                    const float* __restrict__ pold,
+                                                                    float* __restrict__ pnew, float* __restrict__ q,
+                                                                    const CGScalars* sc, double* partials) {
+  if (sc->done) return;
+  using H1 = Halo<1>;
+  __shared__ float ps[H1::N];
+  const bool first = sc->first;
+  const float beta = (float)sc->beta;
+  const float zmu = (float)sc->zmu;
+  int i0, j0, k0;
+  tile_origin(d, i0, j0, k0);
+  {
+    constexpr int T = trips(H1::N);
+    RegionCell cell[T];
+    float zv[T], pv[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      cell[u] = region_cell<1>(d, i0, j0, k0, u);
+      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
+      zv[u] = z[c];
+      pv[u] = first ? 0.0f : pold[c];
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int qq = cell[u].q;
+      if (qq >= H1::N) continue;
+      float p = 0.0f;
+      if (cell[u].ok) {
+        p = first ? zv[u] - zmu : (zv[u] - zmu) + beta * pv[u];
+        const int li = qq % H1::X, lj = (qq / H1::X) % H1::Y, lk = qq / (H1::X * H1::Y);
+        if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ)
+          pnew[d.c(cell[u].i, cell[u].j, cell[u].k)] = p;
+      }
+      ps[qq] = p;
+    }
+  }
+  __syncthreads();
+  double acc[1] = {0.0};
+  {
+    constexpr int T = trips(kTX * kTY * kTZ);
+    bool ok[T];
+    int cl[T];
+    long cc[T];
+    Faces<float> fw[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      const int qq = threadIdx.x + u * kTileThreads;
+      const int li = qq % kTX, lj = (qq / kTX) % kTY, lk = qq / (kTX * kTY);
+      int i = i0 + li, j = j0 + lj, k = k0 + lk;
+      ok[u] = in_dom(d, i, j, k);
+      if (!ok[u]) i = j = k = 0;
+      cl[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+      cc[u] = d.c(i, j, k);
+      fw[u] = Faces<float>(d, ax, ay, az, i, j, k);
+    }
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+      if (!ok[u]) continue;
+      const float qc = apply_local(fw[u], ps, cl[u], H1::X, H1::X * H1::Y);
+      q[cc[u]] = qc;
+      acc[0] += (double)ps[cl[u]] * qc;
+    }
+  }
+  block_partials<1, kTileThreads>(acc, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -929,10 +1102,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
         NF_TIMED(S.prof, SIM_K_MG_DOWN, st,
-                 hipLaunchKernelGGL((k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(0),
+                 hipLaunchKernelGGL((k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(0),
                                     Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1));
       } else {
-        hipLaunchKernelGGL((k_mg_down<T, T, T, T>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(l), Ay(l), Az(l),
+        hipLaunchKernelGGL((k_mg_down<T, T, T, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
                            ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0);
       }
     }
@@ -945,12 +1118,12 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
         NF_TIMED(S.prof, SIM_K_MG_UP, st,
-                 hipLaunchKernelGGL((k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kBlock), 0, st,
+                 hipLaunchKernelGGL((k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kTileThreads), 0, st,
                                     d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
                                     S.partials));
         hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d), S.partials, sc, S.project);
       } else {
-        hipLaunchKernelGGL((k_mg_up<T, T, T, T, T, false>), dim3(tiles(d)), dim3(kBlock), 0, st, d, cd, A(l), Ay(l),
+        hipLaunchKernelGGL((k_mg_up<T, T, T, T, T, false>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
                            Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
                            S.partials);
       }
@@ -1098,10 +1271,18 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     float* pold = S.pcur ? S.p1 : S.p0;
     float* pnew = S.pcur ? S.p0 : S.p1;
     const int nb = (int)nblocks(n);
-    NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
-             hipLaunchKernelGGL(k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
-                                pnew, S.q, S.sc, S.partials));
-    hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc);
+    if (S.fused) {
+      const int nt = (int)(((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ));
+      NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
+               hipLaunchKernelGGL(k_cg_dir_apply_tile, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay, S.az,
+                                  S.z, pold, pnew, S.q, S.sc, S.partials));
+      hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nt, S.partials, S.sc);
+    } else {
+      NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
+               hipLaunchKernelGGL(k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
+                                  pnew, S.q, S.sc, S.partials));
+      hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc);
+    }
     NF_TIMED(S.prof, SIM_K_CG_UPDATE, st,
              hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
                                 S.partials));
