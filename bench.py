@@ -33,6 +33,30 @@ T = 64
 EVERY = 8
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_KERNEL = "mg_up"
+# A launch enqueued after the solver converged exits at once (about 1 us); the
+# roofline averages launches of at least this length.
+NOOP_MS = 0.003
+# HBM bytes per (working) launch of the finest-level k_mg_up, FP16 form, from
+# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch) scaled by the same counters of a plain 256 MiB device copy
+# (--copy-probe 256: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x);
+# see profiles/mg_up_128_fp16_traffic.md.  Valid only for the kernel sources
+# it was measured on (first 16 hex digits of their SHA-256).
+TRAFFIC = {"fp16": 54258012}
+TRAFFIC_SOURCES = {"paper_2405_14903_amd/csrc/nf_solver.hip": "becd32dc2527bfbd",
+                   "paper_2405_14903_amd/csrc/nf_internal.h": "1c555b761b829b27"}
+
+
+def measured_traffic(precision):
+    import hashlib
+    for rel, want in TRAFFIC_SOURCES.items():
+        try:
+            with open(os.path.join(ROOT, rel), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest()[:16] != want:
+                    return None
+        except OSError:
+            return None
+    return TRAFFIC.get(precision)
 
 
 def parse():
@@ -116,7 +140,7 @@ def run_form(precision, steps, warmup, scene, torch, profile_kernel=None):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     print(f"[bench] {precision}: {steps} rollouts in {wall:.2f} s", file=sys.stderr, flush=True)
-    prof = sim.profile_read() if profile_kernel else None
+    prof = sim.profile_read(min_ms=NOOP_MS) if profile_kernel else None
     sim.profile(None)
     fwd = timer.latencies("fwd")
     adj = timer.latencies("adj")
@@ -160,7 +184,7 @@ def roofline(prof, precision):
     avg_s = ms / cnt / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision),
             "kernel": "k_mg_up (finest level, " + precision + ")", "launches": cnt,
             "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch}
 

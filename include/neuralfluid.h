@@ -178,11 +178,15 @@ int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, 
 int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
                      hipStream_t stream);
 
-/* Kernel timing for measurement: while enabled, HIP events are recorded on
- * the launch stream around every launch of one kernel family (multigrid
- * kernels: finest level only).  sim_profile_read synchronises those events and
- * returns the summed duration (ms) and the number of launches timed, then
- * clears them.  kernel: one of sim_kernel, or -1 to disable.
+/* Kernel timing for measurement: while enabled, the launches of one kernel
+ * family are timed on the launch stream (multigrid kernels: finest level
+ * only).  Single-kernel launches record their start and stop events from the
+ * dispatch itself (the kernel's execution time); composite launches are
+ * bracketed by event records.  sim_profile_read synchronises those events and
+ * returns the summed duration (ms) and the number of launches timed, counting
+ * only launches that took at least min_ms (0: all; a solver kernel enqueued
+ * after convergence exits at once and can be left out this way), then clears
+ * them.  kernel: one of sim_kernel, or -1 to disable.
  * SIM_K_MG_DOWN: finest-level pre-smoothing + restriction (one fused launch,
  * or the first of two when the fused kernels are disabled); SIM_K_MG_DOWN2:
  * the restriction launch of the unfused form; SIM_K_MG_UP: finest-level
@@ -195,7 +199,7 @@ typedef enum {
   SIM_K_MG_DOWN, SIM_K_MG_DOWN2, SIM_K_MG_UP1, SIM_K_MG_UP, SIM_K_MG_COARSE, SIM_K_COUNT
 } sim_kernel;
 int32_t sim_profile(sim_handle h, int32_t kernel);
-int32_t sim_profile_read(sim_handle h, double* total_ms, int64_t* count);
+int32_t sim_profile_read(sim_handle h, double min_ms, double* total_ms, int64_t* count);
 
 /* Rigid ellipsoid pose dynamics (host, FP64).  theta0 (9) = centre c0(3),
  * semi-axes a(3), rotation vector r0(3); R0 = exp([r0]x).  For step n with

@@ -93,7 +93,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_ellipsoid_poses_adjoint": (C.c_int32, [_dp, _dp, C.c_int32, C.c_double, _dp, _dp, _dp, _dp]),
         "sim_loss_box": (C.c_int32, [_vp, _fp, _dp, _dp, _vp, _fp, _vp]),
         "sim_profile": (C.c_int32, [_vp, C.c_int32]),
-        "sim_profile_read": (C.c_int32, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -159,10 +159,16 @@ __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0,
 
 // Adjoint scatter target: component lattice e, flat index `idx`, lattice
 // coordinates (a, b, c).  Targets inside the workgroup's LDS window are
-// accumulated there; others go straight to global memory.
+// accumulated there in 64-bit fixed point (value * scale, rounded): integer
+// LDS atomics run at full rate, float LDS atomics about 3.5x slower than the
+// whole rest of the kernel, and the integer sums are also independent of the
+// order of the adds.  Others, and any value too large for the fixed-point
+// range, go straight to global memory as float atomics.
 struct Window {
-  int o[3];                 // lattice coordinate of the window origin (same for all components)
-  float* lds;               // 3 windows of kWinX * kWinY * kWinZ floats
+  int o[3];                       // lattice coordinate of the window origin (same for all components)
+  unsigned long long* lds;        // 3 windows of kWinX * kWinY * kWinZ fixed-point sums
+  double scale;                   // fixed-point scale of this workgroup
+  double limit;                   // largest |value * scale| accumulated in the window
 };
 // Brick of cells owned by one workgroup (one face per thread: at most
 // 9*8*4 + 8*9*4 + 8*8*5 = 896 faces) and the halo of its scatter windows.
@@ -178,7 +184,7 @@ __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, 
   const double wz[2] = {1.0 - fz, fz}, wy[2] = {1.0 - fy, fy}, wx[2] = {1.0 - fx, fx};
   const int la = t.i0[0] - W.o[0], lb = t.i0[1] - W.o[1], lc = t.i0[2] - W.o[2];
   const bool inside = la >= 0 && lb >= 0 && lc >= 0 && la + 1 < kWinX && lb + 1 < kWinY && lc + 1 < kWinZ;
-  float* win = W.lds + e * kWin3;
+  unsigned long long* win = W.lds + e * kWin3;
 #pragma unroll
   for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
@@ -187,11 +193,10 @@ __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, 
       for (int bx = 0; bx < 2; ++bx) {
         double ww = w * wz[bz] * wy[by] * wx[bx];
         if (ww == 0.0) continue;
-        // distinct scopes keep the two adds apart (merged, they would become
-        // one generic-address atomic instead of an LDS atomic)
-        if (inside)
-          __hip_atomic_fetch_add(win + (la + bx) + kWinX * ((lb + by) + kWinY * (lc + bz)), (float)ww,
-                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const double fixed = ww * W.scale;
+        if (inside && fabs(fixed) <= W.limit)
+          atomicAdd(win + (la + bx) + kWinX * ((lb + by) + kWinY * (lc + bz)),
+                    (unsigned long long)(long long)llrint(fixed));
         else
           __hip_atomic_fetch_add(g + t.base + bx + by * t.sx + bz * t.sxy, (float)ww, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
@@ -210,7 +215,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
                                                                  const double* __restrict__ trace,
                                                                  const float* __restrict__ gout,
                                                                  float* __restrict__ gin, float* __restrict__ stage) {
-  __shared__ float lds[3 * kWin3];
+  __shared__ unsigned long long lds[3 * kWin3];
+  __shared__ float red[2 * (kAdjThreads / 64)];
   const int nbx = (d.nx + kBX - 1) / kBX, nby = (d.ny + kBY - 1) / kBY;
   const int bid = xcd_block(blockIdx.x, gridDim.x);
   const int bxi = bid % nbx, byi = (bid / nbx) % nby, bzi = bid / (nbx * nby);
@@ -220,10 +226,25 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
   W.o[1] = j0 - kHalo;
   W.o[2] = k0 - kHalo;
   W.lds = lds;
-  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) lds[q] = 0.0f;
-  __syncthreads();
   const float* uc[3] = {u, u + d.nfx(), u + d.nfx() + d.nfy()};
   float* gc[3] = {gin, gin + d.nfx(), gin + d.nfx() + d.nfy()};
+  // Fixed-point scale from bounds of this workgroup's contributions: with
+  // G = max |g| over its faces and U = max |u| over the window region, every
+  // scattered value is at most G * max(1, 2 cfl U, 6 cfl^2 U^2) (interpolation
+  // weights <= 1, trilinear gradients in index units <= 2U); 2^50 / bound
+  // leaves room for 2^12 adds per entry below 2^62.  Values that still exceed
+  // the limit (taps of corners outside the window region) take the float path.
+  float um = 0.0f;
+  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) {
+    lds[q] = 0ull;
+    const int e = q / kWin3, r = q % kWin3;
+    int m[3];
+    lattice(d, e, m);
+    const int a = min(max(W.o[0] + r % kWinX, 0), m[0] - 1);
+    const int b = min(max(W.o[1] + (r / kWinX) % kWinY, 0), m[1] - 1);
+    const int c = min(max(W.o[2] + r / (kWinX * kWinY), 0), m[2] - 1);
+    um = fmaxf(um, fabsf(uc[e][a + m[0] * (b + m[1] * c)]));
+  }
   // faces of the brick, per component: extents along each axis
   int ext[3][3];
   const int bn[3] = {min(kBX, d.nx - i0), min(kBY, d.ny - j0), min(kBZ, d.nz - k0)};
@@ -235,6 +256,36 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
     total += ext[e][0] * ext[e][1] * ext[e][2];
   }
   start[3] = total;
+  float gm = 0.0f;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int comp = q < start[1] ? 0 : (q < start[2] ? 1 : 2);
+    const int lq = q - start[comp];
+    const int li = lq % ext[comp][0], lj = (lq / ext[comp][0]) % ext[comp][1], lk = lq / (ext[comp][0] * ext[comp][1]);
+    const long f = comp == 0 ? (long)d.fx(i0 + li, j0 + lj, k0 + lk)
+                             : (comp == 1 ? (long)d.nfx() + d.fy(i0 + li, j0 + lj, k0 + lk)
+                                          : (long)d.nfx() + d.nfy() + d.fz(i0 + li, j0 + lj, k0 + lk));
+    gm = fmaxf(gm, fabsf(gout[f]));
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    um = fmaxf(um, __shfl_down(um, o, 64));
+    gm = fmaxf(gm, __shfl_down(gm, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = um;
+    red[(kAdjThreads / 64) + (threadIdx.x >> 6)] = gm;
+  }
+  __syncthreads();
+  {
+    float U = 0.0f, Gm = 0.0f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      U = fmaxf(U, red[w]);
+      Gm = fmaxf(Gm, red[(kAdjThreads / 64) + w]);
+    }
+    const double cu = cfl * (double)U;
+    const double bound = (double)Gm * fmax(1.0, fmax(2.0 * cu, 6.0 * cu * cu));
+    W.scale = bound > 0.0 && isfinite(bound) ? 1125899906842624.0 / bound : 1.0;   // 2^50 / bound
+    W.limit = 4503599627370496.0;                                                  // 2^52
+  }
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
     const int comp = q < start[1] ? 0 : (q < start[2] ? 1 : 2);
     const int lq = q - start[comp];
@@ -276,9 +327,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
     for (int e = 0; e < 3; ++e) scatter_w(W, gc[e], e, make_tap(d, e, Xf), -0.5 * cfl * gXm[e]);
   }
   __syncthreads();
-  // store the three windows of this brick
+  // store the three windows of this brick (back from fixed point)
   float* dst = stage + (size_t)bid * (3 * kWin3);
-  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) dst[q] = lds[q];
+  const double inv = 1.0 / W.scale;
+  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) dst[q] = (float)((double)(long long)lds[q] * inv);
 }
 
 // gin_f += sum of the staged window entries of face f over the bricks whose

@@ -402,17 +402,20 @@ int32_t sim_profile(sim_handle h, int32_t kernel) {
   return SIM_OK;
 }
 
-int32_t sim_profile_read(sim_handle h, double* total_ms, int64_t* count) {
-  if (!h || !total_ms || !count) return SIM_EINVAL;
+int32_t sim_profile_read(sim_handle h, double min_ms, double* total_ms, int64_t* count) {
+  if (!h || !total_ms || !count || !(min_ms >= 0.0)) return SIM_EINVAL;
   double tot = 0.0;
+  int64_t n = 0;
   for (size_t q = 0; q + 1 < h->prof.used; q += 2) {
     if (hipEventSynchronize(h->prof.ev[q + 1]) != hipSuccess) return SIM_EHIP;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, h->prof.ev[q], h->prof.ev[q + 1]) != hipSuccess) return SIM_EHIP;
+    if ((double)ms < min_ms) continue;
     tot += ms;
+    ++n;
   }
   *total_ms = tot;
-  *count = (int64_t)(h->prof.used / 2);
+  *count = n;
   h->prof.used = 0;
   return SIM_OK;
 }

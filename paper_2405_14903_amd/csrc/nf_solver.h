@@ -3,25 +3,40 @@
 
 #include "nf_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <vector>
 
 namespace nf {
 
-// Optional timing of one kernel family with HIP events recorded around each of
-// its launches on the launch stream (multigrid kernels: the finest level only).
+// Optional timing of one kernel family on the launch stream (multigrid
+// kernels: the finest level only).  Single-kernel launches go through
+// NF_LAUNCH, which has the dispatch itself record the start and stop events
+// (hipExtLaunchKernelGGL: the kernel's own execution time, as a kernel trace
+// reports it); composite launches are bracketed by event records (NF_TIMED).
 struct Profiler {
   int active = -1;
   std::vector<hipEvent_t> ev;   // pairs: begin, end
   size_t used = 0;
   bool want(int id) const { return active == id; }
+  bool reserve() {
+    if (used + 2 <= ev.size()) return true;
+    if (ev.size() >= 2 * 16384) return false;
+    size_t old = ev.size();
+    ev.resize(old ? 2 * old : 512);
+    for (size_t q = old; q < ev.size(); ++q) (void)hipEventCreate(&ev[q]);
+    return true;
+  }
+  // the next event pair for a launch of kernel family id (false: not timed)
+  bool pair(int id, hipEvent_t& a, hipEvent_t& b) {
+    if (active != id || !reserve()) return false;
+    a = ev[used];
+    b = ev[used + 1];
+    used += 2;
+    return true;
+  }
   void begin(int id, hipStream_t s) {
-    if (active != id) return;
-    if (used + 2 > ev.size()) {
-      if (ev.size() >= 2 * 16384) return;
-      size_t old = ev.size();
-      ev.resize(old ? 2 * old : 512);
-      for (size_t q = old; q < ev.size(); ++q) (void)hipEventCreate(&ev[q]);
-    }
+    if (active != id || !reserve()) return;
     (void)hipEventRecord(ev[used], s);
   }
   void end(int id, hipStream_t s) {
@@ -39,6 +54,15 @@ struct Profiler {
     if (prof) (prof)->begin(id, stream); \
     __VA_ARGS__;                         \
     if (prof) (prof)->end(id, stream);   \
+  } while (0)
+
+#define NF_LAUNCH(prof, id, kernel, grid, block, shmem, stream, ...)                              \
+  do {                                                                                            \
+    hipEvent_t nf_e0_, nf_e1_;                                                                    \
+    if ((prof) && (prof)->pair(id, nf_e0_, nf_e1_))                                               \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, nf_e0_, nf_e1_, 0, __VA_ARGS__); \
+    else                                                                                          \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                       \
   } while (0)
 
 struct Level {

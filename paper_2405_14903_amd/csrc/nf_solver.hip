@@ -1086,8 +1086,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
   const size_t lds = (size_t)off * sizeof(float);
   const int bthreads = S.lev[G].d.cells() >= 1024 ? 1024 : (int)((S.lev[G].d.cells() + 63) / 64 * 64);
   if (G == 0) {
-    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
-             hipLaunchKernelGGL((k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1));
+    NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1);
     hipLaunchKernelGGL(k_scale_dot<T>, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, ID(0), r0, z0, sc, S.partials);
     hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n0), S.partials, sc, S.project);
     return;
@@ -1101,26 +1100,22 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       const Dims& cd = S.lev[l + 1].d;
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
-        NF_TIMED(S.prof, SIM_K_MG_DOWN, st,
-                 hipLaunchKernelGGL((k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(0),
-                                    Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1));
+        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st,
+                  d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1);
       } else {
         hipLaunchKernelGGL((k_mg_down<T, T, T, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
                            ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0);
       }
     }
-    NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
-             hipLaunchKernelGGL((k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
-                                (T*)S.lev[G].z, sc, 0));
+    NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
+                                (T*)S.lev[G].z, sc, 0);
     for (int l = G - 1; l >= 0; --l) {
       const Dims& d = S.lev[l].d;
       const Dims& cd = S.lev[l + 1].d;
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
-        NF_TIMED(S.prof, SIM_K_MG_UP, st,
-                 hipLaunchKernelGGL((k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kTileThreads), 0, st,
-                                    d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
-                                    S.partials));
+        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kTileThreads),
+                  0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc, S.partials);
         hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d), S.partials, sc, S.project);
       } else {
         hipLaunchKernelGGL((k_mg_up<T, T, T, T, T, false>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
@@ -1137,12 +1132,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     T* rc = (T*)S.lev[l + 1].r;
     if (l == 0) {
       float* ta0 = (float*)S.lev[0].ta;
-      NF_TIMED(S.prof, SIM_K_MG_DOWN, st,
-               hipLaunchKernelGGL((k_mg_pre<T, float, float>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
-                                  A(0), Ay(0), Az(0), ID(0), r0, ta0, sc, 1));
-      NF_TIMED(S.prof, SIM_K_MG_DOWN2, st,
-               hipLaunchKernelGGL((k_mg_restrict<T, float, float, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0,
-                                  st, d, cd, A(0), Ay(0), Az(0), r0, (const float*)ta0, rc, sc, 1));
+      NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_pre<T, float, float>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
+                                  A(0), Ay(0), Az(0), ID(0), r0, ta0, sc, 1);
+      NF_LAUNCH(S.prof, SIM_K_MG_DOWN2, (k_mg_restrict<T, float, float, T>), dim3(nblocks(cd.cells())), dim3(kBlock), 0,
+                                  st, d, cd, A(0), Ay(0), Az(0), r0, (const float*)ta0, rc, sc, 1);
     } else {
       const T* rl = (const T*)S.lev[l].r;
       hipLaunchKernelGGL((k_mg_pre<T, T, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, A(l), Ay(l),
@@ -1151,9 +1144,8 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
                          Ay(l), Az(l), rl, (const T*)ta, rc, sc, 0);
     }
   }
-  NF_TIMED(S.prof, SIM_K_MG_COARSE, st,
-           hipLaunchKernelGGL((k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
-                              (T*)S.lev[G].z, sc, 0));
+  NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
+                              (T*)S.lev[G].z, sc, 0);
   for (int l = G - 1; l >= 0; --l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
@@ -1163,12 +1155,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     if (l == 0) {
       const float* ta0 = (const float*)S.lev[0].ta;
       float* tb0 = (float*)S.lev[0].tb;
-      NF_TIMED(S.prof, SIM_K_MG_UP1, st,
-               hipLaunchKernelGGL((k_mg_post1<T, float, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
-                                  cd, A(0), Ay(0), Az(0), ID(0), r0, ta0, e, tb0, sc, 1));
-      NF_TIMED(S.prof, SIM_K_MG_UP, st,
-               hipLaunchKernelGGL((k_mg_post2<T, float, float, float, true>), dim3(nblocks(d.cells())), dim3(kBlock),
-                                  0, st, d, A(0), Ay(0), Az(0), ID(0), r0, (const float*)tb0, z0, sc, S.partials));
+      NF_LAUNCH(S.prof, SIM_K_MG_UP1, (k_mg_post1<T, float, float, T>), dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d,
+                                  cd, A(0), Ay(0), Az(0), ID(0), r0, ta0, e, tb0, sc, 1);
+      NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_post2<T, float, float, float, true>), dim3(nblocks(d.cells())), dim3(kBlock),
+                                  0, st, d, A(0), Ay(0), Az(0), ID(0), r0, (const float*)tb0, z0, sc, S.partials);
       hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(d.cells()), S.partials, sc,
                          S.project);
     } else {
@@ -1273,19 +1263,16 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     const int nb = (int)nblocks(n);
     if (S.fused) {
       const int nt = (int)(((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ));
-      NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
-               hipLaunchKernelGGL(k_cg_dir_apply_tile, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay, S.az,
-                                  S.z, pold, pnew, S.q, S.sc, S.partials));
+      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay,
+                S.az, S.z, pold, pnew, S.q, S.sc, S.partials);
       hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nt, S.partials, S.sc);
     } else {
-      NF_TIMED(S.prof, SIM_K_CG_APPLY, st,
-               hipLaunchKernelGGL(k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
-                                  pnew, S.q, S.sc, S.partials));
+      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
+                                  pnew, S.q, S.sc, S.partials);
       hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc);
     }
-    NF_TIMED(S.prof, SIM_K_CG_UPDATE, st,
-             hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
-                                S.partials));
+    NF_LAUNCH(S.prof, SIM_K_CG_UPDATE, k_cg_update, dim3(nb), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
+              S.partials);
     hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc, n);
     vcycle_dispatch(S, S.r, S.z, st);
     S.pcur ^= 1;
@@ -1371,9 +1358,8 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
   CGScalars* sc = S.sc;
   double* x = S.x;
   hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
-  NF_TIMED(S.prof, SIM_K_CG_INIT, st,
-           hipLaunchKernelGGL(k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
-                              S.partials));
+  NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
+                              S.partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
                      S.project);
   if (S.project)
@@ -1403,9 +1389,8 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
     if (h.done || h.iters >= maxit || cnt <= 0) {
       // true residual from the FP64 iterate; restart from it if needed
       const int allow = restarts < kMaxRestarts && h.iters < maxit ? 1 : 0;
-      NF_TIMED(S.prof, SIM_K_CG_TRUE, st,
-               hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
-                                  x, S.r, allow, sc, S.partials));
+      NF_LAUNCH(S.prof, SIM_K_CG_TRUE, k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
+                                  x, S.r, allow, sc, S.partials);
       hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n,
                          S.project);
       r = snapshot(S, st);

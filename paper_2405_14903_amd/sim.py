@@ -199,10 +199,11 @@ class Sim:
         kid = -1 if kernel is None else L.KERNELS.index(kernel)
         L.check(self.lib.sim_profile(self.h, kid), "sim_profile")
 
-    def profile_read(self):
-        """(total ms, launches) of the timed kernel since the last read."""
+    def profile_read(self, min_ms=0.0):
+        """(total ms, launches) of the timed kernel since the last read, over
+        launches that took at least min_ms."""
         ms, cnt = C.c_double(0), C.c_int64(0)
-        L.check(self.lib.sim_profile_read(self.h, C.byref(ms), C.byref(cnt)), "sim_profile_read")
+        L.check(self.lib.sim_profile_read(self.h, float(min_ms), C.byref(ms), C.byref(cnt)), "sim_profile_read")
         return ms.value, cnt.value
 
     def set_geometry(self, theta=None, ctrl=None, alpha_out=None):
