@@ -501,7 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// Fused grid-level kernels.  One workgroup owns a kTX x kTY x kTZ tile of a
+// Fused grid-level kernels.  One workgroup owns a TX x TY x TZ tile of a
 // level and recomputes what its neighbours own on a halo instead of waiting
 // for them, so the four smoother / transfer passes of a level become two
 // launches and each array is read from memory once per launch:
@@ -513,26 +513,36 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
 // Values beyond the domain are 0, as in apply_A.
 // ---------------------------------------------------------------------------
 
-constexpr int kTX = 32, kTY = 8, kTZ = 8;
+// Tile shapes: the finest level uses long x rows (efficient halo reuse), the
+// coarse levels small cubes (their launches are latency-bound: less serial
+// work per thread and more workgroups).
+template <int TX_, int TY_, int TZ_>
+struct TileShape {
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
+};
+using FineTile = TileShape<32, 8, 8>;
+using CoarseTile = TileShape<8, 8, 8>;
 constexpr int kTileThreads = 512;   // 8 waves per tile: more loads in flight per CU
 // Loops over a region have a compile-time trip count, so they unroll fully
 // and every thread issues all of its loads before the first one is used.
 constexpr int trips(int n) { return (n + kTileThreads - 1) / kTileThreads; }
-template <int H>
+template <class S, int H>
 struct Halo {
-  static constexpr int X = kTX + 2 * H, Y = kTY + 2 * H, Z = kTZ + 2 * H, N = X * Y * Z;
+  static constexpr int X = S::TX + 2 * H, Y = S::TY + 2 * H, Z = S::TZ + 2 * H, N = X * Y * Z;
 };
 
-__device__ inline int tiles_of(const Dims& d) {
-  return ((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
+template <class S>
+__host__ __device__ inline int tiles_of(const Dims& d) {
+  return ((d.nx + S::TX - 1) / S::TX) * ((d.ny + S::TY - 1) / S::TY) * ((d.nz + S::TZ - 1) / S::TZ);
 }
 
+template <class S>
 __device__ inline void tile_origin(const Dims& d, int& i0, int& j0, int& k0) {
-  const int tx = (d.nx + kTX - 1) / kTX, ty = (d.ny + kTY - 1) / kTY;
+  const int tx = (d.nx + S::TX - 1) / S::TX, ty = (d.ny + S::TY - 1) / S::TY;
   const int b = xcd_block(blockIdx.x, gridDim.x);
-  i0 = (b % tx) * kTX;
-  j0 = ((b / tx) % ty) * kTY;
-  k0 = (b / (tx * ty)) * kTZ;
+  i0 = (b % tx) * S::TX;
+  j0 = ((b / tx) % ty) * S::TY;
+  k0 = (b / (tx * ty)) * S::TZ;
 }
 
 __device__ inline bool in_dom(const Dims& d, int i, int j, int k) {
@@ -562,9 +572,9 @@ struct RegionCell {
   bool ok;   // q inside the region and (i, j, k) inside the domain
 };
 
-template <int H>
+template <class S, int H>
 __device__ inline RegionCell region_cell(const Dims& d, int i0, int j0, int k0, int u) {
-  using R = Halo<H>;
+  using R = Halo<S, H>;
   RegionCell rc;
   rc.q = threadIdx.x + u * kTileThreads;
   const int q = rc.q < R::N ? rc.q : 0;
@@ -578,195 +588,198 @@ __device__ inline RegionCell region_cell(const Dims& d, int i0, int j0, int k0, 
 }
 
 // local index in the +2 region of a cell at local index q of the +1 region
+template <class S>
 __device__ inline int up1to2(int q) {
-  using H1 = Halo<1>;
-  using H2 = Halo<2>;
+  using H1 = Halo<S, 1>;
+  using H2 = Halo<S, 2>;
   const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
   return (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
 }
 
-template <typename A, typename R, typename Z, typename RC>
+// PRE: issue the loads of all three phases before the first one computes (one
+// memory latency per launch instead of three; for the small coarse levels,
+// whose launches are latency-bound and few tiles wide).  Without PRE each
+// phase loads what it needs, which keeps registers low for the finest level.
+template <class S, typename A, typename R, typename Z, typename RC, bool PRE>
 __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
                                                           const A* __restrict__ ay, const A* __restrict__ az,
                                                           const A* __restrict__ invd, const R* __restrict__ r,
                                                           Z* __restrict__ z2out, RC* __restrict__ rc,
                                                           const CGScalars* sc, int lvl0) {
   if (sc->done) return;
-  using H2 = Halo<2>;
-  using H1 = Halo<1>;
+  using H2 = Halo<S, 2>;
+  using H1 = Halo<S, 1>;
   __shared__ float z1s[H2::N];
   __shared__ float rs[H1::N];
   __shared__ float z2s[H1::N];
   const float s0 = level_scale(sc, lvl0);
   int i0, j0, k0;
-  tile_origin(d, i0, j0, k0);
-  {
-    constexpr int T = trips(H2::N);
-    RegionCell cell[T];
-    float id[T], rv[T];
+  tile_origin<S>(d, i0, j0, k0);
+  constexpr int T1 = trips(H2::N), T2 = trips(H1::N);
+  RegionCell c1[T1], c2[T2];
+  float id1[T1], rv1[T1], id2[T2], rv2[T2];
+  Faces<A> fw2[T2], fw3[8];
+  // restriction: the tile's (S::TX/2) x (S::TY/2) x (S::TZ/2) coarse cells, one per thread
+  const int t = threadIdx.x;
+  const int ci = t % (S::TX / 2), cj = (t / (S::TX / 2)) % (S::TY / 2), ck = t / ((S::TX / 2) * (S::TY / 2));
+  const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
+  const bool rok = t < (S::TX / 2) * (S::TY / 2) * (S::TZ / 2) && I < cd.nx && J < cd.ny && K < cd.nz;
+  auto load2 = [&]() {
 #pragma unroll
-    for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<2>(d, i0, j0, k0, u);
-      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
-      id[u] = ld(invd, c);
-      rv[u] = ld(r, c);
+    for (int u = 0; u < T2; ++u) {
+      c2[u] = region_cell<S, 1>(d, i0, j0, k0, u);
+      const long c = d.c(c2[u].i, c2[u].j, c2[u].k);
+      fw2[u] = Faces<A>(d, ax, ay, az, c2[u].i, c2[u].j, c2[u].k);
+      id2[u] = ld(invd, c);
+      rv2[u] = ld(r, c);
     }
-#pragma unroll
-    for (int u = 0; u < T; ++u)
-      if (cell[u].q < H2::N) z1s[cell[u].q] = cell[u].ok ? kOmega * id[u] * (s0 * rv[u]) : 0.0f;
-  }
-  __syncthreads();
-  {
-    constexpr int T = trips(H1::N);
-    RegionCell cell[T];
-    Faces<A> fw[T];
-    float id[T], rv[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<1>(d, i0, j0, k0, u);
-      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
-      fw[u] = Faces<A>(d, ax, ay, az, cell[u].i, cell[u].j, cell[u].k);
-      id[u] = ld(invd, c);
-      rv[u] = ld(r, c);
-    }
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      const int q = cell[u].q;
-      if (q >= H1::N) continue;
-      float z2 = 0.0f, rr = 0.0f;
-      if (cell[u].ok) {
-        const int q2 = up1to2(q);
-        rr = s0 * rv[u];
-        const Z zs = cvt<Z>(z1s[q2] + kOmega * id[u] * (rr - apply_local(fw[u], z1s, q2, H2::X, H2::X * H2::Y)));
-        z2 = ld(&zs, 0);
-        const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
-        if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ)
-          z2out[d.c(cell[u].i, cell[u].j, cell[u].k)] = zs;
-      }
-      z2s[q] = z2;
-      rs[q] = rr;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < (kTX / 2) * (kTY / 2) * (kTZ / 2)) {
-    // the tile's (kTX/2) x (kTY/2) x (kTZ/2) = 256 coarse cells, one per thread
-    const int t = threadIdx.x;
-    const int ci = t % (kTX / 2), cj = (t / (kTX / 2)) % (kTY / 2), ck = t / ((kTX / 2) * (kTY / 2));
-    const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
-    const bool ok = I < cd.nx && J < cd.ny && K < cd.nz;
-    Faces<A> fw[8];
+  };
+  auto load3 = [&]() {
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      const int i = ok ? 2 * I + (b & 1) : 0, j = ok ? 2 * J + ((b >> 1) & 1) : 0, k = ok ? 2 * K + (b >> 2) : 0;
-      fw[b] = Faces<A>(d, ax, ay, az, i, j, k);
+      const int i = rok ? 2 * I + (b & 1) : 0, j = rok ? 2 * J + ((b >> 1) & 1) : 0, k = rok ? 2 * K + (b >> 2) : 0;
+      fw3[b] = Faces<A>(d, ax, ay, az, i, j, k);
     }
-    if (ok) {
-      float s = 0.0f;
+  };
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
-        const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-        s += rs[q1] - apply_local(fw[b], z2s, q1, H1::X, H1::X * H1::Y);
-      }
-      rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
+  for (int u = 0; u < T1; ++u) {
+    c1[u] = region_cell<S, 2>(d, i0, j0, k0, u);
+    const long c = d.c(c1[u].i, c1[u].j, c1[u].k);
+    id1[u] = ld(invd, c);
+    rv1[u] = ld(r, c);
+  }
+  if (PRE) {
+    load2();
+    load3();
+  }
+#pragma unroll
+  for (int u = 0; u < T1; ++u)
+    if (c1[u].q < H2::N) z1s[c1[u].q] = c1[u].ok ? kOmega * id1[u] * (s0 * rv1[u]) : 0.0f;
+  __syncthreads();
+  if (!PRE) load2();
+#pragma unroll
+  for (int u = 0; u < T2; ++u) {
+    const int q = c2[u].q;
+    if (q >= H1::N) continue;
+    float z2 = 0.0f, rr = 0.0f;
+    if (c2[u].ok) {
+      const int q2 = up1to2<S>(q);
+      rr = s0 * rv2[u];
+      const Z zs = cvt<Z>(z1s[q2] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, q2, H2::X, H2::X * H2::Y)));
+      z2 = ld(&zs, 0);
+      const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
+      if (li >= 1 && li <= S::TX && lj >= 1 && lj <= S::TY && lk >= 1 && lk <= S::TZ)
+        z2out[d.c(c2[u].i, c2[u].j, c2[u].k)] = zs;
     }
+    z2s[q] = z2;
+    rs[q] = rr;
+  }
+  __syncthreads();
+  if (!PRE) load3();
+  if (rok) {
+    float s = 0.0f;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
+      const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+      s += rs[q1] - apply_local(fw3[b], z2s, q1, H1::X, H1::X * H1::Y);
+    }
+    rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
   }
 }
 
-template <typename A, typename R, typename Z, typename E, typename O, bool LVL0>
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE>
 __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
                                                         const A* __restrict__ ay, const A* __restrict__ az,
                                                         const A* __restrict__ invd, const R* __restrict__ r,
                                                         const Z* __restrict__ z2, const E* __restrict__ e,
                                                         O* __restrict__ zout, const CGScalars* sc, double* partials) {
   if (sc->done) return;
-  using H2 = Halo<2>;
-  using H1 = Halo<1>;
+  using H2 = Halo<S, 2>;
+  using H1 = Halo<S, 1>;
   __shared__ float zp[H2::N];
   __shared__ float z3s[H1::N];
   const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
   int i0, j0, k0;
-  tile_origin(d, i0, j0, k0);
-  {
-    constexpr int T = trips(H2::N);
-    RegionCell cell[T];
-    float zv[T], ev[T];
+  tile_origin<S>(d, i0, j0, k0);
+  constexpr int T1 = trips(H2::N), T2 = trips(H1::N), T3 = trips(S::TX * S::TY * S::TZ);
+  RegionCell c1[T1], c2[T2];
+  float zv[T1], ev[T1], id2[T2], rv2[T2], id3[T3], rv3[T3], zold[T3];
+  Faces<A> fw2[T2], fw3[T3];
+  bool ok3[T3];
+  int cl3[T3];
+  auto load2 = [&]() {
 #pragma unroll
-    for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<2>(d, i0, j0, k0, u);
-      zv[u] = ld(z2, d.c(cell[u].i, cell[u].j, cell[u].k));
-      ev[u] = ld(e, cd.c(cell[u].i >> 1, cell[u].j >> 1, cell[u].k >> 1));
+    for (int u = 0; u < T2; ++u) {
+      c2[u] = region_cell<S, 1>(d, i0, j0, k0, u);
+      const long c = d.c(c2[u].i, c2[u].j, c2[u].k);
+      fw2[u] = Faces<A>(d, ax, ay, az, c2[u].i, c2[u].j, c2[u].k);
+      id2[u] = ld(invd, c);
+      rv2[u] = ld(r, c);
     }
+  };
+  auto load3 = [&]() {
 #pragma unroll
-    for (int u = 0; u < T; ++u)
-      if (cell[u].q < H2::N) zp[cell[u].q] = cell[u].ok ? zv[u] + 8.0f * ev[u] : 0.0f;
-  }
-  __syncthreads();
-  {
-    constexpr int T = trips(H1::N);
-    RegionCell cell[T];
-    Faces<A> fw[T];
-    float id[T], rv[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<1>(d, i0, j0, k0, u);
-      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
-      fw[u] = Faces<A>(d, ax, ay, az, cell[u].i, cell[u].j, cell[u].k);
-      id[u] = ld(invd, c);
-      rv[u] = ld(r, c);
-    }
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      const int q = cell[u].q;
-      if (q >= H1::N) continue;
-      float v = 0.0f;
-      if (cell[u].ok) {
-        const int q2 = up1to2(q);
-        v = zp[q2] + kOmega * id[u] * (s0 * rv[u] - apply_local(fw[u], zp, q2, H2::X, H2::X * H2::Y));
-      }
-      z3s[q] = v;
-    }
-  }
-  __syncthreads();
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  {
-    constexpr int T = trips(kTX * kTY * kTZ);
-    int cl[T];
-    bool ok[T];
-    Faces<A> fw[T];
-    float id[T], rv[T], zold[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
+    for (int u = 0; u < T3; ++u) {
       const int q = threadIdx.x + u * kTileThreads;
-      const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
+      const int li = q % S::TX, lj = (q / S::TX) % S::TY, lk = q / (S::TX * S::TY);
       int i = i0 + li, j = j0 + lj, k = k0 + lk;
-      ok[u] = in_dom(d, i, j, k);
-      if (!ok[u]) i = j = k = 0;
-      cl[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
+      ok3[u] = in_dom(d, i, j, k);
+      if (!ok3[u]) i = j = k = 0;
+      cl3[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
       const long c = d.c(i, j, k);
-      fw[u] = Faces<A>(d, ax, ay, az, i, j, k);
-      id[u] = ld(invd, c);
-      rv[u] = ld(r, c);
+      fw3[u] = Faces<A>(d, ax, ay, az, i, j, k);
+      id3[u] = ld(invd, c);
+      rv3[u] = ld(r, c);
       zold[u] = (LVL0 && !first) ? ld(zout, c) : 0.0f;
     }
+  };
 #pragma unroll
-    for (int u = 0; u < T; ++u) {
-      if (!ok[u]) continue;
-      const int q = threadIdx.x + u * kTileThreads;
-      const int li = q % kTX, lj = (q / kTX) % kTY, lk = q / (kTX * kTY);
-      const long c = d.c(i0 + li, j0 + lj, k0 + lk);
-      const int q1 = cl[u];
-      float zo = (z3s[q1] + kOmega * id[u] * (s0 * rv[u] - apply_local(fw[u], z3s, q1, H1::X, H1::X * H1::Y))) * inv;
-      if (LVL0 && !(id[u] > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
-      if (LVL0 && !first) acc[1] += (double)rv[u] * (double)zold[u];   // r_new . z_old
-      zout[c] = cvt<O>(zo);
-      if (LVL0) {
-        acc[0] += (double)rv[u] * (double)zo;
-        acc[2] += (double)zo;
-        acc[3] += (double)rv[u];
-      }
+  for (int u = 0; u < T1; ++u) {
+    c1[u] = region_cell<S, 2>(d, i0, j0, k0, u);
+    zv[u] = ld(z2, d.c(c1[u].i, c1[u].j, c1[u].k));
+    ev[u] = ld(e, cd.c(c1[u].i >> 1, c1[u].j >> 1, c1[u].k >> 1));
+  }
+  if (PRE) {
+    load2();
+    load3();
+  }
+#pragma unroll
+  for (int u = 0; u < T1; ++u)
+    if (c1[u].q < H2::N) zp[c1[u].q] = c1[u].ok ? zv[u] + 8.0f * ev[u] : 0.0f;
+  __syncthreads();
+  if (!PRE) load2();
+#pragma unroll
+  for (int u = 0; u < T2; ++u) {
+    const int q = c2[u].q;
+    if (q >= H1::N) continue;
+    float v = 0.0f;
+    if (c2[u].ok) {
+      const int q2 = up1to2<S>(q);
+      v = zp[q2] + kOmega * id2[u] * (s0 * rv2[u] - apply_local(fw2[u], zp, q2, H2::X, H2::X * H2::Y));
+    }
+    z3s[q] = v;
+  }
+  __syncthreads();
+  if (!PRE) load3();
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < T3; ++u) {
+    if (!ok3[u]) continue;
+    const int q = threadIdx.x + u * kTileThreads;
+    const int li = q % S::TX, lj = (q / S::TX) % S::TY, lk = q / (S::TX * S::TY);
+    const long c = d.c(i0 + li, j0 + lj, k0 + lk);
+    const int q1 = cl3[u];
+    float zo = (z3s[q1] + kOmega * id3[u] * (s0 * rv3[u] - apply_local(fw3[u], z3s, q1, H1::X, H1::X * H1::Y))) * inv;
+    if (LVL0 && !(id3[u] > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
+    if (LVL0 && !first) acc[1] += (double)rv3[u] * (double)zold[u];   // r_new . z_old
+    zout[c] = cvt<O>(zo);
+    if (LVL0) {
+      acc[0] += (double)rv3[u] * (double)zo;
+      acc[2] += (double)zo;
+      acc[3] += (double)rv3[u];
     }
   }
   if (LVL0) block_partials<4, kTileThreads>(acc, partials);
@@ -776,6 +789,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A
 // + 1 cell (in LDS; written out on the tile), q = A p and p.q partials on the
 // tile.  Same arithmetic as k_cg_dir_apply with one load of z and p_old per
 // cell and halo.
+template <class S>
 __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, const float* __restrict__ ax,
                                                                     const float* __restrict__ ay,
                                                                     const float* __restrict__ az,
@@ -784,20 +798,20 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
                                                                     float* __restrict__ pnew, float* __restrict__ q,
                                                                     const CGScalars* sc, double* partials) {
   if (sc->done) return;
-  using H1 = Halo<1>;
+  using H1 = Halo<S, 1>;
   __shared__ float ps[H1::N];
   const bool first = sc->first;
   const float beta = (float)sc->beta;
   const float zmu = (float)sc->zmu;
   int i0, j0, k0;
-  tile_origin(d, i0, j0, k0);
+  tile_origin<S>(d, i0, j0, k0);
   {
     constexpr int T = trips(H1::N);
     RegionCell cell[T];
     float zv[T], pv[T];
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<1>(d, i0, j0, k0, u);
+      cell[u] = region_cell<S, 1>(d, i0, j0, k0, u);
       const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
       zv[u] = z[c];
       pv[u] = first ? 0.0f : pold[c];
@@ -810,7 +824,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
       if (cell[u].ok) {
         p = first ? zv[u] - zmu : (zv[u] - zmu) + beta * pv[u];
         const int li = qq % H1::X, lj = (qq / H1::X) % H1::Y, lk = qq / (H1::X * H1::Y);
-        if (li >= 1 && li <= kTX && lj >= 1 && lj <= kTY && lk >= 1 && lk <= kTZ)
+        if (li >= 1 && li <= S::TX && lj >= 1 && lj <= S::TY && lk >= 1 && lk <= S::TZ)
           pnew[d.c(cell[u].i, cell[u].j, cell[u].k)] = p;
       }
       ps[qq] = p;
@@ -819,7 +833,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
   __syncthreads();
   double acc[1] = {0.0};
   {
-    constexpr int T = trips(kTX * kTY * kTZ);
+    constexpr int T = trips(S::TX * S::TY * S::TZ);
     bool ok[T];
     int cl[T];
     long cc[T];
@@ -827,7 +841,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
 #pragma unroll
     for (int u = 0; u < T; ++u) {
       const int qq = threadIdx.x + u * kTileThreads;
-      const int li = qq % kTX, lj = (qq / kTX) % kTY, lk = qq / (kTX * kTY);
+      const int li = qq % S::TX, lj = (qq / S::TX) % S::TY, lk = qq / (S::TX * S::TY);
       int i = i0 + li, j = j0 + lj, k = k0 + lk;
       ok[u] = in_dom(d, i, j, k);
       if (!ok[u]) i = j = k = 0;
@@ -1092,18 +1106,18 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
     return;
   }
   if (S.fused) {
-    auto tiles = [](const Dims& d) {
-      return (unsigned)(((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ));
+    auto tiles = [](const Dims& d, bool fine) {
+      return (unsigned)(fine ? tiles_of<FineTile>(d) : tiles_of<CoarseTile>(d));
     };
     for (int l = 0; l < G; ++l) {
       const Dims& d = S.lev[l].d;
       const Dims& cd = S.lev[l + 1].d;
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
-        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<T, float, float, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st,
+        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles(d, true)), dim3(kTileThreads), 0, st,
                   d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1);
       } else {
-        hipLaunchKernelGGL((k_mg_down<T, T, T, T>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
+        hipLaunchKernelGGL((k_mg_down<CoarseTile, T, T, T, T, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
                            ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0);
       }
     }
@@ -1114,11 +1128,11 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       const Dims& cd = S.lev[l + 1].d;
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
-        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<T, float, float, T, float, true>), dim3(tiles(d)), dim3(kTileThreads),
+        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles(d, true)), dim3(kTileThreads),
                   0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc, S.partials);
-        hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d), S.partials, sc, S.project);
+        hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d, true), S.partials, sc, S.project);
       } else {
-        hipLaunchKernelGGL((k_mg_up<T, T, T, T, T, false>), dim3(tiles(d)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
+        hipLaunchKernelGGL((k_mg_up<CoarseTile, T, T, T, T, T, false, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
                            Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
                            S.partials);
       }
@@ -1262,8 +1276,8 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     float* pnew = S.pcur ? S.p0 : S.p1;
     const int nb = (int)nblocks(n);
     if (S.fused) {
-      const int nt = (int)(((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ));
-      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay,
+      const int nt = tiles_of<FineTile>(d);
+      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile<FineTile>, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay,
                 S.az, S.z, pold, pnew, S.q, S.sc, S.partials);
       hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nt, S.partials, S.sc);
     } else {
