@@ -308,7 +308,7 @@ static int32_t project_common(sim_handle h, const float* uhat, const GeomParams&
   NF_TIMED(&h->prof, SIM_K_RHS, stream, launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream));
   float* P = p_out ? p_out : h->P;
   launch_fill(P, h->dom.d.cells(), 0.0f, stream);
-  int r = solver_solve(h->S, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
+  int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
   if (r != SIM_OK) return r;
   NF_TIMED(&h->prof, SIM_K_UPDATE, stream, launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream));
   return last_hip_error();
@@ -354,14 +354,14 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
     // no stored pressure: solve the forward system again
     launch_rhs(h->dom, g, 1.0 / kk, h->alpha, h->uhat, h->b, stream);
     launch_fill(h->P, h->dom.d.cells(), 0.0f, stream);
-    int r = solver_solve(h->S, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream);
+    int r = solver_solve(h->S, kSolvePressure, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream);
     if (r != SIM_OK) return r;
     P = h->P;
   }
   // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T S g
   NF_TIMED(&h->prof, SIM_K_ADJ_DIV, stream, launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream));
   launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
-  int r = solver_solve(h->S, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
+  int r = solver_solve(h->S, kSolveAdjoint, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
   if (r != SIM_OK) return r;
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
@@ -382,7 +382,7 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
     solver_setup_levels(h->S, h->alpha, stream);
     h->have_geom = true;
   }
-  int r = solver_solve(h->S, b, x, tol > 0 ? tol : h->desc.tol, max_iter > 0 ? max_iter : h->desc.max_iter, st,
+  int r = solver_solve(h->S, kSolveUser, b, x, tol > 0 ? tol : h->desc.tol, max_iter > 0 ? max_iter : h->desc.max_iter, st,
                        stream);
   if (r != SIM_OK) return r;
   return last_hip_error();

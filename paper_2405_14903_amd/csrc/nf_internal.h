@@ -82,7 +82,7 @@ struct CGScalars {
   int maxit;
   int converged;     // true residual reached the tolerance
   int allow;         // a true residual that misses tol may restart CG
-  int pad2;
+  int checks;        // number of true-residual checks that ran in this solve
 };
 
 // ---------------------------------------------------------------------------

@@ -81,7 +81,9 @@ struct Solver {
   int precision = SIM_FP32;
   int check_every = 2;
   int pcur = 0;        // which of p0 / p1 holds the current direction
-  int last_iters = 0;  // iterations of the previous solve (sizes the first batch)
+  // iterations of the previous solve of each kind (sizes the first batch of
+  // iterations): pressure of a step, adjoint pressure, caller's Poisson solve
+  int last_iters[3] = {0, 0, 0};
   int trace = 0;       // print each convergence snapshot to stderr (NF_TRACE_SOLVER=1)
   size_t lds_bytes = 65536;  // dynamic LDS the one-workgroup bottom solve may use
   // No Dirichlet side: the operator's null space holds the constants, and the
@@ -141,7 +143,9 @@ void launch_loss_box(const Domain& D, const double* lo, const double* hi, const 
                      double* partials, hipStream_t s);
 // nf_solver.hip
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st);
-int solver_solve(Solver& S, const float* b, float* x, double tol, int maxit, sim_stats* stats, hipStream_t st);
+enum SolveKind { kSolvePressure = 0, kSolveAdjoint = 1, kSolveUser = 2 };
+int solver_solve(Solver& S, SolveKind kind, const float* b, float* x, double tol, int maxit, sim_stats* stats,
+                 hipStream_t st);
 void solver_init_device(Solver& S);
 void solver_release(Solver& S);
 

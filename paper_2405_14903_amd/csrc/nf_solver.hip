@@ -183,6 +183,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* pa
     sc->true_rr = tot[1];
     sc->tol2bb = tol * tol * tot[0];
     sc->iters = 0;
+    sc->checks = 0;
     sc->first = 1;
     sc->maxit = maxit;
     sc->nonfinite = !isfinite(tot[1]);
@@ -271,8 +272,11 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_rr(int nb, const double* part
   }
 }
 
-// True residual from the FP64 iterate.  With `allow`, a residual that misses
-// the tolerance replaces r and CG restarts (k_fin_true sets done = 0, first = 1).
+// True residual from the FP64 iterate, once the recursive residual has
+// converged (both kernels do nothing while CG is still iterating, so the check
+// can be enqueued behind every batch of iterations).  With `allow`, a residual
+// that misses the tolerance replaces r and CG restarts (k_fin_true sets
+// done = 0, first = 1).
 __device__ inline bool may_replace(const CGScalars* sc, int allow) {
   return allow && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
 }
@@ -283,6 +287,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
                                                               const float* __restrict__ b,
                                                               const double* __restrict__ x, float* __restrict__ r,
                                                               int allow, const CGScalars* sc, double* partials) {
+  if (!sc->done) return;
   const bool rep = may_replace(sc, allow);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
@@ -301,10 +306,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* partials, CGScalars* sc, int allow,
                                                          long ncells, int project) {
+  if (!sc->done) return;
   const bool rep = may_replace(sc, allow);
   double tot[3];
   finish_partials<3>(partials, nb, tot);
   if (threadIdx.x == 0) {
+    sc->checks += 1;
     tot[0] = projected_rr(tot[0], tot[1], tot[2], project);
     sc->mu = project && tot[2] > 0.0 ? tot[1] / tot[2] : 0.0;
     sc->true_rr = tot[0];
@@ -1366,7 +1373,8 @@ static int snapshot(Solver& S, hipStream_t st) {
   return SIM_OK;
 }
 
-int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, sim_stats* stats, hipStream_t st) {
+int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double tol, int maxit, sim_stats* stats,
+                 hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
   CGScalars* sc = S.sc;
@@ -1380,43 +1388,39 @@ int solver_solve(Solver& S, const float* b, float* xio, double tol, int maxit, s
     hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
   vcycle_dispatch(S, S.r, S.z, st);
   S.pcur = 0;
-  // First batch sized from the previous solve of this handle, then small
-  // batches.  Every pass of the loop either runs iterations on the device or
-  // uses up one of a bounded number of restarts, so the loop terminates.
+  // Each round enqueues a batch of iterations and the (conditional) true-
+  // residual check behind it, then synchronises once.  The first batch is
+  // sized from the previous solve of this handle, so a typical solve needs a
+  // single round; iterations enqueued after convergence exit at once on the
+  // device.  Every round runs iterations or uses up one of a bounded number of
+  // restarts, and the round count is capped, so the loop terminates.
   const int kMaxRestarts = 8;
-  int batch = S.last_iters > 1 ? S.last_iters - 1 : 2;
+  int batch = S.last_iters[kind] > 0 ? S.last_iters[kind] : 2;
   const int chunk = S.check_every > 0 ? S.check_every : 2;
-  int restarts = 0;
-  int r = snapshot(S, st);
-  if (r != SIM_OK) return r;
+  int restarts = 0, checks_seen = 0, rounds = 0;
   for (;;) {
-    const int it_dev = S.host_sc->iters;
-    const int cnt = S.host_sc->done ? 0 : (batch < maxit - it_dev ? batch : maxit - it_dev);
-    if (cnt > 0) {
-      (void)cg_iterations(S, x, cnt, st);
-      r = snapshot(S, st);
-      if (r != SIM_OK) return r;
-    }
+    const int allow = restarts < kMaxRestarts ? 1 : 0;
+    (void)cg_iterations(S, x, batch, st);
+    NF_LAUNCH(S.prof, SIM_K_CG_TRUE, k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay,
+              S.az, b, x, S.r, allow, sc, S.partials);
+    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n,
+                       S.project);
+    int r = snapshot(S, st);
+    if (r != SIM_OK) return r;
     batch = chunk;
     const CGScalars& h = *S.host_sc;
     if (h.nonfinite) break;
-    if (h.done || h.iters >= maxit || cnt <= 0) {
-      // true residual from the FP64 iterate; restart from it if needed
-      const int allow = restarts < kMaxRestarts && h.iters < maxit ? 1 : 0;
-      NF_LAUNCH(S.prof, SIM_K_CG_TRUE, k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b,
-                                  x, S.r, allow, sc, S.partials);
-      hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n,
-                         S.project);
-      r = snapshot(S, st);
-      if (r != SIM_OK) return r;
-      if (S.host_sc->converged || S.host_sc->nonfinite || !allow) break;
-      ++restarts;
-      if (S.project)
-        hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
-      vcycle_dispatch(S, S.r, S.z, st);
-    }
+    if (++rounds > maxit + 2 * kMaxRestarts + 8) break;
+    if (h.checks == checks_seen) continue;   // still iterating
+    checks_seen = h.checks;
+    if (h.converged || !allow || h.iters >= maxit || h.done) break;
+    // the check restarted CG from the true residual
+    ++restarts;
+    if (S.project)
+      hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
+    vcycle_dispatch(S, S.r, S.z, st);
   }
-  S.last_iters = S.host_sc->iters;
+  S.last_iters[kind] = S.host_sc->iters;
   hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
   if (stats) {
     const CGScalars& h = *S.host_sc;
