@@ -900,14 +900,16 @@ template <typename P>
 __device__ inline void bottom_down(const Dims& d, const Dims& cd, const Coef<P>& K, const float* r, float* z, float* t,
                                    float* rc) {
   const int n = (int)d.cells(), T = blockDim.x;
-  for (int c = threadIdx.x; c < n; c += T) t[c] = kOmega * ld(K.invd, c) * r[c];
-  __syncthreads();
+  // the first sweep from 0 (t = w D^-1 r) is formed on the fly at each cell
+  // and its neighbours, so the two sweeps need one barrier
+  auto t1 = [&](long q) { return kOmega * ld(K.invd, q) * r[q]; };
   for (int c = threadIdx.x; c < n; c += T) {
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
-    float Az = apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; });
-    z[c] = t[c] + kOmega * ld(K.invd, c) * (r[c] - Az);
+    const float tc = t1(c);
+    float Az = apply_A(d, fw, i, j, k, c, tc, t1);
+    z[c] = tc + kOmega * ld(K.invd, c) * (r[c] - Az);
   }
   __syncthreads();
   for (int C = threadIdx.x; C < (int)cd.cells(); C += T) {
@@ -936,7 +938,38 @@ __device__ inline void bottom_coarsest(const Dims& d, const Coef<P>& K, const fl
   for (int c = threadIdx.x; c < n; c += T) z[c] = 0.0f;
   __syncthreads();
   float *src = z, *dst = t;
-  if (n <= T) {
+  if (n <= 64) {
+    // one wavefront does all the sweeps: LDS operations of one wavefront are
+    // performed in order, so only the compiler needs a barrier between sweeps
+    if (threadIdx.x < 64) {
+      const int c = threadIdx.x;
+      const bool on = c < n;
+      int i = 0, j = 0, k = 0;
+      if (on) cdec(d, c, i, j, k);
+      Faces<P> fw(d, K.ax, K.ay, K.az, on ? i : 0, on ? j : 0, on ? k : 0);
+      const float idc = on ? ld(K.invd, c) : 0.0f;
+      const float rc = on ? r[c] : 0.0f;
+      for (int s = 0; s < sweeps; ++s) {
+        if (on) {
+          const float* sp = src;
+          float Az = apply_A(d, fw, i, j, k, c, sp[c], [&](long q) { return sp[q]; });
+          dst[c] = sp[c] + kOmega * idc * (rc - Az);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        float* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+    } else {
+      if (sweeps & 1) {
+        float* tmp = src;
+        src = dst;
+        dst = tmp;
+      }
+    }
+    __syncthreads();
+  } else if (n <= T) {
     const int c = threadIdx.x;
     const bool on = c < n;
     int i = 0, j = 0, k = 0;
