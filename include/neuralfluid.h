@@ -120,7 +120,10 @@ int32_t sim_footprint(const sim_desc* desc, size_t* bytes);
 
 /* Allocate all workspace for desc on the current HIP device.  Grid sizes must
  * coarsen by halving to a level of at most 4096 cells (e.g. multiples of 16).
- * nu != 0 or PERIODIC sides return SIM_EUNSUPPORTED. */
+ * nu != 0 or PERIODIC sides return SIM_EUNSUPPORTED.  Workspace is left
+ * unset; with the environment variable NF_POISON_BUFFERS=1 every buffer is
+ * filled with all-ones bytes (NaN in every float format) instead, which makes
+ * a read of a value no kernel wrote visible (a testing aid). */
 int32_t sim_create(const sim_desc* desc, sim_handle* out);
 int32_t sim_destroy(sim_handle h);
 

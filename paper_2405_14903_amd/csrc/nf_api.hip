@@ -4,6 +4,7 @@
 // Back-propagation through Time: projection first, then advection), plus the
 // host-side rigid pose dynamics used to drive the ellipsoid.
 #include "nf_solver.h"
+#include "nf_tile.h"
 
 #include <cmath>
 #include <cstdlib>
@@ -238,6 +239,8 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
     const char* fu = std::getenv("NF_MG_FUSED");
     c->S.fused = !(fu && fu[0] == '0');
   }
+  // the fused tile kernels need 31-bit byte offsets over a tile's region
+  if (!views_fit(p.dims[0].nx, p.dims[0].ny)) c->S.fused = 0;
   c->S.precision = desc->precision;
   for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
   solver_init_device(c->S);
@@ -252,6 +255,10 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   }
   while (c->S.nbottom > 0 && p.dims[c->S.nbottom - 1].cells() <= bottom_cells) --c->S.nbottom;
   bool ok = true;
+  // NF_POISON_BUFFERS=1 fills every buffer with all-ones bytes (NaN in every
+  // float format) so that a read of a value no kernel wrote shows up
+  const char* pz = std::getenv("NF_POISON_BUFFERS");
+  const bool poison = pz && pz[0] == '1';
   for_each_buffer(desc, p, c, [&](size_t b, void** ptr) {
     if (!ok) return;
     void* q = nullptr;
@@ -261,7 +268,9 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
     }
     c->allocs.push_back(q);
     *ptr = q;
+    if (poison && hipMemset(q, 0xff, align256(b)) != hipSuccess) ok = false;
   });
+  if (ok && poison && hipDeviceSynchronize() != hipSuccess) ok = false;
   if (ok && hipHostMalloc((void**)&c->S.host_sc, sizeof(CGScalars), hipHostMallocDefault) != hipSuccess) ok = false;
   if (ok && hipMemset(c->S.sc, 0, sizeof(CGScalars)) != hipSuccess) ok = false;
   if (!ok) {

@@ -30,6 +30,7 @@
 //     scaled back, which keeps FP16 values in range.
 #include "nf_internal.h"
 #include "nf_solver.h"
+#include "nf_tile.h"
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
@@ -517,48 +518,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
 //         residual mean(r - A z2) of the tile's coarse cells;
 //   up:   z' = z2 + 8 e(parent) on the tile + 2 cells, z3 = z' + w D^-1 (r - A z')
 //         on the tile + 1 cell, z4 = z3 + w D^-1 (r - A z3) on the tile.
-// Values beyond the domain are 0, as in apply_A.
+// Values beyond the domain are 0, as in apply_A.  Tile shapes, region walks
+// and the buffer addressing are described in nf_tile.h.
 // ---------------------------------------------------------------------------
-
-// Tile shapes: the finest level uses long x rows (efficient halo reuse), the
-// coarse levels small cubes (their launches are latency-bound: less serial
-// work per thread and more workgroups).
-template <int TX_, int TY_, int TZ_>
-struct TileShape {
-  static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
-};
-using FineTile = TileShape<32, 8, 8>;
-using CoarseTile = TileShape<8, 8, 8>;
-constexpr int kTileThreads = 512;   // 8 waves per tile: more loads in flight per CU
-// Loops over a region have a compile-time trip count, so they unroll fully
-// and every thread issues all of its loads before the first one is used.
-constexpr int trips(int n) { return (n + kTileThreads - 1) / kTileThreads; }
-template <class S, int H>
-struct Halo {
-  static constexpr int X = S::TX + 2 * H, Y = S::TY + 2 * H, Z = S::TZ + 2 * H, N = X * Y * Z;
-};
 
 template <class S>
 __host__ __device__ inline int tiles_of(const Dims& d) {
-  return ((d.nx + S::TX - 1) / S::TX) * ((d.ny + S::TY - 1) / S::TY) * ((d.nz + S::TZ - 1) / S::TZ);
+  return tiles_x<S>(d.nx) * tiles_y<S>(d.ny) * tiles_z<S>(d.nz);
 }
 
 template <class S>
 __device__ inline void tile_origin(const Dims& d, int& i0, int& j0, int& k0) {
-  const int tx = (d.nx + S::TX - 1) / S::TX, ty = (d.ny + S::TY - 1) / S::TY;
-  const int b = xcd_block(blockIdx.x, gridDim.x);
-  i0 = (b % tx) * S::TX;
-  j0 = ((b / tx) % ty) * S::TY;
-  k0 = (b / (tx * ty)) * S::TZ;
-}
-
-__device__ inline bool in_dom(const Dims& d, int i, int j, int k) {
-  return i >= 0 && j >= 0 && k >= 0 && i < d.nx && j < d.ny && k < d.nz;
+  tile_origin_of<S>(xcd_block(blockIdx.x, gridDim.x), d.nx, d.ny, i0, j0, k0);
 }
 
 // sum over the 6 faces of w_f (v[q] - v[nb]) for a cell at local index q of a
-// halo region with row length X and plane size XY (neighbours beyond the
-// domain hold 0 in v, the Dirichlet / closed convention of apply_A)
+// region with row length X and plane size XY (neighbours beyond the domain
+// hold 0 in v, the Dirichlet / closed convention of apply_A)
 template <typename A>
 __device__ inline float apply_local(const Faces<A>& fw, const float* v, int q, int X, int XY) {
   const float c = v[q];
@@ -571,224 +547,395 @@ __device__ inline float apply_local(const Faces<A>& fw, const float* v, int q, i
   return s;
 }
 
-// Each phase first issues every load of the thread's cells (out-of-domain
-// cells load element 0, which always exists, and are masked afterwards), then
-// computes: a thread keeps all its loads in flight at once.
-struct RegionCell {
-  int q, i, j, k;
-  bool ok;   // q inside the region and (i, j, k) inside the domain
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+// Waves per SIMD the tile kernels are compiled for: 8 (at most 64 VGPRs) lets
+// four 512-thread tiles share a compute unit, so a 128^3 level's 1024 finest
+// tiles run in one round on 256 compute units.
+constexpr int kTileWaves = 8;
+
+// Buffer view of an array whose base is the element (i, j, k) of a grid with
+// the given row / plane lengths (elements); the base may precede the array,
+// only the elements a kernel addresses must exist.
+template <typename T>
+__device__ inline Rsrc view(const T* p, int row, int plane, int i, int j, int k) {
+  const long e = (long)i + (long)row * j + (long)plane * k;
+  const uintptr_t a = (uintptr_t)p + (uintptr_t)(e * (long)sizeof(T));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)a, (short)0, kViewRecords, 0x00020000);
+}
+
+template <typename T> __device__ inline float vld(Rsrc r, unsigned v, unsigned s);
+template <> __device__ inline float vld<float>(Rsrc r, unsigned v, unsigned s) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0));
+}
+template <> __device__ inline float vld<__half>(Rsrc r, unsigned v, unsigned s) {
+  return __half2float(__builtin_bit_cast(__half, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0)));
+}
+template <> __device__ inline float vld<__hip_bfloat16>(Rsrc r, unsigned v, unsigned s) {
+  return __bfloat162float(
+      __builtin_bit_cast(__hip_bfloat16, __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0)));
+}
+template <typename T> __device__ inline void vst(Rsrc r, unsigned v, unsigned s, float x);
+template <> __device__ inline void vst<float>(Rsrc r, unsigned v, unsigned s, float x) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, x), r, (int)v, (int)s, 0);
+}
+template <> __device__ inline void vst<__half>(Rsrc r, unsigned v, unsigned s, float x) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2half(x)), r, (int)v, (int)s, 0);
+}
+template <> __device__ inline void vst<__hip_bfloat16>(Rsrc r, unsigned v, unsigned s, float x) {
+  __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, __float2bfloat16(x)), r, (int)v, (int)s,
+                                        0);
+}
+
+// v rounded to the storage type T (what a later read of a stored v returns)
+template <typename T>
+__device__ inline float rnd(float v) {
+  const T x = cvt<T>(v);
+  return ld(&x, 0);
+}
+
+// Byte offset of one access: lane part v and a part s uniform over the wave.
+// When the plane index varies across the wave (U false) the plane part joins
+// the lane part.
+struct At {
+  unsigned v, s;
 };
+template <bool U>
+__device__ inline At at(unsigned lane, unsigned plane) {
+  return U ? At{lane, plane} : At{lane + plane, 0u};
+}
 
+// Extents and plane lengths (elements) of one level's arrays.
+struct Lev {
+  int nx, ny, nz;
+  int pc;   // cells (and z faces) per plane
+  int px;   // x faces per plane
+  int py;   // y faces per plane
+};
+__device__ inline Lev level_of(const Dims& d) {
+  Lev L;
+  L.nx = d.nx;
+  L.ny = d.ny;
+  L.nz = d.nz;
+  L.pc = d.nx * d.ny;
+  L.px = (d.nx + 1) * d.ny;
+  L.py = d.nx * (d.ny + 1);
+  return L;
+}
+
+// Plane group of lane t in the +H walk (uniform over the wave where the walk
+// allows it, so plane offsets stay scalar).
 template <class S, int H>
-__device__ inline RegionCell region_cell(const Dims& d, int i0, int j0, int k0, int u) {
-  using R = Halo<S, H>;
-  RegionCell rc;
-  rc.q = threadIdx.x + u * kTileThreads;
-  const int q = rc.q < R::N ? rc.q : 0;
-  const int li = q % R::X, lj = (q / R::X) % R::Y, lk = q / (R::X * R::Y);
-  rc.i = i0 + li - H;
-  rc.j = j0 + lj - H;
-  rc.k = k0 + lk - H;
-  rc.ok = rc.q < R::N && in_dom(d, rc.i, rc.j, rc.k);
-  if (!rc.ok) rc.i = rc.j = rc.k = 0;
-  return rc;
+__device__ inline int walk_group(int t) {
+  using W = Walk<S, H>;
+  if constexpr (W::P == 1) return 0;
+  else if constexpr (W::kUniform) return uniform_value(t / W::PL);
+  else return t / W::PL;
 }
 
-// local index in the +2 region of a cell at local index q of the +1 region
-template <class S>
-__device__ inline int up1to2(int q) {
-  using H1 = Halo<S, 1>;
-  using H2 = Halo<S, 2>;
-  const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
-  return (li + 1) + H2::X * ((lj + 1) + H2::Y * (lk + 1));
+// A lane's byte offset for trip u: kNoCell when the trip's plane lies outside
+// the domain (ZIN: the tile's whole +2 region is inside).
+template <bool ZIN>
+__device__ inline unsigned on_plane(unsigned lane, unsigned mask, int u) {
+  return (ZIN || ((mask >> u) & 1u)) ? lane : kNoCell;
 }
 
-// PRE: issue the loads of all three phases before the first one computes (one
-// memory latency per launch instead of three; for the small coarse levels,
-// whose launches are latency-bound and few tiles wide).  Without PRE each
-// phase loads what it needs, which keeps registers low for the finest level.
-template <class S, typename A, typename R, typename Z, typename RC, bool PRE>
-__global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
-                                                          const A* __restrict__ ay, const A* __restrict__ az,
-                                                          const A* __restrict__ invd, const R* __restrict__ r,
-                                                          Z* __restrict__ z2out, RC* __restrict__ rc,
-                                                          const CGScalars* sc, int lvl0) {
-  if (sc->done) return;
-  using H2 = Halo<S, 2>;
-  using H1 = Halo<S, 1>;
-  __shared__ float z1s[H2::N];
-  __shared__ float rs[H1::N];
-  __shared__ float z2s[H1::N];
-  const float s0 = level_scale(sc, lvl0);
-  int i0, j0, k0;
-  tile_origin<S>(d, i0, j0, k0);
-  constexpr int T1 = trips(H2::N), T2 = trips(H1::N);
-  RegionCell c1[T1], c2[T2];
-  float id1[T1], rv1[T1], id2[T2], rv2[T2];
-  Faces<A> fw2[T2], fw3[8];
-  // restriction: the tile's (S::TX/2) x (S::TY/2) x (S::TZ/2) coarse cells, one per thread
+// Face views of a level at a tile (base: corner of the +2 region).
+struct FaceViews {
+  Rsrc ax, ay, az;
+};
+template <typename A>
+__device__ inline FaceViews face_views(const A* ax, const A* ay, const A* az, const Lev& L, int i0, int j0, int k0) {
+  return {view(ax, L.nx + 1, L.px, i0 - 2, j0 - 2, k0 - 2), view(ay, L.nx, L.py, i0 - 2, j0 - 2, k0 - 2),
+          view(az, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2)};
+}
+
+// The 6 face weights of a cell in plane kr of the +2 frame, for lane offsets
+// fe (x-face frame) and ce (cell frame), in bytes: x faces at fx, fx + 1;
+// y faces at fy, fy + nx; z faces at fz, fz + nx ny.
+template <typename A, bool U>
+__device__ inline Faces<A> faces_at(const FaceViews& V, unsigned fe, unsigned ce, int kr, const Lev& L) {
+  constexpr unsigned es = sizeof(A);
+  const At x = at<U>(fe, (unsigned)(kr * L.px) * es);
+  const At y = at<U>(ce, (unsigned)(kr * L.py) * es);
+  const At z = at<U>(ce, (unsigned)(kr * L.pc) * es);
+  Faces<A> f;
+  f.w[0] = vld<A>(V.ax, x.v, x.s);
+  f.w[1] = vld<A>(V.ax, x.v + es, x.s);
+  f.w[2] = vld<A>(V.ay, y.v, y.s);
+  f.w[3] = vld<A>(V.ay, y.v, y.s + (unsigned)L.nx * es);
+  f.w[4] = vld<A>(V.az, z.v, z.s);
+  f.w[5] = vld<A>(V.az, z.v, z.s + (unsigned)L.pc * es);
+  return f;
+}
+
+// A cell-frame value of type T in plane kr (lane offset ce in bytes).
+template <typename T, bool U>
+__device__ inline float cell_at(Rsrc v, unsigned ce, int kr, const Lev& L) {
+  const At a = at<U>(ce, (unsigned)(kr * L.pc) * (unsigned)sizeof(T));
+  return vld<T>(v, a.v, a.s);
+}
+template <typename T, bool U>
+__device__ inline void cell_put(Rsrc v, unsigned ce, int kr, const Lev& L, float x) {
+  const At a = at<U>(ce, (unsigned)(kr * L.pc) * (unsigned)sizeof(T));
+  vst<T>(v, a.v, a.s, x);
+}
+
+// Body of k_mg_down for one tile; ZIN: the tile's +2 region lies inside the
+// domain along z (no plane checks).  PRE: issue the loads of all three phases
+// before the first one computes (one memory latency per launch instead of
+// three; for the small coarse levels, whose launches are latency-bound and few
+// tiles wide).  Without PRE each phase loads what it needs, which keeps
+// registers low for the finest level.
+template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN>
+__device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
+                                             const A* invd, const R* r, Z* z2out, RC* rc, float s0, int i0, int j0,
+                                             int k0, float* z1s, float* z2s) {
+  using W2 = Walk<S, 2>;
+  using W1 = Walk<S, 1>;
+  using W0 = Walk<S, 0>;
+  constexpr int eA = sizeof(A), eR = sizeof(R), eZ = sizeof(Z);
+  const Lev L = level_of(d);
   const int t = threadIdx.x;
-  const int ci = t % (S::TX / 2), cj = (t / (S::TX / 2)) % (S::TY / 2), ck = t / ((S::TX / 2) * (S::TY / 2));
-  const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
-  const bool rok = t < (S::TX / 2) * (S::TY / 2) * (S::TZ / 2) && I < cd.nx && J < cd.ny && K < cd.nz;
+  const FaceViews V = face_views(ax, ay, az, L, i0, j0, k0);
+  const Rsrc vid = view(invd, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vr = view(r, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vz = view(z2out, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Lane l2 = lane_of<S, 2>(t, walk_group<S, 2>(t), i0, j0, L.nx, L.ny);
+  const Lane l1 = lane_of<S, 1>(t, walk_group<S, 1>(t), i0, j0, L.nx, L.ny);
+  const Lane l0 = lane_of<S, 0>(t, walk_group<S, 0>(t), i0, j0, L.nx, L.ny);
+  const unsigned m2 = ZIN ? ~0u : plane_mask(k0, l2.z, L.nz, W2::T);
+  const unsigned m1 = ZIN ? ~0u : plane_mask(k0, l1.z, L.nz, W1::T);
+  const unsigned m0 = ZIN ? ~0u : plane_mask(k0, l0.z, L.nz, W0::T);
+  float id1[W2::T], rv1[W2::T], id2[W1::T], rv2[W1::T], rv3[W0::T];
+  Faces<A> fw2[W1::T], fw3[W0::T];
   auto load2 = [&]() {
+    const unsigned fe = lane_bytes(l1.in, l1.fe, eA), ce = lane_bytes(l1.in, l1.ce, eA),
+                   cr = lane_bytes(l1.in, l1.ce, eR);
 #pragma unroll
-    for (int u = 0; u < T2; ++u) {
-      c2[u] = region_cell<S, 1>(d, i0, j0, k0, u);
-      const long c = d.c(c2[u].i, c2[u].j, c2[u].k);
-      fw2[u] = Faces<A>(d, ax, ay, az, c2[u].i, c2[u].j, c2[u].k);
-      id2[u] = ld(invd, c);
-      rv2[u] = ld(r, c);
+    for (int u = 0; u < W1::T; ++u) {
+      const int kr = l1.z + u;
+      fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
+      id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      rv2[u] = cell_at<R, W1::kUniform>(vr, on_plane<ZIN>(cr, m1, u), kr, L);
     }
   };
   auto load3 = [&]() {
+    const unsigned fe = lane_bytes(l0.in, l0.fe, eA), ce = lane_bytes(l0.in, l0.ce, eA),
+                   cr = lane_bytes(l0.in, l0.ce, eR);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int i = rok ? 2 * I + (b & 1) : 0, j = rok ? 2 * J + ((b >> 1) & 1) : 0, k = rok ? 2 * K + (b >> 2) : 0;
-      fw3[b] = Faces<A>(d, ax, ay, az, i, j, k);
+    for (int u = 0; u < W0::T; ++u) {
+      fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), l0.z + u, L);
+      rv3[u] = cell_at<R, W0::kUniform>(vr, on_plane<ZIN>(cr, m0, u), l0.z + u, L);
     }
   };
+  {
+    const unsigned ce = lane_bytes(l2.in, l2.ce, eA), cr = lane_bytes(l2.in, l2.ce, eR);
 #pragma unroll
-  for (int u = 0; u < T1; ++u) {
-    c1[u] = region_cell<S, 2>(d, i0, j0, k0, u);
-    const long c = d.c(c1[u].i, c1[u].j, c1[u].k);
-    id1[u] = ld(invd, c);
-    rv1[u] = ld(r, c);
+    for (int u = 0; u < W2::T; ++u) {
+      id1[u] = cell_at<A, W2::kUniform>(vid, on_plane<ZIN>(ce, m2, u), l2.z + u, L);
+      rv1[u] = cell_at<R, W2::kUniform>(vr, on_plane<ZIN>(cr, m2, u), l2.z + u, L);
+    }
   }
   if (PRE) {
     load2();
     load3();
   }
+  if (l2.on) {
 #pragma unroll
-  for (int u = 0; u < T1; ++u)
-    if (c1[u].q < H2::N) z1s[c1[u].q] = c1[u].ok ? kOmega * id1[u] * (s0 * rv1[u]) : 0.0f;
+    for (int u = 0; u < W2::T; ++u) z1s[l2.q + u * W2::PL] = kOmega * id1[u] * (s0 * rv1[u]);
+  }
   __syncthreads();
   if (!PRE) load2();
+  if (l1.on) {
+    // the tile's own cells of the +1 walk are stored for the way up
+    const bool own_xy = l1.x >= 2 && l1.x < S::TX + 2 && l1.y >= 2 && l1.y < S::TY + 2;
+    const unsigned oz = own_xy ? lane_bytes(l1.in, l1.ce, eZ) : kNoCell;
+    const int q2 = l1.x + W2::X * l1.y + W2::PL * l1.z;
 #pragma unroll
-  for (int u = 0; u < T2; ++u) {
-    const int q = c2[u].q;
-    if (q >= H1::N) continue;
-    float z2 = 0.0f, rr = 0.0f;
-    if (c2[u].ok) {
-      const int q2 = up1to2<S>(q);
-      rr = s0 * rv2[u];
-      const Z zs = cvt<Z>(z1s[q2] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, q2, H2::X, H2::X * H2::Y)));
-      z2 = ld(&zs, 0);
-      const int li = q % H1::X, lj = (q / H1::X) % H1::Y, lk = q / (H1::X * H1::Y);
-      if (li >= 1 && li <= S::TX && lj >= 1 && lj <= S::TY && lk >= 1 && lk <= S::TZ)
-        z2out[d.c(c2[u].i, c2[u].j, c2[u].k)] = zs;
+    for (int u = 0; u < W1::T; ++u) {
+      const int z = l1.z + u;
+      const int qq = q2 + u * W2::PL;
+      const float rr = s0 * rv2[u];
+      const float z2 = rnd<Z>(z1s[qq] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)));
+      cell_put<Z, W1::kUniform>(vz, (z >= 2 && z < S::TZ + 2) ? on_plane<ZIN>(oz, m1, u) : kNoCell, z, L, z2);
+      z2s[l1.q + u * W1::PL] = z2;
     }
-    z2s[q] = z2;
-    rs[q] = rr;
   }
   __syncthreads();
   if (!PRE) load3();
-  if (rok) {
-    float s = 0.0f;
+  if (l0.on) {
+    // residual r - A z2 of the tile's cells (into the first sweep's array)
+    const int q1 = (l0.x - 1) + W1::X * (l0.y - 1) + W1::PL * (l0.z - 1);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
-      const int q1 = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-      s += rs[q1] - apply_local(fw3[b], z2s, q1, H1::X, H1::X * H1::Y);
+    for (int u = 0; u < W0::T; ++u) {
+      const int qq = q1 + u * W1::PL;
+      z1s[l0.q + u * W0::PL] = s0 * rv3[u] - apply_local(fw3[u], z2s, qq, W1::X, W1::PL);
     }
-    rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
+  }
+  __syncthreads();
+  // restriction: the tile's (TX/2) x (TY/2) x (TZ/2) coarse cells, one per
+  // thread, each the mean of its 8 children (all inside the level: levels
+  // are coarsened only while every extent is even)
+  constexpr int CX = S::TX / 2, CY = S::TY / 2, CZ = S::TZ / 2;
+  if (t < CX * CY * CZ) {
+    const int ci = t % CX, cj = (t / CX) % CY, ck = t / (CX * CY);
+    const int I = i0 / 2 + ci, J = j0 / 2 + cj, K = k0 / 2 + ck;
+    if (I < cd.nx && J < cd.ny && K < cd.nz) {
+      float s = 0.0f;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) {
+        const int li = 2 * ci + (b & 1), lj = 2 * cj + ((b >> 1) & 1), lk = 2 * ck + (b >> 2);
+        s += z1s[li + S::TX * (lj + S::TY * lk)];
+      }
+      rc[cd.c(I, J, K)] = cvt<RC>(0.125f * s);
+    }
+  }
+}
+
+template <class S, typename A, typename R, typename Z, typename RC, bool PRE>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kTileWaves))) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
+                                                          const A* __restrict__ ay, const A* __restrict__ az,
+                                                          const A* __restrict__ invd, const R* __restrict__ r,
+                                                          Z* __restrict__ z2out, RC* __restrict__ rc,
+                                                          const CGScalars* sc, int lvl0) {
+  static_assert(Walk<S, 0>::N <= Walk<S, 2>::N, "the tile residual reuses the first sweep's array");
+  __shared__ float z1s[Walk<S, 2>::N];   // first sweep on the +2 region; then the tile's residual
+  __shared__ float z2s[Walk<S, 1>::N];
+  if (sc->done) return;
+  const float s0 = level_scale(sc, lvl0);
+  int i0, j0, k0;
+  tile_origin<S>(d, i0, j0, k0);
+  if (planes_inside<S>(k0, d.nz))
+    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
+  else
+    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
+}
+
+// Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool ZIN>
+__device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
+                                           const A* invd, const R* r, const Z* z2, const E* e, O* zout, float s0,
+                                           float inv, bool first, int i0, int j0, int k0, float* zp, float* z3s,
+                                           double (&acc)[4]) {
+  using W2 = Walk<S, 2>;
+  using W1 = Walk<S, 1>;
+  using W0 = Walk<S, 0>;
+  constexpr int eA = sizeof(A), eR = sizeof(R), eZ = sizeof(Z), eE = sizeof(E), eO = sizeof(O);
+  const Lev L = level_of(d);
+  const int t = threadIdx.x;
+  const FaceViews V = face_views(ax, ay, az, L, i0, j0, k0);
+  const Rsrc vid = view(invd, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vr = view(r, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vz2 = view(z2, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vzo = view(zout, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const int cpc = cd.nx * cd.ny;
+  // parent view base: the parent of the +2 corner (tile origins are even)
+  const Rsrc ve = view(e, cd.nx, cpc, (i0 - 2) / 2, (j0 - 2) / 2, (k0 - 2) / 2);
+  const Lane l2 = lane_of<S, 2>(t, walk_group<S, 2>(t), i0, j0, L.nx, L.ny);
+  const Lane l1 = lane_of<S, 1>(t, walk_group<S, 1>(t), i0, j0, L.nx, L.ny);
+  const Lane l0 = lane_of<S, 0>(t, walk_group<S, 0>(t), i0, j0, L.nx, L.ny);
+  const unsigned m2 = ZIN ? ~0u : plane_mask(k0, l2.z, L.nz, W2::T);
+  const unsigned m1 = ZIN ? ~0u : plane_mask(k0, l1.z, L.nz, W1::T);
+  const unsigned m0 = ZIN ? ~0u : plane_mask(k0, l0.z, L.nz, W0::T);
+  float zv[W2::T], ev[W2::T], id2[W1::T], rv2[W1::T], id3[W0::T], rv3[W0::T], zold[W0::T];
+  Faces<A> fw2[W1::T], fw3[W0::T];
+  auto load2 = [&]() {
+    const unsigned fe = lane_bytes(l1.in, l1.fe, eA), ce = lane_bytes(l1.in, l1.ce, eA),
+                   cr = lane_bytes(l1.in, l1.ce, eR);
+#pragma unroll
+    for (int u = 0; u < W1::T; ++u) {
+      const int kr = l1.z + u;
+      fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
+      id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      rv2[u] = cell_at<R, W1::kUniform>(vr, on_plane<ZIN>(cr, m1, u), kr, L);
+    }
+  };
+  auto load3 = [&]() {
+    const unsigned fe = lane_bytes(l0.in, l0.fe, eA), ce = lane_bytes(l0.in, l0.ce, eA),
+                   cr = lane_bytes(l0.in, l0.ce, eR), co = lane_bytes(l0.in, l0.ce, eO);
+#pragma unroll
+    for (int u = 0; u < W0::T; ++u) {
+      const int kr = l0.z + u;
+      fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), kr, L);
+      id3[u] = cell_at<A, W0::kUniform>(vid, on_plane<ZIN>(ce, m0, u), kr, L);
+      rv3[u] = cell_at<R, W0::kUniform>(vr, on_plane<ZIN>(cr, m0, u), kr, L);
+      zold[u] = (LVL0 && !first) ? cell_at<O, W0::kUniform>(vzo, on_plane<ZIN>(co, m0, u), kr, L) : 0.0f;
+    }
+  };
+  {
+    const unsigned cz = lane_bytes(l2.in, l2.ce, eZ);
+    // the lane's parent column in the parent view's frame
+    const unsigned le = lane_bytes(l2.in, (l2.x >> 1) + cd.nx * (l2.y >> 1), eE);
+#pragma unroll
+    for (int u = 0; u < W2::T; ++u) {
+      const int kr = l2.z + u;
+      zv[u] = cell_at<Z, W2::kUniform>(vz2, on_plane<ZIN>(cz, m2, u), kr, L);
+      const At a = at<W2::kUniform>(on_plane<ZIN>(le, m2, u), (unsigned)((kr >> 1) * cpc) * (unsigned)eE);
+      ev[u] = vld<E>(ve, a.v, a.s);
+    }
+  }
+  if (PRE) {
+    load2();
+    load3();
+  }
+  if (l2.on) {
+#pragma unroll
+    for (int u = 0; u < W2::T; ++u) zp[l2.q + u * W2::PL] = zv[u] + 8.0f * ev[u];
+  }
+  __syncthreads();
+  if (!PRE) load2();
+  if (l1.on) {
+    const int q2 = l1.x + W2::X * l1.y + W2::PL * l1.z;
+#pragma unroll
+    for (int u = 0; u < W1::T; ++u) {
+      const int qq = q2 + u * W2::PL;
+      z3s[l1.q + u * W1::PL] =
+          zp[qq] + kOmega * id2[u] * (s0 * rv2[u] - apply_local(fw2[u], zp, qq, W2::X, W2::PL));
+    }
+  }
+  __syncthreads();
+  if (!PRE) load3();
+  if (l0.on) {
+    const int q1 = (l0.x - 1) + W1::X * (l0.y - 1) + W1::PL * (l0.z - 1);
+    const unsigned co = lane_bytes(l0.in, l0.ce, eO);
+#pragma unroll
+    for (int u = 0; u < W0::T; ++u) {
+      const int qq = q1 + u * W1::PL;
+      float zo = (z3s[qq] + kOmega * id3[u] * (s0 * rv3[u] - apply_local(fw3[u], z3s, qq, W1::X, W1::PL))) * inv;
+      if (LVL0 && !(id3[u] > 0.0f)) zo = 0.0f;   // inactive cell (and every cell outside the domain): no unknown
+      cell_put<O, W0::kUniform>(vzo, on_plane<ZIN>(co, m0, u), l0.z + u, L, zo);
+      if (LVL0) {
+        if (!first) acc[1] += (double)rv3[u] * (double)zold[u];   // r_new . z_old
+        acc[0] += (double)rv3[u] * (double)zo;
+        acc[2] += (double)zo;
+        acc[3] += (double)rv3[u];
+      }
+    }
   }
 }
 
 template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE>
-__global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kTileWaves))) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
                                                         const A* __restrict__ ay, const A* __restrict__ az,
                                                         const A* __restrict__ invd, const R* __restrict__ r,
                                                         const Z* __restrict__ z2, const E* __restrict__ e,
                                                         O* __restrict__ zout, const CGScalars* sc, double* partials) {
+  __shared__ float zp[Walk<S, 2>::N];
+  __shared__ float z3s[Walk<S, 1>::N];
   if (sc->done) return;
-  using H2 = Halo<S, 2>;
-  using H1 = Halo<S, 1>;
-  __shared__ float zp[H2::N];
-  __shared__ float z3s[H1::N];
   const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
-  constexpr int T1 = trips(H2::N), T2 = trips(H1::N), T3 = trips(S::TX * S::TY * S::TZ);
-  RegionCell c1[T1], c2[T2];
-  float zv[T1], ev[T1], id2[T2], rv2[T2], id3[T3], rv3[T3], zold[T3];
-  Faces<A> fw2[T2], fw3[T3];
-  bool ok3[T3];
-  int cl3[T3];
-  auto load2 = [&]() {
-#pragma unroll
-    for (int u = 0; u < T2; ++u) {
-      c2[u] = region_cell<S, 1>(d, i0, j0, k0, u);
-      const long c = d.c(c2[u].i, c2[u].j, c2[u].k);
-      fw2[u] = Faces<A>(d, ax, ay, az, c2[u].i, c2[u].j, c2[u].k);
-      id2[u] = ld(invd, c);
-      rv2[u] = ld(r, c);
-    }
-  };
-  auto load3 = [&]() {
-#pragma unroll
-    for (int u = 0; u < T3; ++u) {
-      const int q = threadIdx.x + u * kTileThreads;
-      const int li = q % S::TX, lj = (q / S::TX) % S::TY, lk = q / (S::TX * S::TY);
-      int i = i0 + li, j = j0 + lj, k = k0 + lk;
-      ok3[u] = in_dom(d, i, j, k);
-      if (!ok3[u]) i = j = k = 0;
-      cl3[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-      const long c = d.c(i, j, k);
-      fw3[u] = Faces<A>(d, ax, ay, az, i, j, k);
-      id3[u] = ld(invd, c);
-      rv3[u] = ld(r, c);
-      zold[u] = (LVL0 && !first) ? ld(zout, c) : 0.0f;
-    }
-  };
-#pragma unroll
-  for (int u = 0; u < T1; ++u) {
-    c1[u] = region_cell<S, 2>(d, i0, j0, k0, u);
-    zv[u] = ld(z2, d.c(c1[u].i, c1[u].j, c1[u].k));
-    ev[u] = ld(e, cd.c(c1[u].i >> 1, c1[u].j >> 1, c1[u].k >> 1));
-  }
-  if (PRE) {
-    load2();
-    load3();
-  }
-#pragma unroll
-  for (int u = 0; u < T1; ++u)
-    if (c1[u].q < H2::N) zp[c1[u].q] = c1[u].ok ? zv[u] + 8.0f * ev[u] : 0.0f;
-  __syncthreads();
-  if (!PRE) load2();
-#pragma unroll
-  for (int u = 0; u < T2; ++u) {
-    const int q = c2[u].q;
-    if (q >= H1::N) continue;
-    float v = 0.0f;
-    if (c2[u].ok) {
-      const int q2 = up1to2<S>(q);
-      v = zp[q2] + kOmega * id2[u] * (s0 * rv2[u] - apply_local(fw2[u], zp, q2, H2::X, H2::X * H2::Y));
-    }
-    z3s[q] = v;
-  }
-  __syncthreads();
-  if (!PRE) load3();
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int u = 0; u < T3; ++u) {
-    if (!ok3[u]) continue;
-    const int q = threadIdx.x + u * kTileThreads;
-    const int li = q % S::TX, lj = (q / S::TX) % S::TY, lk = q / (S::TX * S::TY);
-    const long c = d.c(i0 + li, j0 + lj, k0 + lk);
-    const int q1 = cl3[u];
-    float zo = (z3s[q1] + kOmega * id3[u] * (s0 * rv3[u] - apply_local(fw3[u], z3s, q1, H1::X, H1::X * H1::Y))) * inv;
-    if (LVL0 && !(id3[u] > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
-    if (LVL0 && !first) acc[1] += (double)rv3[u] * (double)zold[u];   // r_new . z_old
-    zout[c] = cvt<O>(zo);
-    if (LVL0) {
-      acc[0] += (double)rv3[u] * (double)zo;
-      acc[2] += (double)zo;
-      acc[3] += (double)rv3[u];
-    }
-  }
+  if (planes_inside<S>(k0, d.nz))
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0, k0,
+                                                  zp, z3s, acc);
+  else
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0,
+                                                   k0, zp, z3s, acc);
   if (LVL0) block_partials<4, kTileThreads>(acc, partials);
 }
 
@@ -796,74 +943,85 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A
 // + 1 cell (in LDS; written out on the tile), q = A p and p.q partials on the
 // tile.  Same arithmetic as k_cg_dir_apply with one load of z and p_old per
 // cell and halo.
+template <class S, bool ZIN>
+__device__ __forceinline__ void cg_dir_apply_tile(const Dims& d, const float* ax, const float* ay, const float* az,
+                                                  const float* z, const float* pold, float* pnew, float* q,
+                                                  bool first, float beta, float zmu, int i0, int j0, int k0,
+                                                  float* ps, double (&acc)[1]) {
+  using W1 = Walk<S, 1>;
+  using W0 = Walk<S, 0>;
+  const Lev L = level_of(d);
+  const int t = threadIdx.x;
+  const FaceViews V = face_views(ax, ay, az, L, i0, j0, k0);
+  const Rsrc vz = view(z, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vpo = view(pold, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vpn = view(pnew, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc vq = view(q, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Lane l1 = lane_of<S, 1>(t, walk_group<S, 1>(t), i0, j0, L.nx, L.ny);
+  const Lane l0 = lane_of<S, 0>(t, walk_group<S, 0>(t), i0, j0, L.nx, L.ny);
+  const unsigned m1 = ZIN ? ~0u : plane_mask(k0, l1.z, L.nz, W1::T);
+  const unsigned m0 = ZIN ? ~0u : plane_mask(k0, l0.z, L.nz, W0::T);
+  {
+    const unsigned ce = lane_bytes(l1.in, l1.ce, 4);
+    float zv[W1::T], pv[W1::T];
+#pragma unroll
+    for (int u = 0; u < W1::T; ++u) {
+      zv[u] = cell_at<float, W1::kUniform>(vz, on_plane<ZIN>(ce, m1, u), l1.z + u, L);
+      pv[u] = first ? 0.0f : cell_at<float, W1::kUniform>(vpo, on_plane<ZIN>(ce, m1, u), l1.z + u, L);
+    }
+    if (l1.on) {
+      const bool own_xy = l1.x >= 2 && l1.x < S::TX + 2 && l1.y >= 2 && l1.y < S::TY + 2;
+      const unsigned op = own_xy ? ce : kNoCell;
+#pragma unroll
+      for (int u = 0; u < W1::T; ++u) {
+        const int zz = l1.z + u;
+        const bool in = l1.in && (ZIN || ((m1 >> u) & 1u));
+        // cells outside the domain hold 0 (z - zmu would not)
+        const float pn = in ? (first ? zv[u] - zmu : (zv[u] - zmu) + beta * pv[u]) : 0.0f;
+        cell_put<float, W1::kUniform>(vpn, (zz >= 2 && zz < S::TZ + 2) ? on_plane<ZIN>(op, m1, u) : kNoCell, zz, L,
+                                      pn);
+        ps[l1.q + u * W1::PL] = pn;
+      }
+    }
+  }
+  __syncthreads();
+  Faces<float> fw[W0::T];
+  const unsigned fe = lane_bytes(l0.in, l0.fe, 4), ce = lane_bytes(l0.in, l0.ce, 4);
+#pragma unroll
+  for (int u = 0; u < W0::T; ++u)
+    fw[u] = faces_at<float, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), l0.z + u, L);
+  if (l0.on) {
+    const int q1 = (l0.x - 1) + W1::X * (l0.y - 1) + W1::PL * (l0.z - 1);
+#pragma unroll
+    for (int u = 0; u < W0::T; ++u) {
+      const int qq = q1 + u * W1::PL;
+      const float qc = apply_local(fw[u], ps, qq, W1::X, W1::PL);
+      cell_put<float, W0::kUniform>(vq, on_plane<ZIN>(ce, m0, u), l0.z + u, L, qc);
+      acc[0] += (double)ps[qq] * qc;
+    }
+  }
+}
+
 template <class S>
-__global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, const float* __restrict__ ax,
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kTileWaves))) void k_cg_dir_apply_tile(Dims d, const float* __restrict__ ax,
                                                                     const float* __restrict__ ay,
                                                                     const float* __restrict__ az,
                                                                     const float* __restrict__ z,
                                                                     const float* __restrict__ pold,
                                                                     float* __restrict__ pnew, float* __restrict__ q,
                                                                     const CGScalars* sc, double* partials) {
+  __shared__ float ps[Walk<S, 1>::N];
   if (sc->done) return;
-  using H1 = Halo<S, 1>;
-  __shared__ float ps[H1::N];
   const bool first = sc->first;
   const float beta = (float)sc->beta;
   const float zmu = (float)sc->zmu;
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
-  {
-    constexpr int T = trips(H1::N);
-    RegionCell cell[T];
-    float zv[T], pv[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      cell[u] = region_cell<S, 1>(d, i0, j0, k0, u);
-      const long c = d.c(cell[u].i, cell[u].j, cell[u].k);
-      zv[u] = z[c];
-      pv[u] = first ? 0.0f : pold[c];
-    }
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      const int qq = cell[u].q;
-      if (qq >= H1::N) continue;
-      float p = 0.0f;
-      if (cell[u].ok) {
-        p = first ? zv[u] - zmu : (zv[u] - zmu) + beta * pv[u];
-        const int li = qq % H1::X, lj = (qq / H1::X) % H1::Y, lk = qq / (H1::X * H1::Y);
-        if (li >= 1 && li <= S::TX && lj >= 1 && lj <= S::TY && lk >= 1 && lk <= S::TZ)
-          pnew[d.c(cell[u].i, cell[u].j, cell[u].k)] = p;
-      }
-      ps[qq] = p;
-    }
-  }
-  __syncthreads();
   double acc[1] = {0.0};
-  {
-    constexpr int T = trips(S::TX * S::TY * S::TZ);
-    bool ok[T];
-    int cl[T];
-    long cc[T];
-    Faces<float> fw[T];
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      const int qq = threadIdx.x + u * kTileThreads;
-      const int li = qq % S::TX, lj = (qq / S::TX) % S::TY, lk = qq / (S::TX * S::TY);
-      int i = i0 + li, j = j0 + lj, k = k0 + lk;
-      ok[u] = in_dom(d, i, j, k);
-      if (!ok[u]) i = j = k = 0;
-      cl[u] = (li + 1) + H1::X * ((lj + 1) + H1::Y * (lk + 1));
-      cc[u] = d.c(i, j, k);
-      fw[u] = Faces<float>(d, ax, ay, az, i, j, k);
-    }
-#pragma unroll
-    for (int u = 0; u < T; ++u) {
-      if (!ok[u]) continue;
-      const float qc = apply_local(fw[u], ps, cl[u], H1::X, H1::X * H1::Y);
-      q[cc[u]] = qc;
-      acc[0] += (double)ps[cl[u]] * qc;
-    }
-  }
+  if (planes_inside<S>(k0, d.nz))
+    cg_dir_apply_tile<S, true>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0, ps, acc);
+  else
+    cg_dir_apply_tile<S, false>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0, ps, acc);
   block_partials<1, kTileThreads>(acc, partials);
 }
 

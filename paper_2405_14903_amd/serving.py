@@ -66,11 +66,17 @@ def make_stream(count, rate, seed=0, sizes=(32, 48, 64, 96, 128, 192), steps=(8,
 # ---------------------------------------------------------------------------
 
 def _blur_axis(x, k, dim):
+    # taps summed in a fixed order with elementwise ops: the same bits whatever
+    # else runs on the device (a library convolution may pick its algorithm,
+    # and so its rounding, by the workspace memory it finds free)
     r = (k.numel() - 1) // 2
     xs = torch.movedim(x, dim, -1)
     shp = xs.shape
-    xp = torch.nn.functional.pad(xs.reshape(-1, 1, shp[-1]), (r, r), mode="reflect")
-    y = torch.nn.functional.conv1d(xp, k.view(1, 1, -1))
+    m = shp[-1]
+    xp = torch.nn.functional.pad(xs.reshape(-1, 1, m), (r, r), mode="reflect").reshape(-1, m + 2 * r)
+    y = k[0] * xp[:, 0:m]
+    for t in range(1, 2 * r + 1):
+        y = y + k[t] * xp[:, t:t + m]
     return torch.movedim(y.reshape(shp), -1, dim)
 
 
