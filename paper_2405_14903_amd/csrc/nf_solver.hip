@@ -50,12 +50,6 @@ template <> __device__ inline float cvt<float>(float v) { return v; }
 template <> __device__ inline __half cvt<__half>(float v) { return __float2half(v); }
 template <> __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
-// Kernels of a CG iteration exit at once when the solve has converged
-// (sc->done).  They read the flag first but test it only after their first
-// loads are issued, so its latency overlaps theirs; loads_issued() keeps the
-// compiler from sinking those loads past the test.
-__device__ inline void loads_issued() { asm volatile("" ::: "memory"); }
-
 __device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) {
   const unsigned cu = (unsigned)c, nx = (unsigned)d.nx, ny = (unsigned)d.ny;
   const unsigned t = cu / nx;
@@ -238,10 +232,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_pq(int nb, const double* partials, CGScalars* sc) {
-  const int done = sc->done;
+  if (sc->done) return;
   double tot[1];
   finish_partials<1>(partials, nb, tot);
-  if (done) return;
   if (threadIdx.x == 0) {
     sc->alpha = tot[0] != 0.0 ? sc->rho / tot[0] : 0.0;
     sc->first = 0;
@@ -253,24 +246,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict
                                                        const float* __restrict__ p,
                                                        const float* __restrict__ q, const CGScalars* sc,
                                                        double* partials) {
-  const int done = sc->done;
+  if (sc->done) return;
   const double a = sc->alpha;
   const float af = (float)a;
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[1] = {0.0};
-  double xv = 0.0;
-  float pv = 0.0f, rv = 0.0f, qv = 0.0f;
   if (c < n) {
-    xv = x[c];
-    pv = p[c];
-    rv = r[c];
-    qv = q[c];
-  }
-  loads_issued();
-  if (done) return;
-  if (c < n) {
-    x[c] = xv + a * (double)pv;
-    float rc = rv - af * qv;
+    x[c] += a * (double)p[c];
+    float rc = r[c] - af * q[c];
     r[c] = rc;
     v[0] = (double)rc * rc;
   }
@@ -278,10 +261,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict
 }
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_rr(int nb, const double* partials, CGScalars* sc, long ncells) {
-  const int done = sc->done;
+  if (sc->done) return;
   double tot[1];
   finish_partials<1>(partials, nb, tot);
-  if (done) return;
   if (threadIdx.x == 0) {
     sc->rr = tot[0];
     sc->iters += 1;
@@ -368,10 +350,9 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(Dims d, const float* __rest
 // those of the projected vectors: r . (z - mu) = r . z - mu sum(r).
 // Partials: r.z_new, r.z_old, sum(z_new), sum(r).
 __global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc, int project) {
-  const int done = sc->done;
+  if (sc->done) return;
   double tot[4];
   finish_partials<4>(partials, nb, tot);
-  if (done) return;
   if (threadIdx.x == 0) {
     const double mu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
     const double rz = tot[0] - mu * tot[3];
@@ -705,7 +686,7 @@ __device__ inline void cell_put(Rsrc v, unsigned ce, int kr, const Lev& L, float
 template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN>
 __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                              const A* invd, const R* r, Z* z2out, RC* rc, float s0, int i0, int j0,
-                                             int k0, float* z1s, float* z2s, int done) {
+                                             int k0, float* z1s, float* z2s) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -756,8 +737,6 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
     load2();
     load3();
   }
-  loads_issued();
-  if (done) return;
   if (l2.on) {
 #pragma unroll
     for (int u = 0; u < W2::T; ++u) z1s[l2.q + u * W2::PL] = kOmega * id1[u] * (s0 * rv1[u]);
@@ -819,23 +798,22 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const
   static_assert(Walk<S, 0>::N <= Walk<S, 2>::N, "the tile residual reuses the first sweep's array");
   __shared__ float z1s[Walk<S, 2>::N];   // first sweep on the +2 region; then the tile's residual
   __shared__ float z2s[Walk<S, 1>::N];
-  const int done = sc->done;
+  if (sc->done) return;
   const float s0 = level_scale(sc, lvl0);
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   if (planes_inside<S>(k0, d.nz))
-    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s, done);
+    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
   else
-    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s, done);
+    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
 }
 
-// Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile); false when
-// the solve had already converged (nothing done).
+// Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
 template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool ZIN>
-__device__ __forceinline__ bool mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
+__device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                            const A* invd, const R* r, const Z* z2, const E* e, O* zout, float s0,
                                            float inv, bool first, int i0, int j0, int k0, float* zp, float* z3s,
-                                           double (&acc)[4], int done) {
+                                           double (&acc)[4]) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -897,8 +875,6 @@ __device__ __forceinline__ bool mg_up_tile(const Dims& d, const Dims& cd, const 
     load2();
     load3();
   }
-  loads_issued();
-  if (done) return false;
   if (l2.on) {
 #pragma unroll
     for (int u = 0; u < W2::T; ++u) zp[l2.q + u * W2::PL] = zv[u] + 8.0f * ev[u];
@@ -933,7 +909,6 @@ __device__ __forceinline__ bool mg_up_tile(const Dims& d, const Dims& cd, const 
       }
     }
   }
-  return true;
 }
 
 template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE>
@@ -944,20 +919,19 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A
                                                         O* __restrict__ zout, const CGScalars* sc, double* partials) {
   __shared__ float zp[Walk<S, 2>::N];
   __shared__ float z3s[Walk<S, 1>::N];
-  const int done = sc->done;
+  if (sc->done) return;
   const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  const bool ran =
-      planes_inside<S>(k0, d.nz)
-          ? mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0,
-                                                          j0, k0, zp, z3s, acc, done)
-          : mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0,
-                                                           j0, k0, zp, z3s, acc, done);
-  if (!ran) return;
+  if (planes_inside<S>(k0, d.nz))
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0, k0,
+                                                  zp, z3s, acc);
+  else
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0,
+                                                   k0, zp, z3s, acc);
   if (LVL0) block_partials<4, kTileThreads>(acc, partials);
 }
 
@@ -966,10 +940,10 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A
 // tile.  Same arithmetic as k_cg_dir_apply with one load of z and p_old per
 // cell and halo.
 template <class S, bool ZIN>
-__device__ __forceinline__ bool cg_dir_apply_tile(const Dims& d, const float* ax, const float* ay, const float* az,
+__device__ __forceinline__ void cg_dir_apply_tile(const Dims& d, const float* ax, const float* ay, const float* az,
                                                   const float* z, const float* pold, float* pnew, float* q,
                                                   bool first, float beta, float zmu, int i0, int j0, int k0,
-                                                  float* ps, double (&acc)[1], int done) {
+                                                  float* ps, double (&acc)[1]) {
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
   const Lev L = level_of(d);
@@ -991,8 +965,6 @@ __device__ __forceinline__ bool cg_dir_apply_tile(const Dims& d, const float* ax
       zv[u] = cell_at<float, W1::kUniform>(vz, on_plane<ZIN>(ce, m1, u), l1.z + u, L);
       pv[u] = first ? 0.0f : cell_at<float, W1::kUniform>(vpo, on_plane<ZIN>(ce, m1, u), l1.z + u, L);
     }
-    loads_issued();
-    if (done) return false;
     if (l1.on) {
       const bool own_xy = l1.x >= 2 && l1.x < S::TX + 2 && l1.y >= 2 && l1.y < S::TY + 2;
       const unsigned op = own_xy ? ce : kNoCell;
@@ -1024,7 +996,6 @@ __device__ __forceinline__ bool cg_dir_apply_tile(const Dims& d, const float* ax
       acc[0] += (double)ps[qq] * qc;
     }
   }
-  return true;
 }
 
 template <class S>
@@ -1036,19 +1007,17 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
                                                                     float* __restrict__ pnew, float* __restrict__ q,
                                                                     const CGScalars* sc, double* partials) {
   __shared__ float ps[Walk<S, 1>::N];
-  const int done = sc->done;
+  if (sc->done) return;
   const bool first = sc->first;
   const float beta = (float)sc->beta;
   const float zmu = (float)sc->zmu;
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   double acc[1] = {0.0};
-  const bool ran = planes_inside<S>(k0, d.nz)
-                       ? cg_dir_apply_tile<S, true>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0, ps,
-                                                    acc, done)
-                       : cg_dir_apply_tile<S, false>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0,
-                                                     ps, acc, done);
-  if (!ran) return;
+  if (planes_inside<S>(k0, d.nz))
+    cg_dir_apply_tile<S, true>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0, ps, acc);
+  else
+    cg_dir_apply_tile<S, false>(d, ax, ay, az, z, pold, pnew, q, first, beta, zmu, i0, j0, k0, ps, acc);
   block_partials<1, kTileThreads>(acc, partials);
 }
 
@@ -1225,7 +1194,7 @@ __device__ inline void bottom_up(const Dims& d, const Dims& cd, const Coef<P>& K
 template <typename A, typename R, typename Z>
 __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __restrict__ rin, Z* __restrict__ zout,
                                                      const CGScalars* sc, int lvl0) {
-  const int done = sc->done;
+  if (sc->done) return;
   extern __shared__ float lds[];
   const float s0 = level_scale(sc, lvl0);
   const int T = blockDim.x;
@@ -1253,7 +1222,6 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __rest
     float* r0 = R_(0);
     for (int c = threadIdx.x; c < n; c += T) r0[c] = s0 * ld(rin, c);
   }
-  if (done) return;
   __syncthreads();
   const int L = B.nl;
   for (int l = 0; l < L - 1; ++l) {
