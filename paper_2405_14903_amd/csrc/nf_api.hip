@@ -115,6 +115,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   size_t nb_faces = (F_ + kBlock - 1) / kBlock, nb_cells = (C + kBlock - 1) / kBlock;
   size_t npart = nb_faces * 21 > nb_cells * 4 ? nb_faces * 21 : nb_cells * 4;
   alloc(npart * 8, (void**)&t->S.partials);
+  alloc(kUpdateBlocks * 8, (void**)&t->S.partials_rr);
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
   for (int l = 0; l < p.nlev; ++l) {
     const Dims& dl = p.dims[l];

@@ -233,4 +233,63 @@ __device__ inline void finish_partials(const double* partials, int nb, double (&
   }
 }
 
+// Fixed-order total of N partial arrays of nb entries by every thread block
+// of BS threads (each block gets the same bits).  Result valid in thread 0.
+template <int N, int BS>
+__device__ inline void block_total(const double* partials, int nb, double (&tot)[N]) {
+  __shared__ double sh[N * (BS / 64) + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += BS) s += partials[(size_t)q * nb + b];
+    s = wave_sum(s);
+    if (lane == 0) sh[q * (BS / 64) + wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < BS / 64; ++w) s += sh[q * (BS / 64) + w];
+      tot[q] = s;
+    }
+  }
+}
+
+// The same total in two steps, so that a kernel can issue its own first loads
+// between them: partials_load reads the (at most K * BS) partials into
+// registers; partials_reduce sums them in block_total's order (result in
+// thread 0 and in *out for every thread; it holds a barrier).
+template <int K, int BS>
+__device__ inline void partials_load(const double* partials, int nb, double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int b = threadIdx.x + k * BS;
+    v[k] = b < nb ? partials[b] : 0.0;
+  }
+}
+template <int K, int BS>
+__device__ inline double partials_reduce(const double (&v)[K], double* out) {
+  __shared__ double sh[BS / 64 + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) s += v[k];
+  s = wave_sum(s);
+  if (lane == 0) sh[wv] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < BS / 64; ++w) t += sh[w];
+    *out = t;
+  }
+  __syncthreads();
+  return *out;
+}
+
+// Blocks of the CG update kernel (grid-stride): few enough that every block of
+// the next kernel can total their r . r partials itself.
+constexpr int kUpdateBlocks = 1024;
+
 }  // namespace nf

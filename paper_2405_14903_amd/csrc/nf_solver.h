@@ -104,6 +104,7 @@ struct Solver {
   CGScalars* sc = nullptr;
   CGScalars* host_sc = nullptr;  // pinned
   double* partials = nullptr;
+  double* partials_rr = nullptr;  // r . r partials of the CG update (kUpdateBlocks)
   float* scratch_a = nullptr;    // FP32 coarse fractions while building a mixed hierarchy
   float* scratch_inv = nullptr;
   size_t scratch_off[kMaxLevels] = {};

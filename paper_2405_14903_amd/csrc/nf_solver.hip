@@ -231,46 +231,101 @@ __global__ __launch_bounds__(kBlock) void k_cg_dir_apply(Dims d, const float* __
   block_partials<1>(v, partials);
 }
 
-__global__ __launch_bounds__(kFinBlock) void k_fin_pq(int nb, const double* partials, CGScalars* sc) {
-  if (sc->done) return;
-  double tot[1];
-  finish_partials<1>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    sc->alpha = tot[0] != 0.0 ? sc->rho / tot[0] : 0.0;
-    sc->first = 0;
-  }
-}
-
-// x += alpha p (FP64); r -= alpha q; partials of r . r.
+// x += alpha p (FP64); r -= alpha q; partials of r . r (grid-stride, at most
+// kUpdateBlocks blocks).  alpha = rho / (p . q) is formed by every block from
+// the direction kernel's p . q partials (fixed order, so all blocks agree);
+// block 0 records it, ends the first iteration and advances the count.  No
+// block reads what block 0 writes.
 __global__ __launch_bounds__(kBlock) void k_cg_update(long n, double* __restrict__ x, float* __restrict__ r,
                                                        const float* __restrict__ p,
-                                                       const float* __restrict__ q, const CGScalars* sc,
-                                                       double* partials) {
+                                                       const float* __restrict__ q, CGScalars* sc,
+                                                       const double* pq_parts, int npq, double* rr_parts) {
   if (sc->done) return;
-  const double a = sc->alpha;
-  const float af = (float)a;
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  double v[1] = {0.0};
-  if (c < n) {
-    x[c] += a * (double)p[c];
-    float rc = r[c] - af * q[c];
-    r[c] = rc;
-    v[0] = (double)rc * rc;
+  __shared__ double tot_sh, alpha_sh;
+  // the partials are read first, then the first cell's operands, so that
+  // totalling the partials waits only for them
+  constexpr int K = 4;
+  double pv[K];
+  const bool in_regs = npq <= K * kBlock;
+  if (in_regs) partials_load<K, kBlock>(pq_parts, npq, pv);
+  const long c0 = (long)blockIdx.x * blockDim.x + threadIdx.x, stride = (long)gridDim.x * blockDim.x;
+  double x0 = 0.0;
+  float p0 = 0.0f, r0 = 0.0f, q0 = 0.0f;
+  if (c0 < n) {
+    x0 = x[c0];
+    p0 = p[c0];
+    r0 = r[c0];
+    q0 = q[c0];
   }
-  block_partials<1>(v, partials);
+  double pq;
+  if (in_regs) {
+    pq = partials_reduce<K, kBlock>(pv, &tot_sh);
+  } else {
+    double tot[1];
+    block_total<1, kBlock>(pq_parts, npq, tot);
+    if (threadIdx.x == 0) tot_sh = tot[0];
+    __syncthreads();
+    pq = tot_sh;
+  }
+  if (threadIdx.x == 0) {
+    const double a = pq != 0.0 ? sc->rho / pq : 0.0;
+    alpha_sh = a;
+    if (blockIdx.x == 0) {
+      sc->alpha = a;
+      sc->first = 0;
+      sc->iters += 1;
+    }
+  }
+  __syncthreads();
+  const double a = alpha_sh;
+  const float af = (float)a;
+  double v[1] = {0.0};
+  if (c0 < n) {
+    x[c0] = x0 + a * (double)p0;
+    const float rc = r0 - af * q0;
+    r[c0] = rc;
+    v[0] += (double)rc * rc;
+  }
+  for (long c = c0 + stride; c < n; c += stride) {
+    x[c] += a * (double)p[c];
+    const float rc = r[c] - af * q[c];
+    r[c] = rc;
+    v[0] += (double)rc * rc;
+  }
+  block_partials<1>(v, rr_parts);
 }
 
+// State after an update from rr = r . r: the V-cycle input scale and the stop
+// test (converged, iteration cap, or a non-finite residual, which is sticky).
+// The finest-level down kernel forms this state in every block while its
+// block 0 stores it; a block that reads `done` or `nonfinite` after block 0
+// stored them reads the values it computes itself.
+struct RRState {
+  double rr, vscale;
+  int nonfinite, done;
+};
+__device__ inline RRState rr_state(const CGScalars* sc, double rr, long ncells) {
+  RRState st;
+  st.rr = rr;
+  st.vscale = vscale_of(rr, ncells);
+  st.nonfinite = (sc->nonfinite || !isfinite(rr)) ? 1 : 0;
+  st.done = (rr <= sc->tol2bb || sc->iters >= sc->maxit || st.nonfinite) ? 1 : 0;
+  return st;
+}
+__device__ inline void put_rr_state(CGScalars* sc, const RRState& st) {
+  sc->rr = st.rr;
+  sc->vscale = st.vscale;
+  sc->nonfinite = st.nonfinite;
+  sc->done = st.done;
+}
+
+// One-block form of the same, ahead of a V-cycle whose first kernel does not
+// total the r . r partials itself.
 __global__ __launch_bounds__(kFinBlock) void k_fin_rr(int nb, const double* partials, CGScalars* sc, long ncells) {
   if (sc->done) return;
   double tot[1];
   finish_partials<1>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    sc->rr = tot[0];
-    sc->iters += 1;
-    sc->vscale = vscale_of(tot[0], ncells);
-    if (!isfinite(tot[0])) sc->nonfinite = 1;
-    if (tot[0] <= sc->tol2bb || sc->iters >= sc->maxit || sc->nonfinite) sc->done = 1;
-  }
+  if (threadIdx.x == 0) put_rr_state(sc, rr_state(sc, tot[0], ncells));
 }
 
 // True residual from the FP64 iterate, once the recursive residual has
@@ -685,8 +740,9 @@ __device__ inline void cell_put(Rsrc v, unsigned ce, int kr, const Lev& L, float
 // registers low for the finest level.
 template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN>
 __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
-                                             const A* invd, const R* r, Z* z2out, RC* rc, float s0, int i0, int j0,
-                                             int k0, float* z1s, float* z2s) {
+                                             const A* invd, const R* r, Z* z2out, RC* rc, CGScalars* sc, int lvl0,
+                                             const double* rr_parts, int nrr, long ncells, int i0, int j0, int k0,
+                                             float* z1s, float* z2s, double* rr_sh) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -705,6 +761,11 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   const unsigned m0 = ZIN ? ~0u : plane_mask(k0, l0.z, L.nz, W0::T);
   float id1[W2::T], rv1[W2::T], id2[W1::T], rv2[W1::T], rv3[W0::T];
   Faces<A> fw2[W1::T], fw3[W0::T];
+  // the update's r . r partials are read before this kernel's own loads, so
+  // that totalling them waits only for them
+  constexpr int KR = (kUpdateBlocks + kTileThreads - 1) / kTileThreads;
+  double prr[KR];
+  if (nrr > 0) partials_load<KR, kTileThreads>(rr_parts, nrr, prr);
   auto load2 = [&]() {
     const unsigned fe = lane_bytes(l1.in, l1.fe, eA), ce = lane_bytes(l1.in, l1.ce, eA),
                    cr = lane_bytes(l1.in, l1.ce, eR);
@@ -736,6 +797,19 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   if (PRE) {
     load2();
     load3();
+  }
+  float s0;
+  if (nrr > 0) {
+    // right after the CG update (the loads above are already in flight):
+    // every block totals the update's r . r partials (the same bits in each),
+    // applies the stop test and scales by the new RMS; block 0 stores the
+    // state for the kernels that follow
+    const RRState st = rr_state(sc, partials_reduce<KR, kTileThreads>(prr, rr_sh), ncells);
+    if (blockIdx.x == 0 && threadIdx.x == 0) put_rr_state(sc, st);
+    if (st.done) return;
+    s0 = (float)st.vscale;
+  } else {
+    s0 = level_scale(sc, lvl0);
   }
   if (l2.on) {
 #pragma unroll
@@ -794,18 +868,21 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const
                                                           const A* __restrict__ ay, const A* __restrict__ az,
                                                           const A* __restrict__ invd, const R* __restrict__ r,
                                                           Z* __restrict__ z2out, RC* __restrict__ rc,
-                                                          const CGScalars* sc, int lvl0) {
+                                                          CGScalars* sc, int lvl0, const double* rr_parts, int nrr,
+                                                          long ncells) {
   static_assert(Walk<S, 0>::N <= Walk<S, 2>::N, "the tile residual reuses the first sweep's array");
   __shared__ float z1s[Walk<S, 2>::N];   // first sweep on the +2 region; then the tile's residual
   __shared__ float z2s[Walk<S, 1>::N];
+  __shared__ double rr_sh;
   if (sc->done) return;
-  const float s0 = level_scale(sc, lvl0);
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   if (planes_inside<S>(k0, d.nz))
-    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
+    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr, ncells, i0,
+                                            j0, k0, z1s, z2s, &rr_sh);
   else
-    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, s0, i0, j0, k0, z1s, z2s);
+    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr, ncells,
+                                             i0, j0, k0, z1s, z2s, &rr_sh);
 }
 
 // Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
@@ -1259,8 +1336,10 @@ static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / 
 // host driver
 // ---------------------------------------------------------------------------
 
+// nrr > 0: the V-cycle follows a CG update whose nrr r . r partials have not
+// been totalled yet (the finest fused down kernel does it, else k_fin_rr).
 template <typename T>
-static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) {
+static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, int nrr) {
   const int L = S.nlev;
   const int G = S.nbottom;  // levels 0 .. G-1 run as grid kernels, G .. L-1 in one workgroup
   CGScalars* sc = S.sc;
@@ -1293,6 +1372,8 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
   }
   const size_t lds = (size_t)off * sizeof(float);
   const int bthreads = S.lev[G].d.cells() >= 1024 ? 1024 : (int)((S.lev[G].d.cells() + 63) / 64 * 64);
+  if (nrr > 0 && !(S.fused && G > 0))
+    hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, st, nrr, S.partials_rr, sc, n0);
   if (G == 0) {
     NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1);
     hipLaunchKernelGGL(k_scale_dot<T>, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, ID(0), r0, z0, sc, S.partials);
@@ -1309,10 +1390,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
         NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles(d, true)), dim3(kTileThreads), 0, st,
-                  d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1);
+                  d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1, S.partials_rr, nrr, n0);
       } else {
         hipLaunchKernelGGL((k_mg_down<CoarseTile, T, T, T, T, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
-                           ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0);
+                           ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
       }
     }
     NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
@@ -1379,13 +1460,13 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st) 
   }
 }
 
-static void vcycle_dispatch(const Solver& S, const float* r0, float* z0, hipStream_t st) {
+static void vcycle_dispatch(const Solver& S, const float* r0, float* z0, hipStream_t st, int nrr = 0) {
   if (S.precision == SIM_MIXED_FP16)
-    vcycle<__half>(S, r0, z0, st);
+    vcycle<__half>(S, r0, z0, st, nrr);
   else if (S.precision == SIM_MIXED_BF16)
-    vcycle<__hip_bfloat16>(S, r0, z0, st);
+    vcycle<__hip_bfloat16>(S, r0, z0, st, nrr);
   else
-    vcycle<float>(S, r0, z0, st);
+    vcycle<float>(S, r0, z0, st, nrr);
 }
 
 template <typename T>
@@ -1469,20 +1550,19 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     float* pold = S.pcur ? S.p1 : S.p0;
     float* pnew = S.pcur ? S.p0 : S.p1;
     const int nb = (int)nblocks(n);
+    int npq = nb;
     if (S.fused) {
-      const int nt = tiles_of<FineTile>(d);
-      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile<FineTile>, dim3(nt), dim3(kTileThreads), 0, st, d, S.ax, S.ay,
-                S.az, S.z, pold, pnew, S.q, S.sc, S.partials);
-      hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nt, S.partials, S.sc);
+      npq = tiles_of<FineTile>(d);
+      NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile<FineTile>, dim3(npq), dim3(kTileThreads), 0, st, d, S.ax,
+                S.ay, S.az, S.z, pold, pnew, S.q, S.sc, S.partials);
     } else {
       NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
                                   pnew, S.q, S.sc, S.partials);
-      hipLaunchKernelGGL(k_fin_pq, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc);
     }
-    NF_LAUNCH(S.prof, SIM_K_CG_UPDATE, k_cg_update, dim3(nb), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
-              S.partials);
-    hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, S.sc, n);
-    vcycle_dispatch(S, S.r, S.z, st);
+    const int nu = nb < kUpdateBlocks ? nb : kUpdateBlocks;
+    NF_LAUNCH(S.prof, SIM_K_CG_UPDATE, k_cg_update, dim3(nu), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
+              S.partials, npq, S.partials_rr);
+    vcycle_dispatch(S, S.r, S.z, st, nu);
     S.pcur ^= 1;
   }
 }
