@@ -19,7 +19,7 @@
 //   * preconditions with one V-cycle: level l+1 halves each axis, coarse face
 //     weight = 1/2 * sum of the 2x2 fine faces it covers, restriction = mean
 //     of the 8 child residuals with prolongation = 8 x injection, two
-//     damped-Jacobi sweeps (omega = 0.8) before and after the correction, and
+//     damped-Jacobi sweeps (omega = 6/7) before and after the correction, and
 //     the levels of at most 4096 cells in one workgroup with the coarsest
 //     level relaxed by up to 40 sweeps;
 //   * uses the flexible (Polak-Ribiere) direction coefficient, since FP16 /
