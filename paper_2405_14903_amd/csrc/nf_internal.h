@@ -16,6 +16,7 @@ constexpr int kMaxLevels = 12;
 constexpr int kCoarseMaxCells = 4096;   // largest coarsest level (it must fit one workgroup's LDS)
 constexpr int kBottomCells = 512;       // levels of at most this many cells run in the one-workgroup bottom solve
 constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coarse correction
+constexpr int kBottomSweeps = 4;     // the same on the levels of the one-workgroup bottom solve (even)
 constexpr float kOmega = 6.0f / 7.0f;   // damped-Jacobi weight: the smoothing optimum for the 7-point stencil in 3D
 constexpr int kCoarseSweepsMax = 40;   // coarsest level: min(40, 2 * (largest extent)^2) sweeps
 constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces

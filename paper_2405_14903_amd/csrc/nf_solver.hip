@@ -1125,8 +1125,28 @@ struct Coef {
   const P* invd;
 };
 
-// z = two damped-Jacobi sweeps from 0 (t holds the first); then the restricted
-// residual mean over the 8 children of (r - A z) into rc.
+// Two more damped-Jacobi sweeps on z (through t), each followed by a barrier.
+template <typename P>
+__device__ inline void bottom_sweep_pair(const Dims& d, const Coef<P>& K, const float* r, float* z, float* t) {
+  const int n = (int)d.cells(), T = blockDim.x;
+  for (int c = threadIdx.x; c < n; c += T) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+    t[c] = z[c] + kOmega * ld(K.invd, c) * (r[c] - apply_A(d, fw, i, j, k, c, z[c], [&](long q) { return z[q]; }));
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += T) {
+    int i, j, k;
+    cdec(d, c, i, j, k);
+    Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+    z[c] = t[c] + kOmega * ld(K.invd, c) * (r[c] - apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; }));
+  }
+  __syncthreads();
+}
+
+// z = kBottomSweeps damped-Jacobi sweeps from 0 (t holds the first); then the
+// restricted residual mean over the 8 children of (r - A z) into rc.
 template <typename P>
 __device__ inline void bottom_down(const Dims& d, const Dims& cd, const Coef<P>& K, const float* r, float* z, float* t,
                                    float* rc) {
@@ -1143,6 +1163,7 @@ __device__ inline void bottom_down(const Dims& d, const Dims& cd, const Coef<P>&
     z[c] = tc + kOmega * ld(K.invd, c) * (r[c] - Az);
   }
   __syncthreads();
+  for (int s = 2; s < kBottomSweeps; s += 2) bottom_sweep_pair(d, K, r, z, t);
   for (int C = threadIdx.x; C < (int)cd.cells(); C += T) {
     int I, J, K_;
     cdec(cd, C, I, J, K_);
@@ -1266,6 +1287,7 @@ __device__ inline void bottom_up(const Dims& d, const Dims& cd, const Coef<P>& K
     z[c] = t[c] + kOmega * ld(K.invd, c) * (r[c] - apply_A(d, fw, i, j, k, c, t[c], [&](long q) { return t[q]; }));
   }
   __syncthreads();
+  for (int s = 2; s < kBottomSweeps; s += 2) bottom_sweep_pair(d, K, r, z, t);
 }
 
 template <typename A, typename R, typename Z>
