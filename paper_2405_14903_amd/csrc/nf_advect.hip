@@ -178,26 +178,41 @@ constexpr int kHalo = 2;
 constexpr int kWinX = kBX + 1 + 2 * kHalo, kWinY = kBY + 1 + 2 * kHalo, kWinZ = kBZ + 1 + 2 * kHalo;
 constexpr int kWin3 = kWinX * kWinY * kWinZ;
 
+// v rounded to the nearest integer (ties to even) as a 64-bit integer, for
+// |v| <= 2^51: adding 1.5 * 2^52 leaves the integer in the low mantissa bits.
+__device__ inline long long fixed_round(double v) {
+  return __double_as_longlong(v + 6755399441055744.0) - 0x4338000000000000LL;
+}
+
 __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, const Tap& t, double w) {
   if (w == 0.0) return;
   const double fx = t.f[0], fy = t.f[1], fz = t.f[2];
-  const double wz[2] = {1.0 - fz, fz}, wy[2] = {1.0 - fy, fy}, wx[2] = {1.0 - fx, fx};
   const int la = t.i0[0] - W.o[0], lb = t.i0[1] - W.o[1], lc = t.i0[2] - W.o[2];
   const bool inside = la >= 0 && lb >= 0 && lc >= 0 && la + 1 < kWinX && lb + 1 < kWinY && lc + 1 < kWinZ;
-  unsigned long long* win = W.lds + e * kWin3;
+  const double ws = w * W.scale;   // every tap's value is at most |ws| (weights <= 1)
+  if (inside && fabs(ws) <= W.limit) {
+    unsigned long long* win = W.lds + e * kWin3 + la + kWinX * (lb + kWinY * lc);
+    const double wz[2] = {ws * (1.0 - fz), ws * fz};
+#pragma unroll
+    for (int bz = 0; bz < 2; ++bz)
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        const double wy = wz[bz] * (by ? fy : 1.0 - fy);
+        unsigned long long* row = win + kWinX * (by + kWinY * bz);
+        atomicAdd(row, (unsigned long long)fixed_round(wy * (1.0 - fx)));
+        atomicAdd(row + 1, (unsigned long long)fixed_round(wy * fx));
+      }
+    return;
+  }
+  const double wz[2] = {1.0 - fz, fz}, wy[2] = {1.0 - fy, fy}, wx[2] = {1.0 - fx, fx};
 #pragma unroll
   for (int bz = 0; bz < 2; ++bz)
 #pragma unroll
     for (int by = 0; by < 2; ++by)
 #pragma unroll
       for (int bx = 0; bx < 2; ++bx) {
-        double ww = w * wz[bz] * wy[by] * wx[bx];
-        if (ww == 0.0) continue;
-        const double fixed = ww * W.scale;
-        if (inside && fabs(fixed) <= W.limit)
-          atomicAdd(win + (la + bx) + kWinX * ((lb + by) + kWinY * (lc + bz)),
-                    (unsigned long long)(long long)llrint(fixed));
-        else
+        const double ww = w * wz[bz] * wy[by] * wx[bx];
+        if (ww != 0.0)
           __hip_atomic_fetch_add(g + t.base + bx + by * t.sx + bz * t.sxy, (float)ww, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -232,8 +247,9 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
   // G = max |g| over its faces and U = max |u| over the window region, every
   // scattered value is at most G * max(1, 2 cfl U, 6 cfl^2 U^2) (interpolation
   // weights <= 1, trilinear gradients in index units <= 2U); 2^50 / bound
-  // leaves room for 2^12 adds per entry below 2^62.  Values that still exceed
-  // the limit (taps of corners outside the window region) take the float path.
+  // leaves room for 2^12 adds per entry below 2^62.  A scatter whose value
+  // still exceeds 2^51 (corners outside the window region) takes the float
+  // path.
   float um = 0.0f;
   for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) {
     lds[q] = 0ull;
@@ -284,7 +300,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
     const double cu = cfl * (double)U;
     const double bound = (double)Gm * fmax(1.0, fmax(2.0 * cu, 6.0 * cu * cu));
     W.scale = bound > 0.0 && isfinite(bound) ? 1125899906842624.0 / bound : 1.0;   // 2^50 / bound
-    W.limit = 4503599627370496.0;                                                  // 2^52
+    W.limit = 2251799813685248.0;                                                  // 2^51 (fixed_round's range)
   }
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
     const int comp = q < start[1] ? 0 : (q < start[2] ? 1 : 2);
