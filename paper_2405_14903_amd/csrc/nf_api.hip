@@ -116,6 +116,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   size_t npart = nb_faces * 21 > nb_cells * 4 ? nb_faces * 21 : nb_cells * 4;
   alloc(npart * 8, (void**)&t->S.partials);
   alloc(kUpdateBlocks * 8, (void**)&t->S.partials_rr);
+  alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
   for (int l = 0; l < p.nlev; ++l) {
     const Dims& dl = p.dims[l];
@@ -239,6 +240,8 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
     c->S.use_graph = !(gr && gr[0] == '0');
     const char* fu = std::getenv("NF_MG_FUSED");
     c->S.fused = !(fu && fu[0] == '0');
+    const char* bl = std::getenv("NF_MG_BOTTOM_LANES");
+    c->S.bottom_lanes = !(bl && bl[0] == '0');
   }
   // the fused tile kernels need 31-bit byte offsets over a tile's region
   if (!views_fit(p.dims[0].nx, p.dims[0].ny)) c->S.fused = 0;

@@ -75,6 +75,8 @@ struct CGScalars {
   double vscale;     // scale applied to the fine residual before the V-cycle
   double mu;         // mean of the residual over active cells (removed when the system is singular)
   double zmu;        // mean of the preconditioned residual over active cells (singular systems)
+  double rho2[2];    // rho and zmu of iteration i in slot i & 1 (read by iteration i + 1 while
+  double zmu2[2];    // iteration i + 1's own values go to the other slot)
   double nact;       // number of active cells
   int iters;
   int done;
@@ -289,8 +291,48 @@ __device__ inline double partials_reduce(const double (&v)[K], double* out) {
   return *out;
 }
 
+// N partial arrays (nb entries each, at most K * BS) read into registers, then
+// totalled by every block in block_total's order (the same bits in each block;
+// result for every thread; holds two barriers).
+template <int N, int K, int BS>
+__device__ inline void partials_load_n(const double* partials, int nb, double (&v)[N][K]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int b = threadIdx.x + k * BS;
+      v[q][k] = b < nb ? partials[(size_t)q * nb + b] : 0.0;
+    }
+}
+template <int N, int K, int BS>
+__device__ inline void partials_reduce_n(const double (&v)[N][K], double (&tot)[N]) {
+  __shared__ double sh[N * (BS / 64)];
+  __shared__ double res[N];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += v[q][k];
+    s = wave_sum(s);
+    if (lane == 0) sh[q * (BS / 64) + wv] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double t = 0.0;
+    for (int w = 0; w < BS / 64; ++w) t += sh[threadIdx.x * (BS / 64) + w];
+    res[threadIdx.x] = t;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < N; ++q) tot[q] = res[q];
+}
+
 // Blocks of the CG update kernel (grid-stride): few enough that every block of
 // the next kernel can total their r . r partials itself.
 constexpr int kUpdateBlocks = 1024;
+// Most r . z partials (tiles of the finest level) that every block of the
+// direction kernel totals itself; beyond, a one-block kernel totals them.
+constexpr int kRzPartsMax = 1024;
 
 }  // namespace nf

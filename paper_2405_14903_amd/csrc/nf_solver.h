@@ -91,6 +91,7 @@ struct Solver {
   // side) is removed at the start and at every restart.
   int project = 0;
   int fused = 1;       // fused tile kernels per grid level (NF_MG_FUSED=0: four passes per level)
+  int bottom_lanes = 1;  // one lane per cell in the bottom solve where it fits (NF_MG_BOTTOM_LANES=0: off)
   Level lev[kMaxLevels];
   const float* ax = nullptr;   // fine FP32 fractions (CG operator)
   const float* ay = nullptr;
@@ -105,6 +106,7 @@ struct Solver {
   CGScalars* host_sc = nullptr;  // pinned
   double* partials = nullptr;
   double* partials_rr = nullptr;  // r . r partials of the CG update (kUpdateBlocks)
+  double* partials_rz = nullptr;  // r . z partials of the V-cycle when the direction kernel totals them (4 x kRzPartsMax)
   float* scratch_a = nullptr;    // FP32 coarse fractions while building a mixed hierarchy
   float* scratch_inv = nullptr;
   size_t scratch_off[kMaxLevels] = {};

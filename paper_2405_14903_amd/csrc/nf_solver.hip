@@ -191,6 +191,8 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* pa
     sc->converged = (tot[0] == 0.0) || (tot[1] <= sc->tol2bb);
     sc->done = sc->converged || sc->nonfinite || maxit <= 0;
     sc->rho = 0.0;
+    sc->rho2[0] = sc->rho2[1] = 0.0;
+    sc->zmu2[0] = sc->zmu2[1] = 0.0;
     sc->beta = 0.0;
     sc->alpha = 0.0;
     sc->vscale = vscale_of(tot[1], ncells);
@@ -404,22 +406,41 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(Dims d, const float* __rest
 // its mean over active cells (k_cg_dir_apply subtracts zmu), and the dots are
 // those of the projected vectors: r . (z - mu) = r . z - mu sum(r).
 // Partials: r.z_new, r.z_old, sum(z_new), sum(r).
+// The same from the totals, as state for one iteration: the previous
+// iteration's rho and zmu come from the slot of the other iteration parity
+// (sc->iters does not change between the V-cycle and the CG update), so a
+// kernel whose block 0 stores this iteration's values may have other blocks
+// reading the previous ones.
+struct RZState {
+  double rho, beta, mu;
+  int slot;
+};
+__device__ inline RZState rz_state(const CGScalars* sc, const double (&tot)[4], int project) {
+  RZState z;
+  z.slot = sc->iters & 1;
+  const int o = z.slot ^ 1;
+  z.mu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
+  z.rho = tot[0] - z.mu * tot[3];
+  z.beta = 0.0;
+  if (!sc->first) {
+    const double rzo = tot[1] - sc->zmu2[o] * tot[3];
+    z.beta = sc->rho2[o] != 0.0 ? (z.rho - rzo) / sc->rho2[o] : 0.0;
+  }
+  return z;
+}
+__device__ inline void put_rz_state(CGScalars* sc, const RZState& z) {
+  sc->rho2[z.slot] = z.rho;
+  sc->zmu2[z.slot] = z.mu;
+  sc->rho = z.rho;
+  sc->zmu = z.mu;
+  if (!sc->first) sc->beta = z.beta;
+}
+
 __global__ __launch_bounds__(kFinBlock) void k_fin_rz(int nb, const double* partials, CGScalars* sc, int project) {
   if (sc->done) return;
   double tot[4];
   finish_partials<4>(partials, nb, tot);
-  if (threadIdx.x == 0) {
-    const double mu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
-    const double rz = tot[0] - mu * tot[3];
-    if (sc->first) {
-      sc->rho = rz;
-    } else {
-      const double rzo = tot[1] - sc->zmu * tot[3];
-      sc->beta = sc->rho != 0.0 ? (rz - rzo) / sc->rho : 0.0;
-      sc->rho = rz;
-    }
-    sc->zmu = mu;
-  }
+  if (threadIdx.x == 0) put_rz_state(sc, rz_state(sc, tot, project));
 }
 
 // z *= 1 / vscale (the V-cycle ran on the scaled residual), 0 on inactive
@@ -1082,12 +1103,29 @@ __global__ __launch_bounds__(kTileThreads) void k_cg_dir_apply_tile(Dims d, cons
                                                                     const float* __restrict__ z,
                                                                     const float* __restrict__ pold,
                                                                     float* __restrict__ pnew, float* __restrict__ q,
-                                                                    const CGScalars* sc, double* partials) {
+                                                                    CGScalars* sc, double* partials,
+                                                                    const double* rz_parts, int nrz, int project) {
   __shared__ float ps[Walk<S, 1>::N];
+  // nrz > 0: the V-cycle's nrz r . z partials have not been totalled yet;
+  // every block totals them (the same bits in each) and forms beta and zmu;
+  // block 0 stores them.  They are read first, so the total waits only for them.
+  constexpr int KZ = kRzPartsMax / kTileThreads;
+  double pz[4][KZ];
+  if (nrz > 0) partials_load_n<4, KZ, kTileThreads>(rz_parts, nrz, pz);
   if (sc->done) return;
   const bool first = sc->first;
-  const float beta = (float)sc->beta;
-  const float zmu = (float)sc->zmu;
+  float beta, zmu;
+  if (nrz > 0) {
+    double tot[4];
+    partials_reduce_n<4, KZ, kTileThreads>(pz, tot);
+    const RZState rz = rz_state(sc, tot, project);
+    if (blockIdx.x == 0 && threadIdx.x == 0) put_rz_state(sc, rz);
+    beta = (float)rz.beta;
+    zmu = (float)rz.mu;
+  } else {
+    beta = (float)sc->beta;
+    zmu = (float)sc->zmu;
+  }
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   double acc[1] = {0.0};
@@ -1346,6 +1384,190 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __rest
   }
 }
 
+// ---------------------------------------------------------------------------
+// bottom with one lane per cell: every bottom level has at most as many cells
+// as the workgroup has lanes, and there are at most kBottomLaneLevels levels.
+// Each lane keeps its cell's fractions, 1/diag, residual and down iterate in
+// registers for the whole bottom; only the iterates go through LDS.  Lanes are
+// numbered children first (bottom_cell), so a restriction sums 8 consecutive
+// lanes by cross-lane exchanges instead of one lane walking 8 children.  Same
+// sweeps, transfers and coarsest sweeps as k_mg_bottom.
+// ---------------------------------------------------------------------------
+
+template <typename A>
+struct LaneCell {
+  bool on;        // the lane has a cell on this level
+  int i, j, k;    // the cell
+  int c;          // its index (x fastest)
+  int pc;         // index of its parent on the next coarser level
+  Faces<A> fw;    // its face fractions
+  float idg;      // its 1 / diag
+  float pidg;     // 1 / diag of the parent
+};
+
+template <typename A>
+__device__ inline float lane_sweep(const Dims& d, const LaneCell<A>& q, float r, float xc, const float* src) {
+  const float Ax = apply_A(d, q.fw, q.i, q.j, q.k, q.c, xc, [&](long p) { return src[p]; });
+  return xc + kOmega * q.idg * (r - Ax);
+}
+
+// Coarsest level l of the bottom from 0: returns the buffer holding the result
+// and leaves the lane's own value in x.
+template <typename A>
+__device__ inline const float* lane_coarsest(const Dims& d, const LaneCell<A>& q, float r, float* Zb, float* Tb,
+                                             float& x) {
+  const int n = (int)d.cells();
+  const int ext = max(d.nx, max(d.ny, d.nz));
+  const int sweeps = min(kCoarseSweepsMax, 2 * ext * ext);
+  // sweep s writes Zb when s is even, Tb when odd; the first starts from 0
+  x = q.on ? kOmega * q.idg * r : 0.0f;
+  if (q.on) Zb[q.c] = x;
+  if (n <= 64) {
+    // the cells sit on lanes 0 .. n-1 of the first wavefront, whose LDS
+    // operations are performed in order: only the compiler needs a barrier
+    if (threadIdx.x < 64) {
+      for (int s = 1; s < sweeps; ++s) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const float* src = (s & 1) ? Zb : Tb;
+        float* dst = (s & 1) ? Tb : Zb;
+        if (q.on) {
+          x = lane_sweep(d, q, r, x, src);
+          dst[q.c] = x;
+        }
+      }
+    }
+  } else {
+    for (int s = 1; s < sweeps; ++s) {
+      __syncthreads();
+      const float* src = (s & 1) ? Zb : Tb;
+      float* dst = (s & 1) ? Tb : Zb;
+      if (q.on) {
+        x = lane_sweep(d, q, r, x, src);
+        dst[q.c] = x;
+      }
+    }
+  }
+  __syncthreads();
+  return ((sweeps - 1) & 1) ? Tb : Zb;
+}
+
+template <typename A, typename R, typename Z>
+__global__ __launch_bounds__(1024) void k_mg_bottom_lanes(Bottom<A> B, const R* __restrict__ rin,
+                                                          Z* __restrict__ zout, const CGScalars* sc, int lvl0) {
+  if (sc->done) return;
+  extern __shared__ float lds[];
+  const int t = threadIdx.x, L = B.nl;
+  const float s0 = level_scale(sc, lvl0);
+  auto R_ = [&](int l) { return lds + B.off[l]; };
+  auto Z_ = [&](int l) { return lds + B.off[l] + (int)B.d[l].cells(); };
+  auto T_ = [&](int l) { return lds + B.off[l] + 2 * (int)B.d[l].cells(); };
+  const Dims dc = B.d[L - 1];
+  // every lane's cell and coefficients on every level, and the residual of
+  // the finest, in one batch of loads
+  LaneCell<A> o[kBottomLaneLevels];
+  float rv[kBottomLaneLevels], zv[kBottomLaneLevels];
+#pragma unroll
+  for (int l = 0; l < kBottomLaneLevels; ++l) {
+    LaneCell<A>& q = o[l];
+    q.i = q.j = q.k = 0;
+    q.on = l < L && bottom_cell(t, l, L, dc.nx, dc.ny, dc.nz, q.i, q.j, q.k);
+    q.c = q.pc = 0;
+    q.idg = q.pidg = 0.0f;
+    for (int f = 0; f < 6; ++f) q.fw.w[f] = 0.0f;
+    rv[l] = zv[l] = 0.0f;
+    if (q.on) {
+      const Dims d = B.d[l];
+      q.c = d.c(q.i, q.j, q.k);
+      q.fw = Faces<A>(d, B.ax[l], B.ay[l], B.az[l], q.i, q.j, q.k);
+      q.idg = ld(B.invd[l], q.c);
+      if (l + 1 < L) {
+        q.pc = B.d[l + 1].c(q.i >> 1, q.j >> 1, q.k >> 1);
+        q.pidg = ld(B.invd[l + 1], q.pc);
+      }
+    }
+  }
+  if (o[0].on) rv[0] = s0 * ld(rin, o[0].c);
+
+  // down: kBottomSweeps sweeps from 0 on every level but the coarsest, then
+  // the residual's mean over the 8 children into the parent, with the
+  // parent's first sweep from 0 (w D^-1 r) beside it
+#pragma unroll
+  for (int l = 0; l + 1 < kBottomLaneLevels; ++l) {
+    if (l + 1 >= L) break;
+    const Dims d = B.d[l];
+    const LaneCell<A>& q = o[l];
+    float* Zb = Z_(l);
+    float* Tb = T_(l);
+    float t1;
+    if (l == 0) {
+      t1 = kOmega * q.idg * rv[0];
+      if (q.on) Tb[q.c] = t1;
+      __syncthreads();
+    } else {
+      rv[l] = q.on ? R_(l)[q.c] : 0.0f;
+      t1 = q.on ? Tb[q.c] : 0.0f;
+    }
+    float z = q.on ? lane_sweep(d, q, rv[l], t1, Tb) : 0.0f;
+    if (q.on) Zb[q.c] = z;
+    __syncthreads();
+    for (int s = 2; s < kBottomSweeps; s += 2) {
+      const float tt = q.on ? lane_sweep(d, q, rv[l], z, Zb) : 0.0f;
+      if (q.on) Tb[q.c] = tt;
+      __syncthreads();
+      z = q.on ? lane_sweep(d, q, rv[l], tt, Tb) : 0.0f;
+      if (q.on) Zb[q.c] = z;
+      __syncthreads();
+    }
+    zv[l] = z;
+    float res = q.on ? rv[l] - apply_A(d, q.fw, q.i, q.j, q.k, q.c, z, [&](long p) { return Zb[p]; }) : 0.0f;
+    res += __shfl_xor(res, 1);
+    res += __shfl_xor(res, 2);
+    res += __shfl_xor(res, 4);
+    if (q.on && (t & 7) == 0) {
+      const float rc = 0.125f * res;
+      R_(l + 1)[q.pc] = rc;
+      T_(l + 1)[q.pc] = kOmega * q.pidg * rc;
+    }
+    __syncthreads();
+  }
+
+  // coarsest
+  const float* e = nullptr;
+#pragma unroll
+  for (int l = 0; l < kBottomLaneLevels; ++l) {
+    if (l != L - 1) continue;
+    const float r = l == 0 ? rv[0] : (o[l].on ? R_(l)[o[l].c] : 0.0f);
+    float x;
+    e = lane_coarsest(B.d[l], o[l], r, Z_(l), T_(l), x);
+    zv[l] = x;
+  }
+
+  // up: z' = z + 8 e(parent), then kBottomSweeps sweeps
+#pragma unroll
+  for (int l = kBottomLaneLevels - 2; l >= 0; --l) {
+    if (l + 1 >= L) continue;
+    const Dims d = B.d[l];
+    const LaneCell<A>& q = o[l];
+    float* Zb = Z_(l);
+    float* Tb = T_(l);
+    float z = q.on ? zv[l] + 8.0f * e[q.pc] : 0.0f;
+    if (q.on) Zb[q.c] = z;   // the down iterate of this level is not read again
+    __syncthreads();
+    for (int s = 0; s < kBottomSweeps; s += 2) {
+      const float tt = q.on ? lane_sweep(d, q, rv[l], z, Zb) : 0.0f;
+      if (q.on) Tb[q.c] = tt;
+      __syncthreads();
+      z = q.on ? lane_sweep(d, q, rv[l], tt, Tb) : 0.0f;
+      if (q.on) Zb[q.c] = z;
+      if (l > 0 || s + 2 < kBottomSweeps) __syncthreads();
+    }
+    zv[l] = z;
+    e = Zb;
+  }
+  if (o[0].on) zout[o[0].c] = cvt<Z>(zv[0]);
+}
+
 template <typename T>
 __global__ void k_cast(long n, const float* __restrict__ src, T* __restrict__ dst, float cap) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1357,6 +1579,13 @@ static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / 
 // ---------------------------------------------------------------------------
 // host driver
 // ---------------------------------------------------------------------------
+
+// Whether the direction kernel totals the V-cycle's r . z partials itself
+// (fused grid levels above the bottom, at most kRzPartsMax finest tiles);
+// otherwise k_fin_rz does, at the end of the V-cycle.
+static bool rz_in_direction(const Solver& S) {
+  return S.fused && S.nbottom > 0 && tiles_of<FineTile>(S.lev[0].d) <= kRzPartsMax;
+}
 
 // nrr > 0: the V-cycle follows a CG update whose nrr r . r partials have not
 // been totalled yet (the finest fused down kernel does it, else k_fin_rr).
@@ -1384,6 +1613,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
     B.coff[q] = -1;
     off += 3 * (int)S.lev[l].d.cells();
   }
+  const size_t lds_lanes = (size_t)off * sizeof(float);
   // stage coefficients in LDS from the coarsest level up, while they fit
   for (int q = B.nl - 1; q >= 0; --q) {
     const Dims& d = S.lev[G + q].d;
@@ -1394,10 +1624,18 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
   }
   const size_t lds = (size_t)off * sizeof(float);
   const int bthreads = S.lev[G].d.cells() >= 1024 ? 1024 : (int)((S.lev[G].d.cells() + 63) / 64 * 64);
+  // one lane per cell when the finest bottom level fits the workgroup
+  const bool lanes = S.bottom_lanes && S.lev[G].d.cells() <= 1024 && B.nl <= kBottomLaneLevels;
+  auto bottom = [&](auto kernel, auto lanes_kernel, auto rin, auto zout, int lvl0) {
+    if (lanes)
+      NF_LAUNCH(S.prof, SIM_K_MG_COARSE, lanes_kernel, dim3(1), dim3(bthreads), lds_lanes, st, B, rin, zout, sc, lvl0);
+    else
+      NF_LAUNCH(S.prof, SIM_K_MG_COARSE, kernel, dim3(1), dim3(bthreads), lds, st, B, rin, zout, sc, lvl0);
+  };
   if (nrr > 0 && !(S.fused && G > 0))
     hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFinBlock), 0, st, nrr, S.partials_rr, sc, n0);
   if (G == 0) {
-    NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, float, float>), dim3(1), dim3(bthreads), lds, st, B, r0, z0, sc, 1);
+    bottom(k_mg_bottom<T, float, float>, k_mg_bottom_lanes<T, float, float>, r0, z0, 1);
     hipLaunchKernelGGL(k_scale_dot<T>, dim3(nblocks(n0)), dim3(kBlock), 0, st, n0, ID(0), r0, z0, sc, S.partials);
     hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n0), S.partials, sc, S.project);
     return;
@@ -1418,16 +1656,18 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
                            ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
       }
     }
-    NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
-                                (T*)S.lev[G].z, sc, 0);
+    bottom(k_mg_bottom<T, T, T>, k_mg_bottom_lanes<T, T, T>, (const T*)S.lev[G].r, (T*)S.lev[G].z, 0);
     for (int l = G - 1; l >= 0; --l) {
       const Dims& d = S.lev[l].d;
       const Dims& cd = S.lev[l + 1].d;
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
+        const bool merged = rz_in_direction(S);
         NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles(d, true)), dim3(kTileThreads),
-                  0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc, S.partials);
-        hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d, true), S.partials, sc, S.project);
+                  0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
+                  merged ? S.partials_rz : S.partials);
+        if (!merged)
+          hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d, true), S.partials, sc, S.project);
       } else {
         hipLaunchKernelGGL((k_mg_up<CoarseTile, T, T, T, T, T, false, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
                            Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
@@ -1455,8 +1695,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
                          Ay(l), Az(l), rl, (const T*)ta, rc, sc, 0);
     }
   }
-  NF_LAUNCH(S.prof, SIM_K_MG_COARSE, (k_mg_bottom<T, T, T>), dim3(1), dim3(bthreads), lds, st, B, (const T*)S.lev[G].r,
-                              (T*)S.lev[G].z, sc, 0);
+  bottom(k_mg_bottom<T, T, T>, k_mg_bottom_lanes<T, T, T>, (const T*)S.lev[G].r, (T*)S.lev[G].z, 0);
   for (int l = G - 1; l >= 0; --l) {
     const Dims& d = S.lev[l].d;
     const Dims& cd = S.lev[l + 1].d;
@@ -1575,8 +1814,9 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     int npq = nb;
     if (S.fused) {
       npq = tiles_of<FineTile>(d);
+      const int nrz = rz_in_direction(S) ? npq : 0;
       NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply_tile<FineTile>, dim3(npq), dim3(kTileThreads), 0, st, d, S.ax,
-                S.ay, S.az, S.z, pold, pnew, S.q, S.sc, S.partials);
+                S.ay, S.az, S.z, pold, pnew, S.q, S.sc, S.partials, S.partials_rz, nrz, S.project);
     } else {
       NF_LAUNCH(S.prof, SIM_K_CG_APPLY, k_cg_dir_apply, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.z, pold,
                                   pnew, S.q, S.sc, S.partials);

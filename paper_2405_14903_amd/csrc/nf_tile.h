@@ -136,4 +136,29 @@ inline __host__ __device__ unsigned lane_bytes(bool in, int elems, int es) {
   return in ? (unsigned)elems * (unsigned)es : kNoCell;
 }
 
+// One-workgroup bottom solve with one lane per cell on every level: levels
+// 0 .. nl-1 of the bottom, each half the one above along every axis, the
+// coarsest cnx x cny x cnz.  Lanes are numbered children first: lane t owns on
+// level l the cell whose ancestor on the coarsest level is cell t >> 3(nl-1-l)
+// (x fastest) and whose child bits (x + 2y + 4z) on the levels below it are
+// the octal digits of t, the lowest for level l.  So lanes 8C .. 8C+7 of level
+// l own the 8 children of the cell lane C owns on level l+1.  Returns false
+// when level l has no cell for lane t.
+constexpr int kBottomLaneLevels = 4;   // most bottom levels the lane layout handles
+inline __host__ __device__ bool bottom_cell(int t, int l, int nl, int cnx, int cny, int cnz, int& i, int& j, int& k) {
+  const int up = 3 * (nl - 1 - l);
+  const int top = t >> up;
+  if (top >= cnx * cny * cnz) return false;
+  i = top % cnx;
+  j = (top / cnx) % cny;
+  k = top / (cnx * cny);
+  for (int s = up - 3; s >= 0; s -= 3) {
+    const int b = (t >> s) & 7;
+    i = 2 * i + (b & 1);
+    j = 2 * j + ((b >> 1) & 1);
+    k = 2 * k + (b >> 2);
+  }
+  return true;
+}
+
 }  // namespace nf

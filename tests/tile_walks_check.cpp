@@ -2,7 +2,8 @@
 // every in-domain cell of each +H region is visited exactly once, every visited
 // element index (cells, x / y / z faces, parent cells) matches the layout and
 // lies inside its array, out-of-domain cells get the out-of-range lane offset,
-// and the 31-bit byte offsets hold.
+// and the 31-bit byte offsets hold; and the one-workgroup bottom solve's lane
+// layout (one lane per cell, the 8 children of a cell on 8 consecutive lanes).
 // nf_tile.h is plain integer code; compiled here for the host only
 #define __host__
 #define __device__
@@ -103,6 +104,34 @@ void check(int nx, int ny, int nz) {
   for (size_t c = 0; c < seen.size(); ++c) CHECK(seen[c] == 1, "cell %zu owned %d times", c, seen[c]);
 }
 
+// The bottom's lane layout: on every level each cell has exactly one lane,
+// lanes 8C .. 8C+7 own the children of lane C's cell on the next coarser level
+// (so 8-lane groups are whole or empty), and no lane beyond the level's cell
+// count has a cell.
+void check_bottom(int cnx, int cny, int cnz, int nl) {
+  for (int l = 0; l < nl; ++l) {
+    const int f = 1 << (nl - 1 - l);
+    const int nx = cnx * f, ny = cny * f, nz = cnz * f, n = nx * ny * nz;
+    std::vector<int> seen((size_t)n, 0);
+    for (int t = 0; t < 1024; ++t) {
+      int i = -1, j = -1, k = -1;
+      const bool on = bottom_cell(t, l, nl, cnx, cny, cnz, i, j, k);
+      CHECK(on == (t < n), "bottom lane %d on %d, level %d of %d cells", t, on, l, n);
+      if (!on) continue;
+      CHECK(i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz, "bottom cell out of level");
+      if (!(i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz)) continue;
+      seen[i + (size_t)nx * (j + (size_t)ny * k)]++;
+      if (l + 1 < nl) {
+        int pi, pj, pk;
+        const bool pon = bottom_cell(t >> 3, l + 1, nl, cnx, cny, cnz, pi, pj, pk);
+        CHECK(pon && pi == i / 2 && pj == j / 2 && pk == k / 2, "lane %d: parent not on lane %d", t, t >> 3);
+        CHECK((i & 1) + 2 * (j & 1) + 4 * (k & 1) == (t & 7), "lane %d: child bits", t);
+      }
+    }
+    for (int c = 0; c < n; ++c) CHECK(seen[c] == 1, "bottom cell %d owned %d times", c, seen[c]);
+  }
+}
+
 int main() {
   const int dims[][3] = {{128, 128, 128}, {64, 64, 64}, {32, 32, 32}, {16, 16, 16}, {20, 24, 36}, {10, 12, 14},
                          {48, 40, 16}, {8, 8, 8}, {34, 18, 10}, {66, 10, 22}, {30, 30, 30}, {12, 12, 12}, {6, 4, 10}};
@@ -111,6 +140,11 @@ int main() {
     check<CoarseTile>(d[0], d[1], d[2]);
     printf("%dx%dx%d done, errors so far %ld\n", d[0], d[1], d[2], errors);
   }
+  // bottom chains of at most 1024 cells on the finest bottom level
+  const int chains[][4] = {{2, 2, 2, 3}, {1, 1, 1, 4}, {2, 4, 8, 2}, {2, 2, 4, 3}, {3, 5, 2, 2}, {2, 2, 128, 1},
+                           {4, 4, 2, 2}, {1, 2, 3, 3}};
+  for (auto& c : chains) check_bottom(c[0], c[1], c[2], c[3]);
+  printf("bottom lane layouts done, errors so far %ld\n", errors);
   printf(errors ? "FAILED %ld\n" : "OK\n", errors);
   return errors != 0;
 }
