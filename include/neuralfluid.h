@@ -79,10 +79,25 @@ typedef enum { SIM_BC_WALL = 0, SIM_BC_INFLOW = 1, SIM_BC_OUTFLOW = 2, SIM_BC_PE
  *                       a(3), rotation R(9, row-major, body -> world);
  *                       phi = k0 (k0 - 1)/k1 with p = R^T (x - c),
  *                       k0 = |p/a|, k1 = |p/a^2|; ctrl (6) = (v, w),
- *                       u_s(x) = v + w x (x - c).                          */
-typedef enum { SIM_GEOM_NONE = 0, SIM_GEOM_SPHERES = 1, SIM_GEOM_ELLIPSOID = 2 } sim_geom;
+ *                       u_s(x) = v + w x (x - c).
+ *  SIM_GEOM_WALL      : deformable wall on the x- side (the channel
+ *                       configuration; a reading of it): displacement
+ *                       d(y, z, t) = amp s(t) h(y, z), s = (1 - cos 2 pi f t)/2,
+ *                       h = sum_mn a_mn B_m(y) B_n(z) a uniform cubic B-spline
+ *                       over the side (knot spacing L/(M - 3), control m
+ *                       centred at m - 1 spacings; M = SIM_WALL_KNOTS_Y along
+ *                       y, SIM_WALL_KNOTS_Z along z); phi = x - d; the wall
+ *                       moves along x: u_s = amp s'(t) h on x faces, 0 on the
+ *                       others.  theta (SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z)
+ *                       = a, y index major (a[m * SIM_WALL_KNOTS_Z + n]);
+ *                       ctrl (3) = (t, f, amp), t the time of the step's
+ *                       end.  The adjoint accumulates dJ/da into g_theta;
+ *                       t, f and amp get no gradient (g_ctrl is untouched). */
+typedef enum { SIM_GEOM_NONE = 0, SIM_GEOM_SPHERES = 1, SIM_GEOM_ELLIPSOID = 2, SIM_GEOM_WALL = 3 } sim_geom;
 
 #define SIM_MAX_SPHERES 32
+#define SIM_WALL_KNOTS_Y 16
+#define SIM_WALL_KNOTS_Z 32
 
 typedef struct {
   int32_t n[3];           /* cells per axis                                   */
@@ -180,6 +195,17 @@ int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, 
  * layout, overwritten).  lo / hi: host double[3]. */
 int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
                      hipStream_t stream);
+
+/* Loss helper (the channel configuration's outflow flux): J = scale * sum
+ * over the outlet faces (z faces on the z+ side) of w_f u_f, u the stored
+ * face-average velocity (Eq. u_next_matrix: alpha W + (1 - alpha) u_s, the
+ * flux density through the face), and g = dJ/du = scale * w on those faces,
+ * 0 elsewhere.  w: device floats, nx * ny outlet weights (x fastest), or
+ * NULL for 1 everywhere.  J: one device double (overwritten, FP64
+ * fixed-order sum); g: device floats (velocity layout, overwritten).  The
+ * time-integrated flux of a step is scale = dt dx^2. */
+int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double scale, double* J, float* g,
+                        hipStream_t stream);
 
 /* Kernel timing for measurement: while enabled, the launches of one kernel
  * family are timed on the launch stream (multigrid kernels: finest level

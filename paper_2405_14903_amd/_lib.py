@@ -14,14 +14,16 @@ LIB_PATH = os.path.join(HERE, "libneuralfluid.so")
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
-SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID = 0, 1, 2
+SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL = 0, 1, 2, 3
 SIM_MAX_SPHERES = 32
+SIM_WALL_KNOTS_Y, SIM_WALL_KNOTS_Z = 16, 32
 
 #: every symbol declared in include/neuralfluid.h
 EXPORTS = [
     "sim_version", "sim_status_string", "sim_footprint", "sim_create", "sim_destroy", "sim_layout",
     "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
-    "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_profile", "sim_profile_read",
+    "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
+    "sim_profile_read",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -92,6 +94,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_ellipsoid_poses": (C.c_int32, [_dp, _dp, C.c_int32, C.c_double, _dp]),
         "sim_ellipsoid_poses_adjoint": (C.c_int32, [_dp, _dp, C.c_int32, C.c_double, _dp, _dp, _dp, _dp]),
         "sim_loss_box": (C.c_int32, [_vp, _fp, _dp, _dp, _vp, _fp, _vp]),
+        "sim_loss_outlet": (C.c_int32, [_vp, _fp, _fp, C.c_double, _vp, _fp, _vp]),
         "sim_profile": (C.c_int32, [_vp, C.c_int32]),
         "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }

@@ -29,6 +29,8 @@ struct sim_ctx {
   float* y = nullptr;       // adjoint pressure
   float* stage = nullptr;   // per-brick LDS windows of the advection adjoint
   double* trace = nullptr;  // back-traced positions (6 FP64 per face) for the advection adjoint
+  double* knots = nullptr;      // B-spline wall: control amplitudes of the current call
+  double* wall_cols = nullptr;  // B-spline wall: per-column totals of its adjoint
   std::vector<void*> allocs;
   GeomParams last_geom;
   bool have_geom = false;
@@ -82,6 +84,9 @@ int validate_desc(const sim_desc* d) {
     case SIM_GEOM_ELLIPSOID:
       if (d->n_params != 15 || d->n_ctrl != 6) return SIM_EINVAL;
       break;
+    case SIM_GEOM_WALL:
+      if (d->n_params != SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z || d->n_ctrl != 3) return SIM_EINVAL;
+      break;
     default:
       return SIM_EINVAL;
   }
@@ -118,6 +123,10 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(kUpdateBlocks * 8, (void**)&t->S.partials_rr);
   alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
+  if (d->geom == SIM_GEOM_WALL) {
+    alloc(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z * 8, (void**)&t->knots);
+    alloc(wall_column_doubles(d0) * 8, (void**)&t->wall_cols);
+  }
   for (int l = 0; l < p.nlev; ++l) {
     const Dims& dl = p.dims[l];
     Level& L = t->S.lev[l];
@@ -147,9 +156,35 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   }
 }
 
-int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g) {
+int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g, hipStream_t st) {
   std::memset(&g, 0, sizeof(g));
   g.kind = c->desc.geom;
+  if (g.kind == SIM_GEOM_WALL) {
+    if (!theta || !ctrl) return SIM_EINVAL;
+    constexpr int nk = SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z;
+    double amax = 0.0;
+    for (int s = 0; s < nk; ++s) {
+      if (!std::isfinite(theta[s])) return SIM_EINVAL;
+      amax = std::max(amax, std::fabs(theta[s]));
+    }
+    for (int s = 0; s < 3; ++s)
+      if (!std::isfinite(ctrl[s])) return SIM_EINVAL;
+    // pageable source: the copy has taken the values when the call returns
+    if (hipMemcpyAsync(c->knots, theta, nk * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+      return SIM_EHIP;
+    const double t = ctrl[0], f = ctrl[1], w = 2.0 * M_PI * f;
+    g.knots = c->knots;
+    g.amp = ctrl[2];
+    g.wall_s = 0.5 * (1.0 - std::cos(w * t));
+    g.wall_sd = M_PI * f * std::sin(w * t);
+    g.ly = c->desc.n[1] * c->desc.dx;
+    g.lz = c->desc.n[2] * c->desc.dx;
+    // |d| <= |amp s| max|a| (the bases are non-negative and sum to one), and
+    // a face with alpha < 1 has a corner with x <= d
+    const double dmax = std::fabs(g.amp * g.wall_s) * amax;
+    g.wall_imax = (int)std::min((double)c->desc.n[0], std::floor(dmax / c->desc.dx) + 1.0);
+    return SIM_OK;
+  }
   if (g.kind == SIM_GEOM_SPHERES) {
     if (!theta) return SIM_EINVAL;
     g.nsph = c->desc.n_params / 4;
@@ -306,7 +341,7 @@ int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, 
                          hipStream_t stream) {
   if (!h) return SIM_EINVAL;
   GeomParams g;
-  int v = make_geom(h, theta, ctrl, g);
+  int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
   if (alpha_out &&
@@ -331,7 +366,7 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
                  sim_stats* st, hipStream_t stream) {
   if (!h || !u_n || !u_n1 || u_n == u_n1) return SIM_EINVAL;
   GeomParams g;
-  int v = make_geom(h, theta, ctrl, g);
+  int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
@@ -343,7 +378,7 @@ int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const 
                     float* p_out, sim_stats* st, hipStream_t stream) {
   if (!h || !u_in || !u_out || u_in == u_out) return SIM_EINVAL;
   GeomParams g;
-  int v = make_geom(h, theta, ctrl, g);
+  int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
   return project_common(h, u_in, g, u_out, p_out, st, stream);
@@ -354,9 +389,10 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
                          hipStream_t stream) {
   if (!h || !u_n || !g_u_n1 || !g_u_n || g_u_n == g_u_n1 || (const float*)g_u_n == u_n) return SIM_EINVAL;
   GeomParams g;
-  int v = make_geom(h, theta, ctrl, g);
+  int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
-  const bool grad = h->desc.geom == SIM_GEOM_ELLIPSOID && (g_theta || g_ctrl);
+  const bool grad = (h->desc.geom == SIM_GEOM_ELLIPSOID && (g_theta || g_ctrl)) ||
+                    (h->desc.geom == SIM_GEOM_WALL && g_theta);
   const double kk = k_factor(h->desc);
   eval_geometry(h, g, stream);
   // the step's advected field (the fluid velocity W on cut faces needs it)
@@ -378,7 +414,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   if (r != SIM_OK) return r;
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
-                            h->S.partials, g_theta, g_ctrl, stream));
+                            h->S.partials, g_theta, g_ctrl, h->wall_cols, stream));
   launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
            launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->trace, h->gu, g_u_n, h->stage, stream));
@@ -405,6 +441,13 @@ int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const doubl
                      hipStream_t stream) {
   if (!h || !u || !lo || !hi || !J || !g || (const float*)g == u) return SIM_EINVAL;
   launch_loss_box(h->dom, lo, hi, u, J, g, h->S.partials, stream);
+  return last_hip_error();
+}
+
+int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double scale, double* J, float* g,
+                        hipStream_t stream) {
+  if (!h || !u || !J || !g || (const float*)g == u || !std::isfinite(scale)) return SIM_EINVAL;
+  launch_loss_outlet(h->dom.d, scale, w, u, J, g, h->S.partials, stream);
   return last_hip_error();
 }
 

@@ -40,6 +40,7 @@ __device__ inline double phi_at(const GeomParams& G, double x, double y, double 
     }
     return k0 * (k0 - 1.0) / k1;
   }
+  if (G.kind == SIM_GEOM_WALL) return x - G.amp * G.wall_s * wall_h(G, y, z);
   return 1.0;
 }
 

@@ -45,6 +45,12 @@ struct GeomParams {
   int nsph;
   double sph[4 * SIM_MAX_SPHERES];
   double c[3], a[3], R[9], v[3], w[3];
+  // B-spline wall: control amplitudes (device, SIM_WALL_KNOTS_Y x SIM_WALL_KNOTS_Z,
+  // y index major), displacement amp * s(t) * h and velocity amp * s'(t) * h
+  const double* knots;
+  double wall_s, wall_sd, amp;
+  double ly, lz;               // extent of the wall side along y and z
+  int wall_imax;               // faces with i > wall_imax are fully fluid
 };
 
 struct Domain {
@@ -127,6 +133,42 @@ __device__ inline int side_kind(const Domain& D, int d, int own) {
   return v;
 }
 
+// Centred cardinal cubic B-spline (support [-2, 2]).
+__host__ __device__ inline double bspline3(double s) {
+  const double a = s < 0.0 ? -s : s;
+  if (a < 1.0) return 2.0 / 3.0 - a * a + 0.5 * a * a * a;
+  if (a < 2.0) {
+    const double b = 2.0 - a;
+    return b * b * b / 6.0;
+  }
+  return 0.0;
+}
+
+// First of the (at most 4) uniform cubic B-spline bases over [0, L] with M
+// controls (spacing L / (M - 3), control m centred at m - 1 spacings) that
+// are nonzero at s; u = s / spacing.
+__host__ __device__ inline int bspline_first(double u) { return (int)floor(u); }
+
+// h(y, z) = sum_mn a_mn B_m(y) B_n(z) of the wall's control amplitudes.
+__device__ inline double wall_h(const GeomParams& G, double y, double z) {
+  const double uy = y * (SIM_WALL_KNOTS_Y - 3) / G.ly, uz = z * (SIM_WALL_KNOTS_Z - 3) / G.lz;
+  const int my = bspline_first(uy), mz = bspline_first(uz);
+  double h = 0.0;
+  for (int p = 0; p < 4; ++p) {
+    const int m = my + p;
+    if (m < 0 || m >= SIM_WALL_KNOTS_Y) continue;
+    const double by = bspline3(uy - (m - 1));
+    double row = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int n = mz + q;
+      if (n < 0 || n >= SIM_WALL_KNOTS_Z) continue;
+      row += G.knots[m * SIM_WALL_KNOTS_Z + n] * bspline3(uz - (n - 1));
+    }
+    h += by * row;
+  }
+  return h;
+}
+
 // Normal component of the solid velocity at face (d, i, j, k), with the
 // domain-side overrides (WALL: 0, INFLOW: speed into the domain).
 __device__ inline double face_solid_velocity(const Domain& D, const GeomParams& G, int d, int i,
@@ -135,6 +177,11 @@ __device__ inline double face_solid_velocity(const Domain& D, const GeomParams& 
   int sk = side_kind(D, d, own);
   if (sk == SIM_BC_WALL) return 0.0;
   if (sk == SIM_BC_INFLOW) return own == 0 ? D.inflow : -D.inflow;
+  if (G.kind == SIM_GEOM_WALL) {
+    // the wall moves along x only
+    if (d != 0) return 0.0;
+    return G.amp * G.wall_sd * wall_h(G, (j + 0.5) * D.dx, (k + 0.5) * D.dx);
+  }
   if (G.kind != SIM_GEOM_ELLIPSOID) return 0.0;
   double x[3] = {(i + (d == 0 ? 0.0 : 0.5)) * D.dx, (j + (d == 1 ? 0.0 : 0.5)) * D.dx,
                  (k + (d == 2 ? 0.0 : 0.5)) * D.dx};

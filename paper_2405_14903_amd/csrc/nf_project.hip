@@ -357,6 +357,155 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_adj_geom(int nb, const double
   }
 }
 
+// ---- the B-spline wall's knot gradient (FP64, fixed order) --------------
+//
+// dJ/da_mn = -amp s sum_nodes dJ/dphi_node B_m(y) B_n(z)
+//            + amp s' sum_(x faces) dJ/du_s,f B_m(y_f) B_n(z_f),
+// phi = x - d depending on (y, z) only, so both sums first collapse along x
+// into per-column totals (k_adj_wall_cols), which each knot then weights over
+// its 4 x 4 support (k_adj_wall_knots).  Faces with alpha < 1 have a corner
+// with phi <= 0, i.e. x <= max d: only the x range up to G.wall_imax
+// contributes.
+
+// dJ/dalpha of face (comp, i, j, k), or 0 where the face does not contribute
+// (alpha = 1, a WALL / INFLOW side, or alpha = 0, whose corners are all solid
+// so that d alpha / d phi = 0); also dJ/du_s = (1 - alpha) h.
+__device__ inline bool wall_face_terms(const Domain& D, const GeomParams& G, float kk, const float* alpha,
+                                       const float* g, const float* y, const float* uhat, const float* p, int comp,
+                                       int i, int j, int k, double& galpha, double& gus) {
+  const Dims& d = D.d;
+  galpha = gus = 0.0;
+  if (i < 0 || j < 0 || k < 0) return false;
+  if (comp == 0 ? (i > d.nx || j >= d.ny || k >= d.nz)
+                : (comp == 1 ? (i >= d.nx || j > d.ny || k >= d.nz) : (i >= d.nx || j >= d.ny || k > d.nz)))
+    return false;
+  const long oy = (long)d.nfx(), oz = oy + (long)d.nfy();
+  const long f = comp == 0 ? (long)d.fx(i, j, k) : (comp == 1 ? oy + d.fy(i, j, k) : oz + d.fz(i, j, k));
+  const float a = alpha[f];
+  if (!(a < 1.0f)) return false;
+  const int own = comp == 0 ? i : (comp == 1 ? j : k);
+  const int sk = side_kind(D, comp, own);
+  if (sk == SIM_BC_WALL || sk == SIM_BC_INFLOW) return false;
+  float yp, ym;
+  face_cells(d, y, comp, i, j, k, yp, ym);
+  const float hf = g[f] + (yp - ym);
+  if (hf == 0.0f) return false;
+  const double us = face_solid_velocity(D, G, comp, i, j, k);
+  if (a > 0.0f) {
+    float pp, pm;
+    face_cells(d, p, comp, i, j, k, pp, pm);
+    const double W = (double)uhat[f] - (double)kk * ((double)pp - (double)pm);
+    galpha = (double)hf * (W - us);
+  }
+  gus = (1.0 - (double)a) * (double)hf;
+  return true;
+}
+
+// dJ/dphi at node (i, j, k) from its face (comp, fi, fj, fk), where the node
+// is the face's cyclic corner q.
+__device__ inline double wall_corner_term(const Domain& D, const GeomParams& G, float kk, const float* alpha,
+                                          const double* phi, const float* g, const float* y, const float* uhat,
+                                          const float* p, int comp, int fi, int fj, int fk, int q) {
+  double galpha, gus;
+  if (!wall_face_terms(D, G, kk, alpha, g, y, uhat, p, comp, fi, fj, fk, galpha, gus) || galpha == 0.0) return 0.0;
+  double ph[4], dg[4];
+  for (int c = 0; c < 4; ++c) ph[c] = phi[corner_node(D.d, comp, fi, fj, fk, c)];
+  fraction_grad(ph, dg);
+  return galpha * dg[q];
+}
+
+// One thread per node column (j, k): cn[j + (ny+1) k] = sum over x of
+// dJ/dphi at the column's nodes; cf[j + ny k] (j < ny, k < nz) = sum over x of
+// dJ/du_s at the column's x faces.  Each node gathers from its 12 faces in a
+// fixed order (node (i, j, k) is corner 0 of the face at (i, j, k) and
+// corners 1 .. 3 of the faces one step down along the face's two tangents).
+__global__ __launch_bounds__(kBlock) void k_adj_wall_cols(Domain D, GeomParams G, float kk,
+                                                           const float* __restrict__ alpha,
+                                                           const double* __restrict__ phi,
+                                                           const float* __restrict__ g,
+                                                           const float* __restrict__ y,
+                                                           const float* __restrict__ uhat,
+                                                           const float* __restrict__ p, double* __restrict__ cn,
+                                                           double* __restrict__ cf) {
+  const Dims& d = D.d;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long)(d.ny + 1) * (d.nz + 1)) return;
+  const int j = (int)(t % (d.ny + 1)), k = (int)(t / (d.ny + 1));
+  const int ilast = min(d.nx, G.wall_imax + 1);
+  double sn = 0.0, sf = 0.0;
+  for (int i = 0; i <= ilast; ++i) {
+    // x faces (tangents y, z): corners (j,k), (j+1,k), (j+1,k+1), (j,k+1)
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k, 0);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k, 1);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k - 1, 2);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k - 1, 3);
+    // y faces (tangents x, z)
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k, 0);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k, 1);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k - 1, 2);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k - 1, 3);
+    // z faces (tangents x, y)
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j, k, 0);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j, k, 1);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j - 1, k, 2);
+    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j - 1, k, 3);
+    if (j < d.ny && k < d.nz) {
+      double galpha, gus;
+      if (wall_face_terms(D, G, kk, alpha, g, y, uhat, p, 0, i, j, k, galpha, gus)) sf += gus;
+    }
+  }
+  cn[t] = sn;
+  if (j < d.ny && k < d.nz) cf[j + (long)d.ny * k] = sf;
+}
+
+// One block per control amplitude (m, n): its bases' weights over the column
+// totals within its support, added to g_theta[m * SIM_WALL_KNOTS_Z + n].
+__global__ __launch_bounds__(kBlock) void k_adj_wall_knots(Domain D, GeomParams G, const double* __restrict__ cn,
+                                                            const double* __restrict__ cf,
+                                                            double* __restrict__ g_theta) {
+  const Dims& d = D.d;
+  const int m = blockIdx.x / SIM_WALL_KNOTS_Z, n = blockIdx.x % SIM_WALL_KNOTS_Z;
+  const double sy = G.ly / (SIM_WALL_KNOTS_Y - 3), sz = G.lz / (SIM_WALL_KNOTS_Z - 3);
+  // nodes and faces with |position / spacing - (m - 1)| < 2
+  const int jlo = max(0, (int)floor((m - 3) * sy / D.dx)), jhi = min(d.ny, (int)ceil((m + 1) * sy / D.dx));
+  const int klo = max(0, (int)floor((n - 3) * sz / D.dx)), khi = min(d.nz, (int)ceil((n + 1) * sz / D.dx));
+  const int wj = jhi - jlo + 1, wk = khi - klo + 1;
+  double v[2] = {0.0, 0.0};
+  for (int q = threadIdx.x; q < wj * wk; q += blockDim.x) {
+    const int j = jlo + q % wj, k = klo + q / wj;
+    const double by = bspline3(j * D.dx / sy - (m - 1)), bz = bspline3(k * D.dx / sz - (n - 1));
+    v[0] += cn[j + (long)(d.ny + 1) * k] * by * bz;
+    if (j < d.ny && k < d.nz) {
+      const double fy = bspline3((j + 0.5) * D.dx / sy - (m - 1)), fz = bspline3((k + 0.5) * D.dx / sz - (n - 1));
+      v[1] += cf[j + (long)d.ny * k] * fy * fz;
+    }
+  }
+  __shared__ double sh[2 * (kBlock / 64) + 1];
+  block_sum<2, kBlock>(v, sh);
+  if (threadIdx.x == 0) g_theta[blockIdx.x] += -G.amp * G.wall_s * v[0] + G.amp * G.wall_sd * v[1];
+}
+
+// J = scale * sum over the outlet faces (z faces with k = nz) of w u; g = scale w
+// there, 0 elsewhere (w = 1 when no weights are given).
+__global__ __launch_bounds__(kBlock) void k_loss_outlet(Dims d, double scale, const float* __restrict__ w,
+                                                         const float* __restrict__ u, float* __restrict__ g,
+                                                         double* __restrict__ partials) {
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (f < (long)d.faces()) {
+    const long o = (long)d.nfx() + (long)d.nfy() + (long)d.nx * d.ny * d.nz;   // first outlet face
+    if (f >= o) {
+      const long q = f - o;
+      const double wf = w ? (double)w[q] : 1.0;
+      g[f] = (float)(scale * wf);
+      v[0] = scale * wf * (double)u[f];
+    } else {
+      g[f] = 0.0f;
+    }
+  }
+  block_partials<1>(v, partials);
+}
+
 // J = sum of u_f^2 over faces whose centre lies in [lo, hi]; g = 2 u there.
 __global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, double lo1, double lo2, double hi0,
                                                       double hi1, double hi2, const float* __restrict__ u,
@@ -445,11 +594,31 @@ FaceBox ellipsoid_face_box(const Dims& d, double dx, const GeomParams& G) {
   return B;
 }
 
+void launch_loss_outlet(const Dims& d, double scale, const float* w, const float* u, double* J, float* g,
+                        double* partials, hipStream_t s) {
+  const int nb = (int)nblocks(d.faces());
+  hipLaunchKernelGGL(k_loss_outlet, dim3(nb), dim3(kBlock), 0, s, d, scale, w, u, g, partials);
+  hipLaunchKernelGGL(k_fin_loss, dim3(1), dim3(kFinBlock), 0, s, nb, partials, J);
+}
+
+size_t wall_column_doubles(const Dims& d) { return (size_t)(d.ny + 1) * (d.nz + 1) + (size_t)d.ny * d.nz; }
+
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, double* g_theta, double* g_ctrl, hipStream_t s) {
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* wall_cols,
+                      hipStream_t s) {
   hipLaunchKernelGGL(k_adj_faces, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D.d, alpha, g, y, gu);
   if (!grad) return;
+  if (G.kind == SIM_GEOM_WALL) {
+    if (!g_theta) return;
+    double* cn = wall_cols;
+    double* cf = wall_cols + (size_t)(D.d.ny + 1) * (D.d.nz + 1);
+    hipLaunchKernelGGL(k_adj_wall_cols, dim3(nblocks((size_t)(D.d.ny + 1) * (D.d.nz + 1))), dim3(kBlock), 0, s, D,
+                       G, (float)kk, alpha, phi, g, y, uhat, p, cn, cf);
+    hipLaunchKernelGGL(k_adj_wall_knots, dim3(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z), dim3(kBlock), 0, s, D, G, cn,
+                       cf, g_theta);
+    return;
+  }
   const FaceBox B = ellipsoid_face_box(D.d, D.dx, G);
   if (B.start[3] == 0) return;
   // a bounded grid with a grid-stride loop keeps the partial count small

@@ -141,7 +141,11 @@ void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rh
 size_t adj_faces_partials(const Dims& d);
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, double* g_theta, double* g_ctrl, hipStream_t s);
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* wall_cols,
+                      hipStream_t s);
+size_t wall_column_doubles(const Dims& d);
+void launch_loss_outlet(const Dims& d, double scale, const float* w, const float* u, double* J, float* g,
+                        double* partials, hipStream_t s);
 void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
                      double* partials, hipStream_t s);
 // nf_solver.hip

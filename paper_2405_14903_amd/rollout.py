@@ -35,12 +35,15 @@ class Rollout:
     ellipsoid use :meth:`ellipsoid`.
     """
 
-    def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None):
+    def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None, step_loss=None):
         self.sim, self.T, self.schedule = sim, int(T), schedule
         self.K = checkpoint_stride(self.T, every)
         self.grad_geometry = grad_geometry
         self.timer = timer
         self.last_stats = []
+        # step_loss(n, u_next) -> (J_n: device double (1,), dJ_n/du_next): a loss
+        # on every step's result, summed over the rollout
+        self.step_loss = step_loss
 
     @staticmethod
     def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None):
@@ -59,13 +62,28 @@ class Rollout:
         if self.timer:
             self.timer.end("fwd")
 
+    @staticmethod
+    def channel(sim: Sim, knots, f, amp, T, every="sqrt", window=None, timer=None):
+        """The B-spline wall channel: the wall at t = (n + 1) dt in step n, and
+        the time-integrated outflow flux sum_n dt dx^2 sum_outlet w U^{n+1}
+        (window w: device float32 over the nx * ny outlet faces, or None)."""
+        knots = np.ascontiguousarray(knots, np.float64).ravel()
+        dt, dx = sim.cfg.dt, sim.cfg.dx
+        ctrl = [np.array([(n + 1) * dt, f, amp], np.float64) for n in range(T)]
+        loss = lambda n, u: sim.loss_outlet(u, dt * dx * dx, window)   # noqa: E731
+        ro = Rollout(sim, T, lambda n: (knots, ctrl[n]), every, grad_geometry=True, timer=timer, step_loss=loss)
+        return ro
+
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
         self.ckpt = {0: u0.detach().clone()}
         a = u0.detach().clone()
         b = torch.empty_like(a)
+        self.J = torch.zeros(1, dtype=torch.float64, device=u0.device) if self.step_loss else None
         for n in range(self.T):
             self._step(n, a, b)
             a, b = b, a
+            if self.step_loss:
+                self.J += self.step_loss(n, a)[0]
             if (n + 1) % self.K == 0 and n + 1 < self.T:
                 self.ckpt[n + 1] = a.clone()
         return a
@@ -87,6 +105,8 @@ class Rollout:
                 self._step(n, states[n - s], states[n - s + 1], press[n - s])
             for n in range(e - 1, s - 1, -1):
                 th, ct = self.schedule(n)
+                if self.step_loss:
+                    g += self.step_loss(n, states[n - s + 1])[1]
                 if self.timer:
                     self.timer.begin("adj")
                 sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
@@ -103,6 +123,29 @@ class Rollout:
         gs = self.g_steps.cpu().numpy()
         gd = self.g_ctrl_direct.cpu().numpy()
         return ellipsoid_poses_adjoint(self.theta0, self.ctrl, self.sim.cfg.dt, gs, gd)
+
+
+class ChannelRolloutFn(torch.autograd.Function):
+    """J = time-integrated outflow flux of the B-spline wall channel, as a
+    torch.autograd.Function of (u0, knots); checkpoints every ceil(sqrt(T))
+    steps by default.  u0: device float32; knots: CPU float64
+    (SIM_WALL_KNOTS_Y x SIM_WALL_KNOTS_Z)."""
+
+    @staticmethod
+    def forward(ctx, u0, knots, sim: Sim, f, amp, T, every="sqrt", window=None):
+        ro = Rollout.channel(sim, knots.detach().cpu().numpy(), f, amp, T, every, window)
+        ro.forward(u0)
+        ctx.ro = ro
+        ctx.kshape, ctx.kdev = knots.shape, knots.device
+        return ro.J.clone()
+
+    @staticmethod
+    def backward(ctx, gJ):
+        ro = ctx.ro
+        s = float(gJ.reshape(-1)[0])
+        g0 = ro.backward(torch.zeros_like(ro.ckpt[0]))
+        gk = ro.g_steps.sum(dim=0).cpu().reshape(ctx.kshape)
+        return s * g0, (s * gk).to(ctx.kdev), None, None, None, None, None, None
 
 
 class EllipsoidRolloutFn(torch.autograd.Function):

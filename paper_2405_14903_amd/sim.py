@@ -18,7 +18,8 @@ from . import _lib as L
 _BC = {"wall": L.SIM_BC_WALL, "inflow": L.SIM_BC_INFLOW, "outflow": L.SIM_BC_OUTFLOW,
        "periodic": L.SIM_BC_PERIODIC}
 _PREC = {"fp32": L.SIM_FP32, "fp16": L.SIM_MIXED_FP16, "bf16": L.SIM_MIXED_BF16}
-_GEOM = {"none": L.SIM_GEOM_NONE, "spheres": L.SIM_GEOM_SPHERES, "ellipsoid": L.SIM_GEOM_ELLIPSOID}
+_GEOM = {"none": L.SIM_GEOM_NONE, "spheres": L.SIM_GEOM_SPHERES, "ellipsoid": L.SIM_GEOM_ELLIPSOID,
+         "wall": L.SIM_GEOM_WALL}
 
 
 @dataclass
@@ -53,6 +54,8 @@ class Config:
             d.n_params, d.n_ctrl = 4 * int(self.n_spheres), 0
         elif d.geom == L.SIM_GEOM_ELLIPSOID:
             d.n_params, d.n_ctrl = 15, 6
+        elif d.geom == L.SIM_GEOM_WALL:
+            d.n_params, d.n_ctrl = L.SIM_WALL_KNOTS_Y * L.SIM_WALL_KNOTS_Z, 3
         else:
             d.n_params, d.n_ctrl = 0, 0
         return d
@@ -192,6 +195,20 @@ class Sim:
         L.check(self.lib.sim_loss_box(self.h, _ptr(u, self.nf, torch.float32, "u"), lop, hip,
                                       _ptr(J, 1, torch.float64, "J"), _ptr(g, self.nf, torch.float32, "g"),
                                       _stream()), "sim_loss_box")
+        return J, g
+
+    def loss_outlet(self, u, scale, w=None, J=None, g=None):
+        """J = scale * sum over the outlet faces of w u (device double) and g = dJ/du;
+        w: nx * ny outlet weights (device float32) or None for 1."""
+        if J is None:
+            J = torch.empty(1, dtype=torch.float64, device=u.device)
+        if g is None:
+            g = torch.empty_like(u)
+        nxy = self.cfg.n[0] * self.cfg.n[1]
+        L.check(self.lib.sim_loss_outlet(self.h, _ptr(u, self.nf, torch.float32, "u"),
+                                         _ptr(w, nxy, torch.float32, "w") if w is not None else None,
+                                         float(scale), _ptr(J, 1, torch.float64, "J"),
+                                         _ptr(g, self.nf, torch.float32, "g"), _stream()), "sim_loss_outlet")
         return J, g
 
     def profile(self, kernel):

@@ -30,7 +30,8 @@ import scipy.ndimage
 __all__ = [
     "face_shapes", "n_faces", "curl_noise", "ellipsoid_theta0", "controls",
     "sphere_center", "random_spheres", "face_noise", "Scene",
-    "scene_sphere_rollout", "scene_ellipsoid_rollout", "scene_spheres_projection",
+    "scene_sphere_rollout", "scene_ellipsoid_rollout", "scene_spheres_projection", "scene_channel",
+    "outlet_window_xy",
 ]
 
 
@@ -114,7 +115,7 @@ class Scene:
     dx: float
     dt: float
     u0: np.ndarray
-    geom: str                       # "none" | "spheres" | "ellipsoid"
+    geom: str                       # "none" | "spheres" | "ellipsoid" | "wall"
     spheres: np.ndarray = None      # (m, 4) for geom == "spheres"
     theta0: np.ndarray = None       # (9,) for geom == "ellipsoid"
     ctrl: np.ndarray = None         # (steps, 6) for geom == "ellipsoid"
@@ -157,3 +158,40 @@ def scene_spheres_projection(seed=0, n=256, count=20):
     dx = 1.0 / n
     u = curl_noise((n, n, n), dx, rng) + face_noise((n, n, n), rng)
     return Scene((n, n, n), dx, 0.5 * dx, u, "spheres", spheres=sph, steps=1)
+
+
+# the channel configuration: 1 x 1 x 2 box, 256 x 256 x 512 cells at full size
+CHANNEL_LENGTH = (1.0, 1.0, 2.0)
+CHANNEL_FULL_N = (256, 256, 512)
+CHANNEL_FULL_STEPS = 200
+
+
+def scene_channel(seed=0, n=(32, 32, 64), steps=200):
+    """Inflow / outflow channel with a deformable B-spline wall on the x- side.
+    Draws (same at every resolution): 16 x 32 control amplitudes U[0, 1], the
+    wall frequency f ~ U[1/T, 2/T] with T = 200 dt of the full-size grid
+    (dt = dx/2, dx = 1/256), and the outlet window's phase psi ~ U[0, 2 pi).
+    Initial velocity: curl noise with max |u| = 1 (normal component 0 on every
+    side).  extra: knots, f, amp (= 0.1), psi."""
+    rng = np.random.default_rng(seed)
+    knots = rng.uniform(0.0, 1.0, size=(16, 32))
+    T = CHANNEL_FULL_STEPS * 0.5 / CHANNEL_FULL_N[0]
+    f = rng.uniform(1.0 / T, 2.0 / T)
+    psi = rng.uniform(0.0, 2.0 * math.pi)
+    n = tuple(int(v) for v in n)
+    dx = CHANNEL_LENGTH[0] / n[0]
+    noise_rng = np.random.default_rng([seed, *n])
+    u0 = curl_noise(n, dx, noise_rng)
+    return Scene(n, dx, 0.5 * dx, u0, "wall", steps=steps, extra=dict(knots=knots, f=f, amp=0.1, psi=psi))
+
+
+def outlet_window_xy(n, dx, psi):
+    """Outlet weights (nx * ny, x fastest) of the smooth window over the half
+    x > Lx/2: sin^2(2 pi (x/Lx - 1/2)) (1 + sin(2 pi y/Ly + psi) / 2) at the face
+    centres, 0 for x <= Lx/2."""
+    nx, ny = int(n[0]), int(n[1])
+    x = (np.arange(nx) + 0.5) * dx / (nx * dx)
+    y = (np.arange(ny) + 0.5) * dx / (ny * dx)
+    wx = np.where(x > 0.5, np.sin(2.0 * math.pi * (x - 0.5)) ** 2, 0.0)
+    wy = 1.0 + 0.5 * np.sin(2.0 * math.pi * y + psi)
+    return (wy[:, None] * wx[None, :]).ravel()
