@@ -69,6 +69,11 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--workload", default="rollout128", choices=["rollout128", "channel"],
+                    help="channel: the 256x256x512 inflow / outflow channel with the B-spline wall, "
+                         "200 steps forward + adjoint, sqrt(T) checkpoints, total outflow flux loss, "
+                         "gradients w.r.t. the 512 control amplitudes (FP16 V-cycle)")
+    ap.add_argument("--channel-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference kernel that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run")
@@ -168,7 +173,7 @@ def pct(v, q):
     return round(s[i], 4)
 
 
-def roofline(prof, precision):
+def roofline(prof, precision, n3=(N, N, N), traffic=True):
     """Algorithmic bytes per launch of the finest-level up kernel of the
     V-cycle (coarse correction z' = z2 + 8 e(parent), two damped-Jacobi sweeps,
     r.z partials): it reads z2 (FP32), the coarse correction e (storage type,
@@ -176,8 +181,9 @@ def roofline(prof, precision):
     arrays (storage type; each face once) and the previous z (FP32, for the
     flexible direction coefficient), and writes z (FP32)."""
     es = 4 if precision == "fp32" else 2
-    C = N ** 3
-    F = (N + 1) * N * N * 3
+    nx, ny, nz = n3
+    C = nx * ny * nz
+    F = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
     bytes_per_launch = C * 4 + (C // 8) * es + C * 4 + C * es + F * es + C * 4 + C * 4
     ms, cnt = prof
     if not cnt:
@@ -185,7 +191,7 @@ def roofline(prof, precision):
     avg_s = ms / cnt / 1e3
     achieved = bytes_per_launch / avg_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision),
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(precision) if traffic else None,
             "kernel": "k_mg_up (finest level, " + precision + ")", "launches": cnt,
             "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch}
 
@@ -215,6 +221,64 @@ def cpu_baseline(steps):
                       f"solve to 1e-10), {wall:.1f} s wall, {cpu:.1f} s CPU (numpy/scipy)"}
 
 
+def run_channel(args, torch):
+    """The channel configuration: one warm-up rollout of a few steps, then one
+    timed rollout of --channel-steps steps forward + adjoint."""
+    import scenes
+    from paper_2405_14903_amd.sim import Config, Sim
+    from paper_2405_14903_amd.rollout import Rollout
+    n3, T = scenes.CHANNEL_FULL_N, args.channel_steps
+    sc = scenes.scene_channel(seed=0, n=n3, steps=T)
+    kn, f, amp = sc.extra["knots"], sc.extra["f"], sc.extra["amp"]
+    cfg = Config(n=n3, dx=sc.dx, dt=sc.dt, bc=("wall", "wall", "wall", "wall", "inflow", "outflow"),
+                 inflow_speed=1.0, geom="wall", tol=1e-6, precision=args.precision, max_iter=400)
+    sim = Sim(cfg)
+    u0 = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
+    zero = torch.zeros_like(u0)
+
+    def one(steps, timer):
+        ro = Rollout.channel(sim, kn, f, amp, steps, every="sqrt", timer=timer)
+        ro.forward(u0)
+        ro.backward(zero)
+        return ro
+
+    one(4, None)
+    torch.cuda.synchronize()
+    print("[bench] channel: warmup done", file=sys.stderr, flush=True)
+    sim.profile(ROOFLINE_KERNEL)
+    timer = StepTimer(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ro = one(T, timer)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    prof = sim.profile_read(min_ms=NOOP_MS)
+    sim.profile(None)
+    print(f"[bench] channel: {T} steps forward + adjoint in {wall:.2f} s", file=sys.stderr, flush=True)
+    gk = ro.g_steps.sum(dim=0)
+    fwd, adj = timer.latencies("fwd"), timer.latencies("adj")
+    C = n3[0] * n3[1] * n3[2]
+    rec = {
+        "metric": "fwd+adjoint cell-steps/s, 256x256x512 channel (mixed); p50/p99 step latency",
+        "value": round(C * T / wall, 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * wall, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": f"256x256x512 channel, B-spline wall (16x32 control amplitudes), inflow / outflow, "
+                               f"{T} steps forward + adjoint, sqrt(T) checkpoints, total outflow flux",
+                   "grid": list(n3), "steps_per_rollout": T, "checkpoint_every": ro.K,
+                   "precision": args.precision, "cg_tol": 1e-6},
+        "latency_ms": {"step_p50": pct(fwd + adj, 50), "step_p99": pct(fwd + adj, 99),
+                       "fwd_p50": pct(fwd, 50), "fwd_p99": pct(fwd, 99), "adj_p50": pct(adj, 50),
+                       "adj_p99": pct(adj, 99)},
+        "loss": float(ro.J.item()), "knot_gradient_norm": float(gk.norm()),
+        "roofline": roofline(prof, args.precision, n3, traffic=False),
+        "cpu_baseline": None,
+    }
+    sim.close()
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -229,6 +293,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(args.copy_probe, torch)
+        return
+    if args.workload == "channel":
+        run_channel(args, torch)
         return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
     main_form, prof, _ = run_form(args.precision, args.steps, args.warmup, scene, torch,
