@@ -1641,19 +1641,23 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
     return;
   }
   if (S.fused) {
-    auto tiles = [](const Dims& d, bool fine) {
-      return (unsigned)(fine ? tiles_of<FineTile>(d) : tiles_of<CoarseTile>(d));
-    };
+    // coarse levels of at least kWideTileCells cells use 16 x 8 x 8 tiles (half
+    // the workgroups and less halo per cell), smaller ones 8 x 8 x 8 (enough
+    // workgroups to spread their latency-bound launches)
+    auto wide = [](const Dims& d) { return d.cells() >= (size_t)kWideTileCells; };
     for (int l = 0; l < G; ++l) {
       const Dims& d = S.lev[l].d;
       const Dims& cd = S.lev[l + 1].d;
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
-        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles(d, true)), dim3(kTileThreads), 0, st,
+        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st,
                   d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1, S.partials_rr, nrr, n0);
+      } else if (wide(d)) {
+        hipLaunchKernelGGL((k_mg_down<CoarseTileH, T, T, T, T, true>), dim3(tiles_of<CoarseTileH>(d)), dim3(kTileThreads), 0, st, d, cd,
+                           A(l), Ay(l), Az(l), ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
       } else {
-        hipLaunchKernelGGL((k_mg_down<CoarseTile, T, T, T, T, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l), Az(l),
-                           ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
+        hipLaunchKernelGGL((k_mg_down<CoarseTile, T, T, T, T, true>), dim3(tiles_of<CoarseTile>(d)), dim3(kTileThreads), 0, st, d, cd,
+                           A(l), Ay(l), Az(l), ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
       }
     }
     bottom(k_mg_bottom<T, T, T>, k_mg_bottom_lanes<T, T, T>, (const T*)S.lev[G].r, (T*)S.lev[G].z, 0);
@@ -1663,14 +1667,18 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
         const bool merged = rz_in_direction(S);
-        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles(d, true)), dim3(kTileThreads),
+        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles_of<FineTile>(d)), dim3(kTileThreads),
                   0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
                   merged ? S.partials_rz : S.partials);
         if (!merged)
-          hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles(d, true), S.partials, sc, S.project);
+          hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles_of<FineTile>(d), S.partials, sc, S.project);
+      } else if (wide(d)) {
+        hipLaunchKernelGGL((k_mg_up<CoarseTileH, T, T, T, T, T, false, true>), dim3(tiles_of<CoarseTileH>(d)), dim3(kTileThreads), 0, st,
+                           d, cd, A(l), Ay(l), Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
+                           S.partials);
       } else {
-        hipLaunchKernelGGL((k_mg_up<CoarseTile, T, T, T, T, T, false, true>), dim3(tiles(d, false)), dim3(kTileThreads), 0, st, d, cd, A(l), Ay(l),
-                           Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
+        hipLaunchKernelGGL((k_mg_up<CoarseTile, T, T, T, T, T, false, true>), dim3(tiles_of<CoarseTile>(d)), dim3(kTileThreads), 0, st,
+                           d, cd, A(l), Ay(l), Az(l), ID(l), (const T*)S.lev[l].r, (const T*)S.lev[l].ta, e, (T*)S.lev[l].z, sc,
                            S.partials);
       }
     }

@@ -38,6 +38,10 @@ struct TileShape {
 // launches are latency-bound: less serial work per thread, more workgroups).
 using FineTile = TileShape<32, 8, 8>;
 using CoarseTile = TileShape<8, 8, 8>;
+// Coarse levels of at least kWideTileCells cells: 16-cell rows, half the
+// workgroups and less halo per cell.
+using CoarseTileH = TileShape<16, 8, 8>;
+constexpr long kWideTileCells = 1L << 18;
 constexpr int kTileThreads = 512;   // 8 waves per tile
 
 constexpr unsigned kNoCell = 0x80000000u;   // lane offset of a lane outside the domain

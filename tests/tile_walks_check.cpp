@@ -138,6 +138,7 @@ int main() {
   for (auto& d : dims) {
     check<FineTile>(d[0], d[1], d[2]);
     check<CoarseTile>(d[0], d[1], d[2]);
+    check<CoarseTileH>(d[0], d[1], d[2]);
     printf("%dx%dx%d done, errors so far %ld\n", d[0], d[1], d[2], errors);
   }
   // bottom chains of at most 1024 cells on the finest bottom level
