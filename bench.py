@@ -69,11 +69,13 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=32)
-    ap.add_argument("--workload", default="rollout128", choices=["rollout128", "channel"],
+    ap.add_argument("--workload", default="rollout128", choices=["rollout128", "channel", "serving"],
                     help="channel: the 256x256x512 inflow / outflow channel with the B-spline wall, "
                          "200 steps forward + adjoint, sqrt(T) checkpoints, total outflow flux loss, "
                          "gradients w.r.t. the 512 control amplitudes (FP16 V-cycle)")
     ap.add_argument("--channel-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference kernel that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run")
@@ -279,6 +281,44 @@ def run_channel(args, torch):
     print(json.dumps(rec), flush=True)
 
 
+def run_serving(args, torch):
+    """The serving configuration on a bounded stream: --serve-requests seeded
+    requests with Poisson arrivals at --serve-rate req/s (grid sizes
+    {32, 48, 64, 96, 128, 192}^3, 8 to 64 steps, half forward-only and half
+    forward + adjoint), served with continuous batching and the FP16 V-cycle
+    within an HBM budget, against the same requests run serially in FP32."""
+    from paper_2405_14903_amd.serving import make_stream, serve, serve_serial
+    N_req, rate = args.serve_requests, args.serve_rate
+    budget = 200 << 30
+
+    def done(tag):
+        return lambda r: print(f"[bench] {tag}: request {r.rid} ({r.n}^3, {r.steps} steps, {r.mode}) done "
+                               f"at {r.finished:.2f} s", file=sys.stderr, flush=True)
+
+    served = serve(make_stream(N_req, rate, seed=0), budget_bytes=budget, precision=args.precision, max_active=8,
+                   realtime=True, on_done=done("served"))
+    print(f"[bench] serving: {served}", file=sys.stderr, flush=True)
+    serial = serve_serial(make_stream(N_req, rate, seed=0), precision="fp32", on_done=done("serial"))
+    print(f"[bench] serial FP32: {serial}", file=sys.stderr, flush=True)
+    rec = {
+        "metric": f"serving: cell-steps/s and p50/p99 step latency, {N_req} requests at {rate:g} req/s",
+        "value": round(served["cell_steps_per_s"], 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(1e3 * served["wall_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
+        "data": "synthetic",
+        "config": {"workload": f"{N_req} requests, Poisson arrivals at {rate:g} req/s, grids {{32..192}}^3, "
+                               f"8-64 steps, half forward-only, half forward + adjoint; continuous batching, "
+                               f"8 concurrent episodes, {budget >> 30} GiB budget",
+                   "precision": args.precision},
+        "served": served, "serial_fp32": serial,
+        "speedup_vs_serial_fp32": round(served["cell_steps_per_s"] / serial["cell_steps_per_s"], 3)
+        if serial["cell_steps_per_s"] else None,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -296,6 +336,9 @@ def main():
         return
     if args.workload == "channel":
         run_channel(args, torch)
+        return
+    if args.workload == "serving":
+        run_serving(args, torch)
         return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
     main_form, prof, _ = run_form(args.precision, args.steps, args.warmup, scene, torch,

@@ -237,8 +237,9 @@ class HandlePool:
         self.free.clear()
 
 
-def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, timing=True):
-    """Run the stream with continuous batching.  Returns a summary dict."""
+def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, timing=True, on_done=None):
+    """Run the stream with continuous batching.  Returns a summary dict.
+    on_done(req), if given, is called from the loop as each request completes."""
     pool = HandlePool(precision)
     adm = Admission(budget_bytes, max_active,
                     lambda r: sim_footprint(pool.cfg(r.n)) + episode_bytes(r.n, r.steps, r.mode))
@@ -284,8 +285,11 @@ def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True,
                     wait = max(0.0, min(wait, pending[i].arrival - (time.perf_counter() - t0)))
                 cv.wait(timeout=wait)
             while done_q:
-                adm.release(done_q.popleft())
+                r = done_q.popleft()
+                adm.release(r)
                 finished += 1
+                if on_done:
+                    on_done(r)
     for th in threads:
         th.join()
     wall = time.perf_counter() - t0
@@ -294,7 +298,7 @@ def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True,
     return summarize(requests, wall, rejected)
 
 
-def serve_serial(requests, precision="fp32", timing=True):
+def serve_serial(requests, precision="fp32", timing=True, on_done=None):
     """Baseline: one request at a time, FIFO, in arrival order (no overlap)."""
     pool = HandlePool(precision)
     stream = torch.cuda.Stream()
@@ -308,6 +312,8 @@ def serve_serial(requests, precision="fp32", timing=True):
             req.error = repr(e)
         req.finished = time.perf_counter() - t0
         pool.put(req.n, sim)
+        if on_done:
+            on_done(req)
     wall = time.perf_counter() - t0
     pool.close()
     return summarize(requests, wall, [])
@@ -316,9 +322,10 @@ def serve_serial(requests, precision="fp32", timing=True):
 def summarize(requests, wall, rejected):
     ok = [r for r in requests if not r.error]
     steps = [ms for r in ok for ms in r.step_ms]
+    # every step counts once (a forward step and its adjoint are one cell-step,
+    # as in the rollout benchmark); a projection request counts as one step
     cell_steps = 0
     for r in ok:
-        mult = 1 if r.mode == "poisson" else r.steps * (2 if r.mode == "fwd+adj" else 1)
         cell_steps += r.n ** 3 * (1 if r.mode == "poisson" else r.steps)
     lat = [r.finished - r.arrival for r in ok if not math.isnan(r.finished)]
 
