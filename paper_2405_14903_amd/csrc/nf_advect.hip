@@ -137,8 +137,11 @@ __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0,
   const float* uc[3] = {u, u + d.nfx(), u + d.nfx() + d.nfy()};
   double Xf[3], v0[3], Xm[3], v1[3], Xs[3];
   face_pos(comp, i, j, k, Xf);
+  // the face's own component at the face is the face's value: its lattice
+  // coordinates are integers, so every fraction is 0 (or 1 on the last face,
+  // where the lerp returns the upper value exactly)
 #pragma unroll
-  for (int e = 0; e < 3; ++e) v0[e] = tap_value(uc[e], make_tap(d, e, Xf));
+  for (int e = 0; e < 3; ++e) v0[e] = e == comp ? (double)u[f] : tap_value(uc[e], make_tap(d, e, Xf));
 #pragma unroll
   for (int a = 0; a < 3; ++a) Xm[a] = Xf[a] - 0.5 * cfl * v0[a];
 #pragma unroll
