@@ -122,6 +122,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(npart * 8, (void**)&t->S.partials);
   alloc(kUpdateBlocks * 8, (void**)&t->S.partials_rr);
   alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
+  if (d->precision != SIM_FP32) alloc(C * 16, &t->S.rec0);
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
   if (d->geom == SIM_GEOM_WALL) {
     alloc(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z * 8, (void**)&t->knots);
@@ -316,6 +317,14 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
     (void)hipGetLastError();
     sim_destroy(c);
     return SIM_ENOMEM;
+  }
+  // with 2-byte multigrid storage the finest fused down kernel reads packed
+  // coefficient records where their views fit 31-bit offsets (NF_MG_RECORDS=0:
+  // the separate arrays)
+  {
+    const char* rc = std::getenv("NF_MG_RECORDS");
+    const bool want = !(rc && rc[0] == '0');
+    if (!want || !c->S.fused || c->S.nbottom == 0 || !views_fit(p.dims[0].nx, p.dims[0].ny, 16)) c->S.rec0 = nullptr;
   }
   *out = c;
   return SIM_OK;

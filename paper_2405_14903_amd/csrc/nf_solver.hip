@@ -741,6 +741,79 @@ __device__ inline Faces<A> faces_at(const FaceViews& V, unsigned fe, unsigned ce
   return f;
 }
 
+// Packed coefficients of one finest-level cell in 2-byte storage: the six
+// face fractions (in Faces order) and 1/diag as storage bits in eight halves
+// (16 bytes), so that a phase reads them with one wide load instead of seven
+// narrow ones.  Built by k_pack_records.  (FP32 storage keeps the arrays: its
+// 32-byte records cost the finest kernels more in bytes than they saved in
+// load instructions.)
+struct alignas(16) Rec16 {
+  unsigned w[4];
+};
+template <typename A> struct RecOf { using T = Rec16; };
+template <typename A> constexpr bool kHasRecords = sizeof(A) == 2;
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename A> __device__ inline float dec_lo(unsigned w);
+template <typename A> __device__ inline float dec_hi(unsigned w);
+template <> __device__ inline float dec_lo<__half>(unsigned w) {
+  return __half2float(__builtin_bit_cast(__half, (unsigned short)(w & 0xffffu)));
+}
+template <> __device__ inline float dec_hi<__half>(unsigned w) {
+  return __half2float(__builtin_bit_cast(__half, (unsigned short)(w >> 16)));
+}
+template <> __device__ inline float dec_lo<__hip_bfloat16>(unsigned w) {
+  return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, (unsigned short)(w & 0xffffu)));
+}
+template <> __device__ inline float dec_hi<__hip_bfloat16>(unsigned w) {
+  return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, (unsigned short)(w >> 16)));
+}
+
+// The record of the cell in plane kr (lane offset ce in bytes): its faces and
+// 1/diag (0 for lanes outside the domain, as the separate arrays give).
+template <typename A, bool U>
+__device__ inline Faces<A> rec_faces(Rsrc v, unsigned ce, int kr, const Lev& L, float& id) {
+  using RT = typename RecOf<A>::T;
+  const At a = at<U>(ce, (unsigned)(kr * L.pc) * (unsigned)sizeof(RT));
+  Faces<A> f;
+  const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(v, (int)a.v, (int)a.s, 0);
+  f.w[0] = dec_lo<A>(q.x);
+  f.w[1] = dec_hi<A>(q.x);
+  f.w[2] = dec_lo<A>(q.y);
+  f.w[3] = dec_hi<A>(q.y);
+  f.w[4] = dec_lo<A>(q.z);
+  f.w[5] = dec_hi<A>(q.z);
+  id = dec_lo<A>(q.w);
+  return f;
+}
+
+template <typename A> __device__ inline unsigned bits_of(A v);
+template <> __device__ inline unsigned bits_of<__half>(__half v) {
+  return __builtin_bit_cast(unsigned short, v);
+}
+template <> __device__ inline unsigned bits_of<__hip_bfloat16>(__hip_bfloat16 v) {
+  return __builtin_bit_cast(unsigned short, v);
+}
+
+// One record per cell of the finest level from its fraction arrays and 1/diag.
+template <typename A>
+__global__ void k_pack_records(Dims d, const A* __restrict__ ax, const A* __restrict__ ay, const A* __restrict__ az,
+                               const A* __restrict__ invd, typename RecOf<A>::T* __restrict__ rec) {
+  static_assert(kHasRecords<A>, "packed records hold 2-byte storage");
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  int i, j, k;
+  cdec(d, c, i, j, k);
+  const unsigned v[8] = {bits_of<A>(ax[d.fx(i, j, k)]), bits_of<A>(ax[d.fx(i + 1, j, k)]),
+                         bits_of<A>(ay[d.fy(i, j, k)]), bits_of<A>(ay[d.fy(i, j + 1, k)]),
+                         bits_of<A>(az[d.fz(i, j, k)]), bits_of<A>(az[d.fz(i, j, k + 1)]),
+                         bits_of<A>(invd[c]),           0u};
+  typename RecOf<A>::T r;
+  for (int q = 0; q < 4; ++q) r.w[q] = v[2 * q] | (v[2 * q + 1] << 16);
+  rec[c] = r;
+}
+
 // A cell-frame value of type T in plane kr (lane offset ce in bytes).
 template <typename T, bool U>
 __device__ inline float cell_at(Rsrc v, unsigned ce, int kr, const Lev& L) {
@@ -759,11 +832,11 @@ __device__ inline void cell_put(Rsrc v, unsigned ce, int kr, const Lev& L, float
 // three; for the small coarse levels, whose launches are latency-bound and few
 // tiles wide).  Without PRE each phase loads what it needs, which keeps
 // registers low for the finest level.
-template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN>
+template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN, bool REC>
 __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                              const A* invd, const R* r, Z* z2out, RC* rc, CGScalars* sc, int lvl0,
                                              const double* rr_parts, int nrr, long ncells, int i0, int j0, int k0,
-                                             float* z1s, float* z2s, double* rr_sh) {
+                                             float* z1s, float* z2s, double* rr_sh, const void* rec) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -773,6 +846,11 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   const FaceViews V = face_views(ax, ay, az, L, i0, j0, k0);
   const Rsrc vid = view(invd, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Rsrc vr = view(r, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  // packed coefficient records (REC): one view over the cell frame
+  static_assert(!REC || kHasRecords<A>, "packed records hold 2-byte storage");
+  using RecT = typename RecOf<A>::T;
+  constexpr int kRB = (int)sizeof(RecT);
+  const Rsrc VR = view((const RecT*)rec, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Rsrc vz = view(z2out, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Lane l2 = lane_of<S, 2>(t, walk_group<S, 2>(t), i0, j0, L.nx, L.ny);
   const Lane l1 = lane_of<S, 1>(t, walk_group<S, 1>(t), i0, j0, L.nx, L.ny);
@@ -793,8 +871,12 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
 #pragma unroll
     for (int u = 0; u < W1::T; ++u) {
       const int kr = l1.z + u;
-      fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
-      id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      if constexpr (REC) {
+        fw2[u] = rec_faces<A, W1::kUniform>(VR, on_plane<ZIN>(lane_bytes(l1.in, l1.ce, kRB), m1, u), kr, L, id2[u]);
+      } else {
+        fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
+        id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      }
       rv2[u] = cell_at<R, W1::kUniform>(vr, on_plane<ZIN>(cr, m1, u), kr, L);
     }
   };
@@ -803,7 +885,12 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
                    cr = lane_bytes(l0.in, l0.ce, eR);
 #pragma unroll
     for (int u = 0; u < W0::T; ++u) {
-      fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), l0.z + u, L);
+      if constexpr (REC) {
+        float idd;
+        fw3[u] = rec_faces<A, W0::kUniform>(VR, on_plane<ZIN>(lane_bytes(l0.in, l0.ce, kRB), m0, u), l0.z + u, L, idd);
+      } else {
+        fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), l0.z + u, L);
+      }
       rv3[u] = cell_at<R, W0::kUniform>(vr, on_plane<ZIN>(cr, m0, u), l0.z + u, L);
     }
   };
@@ -884,13 +971,14 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   }
 }
 
-template <class S, typename A, typename R, typename Z, typename RC, bool PRE>
+// REC (finest level): the coefficients come from the packed records `rec`.
+template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool REC = false>
 __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
                                                           const A* __restrict__ ay, const A* __restrict__ az,
                                                           const A* __restrict__ invd, const R* __restrict__ r,
                                                           Z* __restrict__ z2out, RC* __restrict__ rc,
                                                           CGScalars* sc, int lvl0, const double* rr_parts, int nrr,
-                                                          long ncells) {
+                                                          long ncells, const void* rec = nullptr) {
   static_assert(Walk<S, 0>::N <= Walk<S, 2>::N, "the tile residual reuses the first sweep's array");
   __shared__ float z1s[Walk<S, 2>::N];   // first sweep on the +2 region; then the tile's residual
   __shared__ float z2s[Walk<S, 1>::N];
@@ -899,11 +987,11 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   if (planes_inside<S>(k0, d.nz))
-    mg_down_tile<S, A, R, Z, RC, PRE, true>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr, ncells, i0,
-                                            j0, k0, z1s, z2s, &rr_sh);
+    mg_down_tile<S, A, R, Z, RC, PRE, true, REC>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr,
+                                                 ncells, i0, j0, k0, z1s, z2s, &rr_sh, rec);
   else
-    mg_down_tile<S, A, R, Z, RC, PRE, false>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr, ncells,
-                                             i0, j0, k0, z1s, z2s, &rr_sh);
+    mg_down_tile<S, A, R, Z, RC, PRE, false, REC>(d, cd, ax, ay, az, invd, r, z2out, rc, sc, lvl0, rr_parts, nrr,
+                                                  ncells, i0, j0, k0, z1s, z2s, &rr_sh, rec);
 }
 
 // Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
@@ -1650,8 +1738,19 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
       const Dims& cd = S.lev[l + 1].d;
       T* rc = (T*)S.lev[l + 1].r;
       if (l == 0) {
-        NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st,
-                  d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1, S.partials_rr, nrr, n0);
+        bool done = false;
+        if constexpr (kHasRecords<T>) {
+          if (S.rec0) {
+            NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false, true>),
+                      dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0,
+                      (float*)S.lev[0].ta, rc, sc, 1, S.partials_rr, nrr, n0, (const void*)S.rec0);
+            done = true;
+          }
+        }
+        if (!done)
+          NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false>), dim3(tiles_of<FineTile>(d)),
+                    dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (float*)S.lev[0].ta, rc, sc, 1,
+                    S.partials_rr, nrr, n0, nullptr);
       } else if (wide(d)) {
         hipLaunchKernelGGL((k_mg_down<CoarseTileH, T, T, T, T, true>), dim3(tiles_of<CoarseTileH>(d)), dim3(kTileThreads), 0, st, d, cd,
                            A(l), Ay(l), Az(l), ID(l), (const T*)S.lev[l].r, (T*)S.lev[l].ta, rc, sc, 0, nullptr, 0, 0L);
@@ -1667,6 +1766,8 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
         const bool merged = rz_in_direction(S);
+        // (the up kernel reads the arrays: packed records left its time unchanged
+        // and would add their duplicated faces to its bytes)
         NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles_of<FineTile>(d)), dim3(kTileThreads),
                   0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
                   merged ? S.partials_rz : S.partials);
@@ -1748,6 +1849,16 @@ static void cast_level(const Dims& d, const float* lx, const float* ly, const fl
                      invcap);
 }
 
+// The finest level's packed coefficient records, from its (storage-type)
+// fraction arrays and 1/diag.
+template <typename T>
+static void pack_records(const Solver& S, hipStream_t st) {
+  if (!S.rec0) return;
+  const Level& L = S.lev[0];
+  hipLaunchKernelGGL(k_pack_records<T>, dim3(nblocks(L.d.cells())), dim3(kBlock), 0, st, L.d, (const T*)L.a[0],
+                     (const T*)L.a[1], (const T*)L.a[2], (const T*)L.invd, (typename RecOf<T>::T*)S.rec0);
+}
+
 // Multigrid copies of the fine fractions and inverse diagonals.
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
   const Dims& d0 = S.lev[0].d;
@@ -1810,6 +1921,10 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     else
       cast_level<__hip_bfloat16>(d, lx, ly, lz, S.scratch_inv, S.lev[l], cap, st);
   }
+  if (S.precision == SIM_MIXED_FP16)
+    pack_records<__half>(S, st);
+  else
+    pack_records<__hip_bfloat16>(S, st);
 }
 
 static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) {

@@ -128,11 +128,12 @@ inline __host__ __device__ bool planes_inside(int k0, int nz) {
 }
 
 // Whether a grid's +2 tile regions fit the views' 31-bit byte offsets
-// (largest plane length times the planes a region spans, 4-byte elements).
-inline __host__ __device__ bool views_fit(int nx, int ny) {
+// (largest plane length times the planes a region spans, elements of es
+// bytes: 4 for the arrays, 16 for the finest level's packed records).
+inline __host__ __device__ bool views_fit(int nx, int ny, int es = 4) {
   const long plane = (long)(nx + 1) * ny > (long)nx * (ny + 1) ? (long)(nx + 1) * ny : (long)nx * (ny + 1);
   const int tz = FineTile::TZ > CoarseTile::TZ ? FineTile::TZ : CoarseTile::TZ;
-  return ((long)(tz + 6) * plane + 2L * (nx + 1)) * 4 < (long)kViewRecords;
+  return ((long)(tz + 6) * plane + 2L * (nx + 1)) * es < (long)kViewRecords;
 }
 
 // Lane byte offset of an array of element size es (kNoCell outside the domain).
