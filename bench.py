@@ -42,8 +42,8 @@ NOOP_MS = 0.003
 # (--copy-probe 256: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x);
 # see profiles/mg_up_128_fp16_traffic.md.  Valid only for the kernel sources
 # it was measured on (first 16 hex digits of their SHA-256).
-TRAFFIC = {"fp16": 55700890}
-TRAFFIC_SOURCES = {"paper_2405_14903_amd/csrc/nf_solver.hip": "d154edd116f3bc53",
+TRAFFIC = {"fp16": 92992762}
+TRAFFIC_SOURCES = {"paper_2405_14903_amd/csrc/nf_solver.hip": "e2abe4b9eea82b85",
                    "paper_2405_14903_amd/csrc/nf_internal.h": "b9df1959a6a94b2d",
                    "paper_2405_14903_amd/csrc/nf_tile.h": "e8ea510b23a106e7"}
 
@@ -179,14 +179,14 @@ def roofline(prof, precision, n3=(N, N, N), traffic=True):
     """Algorithmic bytes per launch of the finest-level up kernel of the
     V-cycle (coarse correction z' = z2 + 8 e(parent), two damped-Jacobi sweeps,
     r.z partials): it reads z2 (FP32), the coarse correction e (storage type,
-    C/8 values), r (FP32), 1/diag (storage type), the three face-fraction
-    arrays (storage type; each face once) and the previous z (FP32, for the
-    flexible direction coefficient), and writes z (FP32)."""
+    C/8 values), r (FP32), 1/diag (FP32 in every precision), the three
+    face-fraction arrays (storage type; each face once) and the previous z
+    (FP32, for the flexible direction coefficient), and writes z (FP32)."""
     es = 4 if precision == "fp32" else 2
     nx, ny, nz = n3
     C = nx * ny * nz
     F = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
-    bytes_per_launch = C * 4 + (C // 8) * es + C * 4 + C * es + F * es + C * 4 + C * 4
+    bytes_per_launch = C * 4 + (C // 8) * es + C * 4 + C * 4 + F * es + C * 4 + C * 4
     ms, cnt = prof
     if not cnt:
         return None

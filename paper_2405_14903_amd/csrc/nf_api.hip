@@ -122,7 +122,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(npart * 8, (void**)&t->S.partials);
   alloc(kUpdateBlocks * 8, (void**)&t->S.partials_rr);
   alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
-  if (d->precision != SIM_FP32) alloc(C * 16, &t->S.rec0);
+  if (d->precision != SIM_FP32) alloc(C * (16 + 4), &t->S.rec0);   // records, then 1/diag in FP32
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
   if (d->geom == SIM_GEOM_WALL) {
     alloc(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z * 8, (void**)&t->knots);
@@ -318,7 +318,7 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
     sim_destroy(c);
     return SIM_ENOMEM;
   }
-  // with 2-byte multigrid storage the finest fused down kernel reads packed
+  // with 2-byte multigrid storage the finest fused kernels read packed
   // coefficient records where their views fit 31-bit offsets (NF_MG_RECORDS=0:
   // the separate arrays)
   {

@@ -92,7 +92,7 @@ struct Solver {
   int project = 0;
   int fused = 1;       // fused tile kernels per grid level (NF_MG_FUSED=0: four passes per level)
   int bottom_lanes = 1;  // one lane per cell in the bottom solve where it fits (NF_MG_BOTTOM_LANES=0: off)
-  void* rec0 = nullptr;  // finest level's packed coefficient records, 2-byte storage (null: the fused down kernel reads the arrays)
+  void* rec0 = nullptr;  // finest level's packed coefficient records, 2-byte storage (null: the fused kernels read the arrays)
   Level lev[kMaxLevels];
   const float* ax = nullptr;   // fine FP32 fractions (CG operator)
   const float* ay = nullptr;

@@ -741,12 +741,19 @@ __device__ inline Faces<A> faces_at(const FaceViews& V, unsigned fe, unsigned ce
   return f;
 }
 
-// Packed coefficients of one finest-level cell in 2-byte storage: the six
-// face fractions (in Faces order) and 1/diag as storage bits in eight halves
-// (16 bytes), so that a phase reads them with one wide load instead of seven
-// narrow ones.  Built by k_pack_records.  (FP32 storage keeps the arrays: its
-// 32-byte records cost the finest kernels more in bytes than they saved in
-// load instructions.)
+// Packed coefficients of one finest-level cell with 2-byte multigrid storage
+// (16 bytes, one wide load instead of seven narrow ones): the six face weights
+// beta_f = alpha_f / diag in the storage type (Faces order) and 1/diag in
+// FP32.  The weights lie in [0, 1] whatever the fractions, and 1/diag keeps
+// its full range: the separate 2-byte arrays cap 1/diag at the largest finite
+// FP16 value and hold fractions below its smallest normal with few bits, which
+// a cut cell nearly inside the solid needs (diag < 1/65504 occurs every step
+// of a moving body).  A sweep then reads z + w (r/diag - sum beta_f (z - z_f)).
+// Built by k_pack_records from the FP32 fractions, with 1/diag also as a plain
+// FP32 array right after the records (for reads of 1/diag alone, which would
+// otherwise touch a whole record per value).  (FP32 storage keeps the arrays:
+// its 32-byte records cost the finest kernels more in bytes than they saved
+// in load instructions.)
 struct alignas(16) Rec16 {
   unsigned w[4];
 };
@@ -770,8 +777,14 @@ template <> __device__ inline float dec_hi<__hip_bfloat16>(unsigned w) {
   return __bfloat162float(__builtin_bit_cast(__hip_bfloat16, (unsigned short)(w >> 16)));
 }
 
-// The record of the cell in plane kr (lane offset ce in bytes): its faces and
-// 1/diag (0 for lanes outside the domain, as the separate arrays give).
+// Storage bits to float.  The word is taken by value: a bit cast applied
+// directly to an element of a vector value compiles (with this toolchain) to a
+// read of the vector's first element, whatever the element named.
+__device__ inline float f32_of(unsigned w) { return __builtin_bit_cast(float, w); }
+
+// The record of the cell in plane kr (lane offset ce in bytes): its face
+// weights beta_f and 1/diag (all 0 for inactive cells and lanes outside the
+// domain).
 template <typename A, bool U>
 __device__ inline Faces<A> rec_faces(Rsrc v, unsigned ce, int kr, const Lev& L, float& id) {
   using RT = typename RecOf<A>::T;
@@ -784,8 +797,13 @@ __device__ inline Faces<A> rec_faces(Rsrc v, unsigned ce, int kr, const Lev& L, 
   f.w[3] = dec_hi<A>(q.y);
   f.w[4] = dec_lo<A>(q.z);
   f.w[5] = dec_hi<A>(q.z);
-  id = dec_lo<A>(q.w);
+  id = f32_of(q.w);
   return f;
+}
+
+// The FP32 1/diag array that follows the records of a level of `cells` cells.
+__device__ inline const float* rec_invd_array(const void* rec, long cells) {
+  return (const float*)((const Rec16*)rec + cells);
 }
 
 template <typename A> __device__ inline unsigned bits_of(A v);
@@ -796,22 +814,28 @@ template <> __device__ inline unsigned bits_of<__hip_bfloat16>(__hip_bfloat16 v)
   return __builtin_bit_cast(unsigned short, v);
 }
 
-// One record per cell of the finest level from its fraction arrays and 1/diag.
+// One record per cell of the finest level from its FP32 face fractions (1/diag
+// as k_invdiag forms it).
 template <typename A>
-__global__ void k_pack_records(Dims d, const A* __restrict__ ax, const A* __restrict__ ay, const A* __restrict__ az,
-                               const A* __restrict__ invd, typename RecOf<A>::T* __restrict__ rec) {
+__global__ void k_pack_records(Dims d, const float* __restrict__ ax, const float* __restrict__ ay,
+                               const float* __restrict__ az, typename RecOf<A>::T* __restrict__ rec,
+                               float* __restrict__ invd) {
   static_assert(kHasRecords<A>, "packed records hold 2-byte storage");
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= (long)d.cells()) return;
   int i, j, k;
   cdec(d, c, i, j, k);
-  const unsigned v[8] = {bits_of<A>(ax[d.fx(i, j, k)]), bits_of<A>(ax[d.fx(i + 1, j, k)]),
-                         bits_of<A>(ay[d.fy(i, j, k)]), bits_of<A>(ay[d.fy(i, j + 1, k)]),
-                         bits_of<A>(az[d.fz(i, j, k)]), bits_of<A>(az[d.fz(i, j, k + 1)]),
-                         bits_of<A>(invd[c]),           0u};
+  const float a[6] = {ax[d.fx(i, j, k)], ax[d.fx(i + 1, j, k)], ay[d.fy(i, j, k)],
+                      ay[d.fy(i, j + 1, k)], az[d.fz(i, j, k)], az[d.fz(i, j, k + 1)]};
+  const float s = a[0] + a[1] + a[2] + a[3] + a[4] + a[5];
+  const float id = s > 0.0f ? 1.0f / s : 0.0f;
+  unsigned b[6];
+  for (int f = 0; f < 6; ++f) b[f] = bits_of<A>(cvt<A>(a[f] * id));
   typename RecOf<A>::T r;
-  for (int q = 0; q < 4; ++q) r.w[q] = v[2 * q] | (v[2 * q + 1] << 16);
+  for (int q = 0; q < 3; ++q) r.w[q] = b[2 * q] | (b[2 * q + 1] << 16);
+  r.w[3] = __builtin_bit_cast(unsigned, id);
   rec[c] = r;
+  invd[c] = id;
 }
 
 // A cell-frame value of type T in plane kr (lane offset ce in bytes).
@@ -851,6 +875,8 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   using RecT = typename RecOf<A>::T;
   constexpr int kRB = (int)sizeof(RecT);
   const Rsrc VR = view((const RecT*)rec, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  const Rsrc VI = view(REC ? rec_invd_array(rec, (long)d.cells()) : (const float*)nullptr, L.nx, L.pc, i0 - 2,
+                       j0 - 2, k0 - 2);
   const Rsrc vz = view(z2out, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Lane l2 = lane_of<S, 2>(t, walk_group<S, 2>(t), i0, j0, L.nx, L.ny);
   const Lane l1 = lane_of<S, 1>(t, walk_group<S, 1>(t), i0, j0, L.nx, L.ny);
@@ -858,7 +884,7 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   const unsigned m2 = ZIN ? ~0u : plane_mask(k0, l2.z, L.nz, W2::T);
   const unsigned m1 = ZIN ? ~0u : plane_mask(k0, l1.z, L.nz, W1::T);
   const unsigned m0 = ZIN ? ~0u : plane_mask(k0, l0.z, L.nz, W0::T);
-  float id1[W2::T], rv1[W2::T], id2[W1::T], rv2[W1::T], rv3[W0::T];
+  float id1[W2::T], rv1[W2::T], id2[W1::T], rv2[W1::T], id3[W0::T], rv3[W0::T];
   Faces<A> fw2[W1::T], fw3[W0::T];
   // the update's r . r partials are read before this kernel's own loads, so
   // that totalling them waits only for them
@@ -886,10 +912,10 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
 #pragma unroll
     for (int u = 0; u < W0::T; ++u) {
       if constexpr (REC) {
-        float idd;
-        fw3[u] = rec_faces<A, W0::kUniform>(VR, on_plane<ZIN>(lane_bytes(l0.in, l0.ce, kRB), m0, u), l0.z + u, L, idd);
+        fw3[u] = rec_faces<A, W0::kUniform>(VR, on_plane<ZIN>(lane_bytes(l0.in, l0.ce, kRB), m0, u), l0.z + u, L, id3[u]);
       } else {
         fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), l0.z + u, L);
+        id3[u] = 0.0f;
       }
       rv3[u] = cell_at<R, W0::kUniform>(vr, on_plane<ZIN>(cr, m0, u), l0.z + u, L);
     }
@@ -898,7 +924,10 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
     const unsigned ce = lane_bytes(l2.in, l2.ce, eA), cr = lane_bytes(l2.in, l2.ce, eR);
 #pragma unroll
     for (int u = 0; u < W2::T; ++u) {
-      id1[u] = cell_at<A, W2::kUniform>(vid, on_plane<ZIN>(ce, m2, u), l2.z + u, L);
+      if constexpr (REC)
+        id1[u] = cell_at<float, W2::kUniform>(VI, on_plane<ZIN>(lane_bytes(l2.in, l2.ce, 4), m2, u), l2.z + u, L);
+      else
+        id1[u] = cell_at<A, W2::kUniform>(vid, on_plane<ZIN>(ce, m2, u), l2.z + u, L);
       rv1[u] = cell_at<R, W2::kUniform>(vr, on_plane<ZIN>(cr, m2, u), l2.z + u, L);
     }
   }
@@ -935,7 +964,9 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
       const int z = l1.z + u;
       const int qq = q2 + u * W2::PL;
       const float rr = s0 * rv2[u];
-      const float z2 = rnd<Z>(z1s[qq] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)));
+      const float z2 =
+          REC ? rnd<Z>(z1s[qq] + kOmega * (id2[u] * rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)))
+              : rnd<Z>(z1s[qq] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)));
       cell_put<Z, W1::kUniform>(vz, (z >= 2 && z < S::TZ + 2) ? on_plane<ZIN>(oz, m1, u) : kNoCell, z, L, z2);
       z2s[l1.q + u * W1::PL] = z2;
     }
@@ -948,7 +979,9 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
 #pragma unroll
     for (int u = 0; u < W0::T; ++u) {
       const int qq = q1 + u * W1::PL;
-      z1s[l0.q + u * W0::PL] = s0 * rv3[u] - apply_local(fw3[u], z2s, qq, W1::X, W1::PL);
+      const float Az = apply_local(fw3[u], z2s, qq, W1::X, W1::PL);
+      // records: A z2 = diag * (the weighted sum); an inactive cell has none
+      z1s[l0.q + u * W0::PL] = s0 * rv3[u] - (REC ? (id3[u] > 0.0f ? Az / id3[u] : 0.0f) : Az);
     }
   }
   __syncthreads();
@@ -995,11 +1028,11 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const
 }
 
 // Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
-template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool ZIN>
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool ZIN, bool REC>
 __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                            const A* invd, const R* r, const Z* z2, const E* e, O* zout, float s0,
                                            float inv, bool first, int i0, int j0, int k0, float* zp, float* z3s,
-                                           double (&acc)[4]) {
+                                           double (&acc)[4], const void* rec) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -1009,6 +1042,10 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
   const FaceViews V = face_views(ax, ay, az, L, i0, j0, k0);
   const Rsrc vid = view(invd, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Rsrc vr = view(r, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
+  // packed coefficient records (REC): one view over the cell frame
+  static_assert(!REC || kHasRecords<A>, "packed records hold 2-byte storage");
+  constexpr int kRB = (int)sizeof(Rec16);
+  const Rsrc VR = view((const Rec16*)rec, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Rsrc vz2 = view(z2, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const Rsrc vzo = view(zout, L.nx, L.pc, i0 - 2, j0 - 2, k0 - 2);
   const int cpc = cd.nx * cd.ny;
@@ -1028,8 +1065,12 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
 #pragma unroll
     for (int u = 0; u < W1::T; ++u) {
       const int kr = l1.z + u;
-      fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
-      id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      if constexpr (REC) {
+        fw2[u] = rec_faces<A, W1::kUniform>(VR, on_plane<ZIN>(lane_bytes(l1.in, l1.ce, kRB), m1, u), kr, L, id2[u]);
+      } else {
+        fw2[u] = faces_at<A, W1::kUniform>(V, on_plane<ZIN>(fe, m1, u), on_plane<ZIN>(ce, m1, u), kr, L);
+        id2[u] = cell_at<A, W1::kUniform>(vid, on_plane<ZIN>(ce, m1, u), kr, L);
+      }
       rv2[u] = cell_at<R, W1::kUniform>(vr, on_plane<ZIN>(cr, m1, u), kr, L);
     }
   };
@@ -1039,8 +1080,12 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
 #pragma unroll
     for (int u = 0; u < W0::T; ++u) {
       const int kr = l0.z + u;
-      fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), kr, L);
-      id3[u] = cell_at<A, W0::kUniform>(vid, on_plane<ZIN>(ce, m0, u), kr, L);
+      if constexpr (REC) {
+        fw3[u] = rec_faces<A, W0::kUniform>(VR, on_plane<ZIN>(lane_bytes(l0.in, l0.ce, kRB), m0, u), kr, L, id3[u]);
+      } else {
+        fw3[u] = faces_at<A, W0::kUniform>(V, on_plane<ZIN>(fe, m0, u), on_plane<ZIN>(ce, m0, u), kr, L);
+        id3[u] = cell_at<A, W0::kUniform>(vid, on_plane<ZIN>(ce, m0, u), kr, L);
+      }
       rv3[u] = cell_at<R, W0::kUniform>(vr, on_plane<ZIN>(cr, m0, u), kr, L);
       zold[u] = (LVL0 && !first) ? cell_at<O, W0::kUniform>(vzo, on_plane<ZIN>(co, m0, u), kr, L) : 0.0f;
     }
@@ -1072,8 +1117,9 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
 #pragma unroll
     for (int u = 0; u < W1::T; ++u) {
       const int qq = q2 + u * W2::PL;
+      const float Az = apply_local(fw2[u], zp, qq, W2::X, W2::PL);
       z3s[l1.q + u * W1::PL] =
-          zp[qq] + kOmega * id2[u] * (s0 * rv2[u] - apply_local(fw2[u], zp, qq, W2::X, W2::PL));
+          REC ? zp[qq] + kOmega * (id2[u] * (s0 * rv2[u]) - Az) : zp[qq] + kOmega * id2[u] * (s0 * rv2[u] - Az);
     }
   }
   __syncthreads();
@@ -1084,7 +1130,9 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
 #pragma unroll
     for (int u = 0; u < W0::T; ++u) {
       const int qq = q1 + u * W1::PL;
-      float zo = (z3s[qq] + kOmega * id3[u] * (s0 * rv3[u] - apply_local(fw3[u], z3s, qq, W1::X, W1::PL))) * inv;
+      const float Az = apply_local(fw3[u], z3s, qq, W1::X, W1::PL);
+      float zo = (REC ? z3s[qq] + kOmega * (id3[u] * (s0 * rv3[u]) - Az)
+                      : z3s[qq] + kOmega * id3[u] * (s0 * rv3[u] - Az)) * inv;
       if (LVL0 && !(id3[u] > 0.0f)) zo = 0.0f;   // inactive cell (and every cell outside the domain): no unknown
       cell_put<O, W0::kUniform>(vzo, on_plane<ZIN>(co, m0, u), l0.z + u, L, zo);
       if (LVL0) {
@@ -1097,12 +1145,14 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
   }
 }
 
-template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE>
+// REC (finest level): the coefficients come from the packed records `rec`.
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool REC = false>
 __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
                                                         const A* __restrict__ ay, const A* __restrict__ az,
                                                         const A* __restrict__ invd, const R* __restrict__ r,
                                                         const Z* __restrict__ z2, const E* __restrict__ e,
-                                                        O* __restrict__ zout, const CGScalars* sc, double* partials) {
+                                                        O* __restrict__ zout, const CGScalars* sc, double* partials,
+                                                        const void* rec = nullptr) {
   __shared__ float zp[Walk<S, 2>::N];
   __shared__ float z3s[Walk<S, 1>::N];
   if (sc->done) return;
@@ -1113,11 +1163,11 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A
   tile_origin<S>(d, i0, j0, k0);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (planes_inside<S>(k0, d.nz))
-    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0, k0,
-                                                  zp, z3s, acc);
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true, REC>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0,
+                                                       k0, zp, z3s, acc, rec);
   else
-    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0,
-                                                   k0, zp, z3s, acc);
+    mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false, REC>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0,
+                                                        j0, k0, zp, z3s, acc, rec);
   if (LVL0) block_partials<4, kTileThreads>(acc, partials);
 }
 
@@ -1766,11 +1816,19 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
       const T* e = (const T*)S.lev[l + 1].z;
       if (l == 0) {
         const bool merged = rz_in_direction(S);
-        // (the up kernel reads the arrays: packed records left its time unchanged
-        // and would add their duplicated faces to its bytes)
-        NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>), dim3(tiles_of<FineTile>(d)), dim3(kTileThreads),
-                  0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0, (const float*)S.lev[0].ta, e, z0, sc,
-                  merged ? S.partials_rz : S.partials);
+        bool done = false;
+        if constexpr (kHasRecords<T>) {
+          if (S.rec0) {
+            NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false, true>),
+                      dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0,
+                      (const float*)S.lev[0].ta, e, z0, sc, merged ? S.partials_rz : S.partials, (const void*)S.rec0);
+            done = true;
+          }
+        }
+        if (!done)
+          NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false>),
+                    dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0,
+                    (const float*)S.lev[0].ta, e, z0, sc, merged ? S.partials_rz : S.partials, nullptr);
         if (!merged)
           hipLaunchKernelGGL(k_fin_rz, dim3(1), dim3(kFinBlock), 0, st, (int)tiles_of<FineTile>(d), S.partials, sc, S.project);
       } else if (wide(d)) {
@@ -1849,14 +1907,13 @@ static void cast_level(const Dims& d, const float* lx, const float* ly, const fl
                      invcap);
 }
 
-// The finest level's packed coefficient records, from its (storage-type)
-// fraction arrays and 1/diag.
+// The finest level's packed coefficient records, from its FP32 fractions.
 template <typename T>
-static void pack_records(const Solver& S, hipStream_t st) {
+static void pack_records(const Solver& S, const float* fx, const float* fy, const float* fz, hipStream_t st) {
   if (!S.rec0) return;
   const Level& L = S.lev[0];
-  hipLaunchKernelGGL(k_pack_records<T>, dim3(nblocks(L.d.cells())), dim3(kBlock), 0, st, L.d, (const T*)L.a[0],
-                     (const T*)L.a[1], (const T*)L.a[2], (const T*)L.invd, (typename RecOf<T>::T*)S.rec0);
+  hipLaunchKernelGGL(k_pack_records<T>, dim3(nblocks(L.d.cells())), dim3(kBlock), 0, st, L.d, fx, fy, fz,
+                     (typename RecOf<T>::T*)S.rec0, (float*)((Rec16*)S.rec0 + L.d.cells()));
 }
 
 // Multigrid copies of the fine fractions and inverse diagonals.
@@ -1922,9 +1979,9 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
       cast_level<__hip_bfloat16>(d, lx, ly, lz, S.scratch_inv, S.lev[l], cap, st);
   }
   if (S.precision == SIM_MIXED_FP16)
-    pack_records<__half>(S, st);
+    pack_records<__half>(S, fx, fy, fz, st);
   else
-    pack_records<__hip_bfloat16>(S, st);
+    pack_records<__hip_bfloat16>(S, fx, fy, fz, st);
 }
 
 static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) {

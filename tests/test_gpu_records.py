@@ -1,10 +1,11 @@
-"""The finest fused multigrid down kernel reading packed per-cell coefficient
-records against the same kernel reading the separate fraction and 1/diag
-arrays (NF_MG_RECORDS=0): the records hold the same storage bits, so forward
-steps agree bitwise and the adjoint to the rounding of the advection
-scatter's float-atomic fallback (0 when it does not fire).  Grids with ragged
-tiles along every axis, both 2-byte storage types (FP32 storage keeps the
-arrays)."""
+"""The finest fused multigrid kernels reading packed per-cell coefficient
+records against the same kernels reading the separate 2-byte fraction and
+1/diag arrays (NF_MG_RECORDS=0).  The records hold the face weights
+alpha_f / diag in 2 bytes and 1/diag in FP32, so the two preconditioners differ
+by rounding (and where the arrays cap 1/diag): both solves must converge, the
+records with no more CG iterations, and steps and the adjoint must agree to
+the solver tolerance.  Grids with ragged tiles along every axis, both 2-byte
+storage types (FP32 storage keeps the arrays)."""
 import os
 
 import numpy as np
@@ -26,7 +27,7 @@ def _run(n3, precision, records):
         dx = 1.0 / n3[0]
         poses = ellipsoid_poses(sc.theta0, sc.ctrl, 0.5 * dx)
         u0 = scenes.curl_noise(n3, dx, np.random.default_rng(7))
-        with Sim(ellipsoid_cfg(n3, tol=1e-6, precision=precision)) as sim:
+        with Sim(ellipsoid_cfg(n3, tol=1e-7, precision=precision)) as sim:
             u = dev(u0)
             outs, iters = [], []
             for s in range(2):
@@ -45,16 +46,18 @@ def _run(n3, precision, records):
 
 @pytest.mark.parametrize("n3,precision", [((64, 64, 64), "fp16"), ((64, 64, 64), "bf16"), ((48, 40, 56), "bf16"),
                                           ((40, 24, 56), "fp16"), ((68, 36, 20), "fp16")])
-def test_records_match_arrays_bitwise(n3, precision):
+def test_records_match_arrays(n3, precision):
     announce(f"packed records vs arrays n={n3} {precision}")
     ref, gref, it_ref = _run(n3, precision, False)
     got, g, it = _run(n3, precision, True)
     announce(f"  CG iterations arrays {it_ref} records {it}")
-    assert it == it_ref
+    assert sum(it) <= sum(it_ref)
     for a, b in zip(ref, got):
         assert torch.isfinite(b).all()
-        assert torch.equal(a, b)
+        e = float((b.double() - a.double()).norm() / a.double().norm())
+        announce(f"  velocity rel diff {e:.2e}")
+        assert e <= 1e-5
     assert torch.isfinite(g).all()
     e = float((g.double() - gref.double()).norm() / gref.double().norm())
     announce(f"  adjoint rel diff {e:.2e}")
-    assert e <= 1e-6
+    assert e <= 1e-4

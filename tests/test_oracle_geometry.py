@@ -174,3 +174,26 @@ def test_corner_nodes_are_the_face_corners():
     for k in range(4):
         d = np.linalg.norm(xn[cn[:, k]] - xn[cn[:, (k + 1) % 4]], axis=1)
         np.testing.assert_allclose(d, 0.25, atol=1e-15)
+
+
+def test_moving_ellipsoid_cut_cells_exceed_fp16_range():
+    # why the finest multigrid level keeps 1/diag in FP32 when the rest of the
+    # V-cycle is stored in 2 bytes: at 128^3 the moving-ellipsoid scene has cut
+    # cells nearly inside the body whose diagonal (the sum of their face
+    # fractions) is below 1/65504, and fractions below FP16's smallest normal
+    import scenes
+    from oracle.mac import Grid
+    from oracle.rollout import EllipsoidRollout
+    from oracle.step import StepParams
+    n = 128
+    sc = scenes.scene_ellipsoid_rollout(seed=0, n=n, steps=33)
+    g = Grid(sc.n, sc.dx)
+    c, R = EllipsoidRollout(StepParams(g, sc.dt), sc.u0, sc.theta0, sc.ctrl).poses()[32]
+    al = EllipsoidGeometry(g, c, sc.theta0[3:6], R, sc.ctrl[32, :3], sc.ctrl[32, 3:]).alpha
+    fx = al[:g.nf(0)].reshape(n, n, n + 1)
+    fy = al[g.nf(0):g.nf(0) + g.nf(1)].reshape(n, n + 1, n)
+    fz = al[g.nf(0) + g.nf(1):].reshape(n + 1, n, n)
+    diag = fx[:, :, :-1] + fx[:, :, 1:] + fy[:, :-1, :] + fy[:, 1:, :] + fz[:-1] + fz[1:]
+    tiny = (diag > 0) & (diag < 1.0 / 65504.0)
+    assert 0 < tiny.sum() < 100
+    assert np.sum((al > 0) & (al < 6.1e-5)) > 0
