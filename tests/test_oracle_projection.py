@@ -122,3 +122,36 @@ def test_hydrostatic_balance():
     zf = np.concatenate([np.zeros(g.nf(0) + g.nf(1)), np.ones(g.nf(2))])
     m = geo.alpha > 0
     np.testing.assert_allclose(gp[m], (-9.8 * 0.05 * zf)[m], atol=1e-11)
+
+
+@pytest.mark.parametrize("bc", ["closed", "outflow", "periodic"])
+def test_mgpcg_matches_dense_direct_solve(bc):
+    # a deep hierarchy (coarsest level of at most 8 unknowns) on a tiny grid:
+    # the multigrid only preconditions CG, the answer is the dense solution
+    from oracle.projection import mgpcg, dense_solve
+    g, geo, uhat = _setup(bc, seed=5)
+    ops = Operators(g, geo.alpha)
+    b = ops.remove_null(np.where(ops.active, ops.GT @ (geo.alpha * uhat + (1 - geo.alpha) * geo.us), 0.0))
+    xd = ops.remove_null(dense_solve(ops.L, b, ops.active))
+    xm, it, rel = mgpcg(ops.L, b, ops.active, g.n, 1e-13, coarsest=8)
+    xm = ops.remove_null(xm)
+    assert rel <= 1e-13 and it > 0
+    np.testing.assert_allclose(xm, xd, atol=1e-10 * np.abs(xd).max())
+
+
+def test_mgpcg_matches_pcg_with_pockets_and_outflow():
+    from oracle.projection import mgpcg, pcg
+    n = 16
+    rng = np.random.default_rng(6)
+    for bc in [(WALL,) * 6, (WALL, WALL, WALL, WALL, INFLOW, OUTFLOW)]:
+        g = Grid((n, n, n), 1.0 / n, bc=bc, inflow_speed=0.5)
+        geo = sphere_geometry(g, np.array([[0.5, 0.5, 0.5, 0.74]]))
+        ops = Operators(g, geo.alpha)
+        if bc[5] == WALL:
+            assert ops.n_floating == 8
+        b = ops.remove_null(np.where(ops.active, rng.uniform(-1, 1, g.ncells), 0.0))
+        xp, _, _ = pcg(ops.L, b, ops.active, 1e-13)
+        xm, it, rel = mgpcg(ops.L, b, ops.active, g.n, 1e-13, coarsest=16)
+        assert rel <= 1e-13
+        xp, xm = ops.remove_null(xp), ops.remove_null(xm)
+        np.testing.assert_allclose(xm, xp, atol=1e-9 * np.abs(xp).max())
