@@ -10,10 +10,20 @@ steps), for the mixed-precision form (FP16 multigrid preconditioner); the
 plain FP32 form is timed beside it.  Per-step latencies (HIP events around each
 sim_step / sim_step_adjoint) give p50 / p99.
 
-The roofline object reports the dominant kernel (the finest-level multigrid
-post-smoother), timed live with HIP events on the launch stream, against the
-MI355X HBM peak.  The cpu_baseline object times the FP64 oracle on a bounded
-sample (the same scene at 32^3, a few steps forward + adjoint).
+Both precision forms are timed the same way: CG iterations replayed from a
+captured graph, no profiling.  After each form's timed rollouts, one more
+rollout (outside the timed region) times the dominant kernel, the finest-level
+multigrid post-smoother k_mg_up, with HIP events recorded by its own dispatches
+on the launch stream; the roofline object sets its algorithmic bytes against
+the MI355X HBM peak.  cg_iters gives the mean / max CG iterations per forward
+and adjoint solve of the timed rollouts.
+
+The cpu_baseline object times the FP64 oracle (child processes, before this
+process touches the GPU) on a bounded sample: the same scene at 64^3, one
+step forward + adjoint, once on one thread and once with every core allowed.
+oracle_error compares the GPU's rollout of that sample (both precision forms,
+benchmark tolerance) with the oracle's: final velocity, loss, shape and
+control gradients.
 """
 from __future__ import annotations
 
@@ -31,6 +41,8 @@ if ROOT not in sys.path:
 N = 128
 T = 64
 EVERY = 8
+# CG tolerance (relative residual) of every solve in the benchmark rollouts
+CG_TOL = 1e-6
 HBM_PEAK_GBS = 8000.0
 ROOFLINE_KERNEL = "mg_up"
 # A launch enqueued after the solver converged exits at once (about 1 us); the
@@ -68,7 +80,15 @@ def parse():
     ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-steps", type=int, default=32)
+    ap.add_argument("--cpu-steps", type=int, default=1, help="steps of the oracle's sample rollout")
+    ap.add_argument("--cpu-n", type=int, default=64, help="grid of the oracle's sample rollout")
+    ap.add_argument("--cpu-oracle-run", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--summarize-trace", default=None, metavar="CSV",
+                    help="only summarize a rocprofv3 kernel-trace CSV (kernel_trace.csv) as a markdown table")
+    ap.add_argument("--summarize-title", default="kernel profile")
+    ap.add_argument("--summarize-grid", type=int, default=0,
+                    help="with --summarize-trace: also report the working launches (>= 3 us) of the finest-level "
+                         "k_mg_up, recognised by this grid size in threads")
     ap.add_argument("--workload", default="rollout128", choices=["rollout128", "channel", "serving"],
                     help="channel: the 256x256x512 inflow / outflow channel with the B-spline wall, "
                          "200 steps forward + adjoint, sqrt(T) checkpoints, total outflow flux loss, "
@@ -115,44 +135,51 @@ class StepTimer:
         return [a.elapsed_time(b) for a, b in self.pairs[kind]]
 
 
-def run_form(precision, steps, warmup, scene, torch, profile_kernel=None):
+def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
+    """Time `steps` rollouts of one precision form (graph-replayed CG, no
+    profiling), then, outside the timed region, one more rollout with the
+    finest-level k_mg_up timed by HIP events (the roofline kernel)."""
     from paper_2405_14903_amd.sim import Config, Sim
     from paper_2405_14903_amd.rollout import Rollout
-    cfg = Config(n=scene.n, dx=scene.dx, dt=scene.dt, geom="ellipsoid", tol=1e-6, precision=precision,
+    cfg = Config(n=scene.n, dx=scene.dx, dt=scene.dt, geom="ellipsoid", tol=CG_TOL, precision=precision,
                  max_iter=200)
     sim = Sim(cfg)
     u0 = torch.tensor(scene.u0, dtype=torch.float32, device="cuda")
     J = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.empty_like(u0)
-    grads = None
+    iters = {"fwd": [], "adj": []}
 
     def one(timer):
-        nonlocal grads
         ro = Rollout.ellipsoid(sim, scene.theta0, scene.ctrl, every=EVERY, timer=timer)
         uT = ro.forward(u0)
         sim.loss_box(uT, J=J, g=g)
-        g0 = ro.backward(g)
-        grads = (g0, ro.geometry_gradients())
+        ro.backward(g)
+        ro.geometry_gradients()
+        return ro
 
     for _ in range(warmup):
         one(None)
     print(f"[bench] {precision}: warmup done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    if profile_kernel:
-        sim.profile(profile_kernel)
     timer = StepTimer(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        one(timer)
+        ro = one(timer)
+        for k in iters:
+            iters[k] += ro.iters[k]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     print(f"[bench] {precision}: {steps} rollouts in {wall:.2f} s", file=sys.stderr, flush=True)
-    prof = sim.profile_read(min_ms=NOOP_MS) if profile_kernel else None
-    sim.profile(None)
+    prof = None
+    if roofline_pass:
+        sim.profile(ROOFLINE_KERNEL)
+        one(None)
+        torch.cuda.synchronize()
+        prof = sim.profile_read(min_ms=NOOP_MS)
+        sim.profile(None)
+        print(f"[bench] {precision}: roofline pass done", file=sys.stderr, flush=True)
     fwd = timer.latencies("fwd")
     adj = timer.latencies("adj")
-    stats = sim.step(u0, *Rollout.ellipsoid(sim, scene.theta0, scene.ctrl).schedule(0))[1]
     out = {
         "wall_s": wall,
         "cell_steps_per_s": (N ** 3) * T * steps / wall,
@@ -160,11 +187,21 @@ def run_form(precision, steps, warmup, scene, torch, profile_kernel=None):
         "fwd_ms_p50": pct(fwd, 50), "fwd_ms_p99": pct(fwd, 99),
         "adj_ms_p50": pct(adj, 50), "adj_ms_p99": pct(adj, 99),
         "step_ms_p50": pct(fwd + adj, 50), "step_ms_p99": pct(fwd + adj, 99),
-        "first_step_cg_iters": stats["iters"], "first_step_true_rel_res": stats["true_rel_res"],
+        "cg_iters": iter_summary(iters),
         "loss": float(J.item()),
     }
     sim.close()
-    return out, prof, grads
+    return out, prof
+
+
+def iter_summary(iters):
+    """Mean / max CG iterations per forward solve (the timed forward and the
+    recomputed segments) and per adjoint solve."""
+    out = {}
+    for k, v in iters.items():
+        if v:
+            out[k] = {"mean": round(sum(v) / len(v), 2), "max": max(v), "solves": len(v)}
+    return out
 
 
 def pct(v, q):
@@ -198,29 +235,105 @@ def roofline(prof, precision, n3=(N, N, N), traffic=True):
             "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": bytes_per_launch}
 
 
-def cpu_baseline(steps):
-    """The FP64 oracle as it stands, single-threaded numpy/scipy, on the same
-    scene at 32^3: `steps` steps forward + the full adjoint."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_run(path, n, steps):
+    """Child process: the FP64 oracle as it stands on the benchmark scene at
+    n^3, `steps` steps forward + the full adjoint (octant loss); writes its
+    results to `path` (npz) and prints its timing as one JSON line."""
     import numpy as np
     import scenes
     from oracle.mac import Grid
     from oracle.step import StepParams
     from oracle.rollout import EllipsoidRollout, octant_loss
-    n = 32
     sc = scenes.scene_ellipsoid_rollout(seed=0, n=n, steps=steps)
     g = Grid(sc.n, sc.dx)
     prm = StepParams(g, sc.dt, tol=1e-10)
-    t0 = time.perf_counter()
-    c0 = time.process_time()
+    t0, c0 = time.perf_counter(), time.process_time()
     ro = EllipsoidRollout(prm, sc.u0, sc.theta0, sc.ctrl)
-    _, gT = octant_loss(g, ro.forward())
-    ro.backward(gT)
-    wall = time.perf_counter() - t0
-    cpu = time.process_time() - c0
-    cores = max(1, round(cpu / wall))
-    return {"value": round(n ** 3 * steps / wall, 1), "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"same moving-ellipsoid scene at 32^3, {steps} steps forward + adjoint (FP64, "
-                      f"solve to 1e-10), {wall:.1f} s wall, {cpu:.1f} s CPU (numpy/scipy)"}
+    uT = ro.forward()
+    J, gT = octant_loss(g, uT)
+    _, gth, gct = ro.backward(gT)
+    wall, cpu = time.perf_counter() - t0, time.process_time() - c0
+    np.savez(path, uT=uT, gth=gth, gct=gct, J=J)
+    print(json.dumps({"wall_s": wall, "cpu_s": cpu}), flush=True)
+
+
+def cpu_baseline(n, steps):
+    """The oracle timed in child processes on the host cores, once limited to
+    one thread and once allowed every core of this process' affinity mask
+    (numpy / scipy's own threading: the sparse products it spends its time in
+    run on one thread either way).  Returns (baseline object, path of the
+    all-cores run's results)."""
+    import subprocess
+    import tempfile
+    ncores = len(os.sched_getaffinity(0))
+    runs = {}
+    path = None
+    for threads in (1, ncores):
+        fd, out = tempfile.mkstemp(suffix=".npz")
+        os.close(fd)
+        env = dict(os.environ)
+        for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+            env[var] = str(threads)
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-run", out, "--cpu-n", str(n),
+                            "--cpu-steps", str(steps)], env=env, capture_output=True, text=True, check=True)
+        runs[threads] = json.loads(r.stdout.strip().splitlines()[-1])
+        print(f"[bench] oracle on {threads} thread(s): {runs[threads]['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        if threads == ncores:
+            path = out
+        else:
+            os.remove(out)
+    full, one = runs[ncores], runs[1]
+    rate = lambda r: round(n ** 3 * steps / r["wall_s"], 1)  # noqa: E731
+    cores = max(1, round(full["cpu_s"] / full["wall_s"]))
+    base = {"value": rate(full), "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"the benchmark scene (moving ellipsoid, curl noise, same shape parameters and controls) at "
+                      f"{n}^3, {steps} steps forward + adjoint with the octant loss (FP64 numpy / scipy, "
+                      f"Jacobi-PCG to 1e-10), {full['wall_s']:.1f} s wall, {full['cpu_s']:.1f} s CPU with "
+                      f"{ncores} threads allowed on {cpu_model()}; cores = CPU time / wall time",
+            "threads_allowed": ncores,
+            "single_thread": {"value": rate(one), "wall_s": round(one["wall_s"], 2)}}
+    return base, path
+
+
+def oracle_check(path, n, steps, torch):
+    """Error against the FP64 oracle on the same scene at n^3 and `steps`
+    steps: the GPU rollout (benchmark tolerance) in both precision forms,
+    final velocity and shape / control gradients."""
+    import numpy as np
+    import scenes
+    from paper_2405_14903_amd.sim import Config, Sim
+    from paper_2405_14903_amd.rollout import Rollout
+    ref = np.load(path)
+    sc = scenes.scene_ellipsoid_rollout(seed=0, n=n, steps=steps)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))  # noqa: E731
+    out = {"grid": [n, n, n], "steps": steps, "cg_tol": CG_TOL}
+    for prec in ("fp16", "fp32"):
+        cfg = Config(n=sc.n, dx=sc.dx, dt=sc.dt, geom="ellipsoid", tol=CG_TOL, precision=prec, max_iter=200)
+        with Sim(cfg) as sim:
+            u0 = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
+            ro = Rollout.ellipsoid(sim, sc.theta0, sc.ctrl, every=EVERY)
+            uT = ro.forward(u0)
+            J, g = sim.loss_box(uT)
+            ro.backward(g)
+            gth, gct = ro.geometry_gradients()
+            torch.cuda.synchronize()
+            uh = uT.double().cpu().numpy()
+        out[prec] = {"velocity_rel_l2": rel(uh, ref["uT"]), "loss_rel": abs(float(J.item()) - float(ref["J"])) /
+                     abs(float(ref["J"])), "theta_grad_rel_l2": rel(gth, ref["gth"]),
+                     "ctrl_grad_rel_l2": rel(gct, ref["gct"])}
+    os.remove(path)
+    return out
 
 
 def run_channel(args, torch):
@@ -319,12 +432,56 @@ def run_serving(args, torch):
     print(json.dumps(rec), flush=True)
 
 
+def summarize_trace(path, title, fine_grid=0):
+    """Markdown summary of a rocprofv3 --kernel-trace CSV: one row per kernel
+    name and grid size (the grid tells the multigrid levels apart)."""
+    import csv
+    rows = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r.get("Kernel_Name", "?")
+            grid = int(r.get("Grid_Size_X", r.get("Grid_Size", "0")) or 0) * int(r.get("Grid_Size_Y", "1") or 1) * \
+                int(r.get("Grid_Size_Z", "1") or 1)
+            wg = int(r.get("Workgroup_Size_X", r.get("Workgroup_Size", "0")) or 0) * \
+                int(r.get("Workgroup_Size_Y", "1") or 1) * int(r.get("Workgroup_Size_Z", "1") or 1)
+            us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+            rows.setdefault((name, grid, wg), []).append(us)
+    total = sum(sum(v) for v in rows.values())
+    ndisp = sum(len(v) for v in rows.values())
+    print(f"# {title}\n")
+    print(f"Source: `{os.path.basename(path)}` (rocprofv3 kernel trace).  Grid = launch size in threads.\n")
+    if fine_grid:
+        up = [u for (name, grid, wg), v in rows.items() if "k_mg_up" in name and grid == fine_grid for u in v]
+        work = [u for u in up if u >= NOOP_MS * 1e3]
+        avg = sum(work) / len(work) if work else 0.0
+        print(f"Finest-level `k_mg_up` (grid {fine_grid}): {len(up)} launches; the {len(work)} of at least "
+              f"{NOOP_MS * 1e3:g} us (the others were enqueued after a solve converged and exit at once) average "
+              f"{avg:.2f} us.\n")
+    print("| kernel | grid (threads) | wg | calls | avg us | min us | max us | total ms | % of kernel time |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for (name, grid, wg), v in sorted(rows.items(), key=lambda kv: -sum(kv[1]))[:40]:
+        print(f"| `{name}` | {grid} | {wg} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} | "
+              f"{sum(v) / 1e3:.2f} | {100 * sum(v) / total:.1f} |")
+    print(f"\nTotal kernel time {total / 1e3:.1f} ms over {ndisp} dispatches.")
+
+
 def main():
     args = parse()
+    if args.cpu_oracle_run:
+        cpu_oracle_run(args.cpu_oracle_run, args.cpu_n, args.cpu_steps)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace, args.summarize_title, args.summarize_grid)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the rollout of one episode is a "
               f"single-GPU workload here, and no multi-GPU path is built", file=sys.stderr)
         sys.exit(2)
+    # the oracle's CPU leg runs first, in child processes, before this process
+    # touches the GPU
+    cpu, oracle_path = (None, None)
+    if not args.no_cpu and args.workload == "rollout128" and not args.copy_probe:
+        cpu, oracle_path = cpu_baseline(args.cpu_n, args.cpu_steps)
     import torch
     import scenes
     if not torch.cuda.is_available():
@@ -341,11 +498,10 @@ def main():
         run_serving(args, torch)
         return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
-    main_form, prof, _ = run_form(args.precision, args.steps, args.warmup, scene, torch,
-                                  profile_kernel=ROOFLINE_KERNEL)
+    main_form, prof = run_form(args.precision, args.steps, args.warmup, scene, torch)
     cmp_form = None
     if not args.no_compare and args.precision != "fp32":
-        cmp_form, _, _ = run_form("fp32", args.steps, args.warmup, scene, torch)
+        cmp_form, cmp_prof = run_form("fp32", args.steps, args.warmup, scene, torch)
     rec = {
         "metric": "fwd+adjoint cell-steps/s at 128^3 (mixed vs FP32); p50/p99 step latency",
         "value": round(main_form["cell_steps_per_s"], 1),
@@ -362,21 +518,23 @@ def main():
         "config": {"workload": "128^3 closed box, moving ellipsoid (9 shape params, 6 controls/step), "
                                "64 steps forward + adjoint, checkpoint every 8, octant loss",
                    "grid": [N, N, N], "steps_per_rollout": T, "checkpoint_every": EVERY,
-                   "precision": args.precision, "cg_tol": 1e-6},
+                   "precision": args.precision, "cg_tol": CG_TOL},
         "latency_ms": {"step_p50": main_form["step_ms_p50"], "step_p99": main_form["step_ms_p99"],
                        "fwd_p50": main_form["fwd_ms_p50"], "fwd_p99": main_form["fwd_ms_p99"],
                        "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"]},
-        "first_step_cg_iters": main_form["first_step_cg_iters"],
+        "cg_iters": main_form["cg_iters"],
         "roofline": roofline(prof, args.precision),
     }
     if cmp_form:
         rec["fp32"] = {"value": round(cmp_form["cell_steps_per_s"], 1),
                        "ms_per_step": round(cmp_form["ms_per_rollout"], 3),
                        "step_p50_ms": cmp_form["step_ms_p50"], "step_p99_ms": cmp_form["step_ms_p99"],
-                       "first_step_cg_iters": cmp_form["first_step_cg_iters"]}
+                       "cg_iters": cmp_form["cg_iters"],
+                       "roofline": roofline(cmp_prof, "fp32", traffic=False)}
         rec["mixed_over_fp32"] = round(main_form["cell_steps_per_s"] / cmp_form["cell_steps_per_s"], 3)
-    if not args.no_cpu:
-        rec["cpu_baseline"] = cpu_baseline(args.cpu_steps)
+    if oracle_path:
+        rec["oracle_error"] = oracle_check(oracle_path, args.cpu_n, args.cpu_steps, torch)
+    rec["cpu_baseline"] = cpu
     print(json.dumps(rec), flush=True)
 
 

@@ -30,14 +30,21 @@
  *
  * Memory: every float / double array argument named u_*, p_*, b, x, alpha,
  * g_* is DEVICE memory owned by the caller.  theta and ctrl are HOST double
- * arrays read at call time.  sim_stats is a host struct (nullable).
+ * arrays read at call time.  sim_stats (nullable) is a host struct in the
+ * default solve mode and device-writable memory (device or pinned host) in
+ * the device solve mode (sim_set_solve_mode).
  * Streams: work is enqueued on the caller's hipStream_t (0 = null stream).
- * Calls that solve a Poisson system wait on that stream for the solver's
- * convergence checks; the final kernels of a call may still be running when it
+ * In the default (host-checked) solve mode, calls that solve a Poisson system
+ * wait on that stream for the solver's convergence checks; in the device
+ * solve mode no call waits on the host, and a whole step can be captured
+ * into a graph.  The final kernels of a call may still be running when it
  * returns (synchronise the stream before reading outputs).
  * Errors: arguments are validated before anything is enqueued; a negative
- * status means nothing was launched.  Non-convergence and non-finite values
- * are reported in sim_stats (status SIM_OK).  No exception crosses the ABI.
+ * status means nothing was launched.  A positive status (host-checked mode
+ * only) means the call ran to its end but a Poisson solve in it did not reach
+ * the tolerance (SIM_WNOCONV) or met a NaN / Inf (SIM_WNONFINITE); the
+ * outputs are then those of the last iterate.  In the device solve mode these
+ * outcomes appear only in sim_stats.  No exception crosses the ABI.
  * Threading: a handle is not thread-safe; use one handle per concurrent
  * episode.  Distinct handles may be used from distinct threads and streams.
  */
@@ -59,7 +66,9 @@ typedef enum {
   SIM_EINVAL = -1,        /* invalid argument or descriptor               */
   SIM_ENOMEM = -2,        /* device allocation failed in sim_create       */
   SIM_EHIP = -3,          /* a HIP runtime call failed                    */
-  SIM_EUNSUPPORTED = -4   /* valid request this library does not implement */
+  SIM_EUNSUPPORTED = -4,  /* valid request this library does not implement */
+  SIM_WNOCONV = 1,        /* ran; a Poisson solve stopped short of the tolerance */
+  SIM_WNONFINITE = 2      /* ran; a Poisson solve met a NaN / Inf            */
 } sim_status;
 
 typedef enum { SIM_FP32 = 0, SIM_MIXED_FP16 = 1, SIM_MIXED_BF16 = 2 } sim_precision;
@@ -206,6 +215,24 @@ int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const doubl
  * time-integrated flux of a step is scale = dt dx^2. */
 int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double scale, double* J, float* g,
                         hipStream_t stream);
+
+/* Solve control of a handle (every later Poisson solve of sim_step,
+ * sim_project, sim_step_adjoint and poisson_solve).
+ *  SIM_SOLVE_HOST (default): CG runs in batches; after each batch the call
+ *    waits on the stream for the device-resident convergence state, then
+ *    stops, continues, or restarts from the true residual.  Iteration
+ *    batches are replayed from a captured graph.  sim_stats is a host struct.
+ *  SIM_SOLVE_DEVICE: nothing waits on the host.  Each solve enqueues
+ *    min(max_iter, budget) iterations (budget <= 0: max_iter) with an FP64
+ *    true-residual check and a conditional restart behind every 4 of them;
+ *    once converged, the remaining kernels exit at once on the device.  The
+ *    outcome is written by a kernel into sim_stats, which must then be device
+ *    memory or pinned host memory (SIM_EINVAL otherwise); the status is
+ *    SIM_OK whatever the solve's outcome.  A call enqueued on a capturing
+ *    stream is captured whole (wall geometry excepted: its control
+ *    amplitudes are copied from pageable host memory). */
+typedef enum { SIM_SOLVE_HOST = 0, SIM_SOLVE_DEVICE = 1 } sim_solve_mode;
+int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget);
 
 /* Kernel timing for measurement: while enabled, the launches of one kernel
  * family are timed on the launch stream (multigrid kernels: finest level

@@ -12,6 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libneuralfluid.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4
+SIM_WNOCONV, SIM_WNONFINITE = 1, 2
+SIM_SOLVE_HOST, SIM_SOLVE_DEVICE = 0, 1
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
 SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL = 0, 1, 2, 3
@@ -23,7 +25,7 @@ EXPORTS = [
     "sim_version", "sim_status_string", "sim_footprint", "sim_create", "sim_destroy", "sim_layout",
     "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
-    "sim_profile_read",
+    "sim_profile_read", "sim_set_solve_mode",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -97,6 +99,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_loss_outlet": (C.c_int32, [_vp, _fp, _fp, C.c_double, _vp, _fp, _vp]),
         "sim_profile": (C.c_int32, [_vp, C.c_int32]),
         "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "sim_set_solve_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -106,7 +109,19 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     return lib
 
 
-def check(status: int, what: str) -> None:
+class SolveError(RuntimeError):
+    """A call ran to its end but one of its Poisson solves did not reach the
+    tolerance or met a NaN / Inf (positive status); ``stats`` holds the
+    solver's report when the caller asked for one."""
+
+    def __init__(self, msg, status, stats=None):
+        super().__init__(msg)
+        self.status, self.stats = status, stats
+
+
+def check(status: int, what: str, stats=None) -> None:
     if status != SIM_OK:
         msg = load().sim_status_string(status).decode()
+        if status > 0:
+            raise SolveError(f"{what}: {msg} ({status}); solver report {stats}", status, stats)
         raise RuntimeError(f"{what} failed: {msg} ({status})")

@@ -223,6 +223,24 @@ void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st) {
 
 double k_factor(const sim_desc& d) { return d.dt / (d.rho * d.dx); }
 
+// In the device solve mode the stats are written by a kernel: the pointer
+// must be device memory or pinned host memory.
+int check_stats_ptr(const sim_ctx* c, const sim_stats* st) {
+  if (!st || !c->S.device_mode) return SIM_OK;
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, st) != hipSuccess) {
+    (void)hipGetLastError();
+    return SIM_EINVAL;
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeHost && at.type != hipMemoryTypeManaged)
+    return SIM_EINVAL;
+  return SIM_OK;
+}
+
+// Keep the first warning of a call (positive solver status) while the call
+// carries on; negative statuses end it.
+int merge_status(int warn, int r) { return warn != SIM_OK ? warn : r; }
+
 }  // namespace
 
 extern "C" {
@@ -236,6 +254,8 @@ const char* sim_status_string(int32_t s) {
     case SIM_ENOMEM: return "device allocation failed";
     case SIM_EHIP: return "HIP runtime error";
     case SIM_EUNSUPPORTED: return "unsupported configuration";
+    case SIM_WNOCONV: return "a Poisson solve did not reach the tolerance";
+    case SIM_WNONFINITE: return "a Poisson solve met a non-finite value";
     default: return "unknown status";
   }
 }
@@ -365,15 +385,17 @@ static int32_t project_common(sim_handle h, const float* uhat, const GeomParams&
   NF_TIMED(&h->prof, SIM_K_RHS, stream, launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream));
   float* P = p_out ? p_out : h->P;
   launch_fill(P, h->dom.d.cells(), 0.0f, stream);
-  int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
-  if (r != SIM_OK) return r;
+  const int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
+  if (r < 0) return r;
   NF_TIMED(&h->prof, SIM_K_UPDATE, stream, launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream));
-  return last_hip_error();
+  const int e = last_hip_error();
+  return e != SIM_OK ? e : r;
 }
 
 int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const double* ctrl, float* u_n1, float* p_n1,
                  sim_stats* st, hipStream_t stream) {
   if (!h || !u_n || !u_n1 || u_n == u_n1) return SIM_EINVAL;
+  if (check_stats_ptr(h, st) != SIM_OK) return SIM_EINVAL;
   GeomParams g;
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
@@ -386,6 +408,7 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
 int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const double* ctrl, float* u_out,
                     float* p_out, sim_stats* st, hipStream_t stream) {
   if (!h || !u_in || !u_out || u_in == u_out) return SIM_EINVAL;
+  if (check_stats_ptr(h, st) != SIM_OK) return SIM_EINVAL;
   GeomParams g;
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
@@ -397,6 +420,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
                          const float* g_u_n1, float* g_u_n, double* g_theta, double* g_ctrl, sim_stats* st,
                          hipStream_t stream) {
   if (!h || !u_n || !g_u_n1 || !g_u_n || g_u_n == g_u_n1 || (const float*)g_u_n == u_n) return SIM_EINVAL;
+  if (check_stats_ptr(h, st) != SIM_OK) return SIM_EINVAL;
   GeomParams g;
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
@@ -408,32 +432,37 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
            launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, h->trace, stream));
   const float* P = p_n1;
+  int warn = SIM_OK;
   if (!P && grad) {
     // no stored pressure: solve the forward system again
     launch_rhs(h->dom, g, 1.0 / kk, h->alpha, h->uhat, h->b, stream);
     launch_fill(h->P, h->dom.d.cells(), 0.0f, stream);
     int r = solver_solve(h->S, kSolvePressure, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream);
-    if (r != SIM_OK) return r;
+    if (r < 0) return r;
+    warn = r;
     P = h->P;
   }
   // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T S g
   NF_TIMED(&h->prof, SIM_K_ADJ_DIV, stream, launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream));
   launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
   int r = solver_solve(h->S, kSolveAdjoint, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
-  if (r != SIM_OK) return r;
+  if (r < 0) return r;
+  warn = merge_status(warn, r);
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
                             h->S.partials, g_theta, g_ctrl, h->wall_cols, stream));
   launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
            launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->trace, h->gu, g_u_n, h->stage, stream));
-  return last_hip_error();
+  const int e = last_hip_error();
+  return e != SIM_OK ? e : warn;
 }
 
 int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x, double tol, int32_t max_iter,
                       sim_stats* st, hipStream_t stream) {
   if (!h || !b || !x) return SIM_EINVAL;
   if (!alpha && !h->have_geom) return SIM_EINVAL;
+  if (check_stats_ptr(h, st) != SIM_OK) return SIM_EINVAL;
   if (alpha) {
     if (hipMemcpyAsync(h->alpha, alpha, h->dom.d.faces() * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
       return SIM_EHIP;
@@ -442,8 +471,16 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
   }
   int r = solver_solve(h->S, kSolveUser, b, x, tol > 0 ? tol : h->desc.tol, max_iter > 0 ? max_iter : h->desc.max_iter, st,
                        stream);
-  if (r != SIM_OK) return r;
-  return last_hip_error();
+  if (r < 0) return r;
+  const int e = last_hip_error();
+  return e != SIM_OK ? e : r;
+}
+
+int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget) {
+  if (!h || (mode != SIM_SOLVE_HOST && mode != SIM_SOLVE_DEVICE)) return SIM_EINVAL;
+  h->S.device_mode = mode == SIM_SOLVE_DEVICE ? 1 : 0;
+  h->S.budget = budget > 0 ? budget : 0;
+  return SIM_OK;
 }
 
 int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,

@@ -92,7 +92,14 @@ struct CGScalars {
   int converged;     // true residual reached the tolerance
   int allow;         // a true residual that misses tol may restart CG
   int checks;        // number of true-residual checks that ran in this solve
+  int restarts;      // restarts from the true residual in this solve (at most kMaxRestarts)
+  int restarted;     // the last true-residual check restarted CG (cleared after the restart V-cycle)
+  int final_;        // a true-residual check ended the solve (no further checks run)
+  int pad_;
 };
+
+// Restarts of CG from the true residual allowed per solve.
+constexpr int kMaxRestarts = 8;
 
 // ---------------------------------------------------------------------------
 // small device helpers

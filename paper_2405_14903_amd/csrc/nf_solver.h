@@ -115,6 +115,10 @@ struct Solver {
   // CUDA-graph style replay of two CG iterations (captured once per handle on
   // an internal stream, launched on the caller's stream)
   int use_graph = 1;
+  // solves that never wait on the host (sim_set_solve_mode): a fixed budget
+  // of iterations (at most max_iter) per solve, stats written by a kernel
+  int device_mode = 0;
+  int budget = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t iter_graph = nullptr;
   hipGraphExec_t iter_exec = nullptr;

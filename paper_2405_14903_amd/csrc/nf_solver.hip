@@ -185,6 +185,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* pa
     sc->tol2bb = tol * tol * tot[0];
     sc->iters = 0;
     sc->checks = 0;
+    sc->restarts = 0;
+    sc->restarted = 0;
+    sc->final_ = 0;
     sc->first = 1;
     sc->maxit = maxit;
     sc->nonfinite = !isfinite(tot[1]);
@@ -336,7 +339,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_rr(int nb, const double* part
 // that misses the tolerance replaces r and CG restarts (k_fin_true sets
 // done = 0, first = 1).
 __device__ inline bool may_replace(const CGScalars* sc, int allow) {
-  return allow && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
+  return allow && sc->restarts < kMaxRestarts && !sc->nonfinite && sc->iters < sc->maxit && !(sc->bb == 0.0);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float* __restrict__ ax,
@@ -345,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
                                                               const float* __restrict__ b,
                                                               const double* __restrict__ x, float* __restrict__ r,
                                                               int allow, const CGScalars* sc, double* partials) {
-  if (!sc->done) return;
+  if (!sc->done || sc->final_) return;
   const bool rep = may_replace(sc, allow);
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
@@ -364,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
 
 __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* partials, CGScalars* sc, int allow,
                                                          long ncells, int project) {
-  if (!sc->done) return;
+  if (!sc->done || sc->final_) return;
   const bool rep = may_replace(sc, allow);
   double tot[3];
   finish_partials<3>(partials, nb, tot);
@@ -380,8 +383,35 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* pa
       sc->vscale = vscale_of(tot[0], ncells);
       sc->first = 1;
       sc->done = 0;
+      sc->restarts += 1;
+      sc->restarted = 1;
+    } else {
+      sc->final_ = 1;
     }
   }
+}
+
+// Device-only solves enqueue a restart V-cycle behind every true-residual
+// check; it must run only when that check restarted CG.  While CG is still
+// iterating, k_hold_restart parks `done` at 2 (every solver kernel skips on a
+// nonzero `done`) and k_release_restart puts it back afterwards.
+__global__ void k_hold_restart(CGScalars* sc) {
+  if (sc->done == 0 && !sc->restarted) sc->done = 2;
+}
+__global__ void k_release_restart(CGScalars* sc) {
+  if (sc->done == 2) sc->done = 0;
+  sc->restarted = 0;
+}
+
+// The solve's outcome into caller memory that the device can write (device
+// memory or pinned host memory).
+__global__ void k_write_stats(const CGScalars* sc, sim_stats* out) {
+  out->iters = sc->iters;
+  out->nonfinite = sc->nonfinite;
+  out->converged = sc->converged && !sc->nonfinite;
+  out->pad = 0;
+  out->rel_res = sc->bb > 0.0 ? sqrt(sc->rr / sc->bb) : 0.0;
+  out->true_rel_res = sc->bb > 0.0 ? sqrt(sc->true_rr / sc->bb) : 0.0;
 }
 
 // r -= mean on active cells (singular systems, after k_fin_init / a restart).
@@ -2082,12 +2112,45 @@ static int snapshot(Solver& S, hipStream_t st) {
   return SIM_OK;
 }
 
+// Solves that never wait on the host: a fixed budget of iterations with a
+// true-residual check (and a conditional restart) behind every chunk; every
+// kernel enqueued after convergence exits at once on the device.
+static void solve_on_device(Solver& S, const float* b, double* x, int budget, hipStream_t st) {
+  const Dims& d = S.lev[0].d;
+  const long n = (long)d.cells();
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+  // the captured iteration pair is not replayed inside a caller's capture
+  const bool graphs = cap == hipStreamCaptureStatusNone;
+  const int chunk = 4;
+  for (int left = budget; left > 0;) {
+    const int c = left < chunk ? left : chunk;
+    if (graphs)
+      left -= cg_iterations(S, x, c, st);
+    else {
+      enqueue_iterations(S, x, c, st);
+      left -= c;
+    }
+    hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r, 1,
+                       S.sc, S.partials);
+    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, S.sc, 1, n,
+                       S.project);
+    if (left <= 0) break;
+    hipLaunchKernelGGL(k_hold_restart, dim3(1), dim3(1), 0, st, S.sc);
+    if (S.project)
+      hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, S.sc);
+    vcycle_dispatch(S, S.r, S.z, st);
+    hipLaunchKernelGGL(k_release_restart, dim3(1), dim3(1), 0, st, S.sc);
+  }
+}
+
 int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double tol, int maxit, sim_stats* stats,
                  hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
   CGScalars* sc = S.sc;
   double* x = S.x;
+  if (S.device_mode && S.budget > 0 && S.budget < maxit) maxit = S.budget;
   hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
   NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
                               S.partials);
@@ -2097,13 +2160,18 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
   vcycle_dispatch(S, S.r, S.z, st);
   S.pcur = 0;
+  if (S.device_mode) {
+    solve_on_device(S, b, x, maxit, st);
+    hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
+    if (stats) hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(1), 0, st, sc, stats);
+    return SIM_OK;
+  }
   // Each round enqueues a batch of iterations and the (conditional) true-
   // residual check behind it, then synchronises once.  The first batch is
   // sized from the previous solve of this handle, so a typical solve needs a
   // single round; iterations enqueued after convergence exit at once on the
   // device.  Every round runs iterations or uses up one of a bounded number of
   // restarts, and the round count is capped, so the loop terminates.
-  const int kMaxRestarts = 8;
   int batch = S.last_iters[kind] > 0 ? S.last_iters[kind] : 2;
   const int chunk = S.check_every > 0 ? S.check_every : 2;
   int restarts = 0, checks_seen = 0, rounds = 0;
@@ -2125,14 +2193,15 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     if (h.converged || !allow || h.iters >= maxit || h.done) break;
     // the check restarted CG from the true residual
     ++restarts;
+    hipLaunchKernelGGL(k_release_restart, dim3(1), dim3(1), 0, st, sc);
     if (S.project)
       hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
     vcycle_dispatch(S, S.r, S.z, st);
   }
   S.last_iters[kind] = S.host_sc->iters;
   hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
+  const CGScalars& h = *S.host_sc;
   if (stats) {
-    const CGScalars& h = *S.host_sc;
     stats->iters = h.iters;
     stats->nonfinite = h.nonfinite;
     stats->converged = h.converged && !h.nonfinite;
@@ -2140,6 +2209,8 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     stats->rel_res = h.bb > 0.0 ? sqrt(h.rr / h.bb) : 0.0;
     stats->true_rel_res = h.bb > 0.0 ? sqrt(h.true_rr / h.bb) : 0.0;
   }
+  if (h.nonfinite) return SIM_WNONFINITE;
+  if (!h.converged) return SIM_WNOCONV;
   return SIM_OK;
 }
 

@@ -40,7 +40,10 @@ class Rollout:
         self.K = checkpoint_stride(self.T, every)
         self.grad_geometry = grad_geometry
         self.timer = timer
-        self.last_stats = []
+        # CG iterations of every forward and adjoint solve (host solve mode:
+        # the report costs nothing more there)
+        self.iters = {"fwd": [], "adj": []}
+        self.collect = not getattr(sim, "device_mode", False)
         # step_loss(n, u_next) -> (J_n: device double (1,), dJ_n/du_next): a loss
         # on every step's result, summed over the rollout
         self.step_loss = step_loss
@@ -58,9 +61,11 @@ class Rollout:
         th, ct = self.schedule(n)
         if self.timer:
             self.timer.begin("fwd")
-        self.sim.step(u, th, ct, u_out=out, p_out=p, stats=False)
+        _, st = self.sim.step(u, th, ct, u_out=out, p_out=p, stats=self.collect)
         if self.timer:
             self.timer.end("fwd")
+        if st is not None:
+            self.iters["fwd"].append(st["iters"])
 
     @staticmethod
     def channel(sim: Sim, knots, f, amp, T, every="sqrt", window=None, timer=None):
@@ -109,11 +114,13 @@ class Rollout:
                     g += self.step_loss(n, states[n - s + 1])[1]
                 if self.timer:
                     self.timer.begin("adj")
-                sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
-                                 g_theta=g_steps[n] if g_steps is not None else None,
-                                 g_ctrl=g_ctrl[n] if g_ctrl is not None else None, stats=False)
+                _, st = sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
+                                         g_theta=g_steps[n] if g_steps is not None else None,
+                                         g_ctrl=g_ctrl[n] if g_ctrl is not None else None, stats=self.collect)
                 if self.timer:
                     self.timer.end("adj")
+                if st is not None:
+                    self.iters["adj"].append(st["iters"])
                 g, gprev = gprev, g
         self.g_steps, self.g_ctrl_direct = g_steps, g_ctrl
         return g

@@ -14,6 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from ._lib import SolveError  # noqa: F401  (re-exported)
 
 _BC = {"wall": L.SIM_BC_WALL, "inflow": L.SIM_BC_INFLOW, "outflow": L.SIM_BC_OUTFLOW,
        "periodic": L.SIM_BC_PERIODIC}
@@ -95,6 +96,23 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class DeviceStats:
+    """Solver report that a kernel writes into pinned host memory (device
+    solve mode); valid once the stream the call was enqueued on has reached
+    it.  ``as_dict()`` synchronises that stream first."""
+
+    def __init__(self):
+        self.buf = torch.zeros(C.sizeof(L.SimStats), dtype=torch.uint8, pin_memory=True)
+        self.stream = torch.cuda.current_stream()
+
+    def ptr(self):
+        return C.cast(C.c_void_p(self.buf.data_ptr()), C.POINTER(L.SimStats))
+
+    def as_dict(self):
+        self.stream.synchronize()
+        return L.SimStats.from_buffer_copy(bytes(self.buf.numpy().tobytes())).as_dict()
+
+
 def sim_footprint(cfg: Config) -> int:
     lib = L.load()
     out = C.c_size_t(0)
@@ -134,6 +152,36 @@ class Sim:
         self.close()
 
     # ---- entry points --------------------------------------------------
+    def set_solve_mode(self, mode: str = "host", budget: int = 0):
+        """"host": solves wait on the stream for convergence checks (default);
+        "device": nothing waits on the host, each solve runs at most
+        min(max_iter, budget) iterations and its report is written on the
+        device (stats come back as :class:`DeviceStats`)."""
+        m = {"host": L.SIM_SOLVE_HOST, "device": L.SIM_SOLVE_DEVICE}[mode]
+        L.check(self.lib.sim_set_solve_mode(self.h, m, int(budget)), "sim_set_solve_mode")
+        self.device_mode = m == L.SIM_SOLVE_DEVICE
+
+    def _stats(self, want):
+        """(object handed back, pointer passed to the library) for a solver report."""
+        if not want:
+            return None, None
+        if getattr(self, "device_mode", False):
+            ds = DeviceStats()
+            return ds, ds.ptr()
+        st = L.SimStats()
+        return st, C.byref(st)
+
+    @staticmethod
+    def _report(st):
+        if st is None:
+            return None
+        return st if isinstance(st, DeviceStats) else st.as_dict()
+
+    def _done(self, status, what, st):
+        rep = self._report(st)
+        L.check(status, what, rep)
+        return rep
+
     def _geom(self, theta, ctrl):
         th, thp = _host_doubles(theta, self.n_params, "theta")
         ct, ctp = _host_doubles(ctrl, self.n_ctrl, "ctrl")
@@ -144,22 +192,21 @@ class Sim:
         if u_out is None:
             u_out = torch.empty_like(u_n)
         keep, thp, ctp = self._geom(theta, ctrl)
-        st = L.SimStats() if stats else None
-        L.check(self.lib.sim_step(self.h, _ptr(u_n, self.nf, f32, "u_n"), thp, ctp,
-                                  _ptr(u_out, self.nf, f32, "u_n1"), _ptr(p_out, self.nc, f32, "p_n1"),
-                                  C.byref(st) if st is not None else None, _stream()), "sim_step")
-        return u_out, (st.as_dict() if st is not None else None)
+        st, stp = self._stats(stats)
+        rc = self.lib.sim_step(self.h, _ptr(u_n, self.nf, f32, "u_n"), thp, ctp, _ptr(u_out, self.nf, f32, "u_n1"),
+                               _ptr(p_out, self.nc, f32, "p_n1"), stp, _stream())
+        return u_out, self._done(rc, "sim_step", st)
 
     def project(self, u_in, theta=None, ctrl=None, u_out=None, p_out=None, stats=True):
         f32 = torch.float32
         if u_out is None:
             u_out = torch.empty_like(u_in)
         keep, thp, ctp = self._geom(theta, ctrl)
-        st = L.SimStats() if stats else None
-        L.check(self.lib.sim_project(self.h, _ptr(u_in, self.nf, f32, "u_in"), thp, ctp,
-                                     _ptr(u_out, self.nf, f32, "u_out"), _ptr(p_out, self.nc, f32, "p_out"),
-                                     C.byref(st) if st is not None else None, _stream()), "sim_project")
-        return u_out, (st.as_dict() if st is not None else None)
+        st, stp = self._stats(stats)
+        rc = self.lib.sim_project(self.h, _ptr(u_in, self.nf, f32, "u_in"), thp, ctp,
+                                  _ptr(u_out, self.nf, f32, "u_out"), _ptr(p_out, self.nc, f32, "p_out"), stp,
+                                  _stream())
+        return u_out, self._done(rc, "sim_project", st)
 
     def step_adjoint(self, u_n, g_u_n1, theta=None, ctrl=None, p_n1=None, g_u_n=None, g_theta=None, g_ctrl=None,
                      stats=True):
@@ -167,22 +214,20 @@ class Sim:
         if g_u_n is None:
             g_u_n = torch.empty_like(g_u_n1)
         keep, thp, ctp = self._geom(theta, ctrl)
-        st = L.SimStats() if stats else None
-        L.check(self.lib.sim_step_adjoint(
+        st, stp = self._stats(stats)
+        rc = self.lib.sim_step_adjoint(
             self.h, _ptr(u_n, self.nf, f32, "u_n"), _ptr(p_n1, self.nc, f32, "p_n1"), thp, ctp,
             _ptr(g_u_n1, self.nf, f32, "g_u_n1"), _ptr(g_u_n, self.nf, f32, "g_u_n"),
             _ptr(g_theta, self.n_params, f64, "g_theta") if g_theta is not None else None,
-            _ptr(g_ctrl, self.n_ctrl, f64, "g_ctrl") if g_ctrl is not None else None,
-            C.byref(st) if st is not None else None, _stream()), "sim_step_adjoint")
-        return g_u_n, (st.as_dict() if st is not None else None)
+            _ptr(g_ctrl, self.n_ctrl, f64, "g_ctrl") if g_ctrl is not None else None, stp, _stream())
+        return g_u_n, self._done(rc, "sim_step_adjoint", st)
 
     def poisson_solve(self, b, x, alpha=None, tol=0.0, max_iter=0, stats=True):
         f32 = torch.float32
-        st = L.SimStats() if stats else None
-        L.check(self.lib.poisson_solve(self.h, _ptr(alpha, self.nf, f32, "alpha"), _ptr(b, self.nc, f32, "b"),
-                                       _ptr(x, self.nc, f32, "x"), float(tol), int(max_iter),
-                                       C.byref(st) if st is not None else None, _stream()), "poisson_solve")
-        return x, (st.as_dict() if st is not None else None)
+        st, stp = self._stats(stats)
+        rc = self.lib.poisson_solve(self.h, _ptr(alpha, self.nf, f32, "alpha"), _ptr(b, self.nc, f32, "b"),
+                                    _ptr(x, self.nc, f32, "x"), float(tol), int(max_iter), stp, _stream())
+        return x, self._done(rc, "poisson_solve", st)
 
     def loss_box(self, u, lo=(0.5, 0.5, 0.5), hi=(1.0, 1.0, 1.0), J=None, g=None):
         """J = sum of u^2 over faces centred in [lo, hi] (device double) and g = dJ/du."""
