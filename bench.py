@@ -298,7 +298,7 @@ def cpu_baseline(n, steps):
     cores = max(1, round(full["cpu_s"] / full["wall_s"]))
     base = {"value": rate(full), "unit": "cell-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"the benchmark scene (moving ellipsoid, curl noise, same shape parameters and controls) at "
-                      f"{n}^3, {steps} steps forward + adjoint with the octant loss (FP64 numpy / scipy, "
+                      f"{n}^3, {steps} step(s) forward + adjoint with the octant loss (FP64 numpy / scipy, "
                       f"Jacobi-PCG to 1e-10), {full['wall_s']:.1f} s wall, {full['cpu_s']:.1f} s CPU with "
                       f"{ncores} threads allowed on {cpu_model()}; cores = CPU time / wall time",
             "threads_allowed": ncores,

@@ -234,6 +234,32 @@ int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double sca
 typedef enum { SIM_SOLVE_HOST = 0, SIM_SOLVE_DEVICE = 1 } sim_solve_mode;
 int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget);
 
+/* Connected fluid regions (Sec. Projection: cells joined through faces with
+ * alpha > 0).  A region that reaches no OUTFLOW face is floating: its pressure
+ * is defined up to a constant and its right-hand side sums to zero over it up
+ * to rounding.  With labels, every solve removes each floating region's mean
+ * from the residual at its start and at each restart and measures convergence
+ * on that projected residual; without them, closed domains remove one global
+ * mean over the active cells.  Modes:
+ *  SIM_REGIONS_AUTO (default): no labelling up front; a host-checked solve
+ *    that stops short of the tolerance without a NaN / Inf labels the
+ *    regions of its geometry and solves again (labels are kept until the
+ *    geometry is evaluated again).  Device-mode solves never relabel.
+ *  SIM_REGIONS_ALWAYS: label at every geometry evaluation.
+ *  SIM_REGIONS_NEVER: never label.
+ * At most 65536 regions are tracked one by one; beyond that the global mean
+ * is used. */
+typedef enum { SIM_REGIONS_AUTO = 0, SIM_REGIONS_ALWAYS = 1, SIM_REGIONS_NEVER = 2 } sim_regions_mode;
+int32_t sim_set_regions(sim_handle h, int32_t mode);
+
+/* Regions of the handle's current geometry (labelled now if they are not
+ * yet).  region_out (device, cells, nullable): compact region id per cell in
+ * cell order of each region's first cell, -1 on inactive cells.  count
+ * (host): number of regions; floating (host, nullable): number of floating
+ * regions, or -1 when there are more regions than tracked.  Waits on the
+ * stream.  SIM_EINVAL before any geometry was evaluated. */
+int32_t sim_regions(sim_handle h, int32_t* region_out, int32_t* count, int32_t* floating, hipStream_t stream);
+
 /* Kernel timing for measurement: while enabled, the launches of one kernel
  * family are timed on the launch stream (multigrid kernels: finest level
  * only).  Single-kernel launches record their start and stop events from the

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libneuralfluid.so")
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4
 SIM_WNOCONV, SIM_WNONFINITE = 1, 2
 SIM_SOLVE_HOST, SIM_SOLVE_DEVICE = 0, 1
+SIM_REGIONS_AUTO, SIM_REGIONS_ALWAYS, SIM_REGIONS_NEVER = 0, 1, 2
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
 SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL = 0, 1, 2, 3
@@ -25,7 +26,7 @@ EXPORTS = [
     "sim_version", "sim_status_string", "sim_footprint", "sim_create", "sim_destroy", "sim_layout",
     "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
-    "sim_profile_read", "sim_set_solve_mode",
+    "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_profile": (C.c_int32, [_vp, C.c_int32]),
         "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "sim_set_solve_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
+        "sim_set_regions": (C.c_int32, [_vp, C.c_int32]),
+        "sim_regions": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -124,6 +124,17 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
   if (d->precision != SIM_FP32) alloc(C * (16 + 4), &t->S.rec0);   // records, then 1/diag in FP32
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
+  // connected-region labels of the pressure system
+  alloc(C * 4, (void**)&t->S.comp.parent);
+  alloc(C * 4, (void**)&t->S.comp.id);
+  alloc(nb_cells * 4, (void**)&t->S.comp.blockcnt);
+  alloc(nb_cells * 4, (void**)&t->S.comp.blockbase);
+  alloc(2 * 4, (void**)&t->S.comp.info);
+  alloc(kMaxComponents * 4, (void**)&t->S.comp.count);
+  alloc(kMaxComponents * 4, (void**)&t->S.comp.ground);
+  alloc(kMaxComponents * 8, (void**)&t->S.comp.sums);
+  alloc(kMaxComponents * 8, (void**)&t->S.comp.mean);
+  alloc(kMaxComponents * 4, (void**)&t->S.comp.zroot);
   if (d->geom == SIM_GEOM_WALL) {
     alloc(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z * 8, (void**)&t->knots);
     alloc(wall_column_doubles(d0) * 8, (void**)&t->wall_cols);
@@ -305,8 +316,10 @@ int32_t sim_create(const sim_desc* desc, sim_handle* out) {
   for (int l = 0; l < p.nlev; ++l) c->S.lev[l].d = p.dims[l];
   solver_init_device(c->S);
   c->S.project = 1;
-  for (int s = 0; s < 6; ++s)
+  for (int s = 0; s < 6; ++s) {
+    c->S.sides.out[s] = desc->bc[s] == SIM_BC_OUTFLOW ? 1 : 0;
     if (desc->bc[s] == SIM_BC_OUTFLOW) c->S.project = 0;
+  }
   c->S.nbottom = p.nlev - 1;
   size_t bottom_cells = kBottomCells;
   if (const char* bc = std::getenv("NF_MG_BOTTOM_CELLS")) {
@@ -474,6 +487,41 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
   if (r < 0) return r;
   const int e = last_hip_error();
   return e != SIM_OK ? e : r;
+}
+
+int32_t sim_set_regions(sim_handle h, int32_t mode) {
+  if (!h || mode < SIM_REGIONS_AUTO || mode > SIM_REGIONS_NEVER) return SIM_EINVAL;
+  h->S.comp.mode = mode;
+  h->S.comp.valid = false;
+  return SIM_OK;
+}
+
+int32_t sim_regions(sim_handle h, int32_t* region_out, int32_t* count, int32_t* floating, hipStream_t stream) {
+  if (!h || !count || !h->have_geom) return SIM_EINVAL;
+  if (!h->S.comp.valid) components_label(h->S, stream);
+  const size_t C = h->dom.d.cells();
+  if (region_out &&
+      hipMemcpyAsync(region_out, h->S.comp.id, C * 4, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return SIM_EHIP;
+  int info[2] = {0, 0};
+  if (hipMemcpyAsync(info, h->S.comp.info, sizeof(info), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return SIM_EHIP;
+  *count = info[0];
+  if (floating) {
+    *floating = -1;
+    if (info[1]) {
+      std::vector<int> cnt(info[0]), gr(info[0]);
+      if (info[0] > 0 &&
+          (hipMemcpy(cnt.data(), h->S.comp.count, info[0] * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+           hipMemcpy(gr.data(), h->S.comp.ground, info[0] * 4, hipMemcpyDeviceToHost) != hipSuccess))
+        return SIM_EHIP;
+      int f = 0;
+      for (int q = 0; q < info[0]; ++q) f += (cnt[q] > 0 && !gr[q]) ? 1 : 0;
+      *floating = f;
+    }
+  }
+  return last_hip_error();
 }
 
 int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget) {

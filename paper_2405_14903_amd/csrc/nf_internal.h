@@ -95,11 +95,24 @@ struct CGScalars {
   int restarts;      // restarts from the true residual in this solve (at most kMaxRestarts)
   int restarted;     // the last true-residual check restarted CG (cleared after the restart V-cycle)
   int final_;        // a true-residual check ended the solve (no further checks run)
-  int pad_;
+  int use_comp;      // residuals are projected region by region (connected-region labels)
+  double rr_raw;     // r . r of the initial residual before any projection
+  double null_rr;    // the part of r . r along the floating regions' constants
+  double comp_rr;    // r . r of the latest CG update (bound of its region sums)
 };
 
 // Restarts of CG from the true residual allowed per solve.
 constexpr int kMaxRestarts = 8;
+// Blocks (and partial sums) of the box-loss kernel: at most this many.
+constexpr int kLossBlocks = 2048;
+// Connected fluid regions the solver tracks one by one (more: one global mean).
+constexpr int kMaxComponents = 65536;
+
+// V-cycle input scale: the residual is scaled to RMS kVcycleRms.
+__device__ inline double vscale_of_rr(double rr, long n) {
+  double rms = sqrt(rr / (double)n);
+  return rms > 0.0 && isfinite(rms) ? kVcycleRms / rms : 1.0;
+}
 
 // ---------------------------------------------------------------------------
 // small device helpers

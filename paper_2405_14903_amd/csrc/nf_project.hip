@@ -507,13 +507,15 @@ __global__ __launch_bounds__(kBlock) void k_loss_outlet(Dims d, double scale, co
 }
 
 // J = sum of u_f^2 over faces whose centre lies in [lo, hi]; g = 2 u there.
+// Grid-stride over the faces with at most kLossBlocks blocks, so the partial
+// sums never need more than kLossBlocks doubles.
 __global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, double lo1, double lo2, double hi0,
                                                       double hi1, double hi2, const float* __restrict__ u,
                                                       float* __restrict__ g, double* __restrict__ partials) {
   const Dims& d = D.d;
-  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long nf = (long)d.faces();
   double v[1] = {0.0};
-  if (f < (long)d.faces()) {
+  for (long f = (long)blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += (long)gridDim.x * blockDim.x) {
     int comp, i, j, k;
     face_decode(d, f, comp, i, j, k);
     double x = (i + (comp == 0 ? 0.0 : 0.5)) * D.dx, y = (j + (comp == 1 ? 0.0 : 0.5)) * D.dx,
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_loss_box(Domain D, double lo0, doubl
               z <= hi2 + eps;
     float uf = u[f];
     g[f] = in ? 2.0f * uf : 0.0f;
-    v[0] = in ? (double)uf * (double)uf : 0.0;
+    v[0] += in ? (double)uf * (double)uf : 0.0;
   }
   block_partials<1>(v, partials);
 }
@@ -537,9 +539,14 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_loss(int nb, const double* __
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+int loss_box_blocks(const Dims& d) {
+  const unsigned nb = nblocks(d.faces());
+  return (int)(nb < (unsigned)kLossBlocks ? nb : (unsigned)kLossBlocks);
+}
+
 void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
                      double* partials, hipStream_t s) {
-  const int nb = (int)nblocks(D.d.faces());
+  const int nb = loss_box_blocks(D.d);
   hipLaunchKernelGGL(k_loss_box, dim3(nb), dim3(kBlock), 0, s, D, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], u, g,
                      partials);
   hipLaunchKernelGGL(k_fin_loss, dim3(1), dim3(kFinBlock), 0, s, nb, partials, J);

@@ -75,6 +75,27 @@ struct Level {
   void* tb;
 };
 
+// Which domain sides are OUTFLOW (Dirichlet ghost), order x-, x+, y-, y+, z-, z+.
+struct Sides {
+  int out[6];
+};
+
+// Connected fluid regions of the current geometry (nf_components.hip).
+struct Components {
+  int* parent = nullptr;     // union-find parents; then the reference cell of each cell (-1: none)
+  int* id = nullptr;         // compact region id per cell (-1: inactive)
+  int* blockcnt = nullptr;   // region roots per block of cells
+  int* blockbase = nullptr;  // exclusive scan of blockcnt
+  int* info = nullptr;       // [0] region count, [1] 1 if it is at most kMaxComponents
+  int* count = nullptr;      // cells per region
+  int* ground = nullptr;     // 1 if the region reaches an OUTFLOW face
+  long long* sums = nullptr; // fixed-point region sums of r
+  double* mean = nullptr;    // region means subtracted from r (0 on grounded regions)
+  float* zroot = nullptr;    // z at each region's reference cell
+  int mode = SIM_REGIONS_AUTO;
+  bool valid = false;        // labels describe the current geometry
+};
+
 struct Solver {
   int nlev = 0;
   int nbottom = 0;     // first level run in the one-workgroup bottom solve (at most kBottomCells cells)
@@ -119,9 +140,11 @@ struct Solver {
   // of iterations (at most max_iter) per solve, stats written by a kernel
   int device_mode = 0;
   int budget = 0;
+  Sides sides = {};
+  Components comp;
   hipStream_t cap_stream = nullptr;
-  hipGraph_t iter_graph = nullptr;
-  hipGraphExec_t iter_exec = nullptr;
+  hipGraph_t iter_graph[2] = {nullptr, nullptr};      // [1]: with the region shift of z
+  hipGraphExec_t iter_exec[2] = {nullptr, nullptr};
 };
 
 // nf_geom.hip
@@ -151,6 +174,8 @@ void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk
 size_t wall_column_doubles(const Dims& d);
 void launch_loss_outlet(const Dims& d, double scale, const float* w, const float* u, double* J, float* g,
                         double* partials, hipStream_t s);
+// blocks (= partial sums) of the box-loss kernel for a grid (at most kLossBlocks)
+int loss_box_blocks(const Dims& d);
 void launch_loss_box(const Domain& D, const double* lo, const double* hi, const float* u, double* J, float* g,
                      double* partials, hipStream_t s);
 // nf_solver.hip
@@ -159,6 +184,13 @@ enum SolveKind { kSolvePressure = 0, kSolveAdjoint = 1, kSolveUser = 2 };
 int solver_solve(Solver& S, SolveKind kind, const float* b, float* x, double tol, int maxit, sim_stats* stats,
                  hipStream_t st);
 void solver_init_device(Solver& S);
+// nf_components.hip
+void components_label(Solver& S, hipStream_t st);
+void components_project_start(Solver& S, hipStream_t st);
+// iter: the per-iteration projection (skipped unless regions are tracked one by one)
+void components_subtract(Solver& S, hipStream_t st, int iter = 0);
+void components_shift_z(Solver& S, hipStream_t st);
+void components_project_iter(Solver& S, int nrr, hipStream_t st);
 void solver_release(Solver& S);
 
 }  // namespace nf

@@ -106,10 +106,7 @@ __device__ inline double true_residual_at(const Dims& d, const float* ax, const 
   return (double)b[c] - s;
 }
 
-__device__ inline double vscale_of(double rr, long n) {
-  double rms = sqrt(rr / (double)n);
-  return rms > 0.0 && isfinite(rms) ? kVcycleRms / rms : 1.0;
-}
+__device__ inline double vscale_of(double rr, long n) { return vscale_of_rr(rr, n); }
 
 // ---------------------------------------------------------------------------
 // CG kernels (fine level: FP64 iterate, FP32 vectors).  Each reducing kernel
@@ -177,6 +174,9 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_init(int nb, const double* pa
     const double rr = projected_rr(tot[1], tot[2], tot[3], project);
     sc->mu = project && tot[3] > 0.0 ? tot[2] / tot[3] : 0.0;
     sc->nact = tot[3];
+    sc->rr_raw = tot[1];
+    sc->null_rr = 0.0;
+    sc->use_comp = 0;
     sc->zmu = 0.0;
     tot[1] = rr;
     sc->bb = tot[0];
@@ -373,8 +373,14 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_true(int nb, const double* pa
   finish_partials<3>(partials, nb, tot);
   if (threadIdx.x == 0) {
     sc->checks += 1;
-    tot[0] = projected_rr(tot[0], tot[1], tot[2], project);
-    sc->mu = project && tot[2] > 0.0 ? tot[1] / tot[2] : 0.0;
+    // region by region (labels), or one global mean on closed domains
+    if (sc->use_comp) {
+      tot[0] = tot[0] - sc->null_rr > 0.0 ? tot[0] - sc->null_rr : 0.0;
+      sc->mu = 0.0;
+    } else {
+      tot[0] = projected_rr(tot[0], tot[1], tot[2], project);
+      sc->mu = project && tot[2] > 0.0 ? tot[1] / tot[2] : 0.0;
+    }
     sc->true_rr = tot[0];
     if (!isfinite(tot[0])) sc->nonfinite = 1;
     sc->converged = !sc->nonfinite && (sc->bb == 0.0 || tot[0] <= sc->tol2bb);
@@ -449,7 +455,8 @@ __device__ inline RZState rz_state(const CGScalars* sc, const double (&tot)[4], 
   RZState z;
   z.slot = sc->iters & 1;
   const int o = z.slot ^ 1;
-  z.mu = project && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
+  // with region labels z is shifted region by region instead
+  z.mu = project && !sc->use_comp && sc->nact > 0.0 ? tot[2] / sc->nact : 0.0;
   z.rho = tot[0] - z.mu * tot[3];
   z.beta = 0.0;
   if (!sc->first) {
@@ -1955,6 +1962,9 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
   S.ax = fx;
   S.ay = fy;
   S.az = fz;
+  // connected-region labels belong to one geometry
+  S.comp.valid = false;
+  if (S.comp.mode == SIM_REGIONS_ALWAYS) components_label(S, st);
   if (S.precision == SIM_FP32) {
     S.lev[0].a[0] = (void*)fx;
     S.lev[0].a[1] = (void*)fy;
@@ -2014,6 +2024,12 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     pack_records<__hip_bfloat16>(S, fx, fy, fz, st);
 }
 
+// The V-cycle's output, then (with region labels) its region-by-region shift.
+static void precondition(Solver& S, hipStream_t st, int nrr = 0) {
+  vcycle_dispatch(S, S.r, S.z, st, nrr);
+  if (S.comp.valid) components_shift_z(S, st);
+}
+
 static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
@@ -2034,15 +2050,21 @@ static void enqueue_iterations(Solver& S, double* x, int count, hipStream_t st) 
     const int nu = nb < kUpdateBlocks ? nb : kUpdateBlocks;
     NF_LAUNCH(S.prof, SIM_K_CG_UPDATE, k_cg_update, dim3(nu), dim3(kBlock), 0, st, n, x, S.r, pnew, S.q, S.sc,
               S.partials, npq, S.partials_rr);
-    vcycle_dispatch(S, S.r, S.z, st, nu);
+    // with region labels the updated residual is projected region by region
+    // (its FP32 rounding otherwise leaves region sums that the shifted z would
+    // weight with the V-cycle's large region constants in r . z)
+    if (S.comp.valid) components_project_iter(S, nu, st);
+    precondition(S, st, nu);
     S.pcur ^= 1;
   }
 }
 
 // Capture two iterations (starting with p0 as the current direction) into a
-// graph; replaying it leaves the direction parity unchanged.
+// graph; replaying it leaves the direction parity unchanged.  One graph per
+// form of the iteration (with or without the region shift of z).
 static bool capture_pair(Solver& S, double* x) {
-  if (S.iter_exec) return true;
+  const int v = S.comp.valid ? 1 : 0;
+  if (S.iter_exec[v]) return true;
   if (!S.cap_stream && hipStreamCreateWithFlags(&S.cap_stream, hipStreamNonBlocking) != hipSuccess) return false;
   if (hipStreamBeginCapture(S.cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return false;
   const int saved = S.pcur;
@@ -2052,9 +2074,9 @@ static bool capture_pair(Solver& S, double* x) {
   enqueue_iterations(S, x, 2, S.cap_stream);
   S.prof = prof;
   S.pcur = saved;
-  if (hipStreamEndCapture(S.cap_stream, &S.iter_graph) != hipSuccess) return false;
-  if (hipGraphInstantiate(&S.iter_exec, S.iter_graph, nullptr, nullptr, 0) != hipSuccess) {
-    S.iter_exec = nullptr;
+  if (hipStreamEndCapture(S.cap_stream, &S.iter_graph[v]) != hipSuccess) return false;
+  if (hipGraphInstantiate(&S.iter_exec[v], S.iter_graph[v], nullptr, nullptr, 0) != hipSuccess) {
+    S.iter_exec[v] = nullptr;
     return false;
   }
   return true;
@@ -2067,7 +2089,7 @@ static int cg_iterations(Solver& S, double* x, int count, hipStream_t st) {
   const bool timing = S.prof && S.prof->active >= 0;
   if (S.use_graph && !timing && S.pcur == 0 && capture_pair(S, x)) {
     const int pairs = (count + 1) / 2;
-    for (int q = 0; q < pairs; ++q) (void)hipGraphLaunch(S.iter_exec, st);
+    for (int q = 0; q < pairs; ++q) (void)hipGraphLaunch(S.iter_exec[S.comp.valid ? 1 : 0], st);
     return 2 * pairs;
   }
   enqueue_iterations(S, x, count, st);
@@ -2092,11 +2114,13 @@ void solver_init_device(Solver& S) {
 }
 
 void solver_release(Solver& S) {
-  if (S.iter_exec) (void)hipGraphExecDestroy(S.iter_exec);
-  if (S.iter_graph) (void)hipGraphDestroy(S.iter_graph);
+  for (int v = 0; v < 2; ++v) {
+    if (S.iter_exec[v]) (void)hipGraphExecDestroy(S.iter_exec[v]);
+    if (S.iter_graph[v]) (void)hipGraphDestroy(S.iter_graph[v]);
+    S.iter_exec[v] = nullptr;
+    S.iter_graph[v] = nullptr;
+  }
   if (S.cap_stream) (void)hipStreamDestroy(S.cap_stream);
-  S.iter_exec = nullptr;
-  S.iter_graph = nullptr;
   S.cap_stream = nullptr;
 }
 
@@ -2137,9 +2161,11 @@ static void solve_on_device(Solver& S, const float* b, double* x, int budget, hi
                        S.project);
     if (left <= 0) break;
     hipLaunchKernelGGL(k_hold_restart, dim3(1), dim3(1), 0, st, S.sc);
-    if (S.project)
+    if (S.comp.valid)
+      components_subtract(S, st);
+    else if (S.project)
       hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, S.sc);
-    vcycle_dispatch(S, S.r, S.z, st);
+    precondition(S, st);
     hipLaunchKernelGGL(k_release_restart, dim3(1), dim3(1), 0, st, S.sc);
   }
 }
@@ -2156,9 +2182,11 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
                               S.partials);
   hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
                      S.project);
-  if (S.project)
+  if (S.comp.valid)
+    components_project_start(S, st);
+  else if (S.project)
     hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
-  vcycle_dispatch(S, S.r, S.z, st);
+  precondition(S, st);
   S.pcur = 0;
   if (S.device_mode) {
     solve_on_device(S, b, x, maxit, st);
@@ -2194,9 +2222,23 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     // the check restarted CG from the true residual
     ++restarts;
     hipLaunchKernelGGL(k_release_restart, dim3(1), dim3(1), 0, st, sc);
-    if (S.project)
+    if (S.comp.valid)
+      components_subtract(S, st);
+    else if (S.project)
       hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
-    vcycle_dispatch(S, S.r, S.z, st);
+    precondition(S, st);
+  }
+  {
+    // A solve that stalls short of the tolerance without a NaN / Inf on a
+    // geometry whose connected regions are not labelled yet: label them and
+    // solve again with the residual projected region by region (a floating
+    // region's rounding-level incompatibility would otherwise hold the
+    // residual up).  The initial guess is still in xio.
+    const CGScalars& h = *S.host_sc;
+    if (!h.converged && !h.nonfinite && !S.comp.valid && S.comp.mode == SIM_REGIONS_AUTO) {
+      components_label(S, st);
+      return solver_solve(S, kind, b, xio, tol, maxit, stats, st);
+    }
   }
   S.last_iters[kind] = S.host_sc->iters;
   hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);

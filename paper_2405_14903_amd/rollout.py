@@ -44,6 +44,9 @@ class Rollout:
         # the report costs nothing more there)
         self.iters = {"fwd": [], "adj": []}
         self.collect = not getattr(sim, "device_mode", False)
+        # device solve mode: the solver reports written on the device, kept
+        # here when a list is given (the caller reads them after the work)
+        self.device_stats = None
         # step_loss(n, u_next) -> (J_n: device double (1,), dJ_n/du_next): a loss
         # on every step's result, summed over the rollout
         self.step_loss = step_loss
@@ -61,11 +64,18 @@ class Rollout:
         th, ct = self.schedule(n)
         if self.timer:
             self.timer.begin("fwd")
-        _, st = self.sim.step(u, th, ct, u_out=out, p_out=p, stats=self.collect)
+        _, st = self.sim.step(u, th, ct, u_out=out, p_out=p, stats=self.collect or self.device_stats is not None)
         if self.timer:
             self.timer.end("fwd")
-        if st is not None:
-            self.iters["fwd"].append(st["iters"])
+        self._record(st, "fwd")
+
+    def _record(self, st, kind):
+        if st is None:
+            return
+        if self.device_stats is not None and not isinstance(st, dict):
+            self.device_stats.append((kind, st))       # read once the work is done
+        else:
+            self.iters[kind].append(st["iters"])
 
     @staticmethod
     def channel(sim: Sim, knots, f, amp, T, every="sqrt", window=None, timer=None):
@@ -80,6 +90,14 @@ class Rollout:
         return ro
 
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
+        for _ in self.forward_steps(u0):
+            pass
+        return self.uT
+
+    def forward_steps(self, u0: torch.Tensor):
+        """The forward rollout as a generator: each step is enqueued on the
+        current stream, then the generator yields (the serving loop
+        interleaves the steps of many episodes).  The result is ``self.uT``."""
         self.ckpt = {0: u0.detach().clone()}
         a = u0.detach().clone()
         b = torch.empty_like(a)
@@ -91,15 +109,25 @@ class Rollout:
                 self.J += self.step_loss(n, a)[0]
             if (n + 1) % self.K == 0 and n + 1 < self.T:
                 self.ckpt[n + 1] = a.clone()
-        return a
+            self.uT = a
+            yield "fwd"
+        self.uT = a
 
     def backward(self, gT: torch.Tensor):
+        for _ in self.backward_steps(gT):
+            pass
+        return self.g0
+
+    def backward_steps(self, gT: torch.Tensor):
+        """The adjoint as a generator: yields after each recomputed forward
+        step ("fwd") and each adjoint step ("adj").  dJ/du0 is ``self.g0``."""
         sim, T, K = self.sim, self.T, self.K
         dev = gT.device
         g = gT.detach().clone().contiguous()
         gprev = torch.empty_like(g)
         g_steps = torch.zeros((T, sim.n_params), dtype=torch.float64, device=dev) if self.grad_geometry else None
         g_ctrl = torch.zeros((T, sim.n_ctrl), dtype=torch.float64, device=dev) if self.grad_geometry else None
+        self.g_steps, self.g_ctrl_direct = g_steps, g_ctrl
         seg_starts = list(range(0, T, K))
         states = [torch.empty_like(g) for _ in range(K + 1)]
         press = [torch.empty(sim.nc, dtype=torch.float32, device=dev) for _ in range(K)]
@@ -108,6 +136,7 @@ class Rollout:
             states[0].copy_(self.ckpt[s])
             for n in range(s, e):
                 self._step(n, states[n - s], states[n - s + 1], press[n - s])
+                yield "fwd"
             for n in range(e - 1, s - 1, -1):
                 th, ct = self.schedule(n)
                 if self.step_loss:
@@ -116,14 +145,15 @@ class Rollout:
                     self.timer.begin("adj")
                 _, st = sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
                                          g_theta=g_steps[n] if g_steps is not None else None,
-                                         g_ctrl=g_ctrl[n] if g_ctrl is not None else None, stats=self.collect)
+                                         g_ctrl=g_ctrl[n] if g_ctrl is not None else None,
+                                         stats=self.collect or self.device_stats is not None)
                 if self.timer:
                     self.timer.end("adj")
-                if st is not None:
-                    self.iters["adj"].append(st["iters"])
+                self._record(st, "adj")
                 g, gprev = gprev, g
-        self.g_steps, self.g_ctrl_direct = g_steps, g_ctrl
-        return g
+                self.g0 = g
+                yield "adj"
+        self.g0 = g
 
     def geometry_gradients(self):
         """(dJ/dtheta0 (9,), dJ/dctrl (T, 6)) after :meth:`backward` of an ellipsoid rollout."""

@@ -3,26 +3,32 @@
 Requests arrive over time (Poisson arrivals), each with its own grid size,
 step count, mode (forward only, forward + adjoint, or one pressure
 projection) and seeded scene.  A request is admitted as soon as its device
-footprint (the library's workspace, from ``sim_footprint``, plus its episode
-tensors) fits in the remaining HBM budget and a concurrency slot is free; it
-then runs on its own HIP stream, driven by its own host thread (the library
-releases the GIL inside every call), so the kernels of all admitted episodes
-overlap on the GPU.  Library handles are pooled per configuration, so an
-admitted request reuses a warm workspace.  When an episode completes its
-memory and slot are freed and the queue is re-examined.  Results and per-step
-latencies are kept per request.
+memory fits in the HBM budget (every library handle, busy or idle, counts
+with its ``sim_footprint``, plus the episode's own tensors; idle handles are
+freed least recently used first when a request needs the room) and a slot is
+free.  Each admitted episode gets its own HIP stream and runs with the
+library's device solve mode, so no call waits on the host: one host thread
+enqueues the episodes' steps round-robin, one step of an episode at a time,
+and keeps at most two steps of each episode and a bounded number of grid
+cells in flight, so that the kernels of small episodes overlap with each
+other and with one large one while a large step never queues behind many
+others.  Completion is polled with events.  Per-step latencies come from
+event pairs around each step on its episode's stream; the solver reports of
+every step are read when the episode has finished, and a step whose solve
+missed the tolerance makes its request fail.
+
+The serial baseline runs the same requests one at a time, each starting no
+earlier than its arrival, with the plain host-checked FP32 path.
 
 Inputs are generated on the device from each request's seed (a vector
 potential drawn with torch's generator, blurred and curled): they are input
-plumbing, not the method, and are produced before the request's timed steps.
+plumbing, not the method, and are produced before the request's first step.
 """
 from __future__ import annotations
 
-import heapq
 import math
-import threading
 import time
-from collections import defaultdict, deque
+from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -47,17 +53,22 @@ class Request:
     error: str = ""
 
 
-def make_stream(count, rate, seed=0, sizes=(32, 48, 64, 96, 128, 192), steps=(8, 64), kinds=("fwd", "fwd+adj")):
+def make_stream(count, rate, seed=0, sizes=(32, 48, 64, 96, 128, 192), steps=(8, 64), poisson_share=0.1):
     """Seeded request stream: exponential inter-arrival times at `rate` req/s,
-    grid size uniform over `sizes`, steps uniform in [steps[0], steps[1]],
-    mode uniform over `kinds`."""
+    grid size uniform over `sizes`, steps uniform in [steps[0], steps[1]];
+    a share `poisson_share` of the requests are single pressure projections,
+    the rest half forward-only and half forward + adjoint rollouts."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
     for i in range(count):
         t += rng.exponential(1.0 / rate)
-        out.append(Request(i, t, int(rng.choice(sizes)), int(rng.integers(steps[0], steps[1] + 1)),
-                           str(rng.choice(kinds)), int(seed * 100003 + i)))
+        n = int(rng.choice(sizes))
+        st = int(rng.integers(steps[0], steps[1] + 1))
+        u = rng.uniform()
+        mode = "poisson" if u < poisson_share else ("fwd" if u < poisson_share + 0.5 * (1 - poisson_share)
+                                                    else "fwd+adj")
+        out.append(Request(i, t, n, st, mode, int(seed * 100003 + i)))
     return out
 
 
@@ -132,190 +143,346 @@ def episode_bytes(n, steps, mode, every=8):
     return per * 3
 
 
-def run_episode(sim: Sim, req: Request, stream, timing=True, every=8):
-    """Run one request on `stream` with handle `sim`; fills req.result / step_ms."""
+def episode_steps(sim: Sim, req: Request, every=8, stats_sink=None):
+    """The work of one request as a generator: each `next` enqueues one unit
+    (the input set-up, then one forward, recomputed or adjoint step, or the
+    projection) on the current stream and yields its kind.  Results are
+    left as device tensors in req.result; the shape and control gradients
+    need a host read and are formed by :func:`finish_episode` once the work
+    has run."""
     from .rollout import Rollout
+    theta0, ctrl = request_scene(req)
+    u0 = device_curl_noise(req.n, req.seed)
+    if req.mode == "poisson":
+        yield "setup"
+        poses = ellipsoid_poses(theta0, ctrl[:1], sim.cfg.dt)
+        out, st = sim.project(u0, poses[0], ctrl[0], stats=stats_sink is not None)
+        if stats_sink is not None:
+            stats_sink.append(("fwd", st))
+        req.result = {"u": out}
+        yield "poisson"
+        return
+    yield "setup"
+    ro = Rollout.ellipsoid(sim, theta0, ctrl[:req.steps], every=every)
+    if stats_sink is not None:
+        ro.device_stats = stats_sink
+    yield from ro.forward_steps(u0)
+    req.result = {"u": ro.uT}
+    if req.mode == "fwd+adj":
+        J, g = sim.loss_box(ro.uT)
+        yield from ro.backward_steps(g)
+        req.result.update({"g_u0": ro.g0, "loss": J, "_rollout": ro})
+
+
+def finish_episode(req: Request):
+    """Host-side end of a finished episode (its stream has reached its end)."""
+    ro = req.result.pop("_rollout", None)
+    if ro is not None:
+        gth, gct = ro.geometry_gradients()
+        req.result.update({"g_theta0": gth, "g_ctrl": gct})
+
+
+def run_episode(sim: Sim, req: Request, stream, timing=True, every=8):
+    """Run one request to its end on `stream` (its steps back to back); per-
+    step latencies from event pairs on the stream."""
     with torch.cuda.stream(stream):
-        theta0, ctrl = request_scene(req)
-        u0 = device_curl_noise(req.n, req.seed)
-        if req.mode == "poisson":
-            poses = ellipsoid_poses(theta0, ctrl[:1], sim.cfg.dt)
-            t0 = time.perf_counter()
-            out, st = sim.project(u0, poses[0], ctrl[0])
-            stream.synchronize()
-            req.step_ms.append(1e3 * (time.perf_counter() - t0))
-            req.result = {"u": out, "iters": st["iters"]}
-            return
-        timer = _HostTimer(req.step_ms, stream) if timing else None
-        ro = Rollout.ellipsoid(sim, theta0, ctrl[:req.steps], every=every, timer=timer)
-        uT = ro.forward(u0)
-        req.result = {"u": uT}
-        if req.mode == "fwd+adj":
-            J, g = sim.loss_box(uT)
-            g0 = ro.backward(g)
-            gth, gct = ro.geometry_gradients()
-            req.result.update({"g_u0": g0, "g_theta0": gth, "g_ctrl": gct, "loss": J})
+        marks = []
+        for kind in _timed(episode_steps(sim, req, every), marks, timing):
+            pass
         stream.synchronize()
+    req.step_ms += [a.elapsed_time(b) for a, b, k in marks if k != "setup"]
+    finish_episode(req)
 
 
-class _HostTimer:
-    """Per-step wall latency (each library step ends with a stream-synchronised
-    convergence check, so host time brackets the step's device work)."""
-
-    def __init__(self, sink, stream):
-        self.sink, self.stream, self.t = sink, stream, 0.0
-
-    def begin(self, kind):
-        self.t = time.perf_counter()
-
-    def end(self, kind):
-        self.stream.synchronize()
-        self.sink.append(1e3 * (time.perf_counter() - self.t))
+def _timed(gen, marks, timing):
+    """Bracket each unit of a generator with events on the current stream."""
+    while True:
+        a = torch.cuda.Event(enable_timing=True) if timing else None
+        if a is not None:
+            a.record()
+        try:
+            kind = next(gen)
+        except StopIteration:
+            return
+        if a is not None:
+            b = torch.cuda.Event(enable_timing=True)
+            b.record()
+            marks.append((a, b, kind))
+        yield kind
 
 
 # ---------------------------------------------------------------------------
-# admission and the serving loop
+# admission and handles
 # ---------------------------------------------------------------------------
 
 class Admission:
-    """HBM-footprint admission: FIFO queue, admit while the budget and the
-    slot count allow; a request larger than the whole budget is rejected."""
+    """HBM-footprint admission with pooled library handles.
 
-    def __init__(self, budget_bytes, max_active, footprint):
-        self.budget, self.max_active, self.footprint = budget_bytes, max_active, footprint
+    Every live handle, busy or idle, counts with its workspace bytes; an
+    admitted request adds its episode bytes.  The queue is FIFO: the head is
+    admitted when a slot is free and its bytes fit (reusing an idle handle of
+    its grid, whose bytes are already counted, or creating one), after
+    freeing idle handles of other grids least recently used first if that
+    makes it fit.  A request that could not fit even in an empty server is
+    rejected when offered.
+
+    handle_bytes(n) -> workspace bytes of a handle for grid n;
+    episode_bytes(req) -> the request's own device bytes;
+    make(n) -> a new handle (with .close())."""
+
+    def __init__(self, budget_bytes, max_active, handle_bytes, episode_bytes, make):
+        self.budget, self.max_active = budget_bytes, max_active
+        self.handle_bytes, self.episode_bytes, self.make = handle_bytes, episode_bytes, make
         self.queue = deque()
-        self.used = 0
-        self.active = {}
+        self.used = 0                 # live handles + active episodes
+        self.active = {}              # rid -> (episode bytes, grid)
+        self.idle = OrderedDict()     # (grid, serial) -> handle, least recently used first
+        self._serial = 0
 
     def offer(self, req):
-        need = self.footprint(req)
+        need = self.handle_bytes(req.n) + self.episode_bytes(req)
         if need > self.budget:
             req.error = f"needs {need} B > budget {self.budget} B"
             return False
-        self.queue.append((req, need))
+        self.queue.append(req)
         return True
 
+    def _idle_for(self, n):
+        for key in self.idle:
+            if key[0] == n:
+                return key
+        return None
+
     def admit(self):
+        """[(request, handle)] admitted now, in FIFO order."""
         out = []
-        while self.queue and len(self.active) < self.max_active and self.used + self.queue[0][1] <= self.budget:
-            req, need = self.queue.popleft()
+        while self.queue and len(self.active) < self.max_active:
+            req = self.queue[0]
+            ep = self.episode_bytes(req)
+            key = self._idle_for(req.n)
+            need = ep if key is not None else ep + self.handle_bytes(req.n)
+            # free idle handles of other grids, least recently used first
+            while self.used + need > self.budget:
+                victim = next((k for k in self.idle if k != key), None)
+                if victim is None:
+                    break
+                self.idle.pop(victim).close()
+                self.used -= self.handle_bytes(victim[0])
+            if self.used + need > self.budget:
+                break
+            self.queue.popleft()
+            if key is not None:
+                h = self.idle.pop(key)
+            else:
+                h = self.make(req.n)
             self.used += need
-            self.active[req.rid] = need
-            out.append(req)
+            self.active[req.rid] = (ep, req.n)
+            out.append((req, h))
         return out
 
-    def release(self, req):
-        self.used -= self.active.pop(req.rid)
+    def release(self, req, handle):
+        """The request is done: its episode bytes are freed and its handle
+        goes idle (still counted)."""
+        ep, n = self.active.pop(req.rid)
+        self.used -= ep
+        self._serial += 1
+        self.idle[(n, self._serial)] = handle
 
-
-class HandlePool:
-    """Warm library handles keyed by (grid, precision)."""
-
-    def __init__(self, precision, tol=1e-6):
-        self.precision, self.tol = precision, tol
-        self.free = defaultdict(list)
-        self.lock = threading.Lock()
-
-    def cfg(self, n):
-        return Config(n=(n, n, n), dx=1.0 / n, dt=0.5 / n, geom="ellipsoid", tol=self.tol,
-                      precision=self.precision, max_iter=200)
-
-    def get(self, n):
-        with self.lock:
-            if self.free[n]:
-                return self.free[n].pop()
-        return Sim(self.cfg(n))
-
-    def put(self, n, sim):
-        with self.lock:
-            self.free[n].append(sim)
+    def warm(self, n):
+        """Create an idle handle for grid n up front (counted); False if it
+        does not fit."""
+        if self.used + self.handle_bytes(n) > self.budget:
+            return False
+        self._serial += 1
+        self.idle[(n, self._serial)] = self.make(n)
+        self.used += self.handle_bytes(n)
+        return True
 
     def close(self):
-        for lst in self.free.values():
-            for s in lst:
-                s.close()
-        self.free.clear()
+        for h in self.idle.values():
+            h.close()
+        for key in list(self.idle):
+            self.used -= self.handle_bytes(key[0])
+        self.idle.clear()
 
 
-def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, timing=True, on_done=None):
+def handle_config(n, precision, tol=1e-6):
+    return Config(n=(n, n, n), dx=1.0 / n, dt=0.5 / n, geom="ellipsoid", tol=tol, precision=precision, max_iter=200)
+
+
+# ---------------------------------------------------------------------------
+# the serving loop
+# ---------------------------------------------------------------------------
+
+class _Episode:
+    def __init__(self, req, sim, timing):
+        self.req, self.sim = req, sim
+        self.stream = torch.cuda.Stream()
+        self.stats = []
+        with torch.cuda.stream(self.stream):
+            self.gen = episode_steps(sim, req, stats_sink=self.stats)
+        self.marks = deque()          # (start, end, kind) of steps in flight
+        self.timing = timing
+        self.exhausted = False
+        self.last = None              # event after the latest enqueued step
+
+    def advance(self):
+        with torch.cuda.stream(self.stream):
+            a = torch.cuda.Event(enable_timing=self.timing)
+            a.record()
+            try:
+                kind = next(self.gen)
+            except StopIteration:
+                self.exhausted = True
+                return False
+            b = torch.cuda.Event(enable_timing=self.timing)
+            b.record()
+        self.marks.append((a, b, kind))
+        self.last = b
+        return True
+
+    def retire(self):
+        """Steps that have run: their latencies (ms)."""
+        while self.marks and self.marks[0][1].query():
+            a, b, kind = self.marks.popleft()
+            if self.timing and kind != "setup":
+                self.req.step_ms.append(a.elapsed_time(b))
+
+    def finished(self):
+        return self.exhausted and not self.marks
+
+
+def warm_up(sim, n):
+    """One short rollout on a fresh handle (its iteration graphs are captured
+    and its kernels loaded before the clock starts)."""
+    req = Request(-1, 0.0, n, 2, "fwd+adj", 7)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in episode_steps(sim, req):
+            pass
+    stream.synchronize()
+    finish_episode(req)
+
+
+def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, timing=True, on_done=None,
+          inflight_cells=2 * 192 ** 3, solve_budget=48, warm_sizes=()):
     """Run the stream with continuous batching.  Returns a summary dict.
-    on_done(req), if given, is called from the loop as each request completes."""
-    pool = HandlePool(precision)
-    adm = Admission(budget_bytes, max_active,
-                    lambda r: sim_footprint(pool.cfg(r.n)) + episode_bytes(r.n, r.steps, r.mode))
-    done_q = deque()
-    cv = threading.Condition()
+    on_done(req), if given, is called from the loop as each request ends.
+    inflight_cells bounds the grid cells of the steps enqueued at once (one
+    step may always run); solve_budget is the CG iteration budget of every
+    device-mode solve; warm_sizes: grids that get a warmed idle handle before
+    the clock starts (counted in the budget like any other)."""
+    def make(n):
+        sim = Sim(handle_config(n, precision))
+        sim.set_solve_mode("device", solve_budget)
+        return sim
+    adm = Admission(budget_bytes, max_active, lambda n: sim_footprint(handle_config(n, precision)),
+                    lambda r: episode_bytes(r.n, r.steps, r.mode), make)
+    for n in warm_sizes:
+        if adm.warm(n):
+            warm_up(next(reversed(adm.idle.values())), n)
     pending = sorted(requests, key=lambda r: r.arrival)
-    t0 = time.perf_counter()
-
-    def worker(req):
-        sim = pool.get(req.n)
-        stream = torch.cuda.Stream()
-        try:
-            req.admitted = time.perf_counter() - t0
-            run_episode(sim, req, stream, timing)
-        except Exception as e:  # a failing request is reported, the others go on
-            req.error = repr(e)
-        finally:
-            req.finished = time.perf_counter() - t0
-            pool.put(req.n, sim)
-            with cv:
-                done_q.append(req)
-                cv.notify()
-
-    threads = []
-    i = 0
-    finished = 0
-    total = len(pending)
+    active = []
     rejected = []
+    i = finished = 0
+    total = len(pending)
+    rr = 0
+    t0 = time.perf_counter()
     while finished + len(rejected) < total:
         now = time.perf_counter() - t0
         while i < total and (not realtime or pending[i].arrival <= now):
             if not adm.offer(pending[i]):
                 rejected.append(pending[i])
             i += 1
-        for req in adm.admit():
-            th = threading.Thread(target=worker, args=(req,), daemon=True)
-            th.start()
-            threads.append(th)
-        with cv:
-            if not done_q:
-                wait = 0.05
-                if realtime and i < total:
-                    wait = max(0.0, min(wait, pending[i].arrival - (time.perf_counter() - t0)))
-                cv.wait(timeout=wait)
-            while done_q:
-                r = done_q.popleft()
-                adm.release(r)
+        for req, sim in adm.admit():
+            req.admitted = time.perf_counter() - t0
+            try:
+                active.append(_Episode(req, sim, timing))
+            except Exception as e:  # a request that cannot start is reported, the others go on
+                req.error = repr(e)
+                req.finished = req.admitted
+                adm.release(req, sim)
                 finished += 1
-                if on_done:
-                    on_done(r)
-    for th in threads:
-        th.join()
-    wall = time.perf_counter() - t0
+        progressed = False
+        cells = sum(ep.req.n ** 3 * len(ep.marks) for ep in active)
+        m = len(active)
+        for q in range(m):
+            ep = active[(rr + q) % m]
+            ep.retire()
+            if ep.exhausted or len(ep.marks) >= 2:
+                continue
+            c = ep.req.n ** 3
+            if cells > 0 and cells + c > inflight_cells:
+                continue
+            try:
+                if ep.advance():
+                    cells += c
+                    progressed = True
+            except Exception as e:
+                ep.req.error = repr(e)
+                ep.exhausted = True
+        rr += 1
+        for ep in [e for e in active if e.finished() or (e.req.error and not e.marks)]:
+            active.remove(ep)
+            req = ep.req
+            ep.stream.synchronize()
+            req.finished = time.perf_counter() - t0
+            if not req.error:
+                try:
+                    bad = [k for k, st in ep.stats if not st.as_dict()["converged"]]
+                    if bad:
+                        req.error = f"{len(bad)} solve(s) missed the tolerance"
+                    finish_episode(req)
+                except Exception as e:
+                    req.error = repr(e)
+            adm.release(req, ep.sim)
+            finished += 1
+            progressed = True
+            if on_done:
+                on_done(req)
+        if not progressed:
+            # nothing could be enqueued: wait for the oldest step in flight, or
+            # for the next arrival
+            waits = [ep.marks[0][1] for ep in active if ep.marks]
+            if waits:
+                waits[0].synchronize()
+            elif realtime and i < total:
+                time.sleep(max(0.0, min(0.05, pending[i].arrival - (time.perf_counter() - t0))))
     torch.cuda.synchronize()
-    pool.close()
+    wall = time.perf_counter() - t0
+    adm.close()
     return summarize(requests, wall, rejected)
 
 
-def serve_serial(requests, precision="fp32", timing=True, on_done=None):
-    """Baseline: one request at a time, FIFO, in arrival order (no overlap)."""
-    pool = HandlePool(precision)
+def serve_serial(requests, precision="fp32", timing=True, on_done=None, realtime=True, warm_sizes=()):
+    """Baseline: one request at a time in arrival order, each starting no
+    earlier than its arrival (the same schedule as :func:`serve`), with the
+    plain host-checked solves."""
+    pool = {}
+    for n in warm_sizes:
+        pool[n] = Sim(handle_config(n, precision))
+        warm_up(pool[n], n)
     stream = torch.cuda.Stream()
     t0 = time.perf_counter()
     for req in sorted(requests, key=lambda r: r.arrival):
+        if realtime:
+            wait = req.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
         sim = pool.get(req.n)
+        if sim is None:
+            sim = pool[req.n] = Sim(handle_config(req.n, precision))
         req.admitted = time.perf_counter() - t0
         try:
             run_episode(sim, req, stream, timing)
         except Exception as e:
             req.error = repr(e)
         req.finished = time.perf_counter() - t0
-        pool.put(req.n, sim)
         if on_done:
             on_done(req)
     wall = time.perf_counter() - t0
-    pool.close()
+    for sim in pool.values():
+        sim.close()
     return summarize(requests, wall, [])
 
 

@@ -161,6 +161,22 @@ class Sim:
         L.check(self.lib.sim_set_solve_mode(self.h, m, int(budget)), "sim_set_solve_mode")
         self.device_mode = m == L.SIM_SOLVE_DEVICE
 
+    def set_regions(self, mode: str = "auto"):
+        """Connected-region labelling: "auto" (label after a stalled solve),
+        "always" (at every geometry evaluation) or "never"."""
+        m = {"auto": L.SIM_REGIONS_AUTO, "always": L.SIM_REGIONS_ALWAYS, "never": L.SIM_REGIONS_NEVER}[mode]
+        L.check(self.lib.sim_set_regions(self.h, m), "sim_set_regions")
+
+    def regions(self, out=None):
+        """(region id per cell (device int32, -1 inactive), region count,
+        floating-region count) of the current geometry."""
+        if out is None:
+            out = torch.empty(self.nc, dtype=torch.int32, device="cuda")
+        cnt, flo = C.c_int32(0), C.c_int32(0)
+        L.check(self.lib.sim_regions(self.h, _ptr(out, self.nc, torch.int32, "regions"), C.byref(cnt),
+                                     C.byref(flo), _stream()), "sim_regions")
+        return out, cnt.value, flo.value
+
     def _stats(self, want):
         """(object handed back, pointer passed to the library) for a solver report."""
         if not want:
