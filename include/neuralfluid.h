@@ -205,6 +205,19 @@ int32_t sim_set_geometry(sim_handle h, const double* theta, const double* ctrl, 
 int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const double* hi, double* J, float* g,
                      hipStream_t stream);
 
+/* sim_loss_box without a handle, for callers that cannot allocate device
+ * memory or must not (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): it allocates nothing.  The grid is given
+ * by n (cells per axis, each 1..4096, at most 2^30 cells) and dx; u, J, g, lo,
+ * hi as for sim_loss_box.  Its partial sums live in one fixed device array of
+ * 2048 doubles per GPU, owned by the library and held until the process
+ * ends; every grid fits it (the kernel strides over the faces).  All calls on
+ * one GPU share that array: calls that overlap on one GPU (distinct streams
+ * or threads) race and must be serialised by the caller.  SIM_EINVAL for an
+ * invalid size or pointer; nothing is enqueued then. */
+int32_t sim_loss_box_noalloc(const int32_t n[3], double dx, const float* u, const double* lo, const double* hi,
+                             double* J, float* g, hipStream_t stream);
+
 /* Loss helper (the channel configuration's outflow flux): J = scale * sum
  * over the outlet faces (z faces on the z+ side) of w_f u_f, u the stored
  * face-average velocity (Eq. u_next_matrix: alpha W + (1 - alpha) u_s, the

@@ -27,6 +27,7 @@ EXPORTS = [
     "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
     "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
+    "sim_loss_box_noalloc",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -102,6 +103,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "sim_set_solve_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
         "sim_set_regions": (C.c_int32, [_vp, C.c_int32]),
+        "sim_loss_box_noalloc": (C.c_int32, [C.POINTER(C.c_int32), C.c_double, _fp, _dp, _dp, _vp, _fp, _vp]),
         "sim_regions": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),
     }
     for name, (res, args) in sig.items():

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -535,6 +536,57 @@ int32_t sim_loss_box(sim_handle h, const float* u, const double* lo, const doubl
                      hipStream_t stream) {
   if (!h || !u || !lo || !hi || !J || !g || (const float*)g == u) return SIM_EINVAL;
   launch_loss_box(h->dom, lo, hi, u, J, g, h->S.partials, stream);
+  return last_hip_error();
+}
+
+}  // extern "C"
+
+// Partial sums of the allocation-free box loss: one fixed array per GPU,
+// shared by every call on that GPU (held until the process ends).  Host code
+// reaches it only through the address hipGetSymbolAddress returns on each
+// device; the array's own name is a host-side stand-in there.
+static __device__ __align__(256) double scratch[kLossBlocks];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_lock;
+double* g_scratch[kScratchDevices] = {};
+
+// The current device's copy of the scratch array (looked up once per device).
+double* scratch_on_device(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_lock);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = (double*)ptr;
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int32_t sim_loss_box_noalloc(const int32_t n[3], double dx, const float* u, const double* lo, const double* hi,
+                             double* J, float* g, hipStream_t stream) {
+  if (!n || !u || !lo || !hi || !J || !g || (const float*)g == u || !(dx > 0.0) || !std::isfinite(dx))
+    return SIM_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 1 || n[a] > 4096) return SIM_EINVAL;
+  if ((long)n[0] * n[1] * n[2] > (1L << 30)) return SIM_EINVAL;
+  Domain D;
+  std::memset(&D, 0, sizeof(D));
+  D.d = Dims{n[0], n[1], n[2]};
+  D.dx = dx;
+  if (loss_box_blocks(D.d) > kLossBlocks) return SIM_EINVAL;   // the scratch holds kLossBlocks partials
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SIM_EHIP;
+  if (dev < 0 || dev >= kScratchDevices) return SIM_EINVAL;
+  double* part = scratch_on_device(dev);
+  if (!part) return SIM_EHIP;
+  launch_loss_box(D, lo, hi, u, J, g, part, stream);
   return last_hip_error();
 }
 

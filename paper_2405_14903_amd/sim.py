@@ -314,6 +314,27 @@ def poisson_solve(sim: Sim, b, x, alpha=None, tol=0.0, max_iter=0):
     return sim.poisson_solve(b, x, alpha, tol, max_iter)
 
 
+def loss_box_noalloc(u, n, dx, lo=(0.5, 0.5, 0.5), hi=(1.0, 1.0, 1.0), J=None, g=None):
+    """The box loss without a handle (the library allocates nothing): J = sum
+    of u^2 over faces centred in [lo, hi] (device double) and g = dJ/du on an
+    n = (nx, ny, nz) grid of cell width dx."""
+    lib = L.load()
+    n = tuple(int(v) for v in n)
+    nx, ny, nz = n
+    nf = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    if J is None:
+        J = torch.empty(1, dtype=torch.float64, device=u.device)
+    if g is None:
+        g = torch.empty_like(u)
+    n_ = (C.c_int32 * 3)(*n)
+    lo_, lop = _host_doubles(lo, 3, "lo")
+    hi_, hip = _host_doubles(hi, 3, "hi")
+    L.check(lib.sim_loss_box_noalloc(n_, float(dx), _ptr(u, nf, torch.float32, "u"), lop, hip,
+                                     _ptr(J, 1, torch.float64, "J"), _ptr(g, nf, torch.float32, "g"), _stream()),
+            "sim_loss_box_noalloc")
+    return J, g
+
+
 def ellipsoid_poses(theta0, ctrl, dt) -> np.ndarray:
     """(T, 15) per-step ellipsoid geometry (c, a, R) from theta0 (9) and ctrl (T, 6)."""
     lib = L.load()
