@@ -86,6 +86,12 @@ def parse():
     ap.add_argument("--summarize-trace", default=None, metavar="CSV",
                     help="only summarize a rocprofv3 kernel-trace CSV (kernel_trace.csv) as a markdown table")
     ap.add_argument("--summarize-title", default="kernel profile")
+    ap.add_argument("--summarize-counters", default=None, metavar="CSV[,CSV]",
+                    help="only summarize rocprofv3 --pmc counter CSVs (one per counter) of one kernel")
+    ap.add_argument("--summarize-copy", default="", metavar="CSV[,CSV]",
+                    help="with --summarize-counters: the same counters' CSVs of a --copy-probe run")
+    ap.add_argument("--summarize-kernel", default="k_mg_up")
+    ap.add_argument("--summarize-copy-mib", type=int, default=256)
     ap.add_argument("--summarize-grid", type=int, default=0,
                     help="with --summarize-trace: also report the working launches (>= 3 us) of the finest-level "
                          "k_mg_up, recognised by this grid size in threads")
@@ -465,8 +471,43 @@ def summarize_trace(path, title, fine_grid=0):
     print(f"\nTotal kernel time {total / 1e3:.1f} ms over {ndisp} dispatches.")
 
 
+def summarize_counters(paths, copy_paths, kernel, grid, copy_mib):
+    """Markdown summary of rocprofv3 --pmc runs: per counter (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch) the mean over the working dispatches of one
+    kernel (name containing `kernel`, launch grid `grid` threads; a working
+    dispatch reads more than a quarter of the largest one, the others were
+    enqueued after a solve converged and exit at once), scaled by the same
+    counter's reading for a plain device copy of copy_mib MiB."""
+    import csv
+
+    def rows(path):
+        with open(path, newline="") as f:
+            return list(csv.DictReader(f))
+    total = 0.0
+    print(f"| counter | copy KiB per dispatch | scale | working dispatches | KiB per working dispatch | bytes |")
+    print("|---|---|---|---|---|---|")
+    for path, cpath in zip(paths, copy_paths):
+        rs = [r for r in rows(path) if kernel in r["Kernel_Name"] and int(r.get("Grid_Size", 0) or 0) == grid]
+        name = rs[0]["Counter_Name"] if rs else "?"
+        vals = [float(r["Counter_Value"]) for r in rs]
+        cs = [float(r["Counter_Value"]) for r in rows(cpath) if "copy" in r["Kernel_Name"].lower()]
+        cmean = sum(cs) / len(cs) if cs else float("nan")
+        scale = copy_mib * 1024.0 / cmean if cs else float("nan")
+        top = max(vals) if vals else 0.0
+        work = [v for v in vals if v > 0.25 * top]
+        mean = sum(work) / len(work) if work else 0.0
+        b = mean * 1024.0 * scale
+        total += b
+        print(f"| {name} | {cmean:.1f} | x {scale:.4f} | {len(work)} of {len(vals)} | {mean:.1f} | {b / 1e6:.2f} MB |")
+    print(f"\nTotal HBM traffic per working dispatch: **{total / 1e6:.2f} MB** ({int(round(total))} bytes).")
+
+
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters.split(","), args.summarize_copy.split(","), args.summarize_kernel,
+                           args.summarize_grid, args.summarize_copy_mib)
+        return
     if args.cpu_oracle_run:
         cpu_oracle_run(args.cpu_oracle_run, args.cpu_n, args.cpu_steps)
         return
@@ -518,7 +559,8 @@ def main():
         "config": {"workload": "128^3 closed box, moving ellipsoid (9 shape params, 6 controls/step), "
                                "64 steps forward + adjoint, checkpoint every 8, octant loss",
                    "grid": [N, N, N], "steps_per_rollout": T, "checkpoint_every": EVERY,
-                   "precision": args.precision, "cg_tol": CG_TOL},
+                   "precision": args.precision, "cg_tol": CG_TOL,
+                   "recompute": "segments replayed from the pressures kept by the first forward (no solve)"},
         "latency_ms": {"step_p50": main_form["step_ms_p50"], "step_p99": main_form["step_ms_p99"],
                        "fwd_p50": main_form["fwd_ms_p50"], "fwd_p99": main_form["fwd_ms_p99"],
                        "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"]},

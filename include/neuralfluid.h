@@ -162,6 +162,16 @@ int32_t sim_layout(sim_handle h, size_t* vel_elems, size_t* cell_elems);
 int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const double* ctrl,
                  float* u_n1, float* p_n1, sim_stats* st, hipStream_t stream);
 
+/* sim_step with the pressure already known (Eq. u_next_matrix with P given):
+ * the geometry and the advection of sim_step, then the update from p_n1, the
+ * pressure sim_step returned for the same u_n, theta and ctrl; no Poisson
+ * solve.  The result equals sim_step's bitwise.  Back-propagation through a
+ * rollout keeps each step's pressure from the first forward pass and
+ * recomputes its segments with this call (one solve less per step, at the
+ * cost of a cell array per step). */
+int32_t sim_step_replay(sim_handle h, const float* u_n, const double* theta, const double* ctrl,
+                        const float* p_n1, float* u_n1, hipStream_t stream);
+
 /* Projection only (Eqs. projection_matrix, u_next_matrix) of a given face
  * field u_in (no advection, no body force): u_out = projected field. */
 int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const double* ctrl,

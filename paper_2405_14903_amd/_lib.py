@@ -24,7 +24,7 @@ SIM_WALL_KNOTS_Y, SIM_WALL_KNOTS_Z = 16, 32
 #: every symbol declared in include/neuralfluid.h
 EXPORTS = [
     "sim_version", "sim_status_string", "sim_footprint", "sim_create", "sim_destroy", "sim_layout",
-    "sim_step", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
+    "sim_step", "sim_step_replay", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
     "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
     "sim_loss_box_noalloc",
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_layout": (C.c_int32, [_vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "sim_step": (C.c_int32, [_vp, _fp, _dp, _dp, _fp, _fp, C.POINTER(SimStats), _vp]),
         "sim_project": (C.c_int32, [_vp, _fp, _dp, _dp, _fp, _fp, C.POINTER(SimStats), _vp]),
+        "sim_step_replay": (C.c_int32, [_vp, _fp, _dp, _dp, _fp, _fp, _vp]),
         "sim_step_adjoint": (C.c_int32, [_vp, _fp, _fp, _dp, _dp, _fp, _fp, _vp, _vp, C.POINTER(SimStats), _vp]),
         "poisson_solve": (C.c_int32, [_vp, _fp, _fp, _fp, C.c_double, C.c_int32, C.POINTER(SimStats), _vp]),
         "sim_set_geometry": (C.c_int32, [_vp, _dp, _dp, _fp, _vp]),

@@ -35,6 +35,7 @@ struct sim_ctx {
   std::vector<void*> allocs;
   GeomParams last_geom;
   bool have_geom = false;
+  bool levels_current = false;   // the solver's hierarchy was built from the current fractions
   Profiler prof;
 };
 
@@ -225,10 +226,13 @@ int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomPar
 
 int last_hip_error() { return hipGetLastError() == hipSuccess ? SIM_OK : SIM_EHIP; }
 
-void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st) {
+// phi and the face fractions of g; with `levels`, also the solver's
+// multigrid hierarchy (a step that reuses a stored pressure needs none).
+void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st, bool levels = true) {
   NF_TIMED(&c->prof, SIM_K_GEOM_PHI, st, launch_phi_nodes(c->dom, g, c->phi, st));
   NF_TIMED(&c->prof, SIM_K_GEOM_ALPHA, st, launch_alpha(c->dom, c->phi, c->alpha, st));
-  solver_setup_levels(c->S, c->alpha, st);
+  if (levels) solver_setup_levels(c->S, c->alpha, st);
+  c->levels_current = levels;
   c->last_geom = g;
   c->have_geom = true;
 }
@@ -419,6 +423,20 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
   return project_common(h, h->uhat, g, u_n1, p_n1, st, stream);
 }
 
+int32_t sim_step_replay(sim_handle h, const float* u_n, const double* theta, const double* ctrl,
+                        const float* p_n1, float* u_n1, hipStream_t stream) {
+  if (!h || !u_n || !u_n1 || !p_n1 || u_n == u_n1) return SIM_EINVAL;
+  GeomParams g;
+  int v = make_geom(h, theta, ctrl, g, stream);
+  if (v != SIM_OK) return v;
+  eval_geometry(h, g, stream, false);
+  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, nullptr, stream));
+  NF_TIMED(&h->prof, SIM_K_UPDATE, stream,
+           launch_update(h->dom, g, k_factor(h->desc), h->alpha, h->uhat, p_n1, u_n1, stream));
+  return last_hip_error();
+}
+
 int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const double* ctrl, float* u_out,
                     float* p_out, sim_stats* st, hipStream_t stream) {
   if (!h || !u_in || !u_out || u_in == u_out) return SIM_EINVAL;
@@ -482,6 +500,10 @@ int32_t poisson_solve(sim_handle h, const float* alpha, const float* b, float* x
       return SIM_EHIP;
     solver_setup_levels(h->S, h->alpha, stream);
     h->have_geom = true;
+    h->levels_current = true;
+  } else if (!h->levels_current) {
+    solver_setup_levels(h->S, h->alpha, stream);
+    h->levels_current = true;
   }
   int r = solver_solve(h->S, kSolveUser, b, x, tol > 0 ? tol : h->desc.tol, max_iter > 0 ? max_iter : h->desc.max_iter, st,
                        stream);
@@ -499,6 +521,10 @@ int32_t sim_set_regions(sim_handle h, int32_t mode) {
 
 int32_t sim_regions(sim_handle h, int32_t* region_out, int32_t* count, int32_t* floating, hipStream_t stream) {
   if (!h || !count || !h->have_geom) return SIM_EINVAL;
+  if (!h->levels_current) {
+    solver_setup_levels(h->S, h->alpha, stream);
+    h->levels_current = true;
+  }
   if (!h->S.comp.valid) components_label(h->S, stream);
   const size_t C = h->dom.d.cells();
   if (region_out &&

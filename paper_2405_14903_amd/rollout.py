@@ -7,10 +7,12 @@ bounded by storing the velocity only every ``every`` steps (``"sqrt"``:
 ceil(sqrt(T))) and recomputing each segment's forward before walking it
 backwards; the forward is deterministic (fixed-order reductions, zero initial
 pressure guess), so the recomputed states equal the original ones bitwise.
-The adjoint pressure solve does not depend on the forward solver's iterates
-(only on the converged operator), so no solver state is stored; the
-recomputed segment keeps each step's pressure, which the adjoint of the
-face-average update needs on cut faces.
+By default the first forward also keeps every step's pressure (one cell array
+per step, a sixth of a velocity field), and the recomputation replays each
+step from it (advection and update, no Poisson solve: the same bits).  The
+adjoint pressure solve does not depend on the forward solver's iterates (only
+on the converged operator), so no solver state is stored; the adjoint of the
+face-average update needs each step's pressure on cut faces.
 """
 from __future__ import annotations
 
@@ -35,8 +37,10 @@ class Rollout:
     ellipsoid use :meth:`ellipsoid`.
     """
 
-    def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None, step_loss=None):
+    def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None, step_loss=None,
+                 store_pressure=True):
         self.sim, self.T, self.schedule = sim, int(T), schedule
+        self.store_pressure = store_pressure
         self.K = checkpoint_stride(self.T, every)
         self.grad_geometry = grad_geometry
         self.timer = timer
@@ -52,10 +56,11 @@ class Rollout:
         self.step_loss = step_loss
 
     @staticmethod
-    def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None):
+    def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None, store_pressure=True):
         ctrl = np.asarray(ctrl, np.float64).reshape(-1, 6)
         poses = ellipsoid_poses(theta0, ctrl, sim.cfg.dt)
-        ro = Rollout(sim, ctrl.shape[0], lambda n: (poses[n], ctrl[n]), every, grad_geometry=True, timer=timer)
+        ro = Rollout(sim, ctrl.shape[0], lambda n: (poses[n], ctrl[n]), every, grad_geometry=True, timer=timer,
+                     store_pressure=store_pressure)
         ro.theta0 = np.asarray(theta0, np.float64).ravel()
         ro.ctrl = ctrl
         return ro
@@ -78,7 +83,7 @@ class Rollout:
             self.iters[kind].append(st["iters"])
 
     @staticmethod
-    def channel(sim: Sim, knots, f, amp, T, every="sqrt", window=None, timer=None):
+    def channel(sim: Sim, knots, f, amp, T, every="sqrt", window=None, timer=None, store_pressure=True):
         """The B-spline wall channel: the wall at t = (n + 1) dt in step n, and
         the time-integrated outflow flux sum_n dt dx^2 sum_outlet w U^{n+1}
         (window w: device float32 over the nx * ny outlet faces, or None)."""
@@ -86,7 +91,8 @@ class Rollout:
         dt, dx = sim.cfg.dt, sim.cfg.dx
         ctrl = [np.array([(n + 1) * dt, f, amp], np.float64) for n in range(T)]
         loss = lambda n, u: sim.loss_outlet(u, dt * dx * dx, window)   # noqa: E731
-        ro = Rollout(sim, T, lambda n: (knots, ctrl[n]), every, grad_geometry=True, timer=timer, step_loss=loss)
+        ro = Rollout(sim, T, lambda n: (knots, ctrl[n]), every, grad_geometry=True, timer=timer, step_loss=loss,
+                     store_pressure=store_pressure)
         return ro
 
     def forward(self, u0: torch.Tensor) -> torch.Tensor:
@@ -102,8 +108,10 @@ class Rollout:
         a = u0.detach().clone()
         b = torch.empty_like(a)
         self.J = torch.zeros(1, dtype=torch.float64, device=u0.device) if self.step_loss else None
+        self.P = torch.empty((self.T, self.sim.nc), dtype=getattr(self.sim, "pressure_dtype", torch.float32),
+                             device=u0.device) if self.store_pressure else None
         for n in range(self.T):
-            self._step(n, a, b)
+            self._step(n, a, b, self.P[n] if self.P is not None else None)
             a, b = b, a
             if self.step_loss:
                 self.J += self.step_loss(n, a)[0]
@@ -130,12 +138,21 @@ class Rollout:
         self.g_steps, self.g_ctrl_direct = g_steps, g_ctrl
         seg_starts = list(range(0, T, K))
         states = [torch.empty_like(g) for _ in range(K + 1)]
-        press = [torch.empty(sim.nc, dtype=torch.float32, device=dev) for _ in range(K)]
+        stored = getattr(self, "P", None) is not None
+        press = None if stored else [torch.empty(sim.nc, dtype=torch.float32, device=dev) for _ in range(K)]
         for s in reversed(seg_starts):
             e = min(s + K, T)
             states[0].copy_(self.ckpt[s])
             for n in range(s, e):
-                self._step(n, states[n - s], states[n - s + 1], press[n - s])
+                if stored:
+                    th, ct = self.schedule(n)
+                    if self.timer:
+                        self.timer.begin("fwd")
+                    sim.step_replay(states[n - s], self.P[n], th, ct, u_out=states[n - s + 1])
+                    if self.timer:
+                        self.timer.end("fwd")
+                else:
+                    self._step(n, states[n - s], states[n - s + 1], press[n - s])
                 yield "fwd"
             for n in range(e - 1, s - 1, -1):
                 th, ct = self.schedule(n)
@@ -143,7 +160,8 @@ class Rollout:
                     g += self.step_loss(n, states[n - s + 1])[1]
                 if self.timer:
                     self.timer.begin("adj")
-                _, st = sim.step_adjoint(states[n - s], g, th, ct, p_n1=press[n - s], g_u_n=gprev,
+                _, st = sim.step_adjoint(states[n - s], g, th, ct, p_n1=self.P[n] if stored else press[n - s],
+                                         g_u_n=gprev,
                                          g_theta=g_steps[n] if g_steps is not None else None,
                                          g_ctrl=g_ctrl[n] if g_ctrl is not None else None,
                                          stats=self.collect or self.device_stats is not None)

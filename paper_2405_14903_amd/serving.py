@@ -135,11 +135,14 @@ def request_scene(req: Request):
 # ---------------------------------------------------------------------------
 
 def episode_bytes(n, steps, mode, every=8):
+    """Device bytes of one episode's own tensors: velocity fields (input,
+    state pair, checkpoints, segment states, gradients) and, for forward +
+    adjoint, the pressure of every step kept by the first forward."""
     nf = 3 * (n + 1) * n * n
     per = 4 * nf
     if mode == "fwd+adj":
         k = max(1, min(every, steps))
-        return per * (steps // every + 2 + (k + 1) + 3) + 4 * n ** 3 * k
+        return per * (steps // every + 2 + (k + 1) + 3) + 4 * n ** 3 * steps
     return per * 3
 
 
@@ -163,7 +166,7 @@ def episode_steps(sim: Sim, req: Request, every=8, stats_sink=None):
         yield "poisson"
         return
     yield "setup"
-    ro = Rollout.ellipsoid(sim, theta0, ctrl[:req.steps], every=every)
+    ro = Rollout.ellipsoid(sim, theta0, ctrl[:req.steps], every=every, store_pressure=req.mode == "fwd+adj")
     if stats_sink is not None:
         ro.device_stats = stats_sink
     yield from ro.forward_steps(u0)

@@ -213,6 +213,17 @@ class Sim:
                                _ptr(p_out, self.nc, f32, "p_n1"), stp, _stream())
         return u_out, self._done(rc, "sim_step", st)
 
+    def step_replay(self, u_n, p_n1, theta=None, ctrl=None, u_out=None):
+        """sim_step with its pressure p_n1 already known (no solve)."""
+        f32 = torch.float32
+        if u_out is None:
+            u_out = torch.empty_like(u_n)
+        keep, thp, ctp = self._geom(theta, ctrl)
+        L.check(self.lib.sim_step_replay(self.h, _ptr(u_n, self.nf, f32, "u_n"), thp, ctp,
+                                         _ptr(p_n1, self.nc, f32, "p_n1"), _ptr(u_out, self.nf, f32, "u_n1"),
+                                         _stream()), "sim_step_replay")
+        return u_out
+
     def project(self, u_in, theta=None, ctrl=None, u_out=None, p_out=None, stats=True):
         f32 = torch.float32
         if u_out is None:

@@ -185,6 +185,24 @@ def test_forward_is_deterministic():
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_step_replay_equals_step(precision):
+    """A step replayed from its stored pressure (no solve) gives the step's
+    result bitwise."""
+    announce(f"step replay from the stored pressure, {precision}")
+    sc = scenes.scene_ellipsoid_rollout(seed=5, n=32, steps=2)
+    poses = ellipsoid_poses(sc.theta0, sc.ctrl, sc.dt)
+    with Sim(ellipsoid_cfg(sc.n, tol=1e-6, precision=precision)) as sim:
+        u0 = dev(sc.u0)
+        P = torch.empty(sim.nc, dtype=torch.float32, device="cuda")
+        u1, _ = sim.step(u0, poses[1], sc.ctrl[1], p_out=P)
+        # another geometry in between, so the replay evaluates its own
+        sim.step(u0, poses[0], sc.ctrl[0])
+        r1 = sim.step_replay(u0, P, poses[1], sc.ctrl[1])
+        torch.cuda.synchronize()
+        assert torch.equal(u1, r1)
+
+
 def test_rest_stays_at_rest_and_nonfinite_flag():
     announce("rest / nonfinite")
     n = (16, 16, 16)

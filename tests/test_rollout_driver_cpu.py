@@ -23,6 +23,8 @@ class OracleHandle:
         self.n_params, self.n_ctrl = (15, 6) if kind == "ellipsoid" else (4 * len(spheres), 0)
         self.cfg = type("C", (), {"dt": prm.dt})()
         self.steps_done = 0
+        self.replays = 0
+        self.pressure_dtype = torch.float64
 
     def _geo(self, th, ct):
         g = self.prm.grid
@@ -40,6 +42,19 @@ class OracleHandle:
         self.steps_done += 1
         return u_out, None
 
+    def step_replay(self, u, p, th, ct, u_out=None):
+        """The update of Eq. u_next_matrix from the given pressure (the oracle's
+        pieces: its advection, G and the face average), no solve."""
+        from oracle.advection import Advection
+        from oracle.projection import Operators
+        geo = self._geo(th, ct)
+        uh = Advection(self.prm.grid, u.double().numpy(), self.prm.dt).result
+        G = Operators(self.prm.grid, geo.alpha).G
+        W = uh - self.prm.k * (G @ p.double().numpy())
+        u_out.copy_(torch.from_numpy(geo.alpha * W + (1.0 - geo.alpha) * geo.us))
+        self.replays += 1
+        return u_out
+
     def step_adjoint(self, u_n, g, th, ct, p_n1=None, g_u_n=None, g_theta=None, g_ctrl=None, stats=False):
         geo = self._geo(th, ct)
         st = Step(self.prm, u_n.double().numpy(), geo.alpha, geo.us)
@@ -52,8 +67,9 @@ class OracleHandle:
         return g_u_n, None
 
 
+@pytest.mark.parametrize("store", [True, False])
 @pytest.mark.parametrize("every", [1, 3, "sqrt"])
-def test_static_rollout_driver_matches_oracle_bptt(every):
+def test_static_rollout_driver_matches_oracle_bptt(every, store):
     sc = scenes.scene_sphere_rollout(seed=0, n=10, steps=5)
     g = Grid(sc.n, sc.dx)
     prm = StepParams(g, sc.dt, tol=1e-12)
@@ -61,11 +77,13 @@ def test_static_rollout_driver_matches_oracle_bptt(every):
     J_o, gT = octant_loss(g, ro_o.forward(5))
     gu_o = ro_o.backward(gT)
     h = OracleHandle(prm, "spheres", sc.spheres)
-    ro = R.Rollout(h, 5, lambda n: (sc.spheres.ravel(), None), every=every)
+    ro = R.Rollout(h, 5, lambda n: (sc.spheres.ravel(), None), every=every, store_pressure=store)
     uT = ro.forward(torch.from_numpy(sc.u0.copy()))
     np.testing.assert_allclose(uT.numpy(), ro_o.hist[-1], atol=1e-13)
     gu = ro.backward(torch.from_numpy(gT.copy()))
     np.testing.assert_allclose(gu.numpy(), gu_o, rtol=1e-9, atol=1e-12 * np.abs(gu_o).max())
+    # stored pressures: the recomputation replays every step (no solve)
+    assert (h.replays == 5) == store and (h.steps_done == 5) == store
 
 
 def test_ellipsoid_rollout_driver_matches_oracle_bptt():
