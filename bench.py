@@ -100,8 +100,13 @@ def parse():
                          "200 steps forward + adjoint, sqrt(T) checkpoints, total outflow flux loss, "
                          "gradients w.r.t. the 512 control amplitudes (FP16 V-cycle)")
     ap.add_argument("--channel-steps", type=int, default=200)
-    ap.add_argument("--serve-requests", type=int, default=100)
-    ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-requests", type=int, default=400, help="requests per rate (--workload serving)")
+    ap.add_argument("--serve-rates", default="10,20,50,100,150,200", help="arrival rates (--workload serving)")
+    ap.add_argument("--no-channel", action="store_true", help="skip the nested channel leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the nested serving leg")
+    ap.add_argument("--nested-channel-steps", type=int, default=200)
+    ap.add_argument("--nested-serve-requests", type=int, default=48)
+    ap.add_argument("--nested-serve-rate", type=float, default=100.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 launches): the reference kernel that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run")
@@ -124,7 +129,7 @@ class StepTimer:
 
     def __init__(self, torch):
         self.torch = torch
-        self.pairs = {"fwd": [], "adj": []}
+        self.pairs = {"fwd": [], "adj": [], "replay": []}
         self.open = None
 
     def begin(self, kind):
@@ -186,6 +191,7 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
         print(f"[bench] {precision}: roofline pass done", file=sys.stderr, flush=True)
     fwd = timer.latencies("fwd")
     adj = timer.latencies("adj")
+    rep = timer.latencies("replay")
     out = {
         "wall_s": wall,
         "cell_steps_per_s": (N ** 3) * T * steps / wall,
@@ -193,6 +199,7 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
         "fwd_ms_p50": pct(fwd, 50), "fwd_ms_p99": pct(fwd, 99),
         "adj_ms_p50": pct(adj, 50), "adj_ms_p99": pct(adj, 99),
         "step_ms_p50": pct(fwd + adj, 50), "step_ms_p99": pct(fwd + adj, 99),
+        "replay_ms_p50": pct(rep, 50), "replay_ms_p99": pct(rep, 99),
         "cg_iters": iter_summary(iters),
         "loss": float(J.item()),
     }
@@ -342,17 +349,17 @@ def oracle_check(path, n, steps, torch):
     return out
 
 
-def run_channel(args, torch):
-    """The channel configuration: one warm-up rollout of a few steps, then one
-    timed rollout of --channel-steps steps forward + adjoint."""
+def channel_leg(args, torch, steps, precision, profile=True):
+    """The channel configuration: a short warm-up rollout, then one timed
+    rollout of `steps` steps forward + adjoint.  Returns its summary."""
     import scenes
     from paper_2405_14903_amd.sim import Config, Sim
     from paper_2405_14903_amd.rollout import Rollout
-    n3, T = scenes.CHANNEL_FULL_N, args.channel_steps
+    n3, T = scenes.CHANNEL_FULL_N, steps
     sc = scenes.scene_channel(seed=0, n=n3, steps=T)
     kn, f, amp = sc.extra["knots"], sc.extra["f"], sc.extra["amp"]
     cfg = Config(n=n3, dx=sc.dx, dt=sc.dt, bc=("wall", "wall", "wall", "wall", "inflow", "outflow"),
-                 inflow_speed=1.0, geom="wall", tol=1e-6, precision=args.precision, max_iter=400)
+                 inflow_speed=1.0, geom="wall", tol=CG_TOL, precision=precision, max_iter=400)
     sim = Sim(cfg)
     u0 = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
     zero = torch.zeros_like(u0)
@@ -366,74 +373,104 @@ def run_channel(args, torch):
     one(4, None)
     torch.cuda.synchronize()
     print("[bench] channel: warmup done", file=sys.stderr, flush=True)
-    sim.profile(ROOFLINE_KERNEL)
     timer = StepTimer(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ro = one(T, timer)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    prof = sim.profile_read(min_ms=NOOP_MS)
-    sim.profile(None)
     print(f"[bench] channel: {T} steps forward + adjoint in {wall:.2f} s", file=sys.stderr, flush=True)
+    prof = None
+    if profile:
+        sim.profile(ROOFLINE_KERNEL)
+        one(min(T, 16), None)
+        torch.cuda.synchronize()
+        prof = sim.profile_read(min_ms=NOOP_MS)
+        sim.profile(None)
     gk = ro.g_steps.sum(dim=0)
     fwd, adj = timer.latencies("fwd"), timer.latencies("adj")
     C = n3[0] * n3[1] * n3[2]
-    rec = {
-        "metric": "fwd+adjoint cell-steps/s, 256x256x512 channel (mixed); p50/p99 step latency",
-        "value": round(C * T / wall, 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": round(1e3 * wall, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
-        "data": "synthetic",
-        "config": {"workload": f"256x256x512 channel, B-spline wall (16x32 control amplitudes), inflow / outflow, "
-                               f"{T} steps forward + adjoint, sqrt(T) checkpoints, total outflow flux",
-                   "grid": list(n3), "steps_per_rollout": T, "checkpoint_every": ro.K,
-                   "precision": args.precision, "cg_tol": 1e-6},
+    out = {
+        "value": round(C * T / wall, 1), "unit": "cell-steps/s", "wall_s": round(wall, 3),
+        "workload": f"256x256x512 channel, B-spline wall (16x32 control amplitudes), inflow / outflow, "
+                    f"{T} steps forward + adjoint, sqrt(T) checkpoints (every {ro.K}), total outflow flux",
+        "precision": precision, "cg_tol": CG_TOL,
         "latency_ms": {"step_p50": pct(fwd + adj, 50), "step_p99": pct(fwd + adj, 99),
                        "fwd_p50": pct(fwd, 50), "fwd_p99": pct(fwd, 99), "adj_p50": pct(adj, 50),
                        "adj_p99": pct(adj, 99)},
+        "cg_iters": iter_summary(ro.iters),
         "loss": float(ro.J.item()), "knot_gradient_norm": float(gk.norm()),
-        "roofline": roofline(prof, args.precision, n3, traffic=False),
-        "cpu_baseline": None,
+        "roofline": roofline(prof, precision, n3, traffic=False) if prof else None,
     }
     sim.close()
+    return out
+
+
+def run_channel(args, torch):
+    """--workload channel: the channel leg as the one JSON line."""
+    leg = channel_leg(args, torch, args.channel_steps, args.precision)
+    rec = {
+        "metric": "fwd+adjoint cell-steps/s, 256x256x512 channel (mixed); p50/p99 step latency",
+        "value": leg["value"], "unit": "cell-steps/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(1e3 * leg["wall_s"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype_of(args.precision), "data": "synthetic",
+        "config": {"workload": leg["workload"], "grid": [256, 256, 512], "precision": args.precision,
+                   "cg_tol": CG_TOL},
+        "latency_ms": leg["latency_ms"], "cg_iters": leg["cg_iters"], "loss": leg["loss"],
+        "knot_gradient_norm": leg["knot_gradient_norm"], "roofline": leg["roofline"], "cpu_baseline": None,
+    }
     print(json.dumps(rec), flush=True)
 
 
-def run_serving(args, torch):
-    """The serving configuration on a bounded stream: --serve-requests seeded
-    requests with Poisson arrivals at --serve-rate req/s (grid sizes
-    {32, 48, 64, 96, 128, 192}^3, 8 to 64 steps, half forward-only and half
-    forward + adjoint), served with continuous batching and the FP16 V-cycle
-    within an HBM budget, against the same requests run serially in FP32."""
+def dtype_of(precision):
+    return "f32+f16" if precision == "fp16" else ("f32+bf16" if precision == "bf16" else "f32")
+
+
+def serving_leg(torch, n_req, rates, precision, seed=0):
+    """The serving configuration on a bounded stream: `n_req` seeded requests
+    per arrival rate (Poisson arrivals; grids {32, 48, 64, 96, 128, 192}^3,
+    8 to 64 steps; one in ten a pressure projection, the rest half
+    forward-only and half forward + adjoint), served with continuous batching
+    and the mixed-precision form within an HBM budget, against the same
+    requests run one at a time in plain FP32 on the same arrival schedule."""
     from paper_2405_14903_amd.serving import make_stream, serve, serve_serial
-    N_req, rate = args.serve_requests, args.serve_rate
     budget = 200 << 30
+    sizes = (32, 48, 64, 96, 128, 192)
+    out = {"workload": f"{n_req} requests per rate, Poisson arrivals, grids {{32..192}}^3, 8-64 steps, 10% pressure "
+                       f"projections, the rest half forward-only and half forward + adjoint; continuous batching "
+                       f"(8 episodes, {budget >> 30} GiB budget) with the {precision} V-cycle and device-mode "
+                       f"solves, against serial plain FP32 on the same schedule",
+           "rates": {}}
+    for rate in rates:
+        served = serve(make_stream(n_req, rate, seed=seed), budget_bytes=budget, precision=precision, max_active=8,
+                       realtime=True, warm_sizes=sizes)
+        serial = serve_serial(make_stream(n_req, rate, seed=seed), precision="fp32", warm_sizes=sizes)
+        print(f"[bench] serving at {rate:g} req/s: served {served['cell_steps_per_s'] / 1e6:.1f} M, serial "
+              f"{serial['cell_steps_per_s'] / 1e6:.1f} M cell-steps/s", file=sys.stderr, flush=True)
+        keep = ("completed", "failed", "rejected", "rerun_host_checked", "wall_s", "cell_steps_per_s", "step_ms_p50", "step_ms_p99",
+                "request_s_p50", "request_s_p99")
+        out["rates"][f"{rate:g}"] = {
+            "served": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in served.items() if k in keep},
+            "serial_fp32": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serial.items() if k in keep},
+            "throughput_over_serial": round(served["cell_steps_per_s"] / serial["cell_steps_per_s"], 3)
+            if serial["cell_steps_per_s"] else None,
+            "step_p99_over_serial": round(served["step_ms_p99"] / serial["step_ms_p99"], 3)
+            if served["step_ms_p99"] and serial["step_ms_p99"] else None}
+    return out
 
-    def done(tag):
-        return lambda r: print(f"[bench] {tag}: request {r.rid} ({r.n}^3, {r.steps} steps, {r.mode}) done "
-                               f"at {r.finished:.2f} s", file=sys.stderr, flush=True)
 
-    served = serve(make_stream(N_req, rate, seed=0), budget_bytes=budget, precision=args.precision, max_active=8,
-                   realtime=True, on_done=done("served"))
-    print(f"[bench] serving: {served}", file=sys.stderr, flush=True)
-    serial = serve_serial(make_stream(N_req, rate, seed=0), precision="fp32", on_done=done("serial"))
-    print(f"[bench] serial FP32: {serial}", file=sys.stderr, flush=True)
+def run_serving(args, torch):
+    """--workload serving: the serving leg as the one JSON line."""
+    rates = [float(r) for r in args.serve_rates.split(",")]
+    leg = serving_leg(torch, args.serve_requests, rates, args.precision)
+    first = leg["rates"][f"{rates[0]:g}"]
     rec = {
-        "metric": f"serving: cell-steps/s and p50/p99 step latency, {N_req} requests at {rate:g} req/s",
-        "value": round(served["cell_steps_per_s"], 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "ms_per_step": round(1e3 * served["wall_s"], 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
-        "data": "synthetic",
-        "config": {"workload": f"{N_req} requests, Poisson arrivals at {rate:g} req/s, grids {{32..192}}^3, "
-                               f"8-64 steps, half forward-only, half forward + adjoint; continuous batching, "
-                               f"8 concurrent episodes, {budget >> 30} GiB budget",
-                   "precision": args.precision},
-        "served": served, "serial_fp32": serial,
-        "speedup_vs_serial_fp32": round(served["cell_steps_per_s"] / serial["cell_steps_per_s"], 3)
-        if serial["cell_steps_per_s"] else None,
-        "roofline": None, "cpu_baseline": None,
+        "metric": "serving: cell-steps/s and p50/p99 step latency against serial FP32",
+        "value": round(first["served"]["cell_steps_per_s"], 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": round(1e3 * first["served"]["wall_s"], 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype_of(args.precision), "data": "synthetic",
+        "config": {"workload": leg["workload"], "rates": rates, "precision": args.precision},
+        "serving": leg, "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(rec), flush=True)
 
@@ -446,6 +483,7 @@ def summarize_trace(path, title, fine_grid=0):
     with open(path, newline="") as f:
         for r in csv.DictReader(f):
             name = r.get("Kernel_Name", "?")
+            name = name.split("(")[0].replace("void ", "").replace("nf::", "").replace("TileShape", "T")
             grid = int(r.get("Grid_Size_X", r.get("Grid_Size", "0")) or 0) * int(r.get("Grid_Size_Y", "1") or 1) * \
                 int(r.get("Grid_Size_Z", "1") or 1)
             wg = int(r.get("Workgroup_Size_X", r.get("Workgroup_Size", "0")) or 0) * \
@@ -554,7 +592,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f16" if args.precision == "fp16" else ("f32+bf16" if args.precision == "bf16" else "f32"),
+        "dtype": dtype_of(args.precision),
         "data": "synthetic",
         "config": {"workload": "128^3 closed box, moving ellipsoid (9 shape params, 6 controls/step), "
                                "64 steps forward + adjoint, checkpoint every 8, octant loss",
@@ -563,7 +601,8 @@ def main():
                    "recompute": "segments replayed from the pressures kept by the first forward (no solve)"},
         "latency_ms": {"step_p50": main_form["step_ms_p50"], "step_p99": main_form["step_ms_p99"],
                        "fwd_p50": main_form["fwd_ms_p50"], "fwd_p99": main_form["fwd_ms_p99"],
-                       "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"]},
+                       "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"],
+                       "replay_p50": main_form["replay_ms_p50"], "replay_p99": main_form["replay_ms_p99"]},
         "cg_iters": main_form["cg_iters"],
         "roofline": roofline(prof, args.precision),
     }
@@ -576,6 +615,10 @@ def main():
         rec["mixed_over_fp32"] = round(main_form["cell_steps_per_s"] / cmp_form["cell_steps_per_s"], 3)
     if oracle_path:
         rec["oracle_error"] = oracle_check(oracle_path, args.cpu_n, args.cpu_steps, torch)
+    if not args.no_channel:
+        rec["channel"] = channel_leg(args, torch, args.nested_channel_steps, args.precision, profile=False)
+    if not args.no_serving:
+        rec["serving"] = serving_leg(torch, args.nested_serve_requests, [args.nested_serve_rate], args.precision)
     rec["cpu_baseline"] = cpu
     print(json.dumps(rec), flush=True)
 

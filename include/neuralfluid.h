@@ -247,7 +247,7 @@ int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double sca
  *    batches are replayed from a captured graph.  sim_stats is a host struct.
  *  SIM_SOLVE_DEVICE: nothing waits on the host.  Each solve enqueues
  *    min(max_iter, budget) iterations (budget <= 0: max_iter) with an FP64
- *    true-residual check and a conditional restart behind every 4 of them;
+ *    true-residual check and a conditional restart behind every 8 of them;
  *    once converged, the remaining kernels exit at once on the device.  The
  *    outcome is written by a kernel into sim_stats, which must then be device
  *    memory or pinned host memory (SIM_EINVAL otherwise); the status is

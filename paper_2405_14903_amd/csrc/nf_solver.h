@@ -75,6 +75,11 @@ struct Level {
   void* tb;
 };
 
+// Device solve mode: iterations between two true-residual checks (each
+// check and its conditional restart costs about a dozen launches, which exit
+// at once when they have nothing to do).
+constexpr int kDeviceCheckEvery = 8;
+
 // Which domain sides are OUTFLOW (Dirichlet ghost), order x-, x+, y-, y+, z-, z+.
 struct Sides {
   int out[6];

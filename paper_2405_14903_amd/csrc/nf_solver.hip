@@ -2146,7 +2146,7 @@ static void solve_on_device(Solver& S, const float* b, double* x, int budget, hi
   if (hipStreamIsCapturing(st, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
   // the captured iteration pair is not replayed inside a caller's capture
   const bool graphs = cap == hipStreamCaptureStatusNone;
-  const int chunk = 4;
+  const int chunk = kDeviceCheckEvery;
   for (int left = budget; left > 0;) {
     const int c = left < chunk ? left : chunk;
     if (graphs)

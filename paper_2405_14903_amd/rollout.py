@@ -147,10 +147,10 @@ class Rollout:
                 if stored:
                     th, ct = self.schedule(n)
                     if self.timer:
-                        self.timer.begin("fwd")
+                        self.timer.begin("replay")
                     sim.step_replay(states[n - s], self.P[n], th, ct, u_out=states[n - s + 1])
                     if self.timer:
-                        self.timer.end("fwd")
+                        self.timer.end("replay")
                 else:
                     self._step(n, states[n - s], states[n - s + 1], press[n - s])
                 yield "fwd"

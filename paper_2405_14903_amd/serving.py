@@ -356,34 +356,56 @@ class _Episode:
 
 
 def warm_up(sim, n):
-    """One short rollout on a fresh handle (its iteration graphs are captured
-    and its kernels loaded before the clock starts)."""
+    """One short rollout on a fresh handle with host-checked solves (its
+    iteration graphs are captured and its kernels loaded before the clock
+    starts).  Returns the most CG iterations a solve took."""
+    from .rollout import Rollout
+    mode = getattr(sim, "device_mode", False)
+    sim.set_solve_mode("host")
     req = Request(-1, 0.0, n, 2, "fwd+adj", 7)
+    theta0, ctrl = request_scene(req)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        for _ in episode_steps(sim, req):
-            pass
+        u0 = device_curl_noise(n, req.seed)
+        ro = Rollout.ellipsoid(sim, theta0, ctrl[:2], every=8)
+        J, g = sim.loss_box(ro.forward(u0))
+        ro.backward(g)
     stream.synchronize()
-    finish_episode(req)
+    if mode:
+        sim.set_solve_mode("device", getattr(sim, "budget", 0))
+    return max(ro.iters["fwd"] + ro.iters["adj"] + [1])
+
+
+def device_budget(iters):
+    """Iteration budget of a device-mode solve from the iterations such solves
+    took: half as many again plus two, in whole check intervals of 8."""
+    return int(8 * math.ceil((1.5 * iters + 2) / 8))
 
 
 def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, timing=True, on_done=None,
-          inflight_cells=2 * 192 ** 3, solve_budget=48, warm_sizes=()):
+          inflight_cells=2 * 192 ** 3, solve_budget=0, warm_sizes=()):
     """Run the stream with continuous batching.  Returns a summary dict.
     on_done(req), if given, is called from the loop as each request ends.
     inflight_cells bounds the grid cells of the steps enqueued at once (one
     step may always run); solve_budget is the CG iteration budget of every
-    device-mode solve; warm_sizes: grids that get a warmed idle handle before
-    the clock starts (counted in the budget like any other)."""
+    device-mode solve (0: per grid, from the iterations a warm-up rollout's
+    host-checked solves took; a request with a solve that missed the
+    tolerance is run again with host-checked solves and doubles its grid's
+    budget); warm_sizes: grids that get a warmed idle handle before the clock
+    starts (counted in the budget like any other)."""
+    budget_for = {}      # grid -> device-mode iteration budget, learned from warm-up and from failures
+
     def make(n):
         sim = Sim(handle_config(n, precision))
-        sim.set_solve_mode("device", solve_budget)
+        if n not in budget_for:
+            budget_for[n] = device_budget(warm_up(sim, n)) if solve_budget <= 0 else solve_budget
+        sim.budget = budget_for[n]
+        sim.set_solve_mode("device", sim.budget)
         return sim
     adm = Admission(budget_bytes, max_active, lambda n: sim_footprint(handle_config(n, precision)),
                     lambda r: episode_bytes(r.n, r.steps, r.mode), make)
     for n in warm_sizes:
-        if adm.warm(n):
-            warm_up(next(reversed(adm.idle.values())), n)
+        adm.warm(n)
     pending = sorted(requests, key=lambda r: r.arrival)
     active = []
     rejected = []
@@ -434,8 +456,17 @@ def serve(requests, budget_bytes, precision="fp16", max_active=8, realtime=True,
                 try:
                     bad = [k for k, st in ep.stats if not st.as_dict()["converged"]]
                     if bad:
-                        req.error = f"{len(bad)} solve(s) missed the tolerance"
-                    finish_episode(req)
+                        # the budget was too small: run the request again with
+                        # host-checked solves, and give its grid more
+                        budget_for[req.n] = 2 * ep.sim.budget
+                        ep.sim.budget = budget_for[req.n]
+                        ep.sim.set_solve_mode("host")
+                        req.result, req.step_ms = {}, []
+                        req.retried = len(bad)
+                        run_episode(ep.sim, req, ep.stream)
+                        ep.sim.set_solve_mode("device", ep.sim.budget)
+                    else:
+                        finish_episode(req)
                 except Exception as e:
                     req.error = repr(e)
             adm.release(req, ep.sim)
@@ -505,6 +536,7 @@ def summarize(requests, wall, rejected):
         s = sorted(v)
         return s[min(len(s) - 1, max(0, int(math.ceil(q / 100 * len(s))) - 1))]
     return {"requests": len(requests), "completed": len(ok), "rejected": len(rejected),
+            "rerun_host_checked": sum(1 for r in ok if getattr(r, "retried", 0)),
             "failed": sum(1 for r in requests if r.error) - len(rejected),
             "wall_s": wall, "cell_steps_per_s": cell_steps / wall if wall > 0 else 0.0,
             "step_ms_p50": p(steps, 50), "step_ms_p99": p(steps, 99),
