@@ -20,10 +20,15 @@ decides ties; along a periodic axis s wraps modulo n_a instead.  The
 derivative of I_e w.r.t. position uses the same cell and is 0 along an axis
 whose coordinate was clamped.  V = (I_x, I_y, I_z).
 
-Viscosity and body force (Eq. viscosity_matrix, App. B Eq. apply_force):
-U^ = U~ + dt (nu L U~ + f), L the per-component 7-point Laplacian / dx^2 on its
-own lattice; implemented for periodic axes only (the only use is the
-Taylor-Green check).
+Viscosity (Eq. viscosity_matrix; App. B Eq. apply_force, explicit in time):
+U^ = (I - nu dt / dx^2 G_f^T G_f) U~, where G_f is the difference operator of
+each velocity component over the edges of its own face lattice (one row per
+pair of neighbouring lattice points; edges wrap along periodic axes).  So
+-G_f^T G_f is the per-component graph Laplacian: the 7-point Laplacian in the
+interior, and no edge leaves the lattice at a domain side (the tangential
+components see a zero normal derivative there, the normal component's
+boundary faces are lattice points like any other).  A body force f (this
+project's addition, used by the hydrostatic check) adds dt f on every face.
 
 Pinned by: tests/test_oracle_advection.py (constant fields stay constant;
 linear fields under uniform flow are translated exactly; an integer-cell shift
@@ -174,6 +179,29 @@ def laplacian_periodic(grid: Grid, u):
         lap = -6.0 * comp
         for ax in range(3):
             lap = lap + np.roll(comp, 1, axis=ax) + np.roll(comp, -1, axis=ax)
+        out.append((lap / grid.dx ** 2).ravel())
+    return np.concatenate(out)
+
+
+def laplacian_faces(grid: Grid, u):
+    """-G_f^T G_f u / dx^2: per component, the sum over the edges of its face
+    lattice at each point of (neighbour - point) / dx^2 (edges wrap along
+    periodic axes, and none leaves the lattice otherwise)."""
+    out = []
+    for e, comp in enumerate(grid.split(u)):
+        lap = np.zeros_like(comp)
+        for a in range(3):
+            ax = 2 - a                      # numpy axis of grid axis a ([k][j][i] order)
+            if grid.periodic[a]:
+                lap = lap + (np.roll(comp, 1, axis=ax) - comp) + (np.roll(comp, -1, axis=ax) - comp)
+            else:
+                d = np.diff(comp, axis=ax)  # one value per edge
+                lo = [slice(None)] * 3
+                hi = [slice(None)] * 3
+                lo[ax] = slice(0, -1)
+                hi[ax] = slice(1, None)
+                lap[tuple(lo)] += d         # the point below each edge gains (upper - lower)
+                lap[tuple(hi)] -= d         # the point above it loses the same
         out.append((lap / grid.dx ** 2).ravel())
     return np.concatenate(out)
 

@@ -2,7 +2,8 @@
 test infrastructure only).
 
 Paper, Sec. Numerical Simulation: advection (Eq. advection_matrix), viscosity
-(Eq. viscosity_matrix; App. B Eq. apply_force with an optional body force),
+(Eq. viscosity_matrix; App. B Eq. apply_force), an optional body force (this
+project's addition, for the hydrostatic check),
 projection (Eqs. projection_matrix, u_next_matrix).  Back-propagation mirrors
 the forward in reverse order (Sec. Back-propagation through Time): projection
 first, then viscosity and advection.  The geometry enters only through the
@@ -21,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 from .mac import Grid
-from .advection import Advection, laplacian_periodic, body_force_faces
+from .advection import Advection, laplacian_faces, body_force_faces
 from .projection import Projection
 
 
@@ -46,7 +47,7 @@ class Step:
         self.adv = Advection(g, u, prm.dt)
         ut = self.adv.result
         if prm.nu != 0.0:
-            ut = ut + prm.dt * prm.nu * laplacian_periodic(g, ut)
+            ut = ut + prm.dt * prm.nu * laplacian_faces(g, ut)
         if np.any(prm.gravity != 0.0):
             ut = ut + prm.dt * body_force_faces(g, prm.gravity)
         self.uhat = ut
@@ -58,13 +59,13 @@ class Step:
         prm = self.prm
         d = self.adv.jvp(du)
         if prm.nu != 0.0:
-            d = d + prm.dt * prm.nu * laplacian_periodic(prm.grid, d)
+            d = d + prm.dt * prm.nu * laplacian_faces(prm.grid, d)
         return self.proj.jvp(d, dalpha, dus)
 
     def vjp(self, g):
         """dJ/dU^{n+1} -> (dJ/dU^n, dJ/dalpha, dJ/du_s)."""
         prm = self.prm
         g_uhat, g_alpha, g_us = self.proj.vjp(g)
-        if prm.nu != 0.0:       # L is symmetric
-            g_uhat = g_uhat + prm.dt * prm.nu * laplacian_periodic(prm.grid, g_uhat)
+        if prm.nu != 0.0:       # -G_f^T G_f is symmetric
+            g_uhat = g_uhat + prm.dt * prm.nu * laplacian_faces(prm.grid, g_uhat)
         return self.adv.vjp(g_uhat), g_alpha, g_us
