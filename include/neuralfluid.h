@@ -5,11 +5,18 @@
  * Method: NeuralFluid (arXiv 2405.14903), Sec. "Differentiable Navier-Stokes
  * Simulation": operator splitting into semi-Lagrangian advection
  * (Eq. advection_matrix; two-stage back-trace of App. B, Eqs. advection_1/2),
- * an optional body force (App. B, Eq. apply_force), and a variational pressure
- * projection with per-face fluid fractions alpha (Eq. projection_matrix,
- * Eq. u_next_matrix), solved matrix-free by multigrid-preconditioned CG; plus
- * the adjoint of each stage (Sec. "Back-propagation through Time" and
- * "Back-propagation through Geometry").
+ * explicit viscosity (Eq. viscosity_matrix; App. B Eq. apply_force), and a
+ * variational pressure projection with per-face fluid fractions alpha
+ * (Eq. projection_matrix, Eq. u_next_matrix), solved matrix-free by
+ * multigrid-preconditioned CG; plus the adjoint of each stage (Sec.
+ * "Back-propagation through Time" and "Back-propagation through Geometry").
+ * A constant body force (gravity) is this library's addition, used to check
+ * hydrostatic balance.
+ * Viscosity: U^ = (I - nu dt/dx^2 G_f^T G_f) U~ with G_f the differences of
+ * each velocity component over the edges of its own face lattice (the 7-point
+ * Laplacian inside; no edge leaves the lattice at a domain side, so the
+ * tangential components have zero normal derivative there).  It is explicit:
+ * stable for nu dt / dx^2 <= 1/6 (sim_set_dt lets a caller sub-step).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -113,8 +120,9 @@ typedef struct {
   double dx;              /* cell width                                       */
   double dt;              /* time step                                        */
   double rho;             /* density (k = dt/(rho dx))                        */
-  double nu;              /* kinematic viscosity: must be 0 (unsupported)     */
-  double gravity[3];      /* body force added to every face: U^ += dt g       */
+  double nu;              /* kinematic viscosity (>= 0; explicit, see below)  */
+  double gravity[3];      /* body force added to every face: U^ += dt g (this
+                             library's addition, for the hydrostatic check)  */
   int32_t bc[6];          /* sim_bc per side                                  */
   double inflow_speed;    /* speed on INFLOW sides                            */
   int32_t precision;      /* sim_precision of the multigrid preconditioner    */
@@ -144,7 +152,7 @@ int32_t sim_footprint(const sim_desc* desc, size_t* bytes);
 
 /* Allocate all workspace for desc on the current HIP device.  Grid sizes must
  * coarsen by halving to a level of at most 4096 cells (e.g. multiples of 16).
- * nu != 0 or PERIODIC sides return SIM_EUNSUPPORTED.  Workspace is left
+ * PERIODIC sides return SIM_EUNSUPPORTED.  Workspace is left
  * unset; with the environment variable NF_POISON_BUFFERS=1 every buffer is
  * filled with all-ones bytes (NaN in every float format) instead, which makes
  * a read of a value no kernel wrote visible (a testing aid). */
@@ -154,7 +162,8 @@ int32_t sim_destroy(sim_handle h);
 /* Sizes (in elements) of the velocity and cell arrays of this handle. */
 int32_t sim_layout(sim_handle h, size_t* vel_elems, size_t* cell_elems);
 
-/* One step n -> n+1 (Eqs. advection_matrix, projection_matrix, u_next_matrix).
+/* One step n -> n+1 (Eqs. advection_matrix, viscosity_matrix, projection_matrix,
+ * u_next_matrix).
  * u_n, u_n1: velocity (float, distinct).  theta: geometry at time n+1,
  * ctrl: solid velocity controls for this step (host doubles; may be NULL when
  * n_params / n_ctrl are 0).  p_n1: optional cell pressure output (NULL: kept
@@ -239,6 +248,15 @@ int32_t sim_loss_box_noalloc(const int32_t n[3], double dx, const float* u, cons
 int32_t sim_loss_outlet(sim_handle h, const float* u, const float* w, double scale, double* J, float* g,
                         hipStream_t stream);
 
+/* The time step of the handle's later calls (k = dt / (rho dx) follows it):
+ * CFL sub-stepping splits a frame into steps of its own length. */
+int32_t sim_set_dt(sim_handle h, double dt);
+
+/* Largest |u_f| over the faces of a velocity field (device), written to the
+ * host double vmax (a NaN counts as +inf); waits on the stream.  The input of
+ * the CFL sub-step count. */
+int32_t sim_max_speed(sim_handle h, const float* u, double* vmax, hipStream_t stream);
+
 /* Solve control of a handle (every later Poisson solve of sim_step,
  * sim_project, sim_step_adjoint and poisson_solve).
  *  SIM_SOLVE_HOST (default): CG runs in batches; after each batch the call
@@ -301,7 +319,7 @@ int32_t sim_regions(sim_handle h, int32_t* region_out, int32_t* count, int32_t* 
 typedef enum {
   SIM_K_GEOM_PHI = 0, SIM_K_GEOM_ALPHA, SIM_K_ADVECT, SIM_K_RHS, SIM_K_UPDATE, SIM_K_ADJ_DIV,
   SIM_K_ADJ_FACES, SIM_K_ADVECT_ADJ, SIM_K_CG_INIT, SIM_K_CG_APPLY, SIM_K_CG_UPDATE, SIM_K_CG_TRUE,
-  SIM_K_MG_DOWN, SIM_K_MG_DOWN2, SIM_K_MG_UP1, SIM_K_MG_UP, SIM_K_MG_COARSE, SIM_K_COUNT
+  SIM_K_MG_DOWN, SIM_K_MG_DOWN2, SIM_K_MG_UP1, SIM_K_MG_UP, SIM_K_MG_COARSE, SIM_K_VISCOSITY, SIM_K_COUNT
 } sim_kernel;
 int32_t sim_profile(sim_handle h, int32_t kernel);
 int32_t sim_profile_read(sim_handle h, double min_ms, double* total_ms, int64_t* count);

@@ -27,12 +27,12 @@ EXPORTS = [
     "sim_step", "sim_step_replay", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
     "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
-    "sim_loss_box_noalloc",
+    "sim_loss_box_noalloc", "sim_set_dt", "sim_max_speed",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
 KERNELS = ["geom_phi", "geom_alpha", "advect", "rhs", "update", "adj_div", "adj_faces", "advect_adj", "cg_init",
-           "cg_apply", "cg_update", "cg_true", "mg_down", "mg_down2", "mg_up1", "mg_up", "mg_coarse"]
+           "cg_apply", "cg_update", "cg_true", "mg_down", "mg_down2", "mg_up1", "mg_up", "mg_coarse", "viscosity"]
 
 
 class SimDesc(C.Structure):
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_profile_read": (C.c_int32, [_vp, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "sim_set_solve_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
         "sim_set_regions": (C.c_int32, [_vp, C.c_int32]),
+        "sim_set_dt": (C.c_int32, [_vp, C.c_double]),
+        "sim_max_speed": (C.c_int32, [_vp, _fp, C.POINTER(C.c_double), _vp]),
         "sim_loss_box_noalloc": (C.c_int32, [C.POINTER(C.c_int32), C.c_double, _fp, _dp, _dp, _vp, _fp, _vp]),
         "sim_regions": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),
     }

@@ -8,7 +8,8 @@
 //   X_src = X_f - cfl v1, U~_f = I_d(u; X_src),
 // I_e trilinear on component e's own staggered lattice (offset 1/2 along the
 // two other axes), coordinates clamped to the lattice and the base index
-// min(floor(s), m - 2).  App. B, Eq. apply_force: U^ = U~ + dt g.
+// min(floor(s), m - 2).  A constant body force g (this library's addition,
+// for the hydrostatic check) is added here: U~ + dt g.
 // Positions, cell choices and weights are computed in FP64 (the velocities
 // are FP32): the derivative of a trilinear interpolant jumps across cell
 // boundaries, so the cell a back-traced point falls in is decided in double
@@ -392,6 +393,58 @@ __global__ void k_fill(float* __restrict__ p, long n, float v) {
 }
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Viscosity (Eq. viscosity_matrix; App. B Eq. apply_force, explicit):
+// out = in + c (-G_f^T G_f) in with c = nu dt / dx^2, G_f the differences of
+// each velocity component over the edges of its own face lattice: the sum over
+// a lattice point's neighbours inside the lattice of (neighbour - point).  The
+// operator is symmetric, so the same kernel applies its adjoint.
+__global__ __launch_bounds__(kBlock) void k_viscosity(Dims d, float c, const float* __restrict__ in,
+                                                      float* __restrict__ out) {
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long)d.faces()) return;
+  int comp, i, j, k;
+  face_decode(d, f, comp, i, j, k);
+  const int mx = d.nx + (comp == 0), my = d.ny + (comp == 1), mz = d.nz + (comp == 2);
+  const long sy = mx, sz = (long)mx * my;
+  const float v = in[f];
+  float s = 0.0f;
+  if (i > 0) s += in[f - 1] - v;
+  if (i < mx - 1) s += in[f + 1] - v;
+  if (j > 0) s += in[f - sy] - v;
+  if (j < my - 1) s += in[f + sy] - v;
+  if (k > 0) s += in[f - sz] - v;
+  if (k < mz - 1) s += in[f + sz] - v;
+  out[f] = v + c * s;
+}
+
+void launch_viscosity(const Dims& d, double c, const float* in, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_viscosity, dim3(nblocks(d.faces())), dim3(kBlock), 0, s, d, (float)c, in, out);
+}
+
+// max over faces of |u_f| (order-free, so the same bits every time): one
+// atomic max per block on the bits of a non-negative float
+__global__ __launch_bounds__(kBlock) void k_max_abs(long n, const float* __restrict__ u, unsigned* __restrict__ out) {
+  __shared__ float sh[kBlock / 64];
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  float v = f < n ? fabsf(u[f]) : 0.0f;
+  if (!(v == v)) v = __int_as_float(0x7f800000);   // a NaN reads as +inf
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_down(v, o, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = sh[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sh[w]);
+    atomicMax(out, __float_as_uint(m));
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+void launch_max_abs(size_t n, const float* u, unsigned* out_bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, out_bits);
+  if (n) hipLaunchKernelGGL(k_max_abs, dim3(nblocks(n)), dim3(kBlock), 0, s, (long)n, u, out_bits);
+}
 
 void launch_fill(float* p, size_t n, float v, hipStream_t s) {
   if (n == 0) return;

@@ -36,6 +36,7 @@ struct sim_ctx {
   GeomParams last_geom;
   bool have_geom = false;
   bool levels_current = false;   // the solver's hierarchy was built from the current fractions
+  unsigned* maxbits = nullptr;   // bits of the largest |u_f| (sim_max_speed)
   Profiler prof;
 };
 
@@ -72,7 +73,7 @@ int validate_desc(const sim_desc* d) {
     if (d->bc[s] < SIM_BC_WALL || d->bc[s] > SIM_BC_PERIODIC) return SIM_EINVAL;
     if (d->bc[s] == SIM_BC_PERIODIC) return SIM_EUNSUPPORTED;
   }
-  if (d->nu != 0.0) return SIM_EUNSUPPORTED;
+  if (!(d->nu >= 0.0) || !std::isfinite(d->nu)) return SIM_EINVAL;
   if (!std::isfinite(d->gravity[0]) || !std::isfinite(d->gravity[1]) || !std::isfinite(d->gravity[2]))
     return SIM_EINVAL;
   switch (d->geom) {
@@ -126,6 +127,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   alloc(4 * kRzPartsMax * 8, (void**)&t->S.partials_rz);
   if (d->precision != SIM_FP32) alloc(C * (16 + 4), &t->S.rec0);   // records, then 1/diag in FP32
   alloc(sizeof(CGScalars), (void**)&t->S.sc);
+  alloc(sizeof(unsigned), (void**)&t->maxbits);
   // connected-region labels of the pressure system
   alloc(C * 4, (void**)&t->S.comp.parent);
   alloc(C * 4, (void**)&t->S.comp.id);
@@ -238,6 +240,19 @@ void eval_geometry(sim_ctx* c, const GeomParams& g, hipStream_t st, bool levels 
 }
 
 double k_factor(const sim_desc& d) { return d.dt / (d.rho * d.dx); }
+
+// U^ of a step into h->uhat: the advected field (with the body force), then,
+// with nu > 0, the explicit viscosity (the advected field goes through h->gu,
+// which holds nothing at this point of a step or of its adjoint).
+void advect_and_diffuse(sim_ctx* h, const float* u_n, double* trace, hipStream_t stream) {
+  const bool visc = h->desc.nu > 0.0;
+  float* adv = visc ? h->gu : h->uhat;
+  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
+           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, adv, trace, stream));
+  if (visc)
+    NF_TIMED(&h->prof, SIM_K_VISCOSITY, stream,
+             launch_viscosity(h->dom.d, h->desc.nu * h->desc.dt / (h->desc.dx * h->desc.dx), adv, h->uhat, stream));
+}
 
 // In the device solve mode the stats are written by a kernel: the pointer
 // must be device memory or pinned host memory.
@@ -418,8 +433,7 @@ int32_t sim_step(sim_handle h, const float* u_n, const double* theta, const doub
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream);
-  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
-           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, nullptr, stream));
+  advect_and_diffuse(h, u_n, nullptr, stream);
   return project_common(h, h->uhat, g, u_n1, p_n1, st, stream);
 }
 
@@ -430,8 +444,7 @@ int32_t sim_step_replay(sim_handle h, const float* u_n, const double* theta, con
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   eval_geometry(h, g, stream, false);
-  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
-           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, nullptr, stream));
+  advect_and_diffuse(h, u_n, nullptr, stream);
   NF_TIMED(&h->prof, SIM_K_UPDATE, stream,
            launch_update(h->dom, g, k_factor(h->desc), h->alpha, h->uhat, p_n1, u_n1, stream));
   return last_hip_error();
@@ -460,9 +473,9 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
                     (h->desc.geom == SIM_GEOM_WALL && g_theta);
   const double kk = k_factor(h->desc);
   eval_geometry(h, g, stream);
-  // the step's advected field (the fluid velocity W on cut faces needs it)
-  NF_TIMED(&h->prof, SIM_K_ADVECT, stream,
-           launch_advect(h->dom.d, h->desc.dx, h->desc.dt, h->desc.gravity, u_n, h->uhat, h->trace, stream));
+  // the step's advected (and diffused) field (the fluid velocity W on cut
+  // faces needs it) and the back-traced positions
+  advect_and_diffuse(h, u_n, h->trace, stream);
   const float* P = p_n1;
   int warn = SIM_OK;
   if (!P && grad) {
@@ -483,9 +496,17 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
                             h->S.partials, g_theta, g_ctrl, h->wall_cols, stream));
+  // through the viscosity (symmetric; h->uhat is no longer needed)
+  const float* g_adv = h->gu;
+  if (h->desc.nu > 0.0) {
+    NF_TIMED(&h->prof, SIM_K_VISCOSITY, stream,
+             launch_viscosity(h->dom.d, h->desc.nu * h->desc.dt / (h->desc.dx * h->desc.dx), h->gu, h->uhat,
+                              stream));
+    g_adv = h->uhat;
+  }
   launch_fill(g_u_n, h->dom.d.faces(), 0.0f, stream);
   NF_TIMED(&h->prof, SIM_K_ADVECT_ADJ, stream,
-           launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->trace, h->gu, g_u_n, h->stage, stream));
+           launch_advect_adjoint(h->dom.d, h->desc.dx, h->desc.dt, u_n, h->trace, g_adv, g_u_n, h->stage, stream));
   const int e = last_hip_error();
   return e != SIM_OK ? e : warn;
 }
@@ -548,6 +569,25 @@ int32_t sim_regions(sim_handle h, int32_t* region_out, int32_t* count, int32_t* 
       *floating = f;
     }
   }
+  return last_hip_error();
+}
+
+int32_t sim_set_dt(sim_handle h, double dt) {
+  if (!h || !(dt > 0.0) || !std::isfinite(dt)) return SIM_EINVAL;
+  h->desc.dt = dt;
+  return SIM_OK;
+}
+
+int32_t sim_max_speed(sim_handle h, const float* u, double* vmax, hipStream_t stream) {
+  if (!h || !u || !vmax) return SIM_EINVAL;
+  launch_max_abs(h->dom.d.faces(), u, h->maxbits, stream);
+  unsigned bits = 0;
+  if (hipMemcpyAsync(&bits, h->maxbits, sizeof(bits), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return SIM_EHIP;
+  float v;
+  std::memcpy(&v, &bits, sizeof(v));
+  *vmax = (double)v;
   return last_hip_error();
 }
 

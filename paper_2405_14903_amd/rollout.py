@@ -65,7 +65,14 @@ class Rollout:
         ro.ctrl = ctrl
         return ro
 
+    def _set_dt(self, n):
+        """Per-step time step (CFL sub-stepping): set the handle's dt when it changes."""
+        dts = getattr(self, "dts", None)
+        if dts is not None and self.sim.dt != dts[n]:
+            self.sim.set_dt(dts[n])
+
     def _step(self, n, u, out, p=None):
+        self._set_dt(n)
         th, ct = self.schedule(n)
         if self.timer:
             self.timer.begin("fwd")
@@ -145,6 +152,7 @@ class Rollout:
             states[0].copy_(self.ckpt[s])
             for n in range(s, e):
                 if stored:
+                    self._set_dt(n)
                     th, ct = self.schedule(n)
                     if self.timer:
                         self.timer.begin("replay")
@@ -155,6 +163,7 @@ class Rollout:
                     self._step(n, states[n - s], states[n - s + 1], press[n - s])
                 yield "fwd"
             for n in range(e - 1, s - 1, -1):
+                self._set_dt(n)
                 th, ct = self.schedule(n)
                 if self.step_loss:
                     g += self.step_loss(n, states[n - s + 1])[1]
@@ -178,6 +187,60 @@ class Rollout:
         gs = self.g_steps.cpu().numpy()
         gd = self.g_ctrl_direct.cpu().numpy()
         return ellipsoid_poses_adjoint(self.theta0, self.ctrl, self.sim.cfg.dt, gs, gd)
+
+
+def cfl_substeps(frame_dt, vmax, dx, cfl=0.5, nu=0.0, visc_limit=1.0 / 6.0):
+    """Steps a frame of length frame_dt is split into (the paper advances a
+    frame by as many solver steps as the CFL condition needs): the smallest m
+    with (frame_dt / m) vmax <= cfl dx and, with viscosity, the explicit
+    limit nu (frame_dt / m) / dx^2 <= visc_limit."""
+    m = 1
+    if vmax > 0.0:
+        m = max(m, math.ceil(frame_dt * vmax / (cfl * dx) - 1e-12))
+    if nu > 0.0:
+        m = max(m, math.ceil(frame_dt * nu / (visc_limit * dx * dx) - 1e-12))
+    return m
+
+
+class FrameRollout(Rollout):
+    """A rollout of `frames` frames of length frame_dt, each split into CFL
+    sub-steps decided from the largest face speed at the frame's start (the
+    sub-step counts are piecewise constant in the inputs: no gradient flows
+    through them).  The geometry is static (schedule(n) gives the same theta
+    for every step); checkpoints every `every` steps (an integer)."""
+
+    def __init__(self, sim: Sim, frames: int, frame_dt: float, schedule, every=8, cfl=0.5, **kw):
+        super().__init__(sim, 0, schedule, every, **kw)
+        self.frames, self.frame_dt, self.cfl = int(frames), float(frame_dt), float(cfl)
+
+    def forward_steps(self, u0: torch.Tensor):
+        sim = self.sim
+        self.ckpt = {0: u0.detach().clone()}
+        a = u0.detach().clone()
+        b = torch.empty_like(a)
+        self.J = torch.zeros(1, dtype=torch.float64, device=u0.device) if self.step_loss else None
+        self.dts, self.substeps, press = [], [], []
+        n = 0
+        for _ in range(self.frames):
+            m = cfl_substeps(self.frame_dt, sim.max_speed(a), sim.cfg.dx, self.cfl, sim.cfg.nu)
+            self.substeps.append(m)
+            for _ in range(m):
+                self.dts.append(self.frame_dt / m)
+                p = torch.empty(sim.nc, dtype=getattr(sim, "pressure_dtype", torch.float32),
+                                device=u0.device) if self.store_pressure else None
+                press.append(p)
+                self._step(n, a, b, p)
+                a, b = b, a
+                if self.step_loss:
+                    self.J += self.step_loss(n, a)[0]
+                n += 1
+                if n % self.K == 0:
+                    self.ckpt[n] = a.clone()
+                self.uT = a
+                yield "fwd"
+        self.T = n
+        self.P = torch.stack(press) if self.store_pressure and press else None
+        self.uT = a
 
 
 class ChannelRolloutFn(torch.autograd.Function):

@@ -29,6 +29,7 @@ class Config:
     dx: float
     dt: float
     rho: float = 1.0
+    nu: float = 0.0
     gravity: tuple = (0.0, 0.0, 0.0)
     bc: tuple = ("wall",) * 6
     inflow_speed: float = 0.0
@@ -43,7 +44,7 @@ class Config:
         for a in range(3):
             d.n[a] = int(self.n[a])
             d.gravity[a] = float(self.gravity[a])
-        d.dx, d.dt, d.rho, d.nu = float(self.dx), float(self.dt), float(self.rho), 0.0
+        d.dx, d.dt, d.rho, d.nu = float(self.dx), float(self.dt), float(self.rho), float(self.nu)
         for s in range(6):
             b = self.bc[s]
             d.bc[s] = _BC[b] if isinstance(b, str) else int(b)
@@ -133,6 +134,7 @@ class Sim:
         self.h = h
         self.nf, self.nc = cfg.nfaces, cfg.ncells
         self.n_params, self.n_ctrl = self._desc.n_params, self._desc.n_ctrl
+        self.dt = float(cfg.dt)
 
     def close(self):
         if self.h is not None and self.h.value:
@@ -152,6 +154,18 @@ class Sim:
         self.close()
 
     # ---- entry points --------------------------------------------------
+    def set_dt(self, dt: float):
+        """Time step of the handle's later calls (CFL sub-stepping)."""
+        L.check(self.lib.sim_set_dt(self.h, float(dt)), "sim_set_dt")
+        self.dt = float(dt)
+
+    def max_speed(self, u) -> float:
+        """Largest |u_f| over the faces (waits on the stream)."""
+        v = C.c_double(0.0)
+        L.check(self.lib.sim_max_speed(self.h, _ptr(u, self.nf, torch.float32, "u"), C.byref(v), _stream()),
+                "sim_max_speed")
+        return v.value
+
     def set_solve_mode(self, mode: str = "host", budget: int = 0):
         """"host": solves wait on the stream for convergence checks (default);
         "device": nothing waits on the host, each solve runs at most

@@ -1,4 +1,5 @@
-"""Hydrostatic balance on the GPU (App. B, Eq. apply_force): a fluid at rest
+"""Hydrostatic balance on the GPU (a constant body force, this project's
+addition for this check; the paper has none): a fluid at rest
 around a static sphere under gravity stays at rest, and the pressure is the
 discrete linear potential, k (G P) = dt g on every face carrying fluid; the
 step matches the oracle's."""

@@ -52,7 +52,9 @@ def test_footprint_and_validation():
         assert lib.sim_footprint(C.byref(d), C.byref(out)) == code, bad
     d = _cfg().desc()
     d.nu = 0.1
-    assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_EUNSUPPORTED
+    assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_OK      # explicit viscosity
+    d.nu = -0.1
+    assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_EINVAL
     assert lib.sim_footprint(None, C.byref(out)) == L.SIM_EINVAL
     for n in [(48, 48, 48), (96, 96, 96), (192, 192, 192), (256, 256, 512), (16, 16, 16), (8, 8, 8)]:
         assert sim_footprint(_cfg(n=n)) > 0

@@ -45,10 +45,12 @@ class OracleHandle:
     def step_replay(self, u, p, th, ct, u_out=None):
         """The update of Eq. u_next_matrix from the given pressure (the oracle's
         pieces: its advection, G and the face average), no solve."""
-        from oracle.advection import Advection
+        from oracle.advection import Advection, laplacian_faces
         from oracle.projection import Operators
         geo = self._geo(th, ct)
         uh = Advection(self.prm.grid, u.double().numpy(), self.prm.dt).result
+        if self.prm.nu:
+            uh = uh + self.prm.dt * self.prm.nu * laplacian_faces(self.prm.grid, uh)
         G = Operators(self.prm.grid, geo.alpha).G
         W = uh - self.prm.k * (G @ p.double().numpy())
         u_out.copy_(torch.from_numpy(geo.alpha * W + (1.0 - geo.alpha) * geo.us))
@@ -102,3 +104,44 @@ def test_ellipsoid_rollout_driver_matches_oracle_bptt():
     np.testing.assert_allclose(gu.numpy(), gu_o, rtol=1e-9, atol=1e-12 * np.abs(gu_o).max())
     np.testing.assert_allclose(gth, gth_o, rtol=1e-8, atol=1e-12)
     np.testing.assert_allclose(gct, gct_o, rtol=1e-8, atol=1e-12)
+
+
+def test_frame_rollout_substeps_and_gradient():
+    """CFL frames on the oracle stand-in: sub-step counts from the definition
+    (advective and viscous limits) and the driver's gradient against a plain
+    chain of the oracle's step adjoints with the same time steps."""
+    import math
+    sc = scenes.scene_sphere_rollout(seed=2, n=8, steps=3)
+    g = Grid(sc.n, sc.dx)
+    nu, frame_dt, cfl = 0.02, 2.0 * sc.dx, 0.5
+    prm0 = StepParams(g, frame_dt, nu=nu, tol=1e-12)
+    h = OracleHandle(prm0, "spheres", sc.spheres)
+    h.cfg.dx, h.cfg.nu, h.dt = g.dx, nu, frame_dt
+
+    def set_dt(dt):
+        h.prm = StepParams(g, dt, nu=nu, tol=1e-12)
+        h.dt = dt
+    h.set_dt = set_dt
+    h.max_speed = lambda u: float(u.abs().max())
+    ro = R.FrameRollout(h, 3, frame_dt, lambda n: (sc.spheres.ravel(), None), every=2, cfl=cfl)
+    uT = ro.forward(torch.from_numpy(sc.u0.copy()))
+    # the counts from the definition, on the oracle's own states
+    geo = sphere_geometry(g, sc.spheres)
+    u, us, dts = sc.u0.copy(), [], []
+    for m in ro.substeps:
+        want = max(1, math.ceil(frame_dt * np.abs(u).max() / (cfl * g.dx) - 1e-12),
+                   math.ceil(frame_dt * nu / (g.dx ** 2 / 6.0) - 1e-12))
+        assert m == want
+        for _ in range(m):
+            st = Step(StepParams(g, frame_dt / m, nu=nu, tol=1e-12), u, geo.alpha, geo.us)
+            us.append(st)
+            dts.append(frame_dt / m)
+            u = st.result
+    assert ro.dts == dts and sum(ro.substeps) == ro.T > 3
+    np.testing.assert_allclose(uT.numpy(), u, atol=1e-12)
+    _, gT = octant_loss(g, u)
+    gu = ro.backward(torch.from_numpy(gT.copy()))
+    gref = gT
+    for st in reversed(us):
+        gref = st.vjp(gref)[0]
+    np.testing.assert_allclose(gu.numpy(), gref, rtol=1e-9, atol=1e-12 * np.abs(gref).max())
