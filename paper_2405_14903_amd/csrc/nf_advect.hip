@@ -202,9 +202,12 @@ __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, 
 #pragma unroll
       for (int by = 0; by < 2; ++by) {
         const double wy = wz[bz] * (by ? fy : 1.0 - fy);
+        if (wy == 0.0) continue;
         unsigned long long* row = win + kWinX * (by + kWinY * bz);
-        atomicAdd(row, (unsigned long long)fixed_round(wy * (1.0 - fx)));
-        atomicAdd(row + 1, (unsigned long long)fixed_round(wy * fx));
+        // taps of weight 0 (a fraction of exactly 0 or 1, as at face centres) add nothing
+        const long long lo = fixed_round(wy * (1.0 - fx)), hi = fixed_round(wy * fx);
+        if (lo) atomicAdd(row, (unsigned long long)lo);
+        if (hi) atomicAdd(row + 1, (unsigned long long)hi);
       }
     return;
   }
