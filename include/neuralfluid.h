@@ -108,12 +108,48 @@ typedef enum { SIM_BC_WALL = 0, SIM_BC_INFLOW = 1, SIM_BC_OUTFLOW = 2, SIM_BC_PE
  *                       = a, y index major (a[m * SIM_WALL_KNOTS_Z + n]);
  *                       ctrl (3) = (t, f, amp), t the time of the step's
  *                       end.  The adjoint accumulates dJ/da into g_theta;
- *                       t, f and amp get no gradient (g_ctrl is untouched). */
-typedef enum { SIM_GEOM_NONE = 0, SIM_GEOM_SPHERES = 1, SIM_GEOM_ELLIPSOID = 2, SIM_GEOM_WALL = 3 } sim_geom;
+ *                       t, f and amp get no gradient (g_ctrl is untouched).
+ *  SIM_GEOM_BEZIER    : static CSG scene of m parametric solids (Sec.
+ *                       Geometry Representation; App. Geometry
+ *                       Representation Implementation).  A cross-section is
+ *                       SIM_BEZIER_SEGMENTS cubic Bezier segments around a
+ *                       centre c; segment s spans the polar angles
+ *                       [2 pi s/N, 2 pi (s+1)/N] and its two inner control
+ *                       points lie 2 pi/(3N) inside that span at polar
+ *                       distances rho[2s], rho[2s+1]; a joint is the midpoint
+ *                       of the control points around it.  A solid stacks
+ *                       SIM_BEZIER_KEYS key cross-sections evenly on the z
+ *                       axis of its frame between z0 and z1, interpolated
+ *                       linearly between keys (clamped outside [z0, z1]);
+ *                       each segment is taken as its polygon through
+ *                       SIM_BEZIER_SAMPLES points (t = k / samples), and the
+ *                       solid's signed distance in its frame p = R^T (x - o)
+ *                       is max(d(p_x, p_y), z0 - p_z, p_z - z1), d the
+ *                       signed distance to the cross-section's polygon
+ *                       (negative inside).  phi is the CSG of the solids'
+ *                       distances, left to right: min for a union (op 0),
+ *                       max for an intersection (op 1).  u_s = 0.
+ *                       theta = [m, op_1 .. op_m (op_1 unused), solid_1 ..
+ *                       solid_m], each solid SIM_BEZIER_SHAPE_PARAMS values:
+ *                       o(3), R(9, row-major, body -> world), z0, z1 (z1 >
+ *                       z0), key centres (KEYS x 2), key radii (KEYS x 2N,
+ *                       key-major).  n_params = 1 + m (1 +
+ *                       SIM_BEZIER_SHAPE_PARAMS), 1 <= m <= SIM_MAX_SOLIDS;
+ *                       n_ctrl = 0.  theta[0] must equal m and every op be 0
+ *                       or 1 (else SIM_EINVAL).  The adjoint accumulates
+ *                       dJ/dtheta into g_theta (zero for m and the ops). */
+typedef enum {
+  SIM_GEOM_NONE = 0, SIM_GEOM_SPHERES = 1, SIM_GEOM_ELLIPSOID = 2, SIM_GEOM_WALL = 3, SIM_GEOM_BEZIER = 4
+} sim_geom;
 
 #define SIM_MAX_SPHERES 32
 #define SIM_WALL_KNOTS_Y 16
 #define SIM_WALL_KNOTS_Z 32
+#define SIM_MAX_SOLIDS 8
+#define SIM_BEZIER_SEGMENTS 4
+#define SIM_BEZIER_SAMPLES 16
+#define SIM_BEZIER_KEYS 3
+#define SIM_BEZIER_SHAPE_PARAMS 44
 
 typedef struct {
   int32_t n[3];           /* cells per axis                                   */
@@ -193,7 +229,8 @@ int32_t sim_project(sim_handle h, const float* u_in, const double* theta, const 
  * g_u_n1 = dJ/dU^{n+1}.  Output: g_u_n = dJ/dU^n (overwritten; must alias
  * neither g_u_n1 nor u_n).  g_theta (n_params doubles) and g_ctrl (n_ctrl
  * doubles), device, are ACCUMULATED (+=) with this step's direct partials
- * dJ/dtheta and dJ/dctrl (SIM_GEOM_ELLIPSOID only; NULL to skip).  The
+ * dJ/dtheta and dJ/dctrl (ELLIPSOID: both; WALL, BEZIER: dJ/dtheta only;
+ * NULL to skip).  The
  * adjoint pressure system (G^T S G) y = -G^T S g_u_n1 is solved with the same
  * operator (it is symmetric); st reports that solve.  Float atomics make
  * g_u_n reproducible only to rounding. */

@@ -17,9 +17,11 @@ SIM_SOLVE_HOST, SIM_SOLVE_DEVICE = 0, 1
 SIM_REGIONS_AUTO, SIM_REGIONS_ALWAYS, SIM_REGIONS_NEVER = 0, 1, 2
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
-SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL = 0, 1, 2, 3
+SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL, SIM_GEOM_BEZIER = 0, 1, 2, 3, 4
 SIM_MAX_SPHERES = 32
 SIM_WALL_KNOTS_Y, SIM_WALL_KNOTS_Z = 16, 32
+SIM_MAX_SOLIDS = 8
+SIM_BEZIER_SEGMENTS, SIM_BEZIER_SAMPLES, SIM_BEZIER_KEYS, SIM_BEZIER_SHAPE_PARAMS = 4, 16, 3, 44
 
 #: every symbol declared in include/neuralfluid.h
 EXPORTS = [

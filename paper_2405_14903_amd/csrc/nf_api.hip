@@ -32,6 +32,9 @@ struct sim_ctx {
   double* trace = nullptr;  // back-traced positions (6 FP64 per face) for the advection adjoint
   double* knots = nullptr;      // B-spline wall: control amplitudes of the current call
   double* wall_cols = nullptr;  // B-spline wall: per-column totals of its adjoint
+  double* solids = nullptr;     // parametric solids: the packed solids of the current call
+  double* solids_part = nullptr;  // parametric solids: partial sums of their gradient
+  std::vector<double> solids_host;  // host staging of the packed solids
   std::vector<void*> allocs;
   GeomParams last_geom;
   bool have_geom = false;
@@ -90,6 +93,13 @@ int validate_desc(const sim_desc* d) {
     case SIM_GEOM_WALL:
       if (d->n_params != SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z || d->n_ctrl != 3) return SIM_EINVAL;
       break;
+    case SIM_GEOM_BEZIER: {
+      const int per = 1 + SIM_BEZIER_SHAPE_PARAMS;
+      if (d->n_ctrl != 0 || d->n_params < 1 + per || (d->n_params - 1) % per ||
+          (d->n_params - 1) / per > SIM_MAX_SOLIDS)
+        return SIM_EINVAL;
+      break;
+    }
     default:
       return SIM_EINVAL;
   }
@@ -143,6 +153,10 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
     alloc(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z * 8, (void**)&t->knots);
     alloc(wall_column_doubles(d0) * 8, (void**)&t->wall_cols);
   }
+  if (d->geom == SIM_GEOM_BEZIER) {
+    alloc(solids_buffer_doubles() * 8, (void**)&t->solids);
+    alloc(solids_partials_doubles() * 8, (void**)&t->solids_part);
+  }
   for (int l = 0; l < p.nlev; ++l) {
     const Dims& dl = p.dims[l];
     Level& L = t->S.lev[l];
@@ -172,9 +186,20 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   }
 }
 
-int make_geom(const sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g, hipStream_t st) {
+int make_geom(sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g, hipStream_t st) {
   std::memset(&g, 0, sizeof(g));
   g.kind = c->desc.geom;
+  if (g.kind == SIM_GEOM_BEZIER) {
+    c->solids_host.assign(solids_buffer_doubles(), 0.0);
+    const int v = pack_solids(c->desc, theta, c->solids_host.data(), g);
+    if (v != SIM_OK) return v;
+    // pageable source: the copy has taken the values when the call returns
+    if (hipMemcpyAsync(c->solids, c->solids_host.data(), solids_buffer_doubles() * sizeof(double),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return SIM_EHIP;
+    g.solids = c->solids;
+    return SIM_OK;
+  }
   if (g.kind == SIM_GEOM_WALL) {
     if (!theta || !ctrl) return SIM_EINVAL;
     constexpr int nk = SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z;
@@ -470,7 +495,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   int v = make_geom(h, theta, ctrl, g, stream);
   if (v != SIM_OK) return v;
   const bool grad = (h->desc.geom == SIM_GEOM_ELLIPSOID && (g_theta || g_ctrl)) ||
-                    (h->desc.geom == SIM_GEOM_WALL && g_theta);
+                    ((h->desc.geom == SIM_GEOM_WALL || h->desc.geom == SIM_GEOM_BEZIER) && g_theta);
   const double kk = k_factor(h->desc);
   eval_geometry(h, g, stream);
   // the step's advected (and diffused) field (the fluid velocity W on cut
@@ -495,7 +520,8 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   warn = merge_status(warn, r);
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
-                            h->S.partials, g_theta, g_ctrl, h->wall_cols, stream));
+                            h->S.partials, g_theta, g_ctrl,
+                            h->desc.geom == SIM_GEOM_BEZIER ? h->solids_part : h->wall_cols, stream));
   // through the viscosity (symmetric; h->uhat is no longer needed)
   const float* g_adv = h->gu;
   if (h->desc.nu > 0.0) {

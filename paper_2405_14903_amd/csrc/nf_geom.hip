@@ -10,7 +10,11 @@
 // FP64 so that the decision alpha > 0 (which selects the update of a face) is
 // taken in double precision; alpha is then stored in FP32 and never rounded
 // down to zero when positive.
+#include <algorithm>
+#include <cmath>
+
 #include "nf_internal.h"
+#include "nf_shapes.h"
 
 namespace nf {
 
@@ -54,6 +58,19 @@ __global__ void k_phi_nodes(Dims d, double dx, GeomParams G, double* __restrict_
   int j = (int)(t % sy);
   int k = (int)(t / sy);
   phi[n] = phi_at(G, i * dx, j * dx, k * dx);
+}
+
+// phi of the parametric-solid scene at every node (its own kernel: the
+// per-node work is m polygon walks, read from the packed solids).
+__global__ __launch_bounds__(kBlock) void k_phi_solids(Dims d, double dx, GeomParams G, double* __restrict__ phi) {
+  const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= (long)d.nodes()) return;
+  const int sx = d.nx + 1, sy = d.ny + 1;
+  const int i = (int)(n % sx);
+  const long t = n / sx;
+  const int j = (int)(t % sy), k = (int)(t / sy);
+  int active;
+  phi[n] = scene_phi(G.solids, G.nsolid, i * dx, j * dx, k * dx, active);
 }
 
 // Fraction along an edge from the corner with value a to the sign change.
@@ -183,7 +200,101 @@ __global__ void k_coarsen_alpha(Dims fd, Dims cd, const float* __restrict__ fax,
 
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+size_t solids_buffer_doubles() { return shape_buffer_doubles(); }
+
+int pack_solids(const sim_desc& d, const double* theta, double* host, GeomParams& G) {
+  if (!theta) return SIM_EINVAL;
+  const int m = (d.n_params - 1) / (1 + kShapeParams);
+  for (int t = 0; t < d.n_params; ++t)
+    if (!std::isfinite(theta[t])) return SIM_EINVAL;
+  if (theta[0] != (double)m) return SIM_EINVAL;
+  for (int q = 0; q < m; ++q)
+    if (theta[1 + q] != 0.0 && theta[1 + q] != 1.0) return SIM_EINVAL;
+  // unit vectors of the control angles: segment s's two inner control points
+  // sit 2 pi / (3N) inside [2 pi s / N, 2 pi (s + 1) / N]
+  for (int r = 0; r < kRadii; ++r) {
+    const int sg = r / 2;
+    const double off = 2.0 * M_PI / (3.0 * kSegs);
+    const double ang = (r % 2 == 0) ? 2.0 * M_PI * sg / kSegs + off : 2.0 * M_PI * (sg + 1) / kSegs - off;
+    host[2 * r] = std::cos(ang);
+    host[2 * r + 1] = std::sin(ang);
+  }
+  const int n[3] = {d.n[0], d.n[1], d.n[2]};
+  for (int q = 0; q < m; ++q) {
+    const double* th = theta + 1 + m + (size_t)q * kShapeParams;
+    double* S = host + kShapeHead + (size_t)q * kShapeStride;
+    if (!(th[13] > th[12])) return SIM_EINVAL;
+    for (int t = 0; t < 14; ++t) S[t] = th[t];
+    S[14] = q == 0 ? 0.0 : theta[1 + q];
+    S[15] = 0.0;
+    const double* C = th + 14;
+    const double* P = th + 14 + 2 * kKeys;
+    for (int t = 0; t < 2 * kKeys; ++t) S[kOffC + t] = C[t];
+    for (int t = 0; t < kRadii * kKeys; ++t) S[kOffRho + t] = P[t];
+    double reach = 0.0;   // bound on |vertex| in the solid's frame (a vertex is c plus a convex mix of rho dir)
+    for (int key = 0; key < kKeys; ++key) {
+      double rmax = 0.0;
+      for (int r = 0; r < kRadii; ++r) rmax = std::max(rmax, std::fabs(P[kRadii * key + r]));
+      reach = std::max(reach, std::hypot(C[2 * key], C[2 * key + 1]) + rmax);
+      for (int v = 0; v < kVerts; ++v) {
+        int rr[4];
+        double w[4];
+        vertex_taps(v, rr, w);
+        double vx = C[2 * key], vy = C[2 * key + 1];
+        for (int t = 0; t < 4; ++t) {
+          vx += w[t] * P[kRadii * key + rr[t]] * host[2 * rr[t]];
+          vy += w[t] * P[kRadii * key + rr[t]] * host[2 * rr[t] + 1];
+        }
+        S[kOffVert + 2 * (kVerts * key + v)] = vx;
+        S[kOffVert + 2 * (kVerts * key + v) + 1] = vy;
+      }
+    }
+    // A node within 2 dx of the zero set whose CSG term is this solid has a
+    // distance in [-2 dx, 2 dx] to it, so its frame point p lies in the box
+    // [-reach - e, reach + e]^2 x [z0 - e, z1 + e], e = 2 dx: the world
+    // bounds of that box's corners x = o + (R^T)^-1 p, widened by one node.
+    // T = R^T: T[a][b] = R[b][a]; (R^T)^-1 = adj(T) / det(T).
+    double T[3][3], Ti[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) T[a][b] = th[3 + 3 * b + a];
+    Ti[0][0] = T[1][1] * T[2][2] - T[1][2] * T[2][1];
+    Ti[0][1] = T[0][2] * T[2][1] - T[0][1] * T[2][2];
+    Ti[0][2] = T[0][1] * T[1][2] - T[0][2] * T[1][1];
+    Ti[1][0] = T[1][2] * T[2][0] - T[1][0] * T[2][2];
+    Ti[1][1] = T[0][0] * T[2][2] - T[0][2] * T[2][0];
+    Ti[1][2] = T[0][2] * T[1][0] - T[0][0] * T[1][2];
+    Ti[2][0] = T[1][0] * T[2][1] - T[1][1] * T[2][0];
+    Ti[2][1] = T[0][1] * T[2][0] - T[0][0] * T[2][1];
+    Ti[2][2] = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+    const double det = T[0][0] * Ti[0][0] + T[0][1] * Ti[1][0] + T[0][2] * Ti[2][0];
+    if (!(std::fabs(det) > 1e-12)) return SIM_EINVAL;
+    const double e = 2.0 * d.dx;
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int c = 0; c < 8; ++c) {
+      const double p[3] = {(c & 1) ? reach + e : -reach - e, (c & 2) ? reach + e : -reach - e,
+                           (c & 4) ? th[13] + e : th[12] - e};
+      for (int a = 0; a < 3; ++a) {
+        const double w = th[a] + (Ti[a][0] * p[0] + Ti[a][1] * p[1] + Ti[a][2] * p[2]) / det;
+        lo[a] = std::min(lo[a], w);
+        hi[a] = std::max(hi[a], w);
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      const double l = std::max(0.0, std::floor(lo[a] / d.dx) - 1.0);
+      const double h = std::min((double)n[a], std::ceil(hi[a] / d.dx) + 1.0);
+      G.sbox[q][a] = (int)std::min(l, (double)n[a] + 1.0);
+      G.sbox[q][3 + a] = h >= l ? (int)(h - l) + 1 : 0;
+    }
+  }
+  G.nsolid = m;
+  return SIM_OK;
+}
+
 void launch_phi_nodes(const Domain& D, const GeomParams& G, double* phi, hipStream_t s) {
+  if (G.kind == SIM_GEOM_BEZIER) {
+    hipLaunchKernelGGL(k_phi_solids, dim3(nblocks(D.d.nodes())), dim3(kBlock), 0, s, D.d, D.dx, G, phi);
+    return;
+  }
   hipLaunchKernelGGL(k_phi_nodes, dim3(nblocks(D.d.nodes())), dim3(kBlock), 0, s, D.d, D.dx, G, phi);
 }
 

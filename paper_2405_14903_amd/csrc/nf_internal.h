@@ -51,6 +51,12 @@ struct GeomParams {
   double wall_s, wall_sd, amp;
   double ly, lz;               // extent of the wall side along y and z
   int wall_imax;               // faces with i > wall_imax are fully fluid
+  // parametric solids: the packed solids (device) and, per solid, the node
+  // box (lo x3, extent x3) outside which it cannot be the CSG term of a node
+  // within two cells of the zero set
+  const double* solids;
+  int nsolid;
+  int sbox[SIM_MAX_SOLIDS][6];
 };
 
 struct Domain {

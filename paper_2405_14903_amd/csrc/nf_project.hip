@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "nf_internal.h"
+#include "nf_shapes.h"
 
 namespace nf {
 
@@ -414,11 +415,34 @@ __device__ inline double wall_corner_term(const Domain& D, const GeomParams& G, 
   return galpha * dg[q];
 }
 
+// dJ/dphi at node (i, j, k), gathered from its 12 faces in a fixed order
+// (the node is corner 0 of the face at (i, j, k) and corners 1 .. 3 of the
+// faces one step down along the face's two tangents).
+__device__ inline double node_phi_adjoint(const Domain& D, const GeomParams& G, float kk, const float* alpha,
+                                          const double* phi, const float* g, const float* y, const float* uhat,
+                                          const float* p, int i, int j, int k) {
+  double sn = 0.0;
+  // x faces (tangents y, z): corners (j,k), (j+1,k), (j+1,k+1), (j,k+1)
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k, 0);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k, 1);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k - 1, 2);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k - 1, 3);
+  // y faces (tangents x, z)
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k, 0);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k, 1);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k - 1, 2);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k - 1, 3);
+  // z faces (tangents x, y)
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j, k, 0);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j, k, 1);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j - 1, k, 2);
+  sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j - 1, k, 3);
+  return sn;
+}
+
 // One thread per node column (j, k): cn[j + (ny+1) k] = sum over x of
 // dJ/dphi at the column's nodes; cf[j + ny k] (j < ny, k < nz) = sum over x of
-// dJ/du_s at the column's x faces.  Each node gathers from its 12 faces in a
-// fixed order (node (i, j, k) is corner 0 of the face at (i, j, k) and
-// corners 1 .. 3 of the faces one step down along the face's two tangents).
+// dJ/du_s at the column's x faces.
 __global__ __launch_bounds__(kBlock) void k_adj_wall_cols(Domain D, GeomParams G, float kk,
                                                            const float* __restrict__ alpha,
                                                            const double* __restrict__ phi,
@@ -434,21 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_cols(Domain D, GeomParams G
   const int ilast = min(d.nx, G.wall_imax + 1);
   double sn = 0.0, sf = 0.0;
   for (int i = 0; i <= ilast; ++i) {
-    // x faces (tangents y, z): corners (j,k), (j+1,k), (j+1,k+1), (j,k+1)
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k, 0);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k, 1);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j - 1, k - 1, 2);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 0, i, j, k - 1, 3);
-    // y faces (tangents x, z)
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k, 0);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k, 1);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i - 1, j, k - 1, 2);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 1, i, j, k - 1, 3);
-    // z faces (tangents x, y)
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j, k, 0);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j, k, 1);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i - 1, j - 1, k, 2);
-    sn += wall_corner_term(D, G, kk, alpha, phi, g, y, uhat, p, 2, i, j - 1, k, 3);
+    sn += node_phi_adjoint(D, G, kk, alpha, phi, g, y, uhat, p, i, j, k);
     if (j < d.ny && k < d.nz) {
       double galpha, gus;
       if (wall_face_terms(D, G, kk, alpha, g, y, uhat, p, 0, i, j, k, galpha, gus)) sf += gus;
@@ -484,6 +494,56 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_knots(Domain D, GeomParams 
   block_sum<2, kBlock>(v, sh);
   if (threadIdx.x == 0) g_theta[blockIdx.x] += -G.amp * G.wall_s * v[0] + G.amp * G.wall_sd * v[1];
 }
+
+// ---- the parametric solids' parameter gradient (FP64, fixed order) -------
+//
+// dJ/dtheta_q = sum over nodes whose CSG term is solid q of dJ/dphi_node
+// d(distance to q)/dtheta_q.  Block row blockIdx.y = q walks q's node box
+// (nodes outside it have dJ/dphi = 0 or another CSG term); a node with a
+// nonzero dJ/dphi evaluates the whole scene to find its term.  Partials:
+// partials[(q * kShapeParams + s) * gridDim.x + blockIdx.x].
+__global__ __launch_bounds__(kBlock) void k_adj_solids(Domain D, GeomParams G, float kk,
+                                                        const float* __restrict__ alpha,
+                                                        const double* __restrict__ phi,
+                                                        const float* __restrict__ g,
+                                                        const float* __restrict__ y,
+                                                        const float* __restrict__ uhat,
+                                                        const float* __restrict__ p, double* __restrict__ partials) {
+  const int q = blockIdx.y;
+  const int* box = G.sbox[q];
+  const int ex = box[3], ey = box[4], ez = box[5];
+  const long total = (long)ex * ey * ez;
+  const double* dirs = G.solids;
+  const double* S = G.solids + kShapeHead + (size_t)q * kShapeStride;
+  double acc[kShapeParams];
+#pragma unroll
+  for (int t = 0; t < kShapeParams; ++t) acc[t] = 0.0;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int i = box[0] + (int)(t % ex);
+    const int j = box[1] + (int)((t / ex) % ey);
+    const int k = box[2] + (int)(t / ((long)ex * ey));
+    const double gphi = node_phi_adjoint(D, G, kk, alpha, phi, g, y, uhat, p, i, j, k);
+    if (gphi == 0.0) continue;
+    const double x0 = i * D.dx, x1 = j * D.dx, x2 = k * D.dx;
+    int active;
+    scene_phi(G.solids, G.nsolid, x0, x1, x2, active);
+    if (active != q) continue;
+    solid_distance_grad(dirs, S, x0, x1, x2, gphi, acc);
+  }
+  block_partials<kShapeParams>(acc, partials + (size_t)q * kShapeParams * gridDim.x);
+}
+
+// One block per (parameter, solid): fixed-order total added to g_theta.
+__global__ __launch_bounds__(kFinBlock) void k_fin_adj_solids(int nb, int m, const double* __restrict__ partials,
+                                                               double* __restrict__ g_theta) {
+  const int s = blockIdx.x, q = blockIdx.y;
+  double tot[1];
+  finish_partials<1>(partials + ((size_t)q * kShapeParams + s) * nb, nb, tot);
+  if (threadIdx.x == 0) g_theta[1 + m + (size_t)q * kShapeParams + s] += tot[0];
+}
+
+constexpr int kSolidBlocks = 128;   // blocks per solid of the gradient walk
+size_t solids_partials_doubles() { return (size_t)SIM_MAX_SOLIDS * kShapeParams * kSolidBlocks; }
 
 // J = scale * sum over the outlet faces (z faces with k = nz) of w u; g = scale w
 // there, 0 elsewhere (w = 1 when no weights are given).
@@ -612,14 +672,25 @@ size_t wall_column_doubles(const Dims& d) { return (size_t)(d.ny + 1) * (d.nz + 
 
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* wall_cols,
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* geom_scratch,
                       hipStream_t s) {
   hipLaunchKernelGGL(k_adj_faces, dim3(nblocks(D.d.faces())), dim3(kBlock), 0, s, D.d, alpha, g, y, gu);
   if (!grad) return;
+  if (G.kind == SIM_GEOM_BEZIER) {
+    if (!g_theta) return;
+    long most = 1;
+    for (int q = 0; q < G.nsolid; ++q) most = std::max(most, (long)G.sbox[q][3] * G.sbox[q][4] * G.sbox[q][5]);
+    const int nb = (int)std::min<size_t>(nblocks((size_t)most), kSolidBlocks);
+    hipLaunchKernelGGL(k_adj_solids, dim3(nb, G.nsolid), dim3(kBlock), 0, s, D, G, (float)kk, alpha, phi, g, y, uhat,
+                       p, geom_scratch);
+    hipLaunchKernelGGL(k_fin_adj_solids, dim3(kShapeParams, G.nsolid), dim3(kFinBlock), 0, s, nb, G.nsolid,
+                       geom_scratch, g_theta);
+    return;
+  }
   if (G.kind == SIM_GEOM_WALL) {
     if (!g_theta) return;
-    double* cn = wall_cols;
-    double* cf = wall_cols + (size_t)(D.d.ny + 1) * (D.d.nz + 1);
+    double* cn = geom_scratch;
+    double* cf = geom_scratch + (size_t)(D.d.ny + 1) * (D.d.nz + 1);
     hipLaunchKernelGGL(k_adj_wall_cols, dim3(nblocks((size_t)(D.d.ny + 1) * (D.d.nz + 1))), dim3(kBlock), 0, s, D,
                        G, (float)kk, alpha, phi, g, y, uhat, p, cn, cf);
     hipLaunchKernelGGL(k_adj_wall_knots, dim3(SIM_WALL_KNOTS_Y * SIM_WALL_KNOTS_Z), dim3(kBlock), 0, s, D, G, cn,

@@ -154,6 +154,13 @@ struct Solver {
 
 // nf_geom.hip
 void launch_phi_nodes(const Domain& D, const GeomParams& G, double* phi, hipStream_t s);
+// Parametric solids: check theta (n_params values) and pack it into `host`
+// (solids_buffer_doubles() doubles; the caller copies it to the device buffer
+// that G.solids then names), with the per-solid adjoint boxes in G.
+int pack_solids(const sim_desc& d, const double* theta, double* host, GeomParams& G);
+size_t solids_buffer_doubles();
+// Partial sums of the solids' parameter gradient (doubles).
+size_t solids_partials_doubles();
 void launch_alpha(const Domain& D, const double* phi, float* alpha, hipStream_t s);
 void launch_invdiag(const Dims& d, const float* ax, const float* ay, const float* az, float* invd, hipStream_t s);
 void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, const float* fay, const float* faz,
@@ -176,7 +183,7 @@ void launch_adj_div(const Dims& d, const float* alpha, const float* g, float* rh
 size_t adj_faces_partials(const Dims& d);
 void launch_adj_faces(const Domain& D, const GeomParams& G, bool grad, double kk, const float* alpha,
                       const double* phi, const float* g, const float* y, const float* uhat, const float* p,
-                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* wall_cols,
+                      float* gu, double* partials, double* g_theta, double* g_ctrl, double* geom_scratch,
                       hipStream_t s);
 size_t wall_column_doubles(const Dims& d);
 void launch_loss_outlet(const Dims& d, double scale, const float* w, const float* u, double* J, float* g,

@@ -20,7 +20,7 @@ _BC = {"wall": L.SIM_BC_WALL, "inflow": L.SIM_BC_INFLOW, "outflow": L.SIM_BC_OUT
        "periodic": L.SIM_BC_PERIODIC}
 _PREC = {"fp32": L.SIM_FP32, "fp16": L.SIM_MIXED_FP16, "bf16": L.SIM_MIXED_BF16}
 _GEOM = {"none": L.SIM_GEOM_NONE, "spheres": L.SIM_GEOM_SPHERES, "ellipsoid": L.SIM_GEOM_ELLIPSOID,
-         "wall": L.SIM_GEOM_WALL}
+         "wall": L.SIM_GEOM_WALL, "bezier": L.SIM_GEOM_BEZIER}
 
 
 @dataclass
@@ -38,6 +38,7 @@ class Config:
     max_iter: int = 200
     geom: str = "none"
     n_spheres: int = 0
+    n_solids: int = 0           # "bezier": parametric solids in the CSG scene
 
     def desc(self) -> L.SimDesc:
         d = L.SimDesc()
@@ -58,6 +59,8 @@ class Config:
             d.n_params, d.n_ctrl = 15, 6
         elif d.geom == L.SIM_GEOM_WALL:
             d.n_params, d.n_ctrl = L.SIM_WALL_KNOTS_Y * L.SIM_WALL_KNOTS_Z, 3
+        elif d.geom == L.SIM_GEOM_BEZIER:
+            d.n_params, d.n_ctrl = 1 + int(self.n_solids) * (1 + L.SIM_BEZIER_SHAPE_PARAMS), 0
         else:
             d.n_params, d.n_ctrl = 0, 0
         return d

@@ -18,6 +18,12 @@ Random-number recipe (numpy ``default_rng(seed)``, PCG64):
   normal velocity on walls is zero), the discrete curl is taken on faces
   (exactly divergence-free), and the field is scaled so max |u_f| = 1;
 * scene parameters are drawn after the noise, from the same generator.
+
+Parametric solids (44 values each: origin, rotation matrix, z0, z1, three
+key centres, three x eight key radii) are drawn as: origin U[0.35, 0.65]^3,
+rotation from a rotation vector uniform in the ball of radius pi (scipy's
+Rotation), z0 U[-0.25, -0.12], z1 U[0.12, 0.25], centres U[-0.03, 0.03],
+radii U[0.08, 0.16].
 """
 from __future__ import annotations
 
@@ -31,7 +37,7 @@ __all__ = [
     "face_shapes", "n_faces", "curl_noise", "ellipsoid_theta0", "controls",
     "sphere_center", "random_spheres", "face_noise", "Scene",
     "scene_sphere_rollout", "scene_ellipsoid_rollout", "scene_spheres_projection", "scene_channel",
-    "outlet_window_xy",
+    "outlet_window_xy", "random_solid", "solids_theta", "scene_solids",
 ]
 
 
@@ -108,6 +114,27 @@ def face_noise(n, rng, lo=-1.0, hi=1.0):
     return rng.uniform(lo, hi, size=n_faces(n))
 
 
+def random_solid(rng, lo=0.35, hi=0.65):
+    """One parametric solid's 44 parameters (origin, rotation matrix row-major,
+    z0, z1, 3 key centres, 3 x 8 key radii)."""
+    from scipy.spatial.transform import Rotation
+    o = rng.uniform(lo, hi, size=3)
+    d = rng.standard_normal(3)
+    d /= np.linalg.norm(d)
+    R = Rotation.from_rotvec(d * (math.pi * rng.uniform() ** (1.0 / 3.0))).as_matrix()
+    z0, z1 = rng.uniform(-0.25, -0.12), rng.uniform(0.12, 0.25)
+    c = rng.uniform(-0.03, 0.03, size=6)
+    rho = rng.uniform(0.08, 0.16, size=24)
+    return np.concatenate([o, R.ravel(), [z0, z1], c, rho])
+
+
+def solids_theta(solids, ops=None):
+    """Scene vector [m, op_1 .. op_m, solid_1 .. solid_m] (op 0 union, 1 intersection)."""
+    m = len(solids)
+    ops = [0] * m if ops is None else list(ops)
+    return np.concatenate([[float(m)], np.asarray(ops, float), *solids])
+
+
 @dataclass
 class Scene:
     """A seeded scene: grid, time step, solid description and initial velocity."""
@@ -115,7 +142,7 @@ class Scene:
     dx: float
     dt: float
     u0: np.ndarray
-    geom: str                       # "none" | "spheres" | "ellipsoid" | "wall"
+    geom: str                       # "none" | "spheres" | "ellipsoid" | "wall" | "bezier"
     spheres: np.ndarray = None      # (m, 4) for geom == "spheres"
     theta0: np.ndarray = None       # (9,) for geom == "ellipsoid"
     ctrl: np.ndarray = None         # (steps, 6) for geom == "ellipsoid"
@@ -195,3 +222,14 @@ def outlet_window_xy(n, dx, psi):
     wx = np.where(x > 0.5, np.sin(2.0 * math.pi * (x - 0.5)) ** 2, 0.0)
     wy = 1.0 + 0.5 * np.sin(2.0 * math.pi * y + psi)
     return (wy[:, None] * wx[None, :]).ravel()
+
+
+def scene_solids(seed=0, n=32, count=2, ops=None):
+    """Closed unit box with a static CSG scene of ``count`` parametric solids
+    (``ops`` per solid, default all unions), curl-noise initial velocity,
+    dt = dx/2.  The scene vector is ``extra["theta"]``."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    u0 = curl_noise((n, n, n), dx, rng)
+    solids = [random_solid(rng) for _ in range(count)]
+    return Scene((n, n, n), dx, 0.5 * dx, u0, "bezier", steps=1, extra={"theta": solids_theta(solids, ops)})

@@ -56,6 +56,18 @@ def test_footprint_and_validation():
     d.nu = -0.1
     assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_EINVAL
     assert lib.sim_footprint(None, C.byref(out)) == L.SIM_EINVAL
+    # parametric solids: 1 .. SIM_MAX_SOLIDS of them, n_params = 1 + m (1 + 44), no controls
+    for m, code in [(0, L.SIM_EINVAL), (1, L.SIM_OK), (L.SIM_MAX_SOLIDS, L.SIM_OK),
+                    (L.SIM_MAX_SOLIDS + 1, L.SIM_EINVAL)]:
+        d = _cfg(geom="bezier", n_solids=m).desc()
+        assert lib.sim_footprint(C.byref(d), C.byref(out)) == code, m
+    d = _cfg(geom="bezier", n_solids=2).desc()
+    assert d.n_params == 1 + 2 * 45
+    d.n_params += 1
+    assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_EINVAL
+    d.n_params -= 1
+    d.n_ctrl = 6
+    assert lib.sim_footprint(C.byref(d), C.byref(out)) == L.SIM_EINVAL
     for n in [(48, 48, 48), (96, 96, 96), (192, 192, 192), (256, 256, 512), (16, 16, 16), (8, 8, 8)]:
         assert sim_footprint(_cfg(n=n)) > 0
 
