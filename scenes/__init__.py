@@ -37,7 +37,7 @@ __all__ = [
     "face_shapes", "n_faces", "curl_noise", "ellipsoid_theta0", "controls",
     "sphere_center", "random_spheres", "face_noise", "Scene",
     "scene_sphere_rollout", "scene_ellipsoid_rollout", "scene_spheres_projection", "scene_channel",
-    "outlet_window_xy", "random_solid", "solids_theta", "scene_solids",
+    "outlet_window_xy", "random_solid", "solids_theta", "scene_solids", "scene_karman",
 ]
 
 
@@ -233,3 +233,41 @@ def scene_solids(seed=0, n=32, count=2, ops=None):
     u0 = curl_noise((n, n, n), dx, rng)
     solids = [random_solid(rng) for _ in range(count)]
     return Scene((n, n, n), dx, 0.5 * dx, u0, "bezier", steps=1, extra={"theta": solids_theta(solids, ops)})
+
+
+KARMAN_BC = ("wall", "wall", "wall", "wall", "inflow", "outflow")
+
+
+def scene_karman(n=(16, 256, 512), diameter=0.1, speed=1.0, centre=(0.5, 0.4), dt=2e-3, kick=0.1):
+    """Flow past a cylinder in a channel, as an x-independent slab: the
+    cylinder's axis is the x axis and it spans the slab, the channel is
+    [0, 1] across (y, walls) and n_z / n_y along z (inflow at z = 0 with
+    ``speed``, outflow at the far end), the slab's x sides are walls.  The
+    cylinder is one parametric solid whose eight equal control radii
+    D / (2 cos(pi/6)) put its joints on the circle of diameter D (the
+    cross-section's radius then stays within 1.4 percent of D / 2).  Initial
+    velocity: u_z = speed on every z face, u_x = 0, and a transverse bump
+    u_y = kick * speed * exp(-r^2 / D^2) centred 2 D behind the cylinder
+    (r the distance in the (y, z) plane; zero on the y walls) that breaks the
+    up/down symmetry.  extra: theta, bc, inflow, diameter, centre."""
+    n = tuple(int(v) for v in n)
+    dx = 1.0 / n[1]
+    nx, ny, nz = n
+    yc, zc = centre
+    # frame: body z -> world x, body x -> world y, body y -> world z
+    R = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    rho = diameter / (2.0 * math.cos(math.pi / 6.0))
+    solid = np.concatenate([[0.0, yc, zc], R.ravel(), [-1.0, nx * dx + 1.0], np.zeros(6), np.full(24, rho)])
+    theta = solids_theta([solid])
+    ux = np.zeros((nz, ny, nx + 1))
+    k = np.arange(nz)[:, None, None]
+    j = np.arange(ny + 1)[None, :, None]
+    yy, zz = j * dx, (k + 0.5) * dx
+    uy = np.broadcast_to(kick * speed * np.exp(-((yy - yc) ** 2 + (zz - zc - 2 * diameter) ** 2) / diameter ** 2),
+                         (nz, ny + 1, nx)).copy()
+    uy[:, 0, :] = 0.0
+    uy[:, ny, :] = 0.0
+    uz = np.full((nz + 1, ny, nx), speed)
+    u0 = np.concatenate([ux.ravel(), uy.ravel(), uz.ravel()])
+    return Scene(n, dx, dt, u0, "bezier", steps=0,
+                 extra=dict(theta=theta, bc=KARMAN_BC, inflow=speed, diameter=diameter, centre=centre))
