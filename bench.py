@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP32 comparison run")
+    ap.add_argument("--solve-mode", default="host", choices=["host", "device"],
+                    help="device: fixed iteration budget per solve, nothing waits on the host")
+    ap.add_argument("--solve-budget", type=int, default=0, help="device solve mode's budget (0: from the warm-up)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=1, help="steps of the oracle's sample rollout")
     ap.add_argument("--cpu-n", type=int, default=64, help="grid of the oracle's sample rollout")
@@ -146,10 +149,16 @@ class StepTimer:
         return [a.elapsed_time(b) for a, b in self.pairs[kind]]
 
 
-def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
+def run_form(precision, steps, warmup, scene, torch, roofline_pass=True, solve_mode="host", budget=0):
     """Time `steps` rollouts of one precision form (graph-replayed CG, no
     profiling), then, outside the timed region, one more rollout with the
-    finest-level k_mg_up timed by HIP events (the roofline kernel)."""
+    finest-level k_mg_up timed by HIP events (the roofline kernel).
+
+    solve_mode "device": after the warm-up (host-checked solves), every solve
+    runs at most `budget` iterations (0: the warm-up's most iterations plus
+    two, in whole check intervals of 8) with nothing waiting on the host; the
+    solver reports are written on the device during the timed rollouts and
+    read after them, and every solve must have converged."""
     from paper_2405_14903_amd.sim import Config, Sim
     from paper_2405_14903_amd.rollout import Rollout
     cfg = Config(n=scene.n, dx=scene.dx, dt=scene.dt, geom="ellipsoid", tol=CG_TOL, precision=precision,
@@ -159,18 +168,27 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
     J = torch.empty(1, dtype=torch.float64, device="cuda")
     g = torch.empty_like(u0)
     iters = {"fwd": [], "adj": []}
+    device_stats = []
 
     def one(timer):
         ro = Rollout.ellipsoid(sim, scene.theta0, scene.ctrl, every=EVERY, timer=timer)
+        if solve_mode == "device" and timer is not None:
+            ro.device_stats = device_stats
         uT = ro.forward(u0)
         sim.loss_box(uT, J=J, g=g)
         ro.backward(g)
         ro.geometry_gradients()
         return ro
 
+    most = 0
     for _ in range(warmup):
-        one(None)
-    print(f"[bench] {precision}: warmup done", file=sys.stderr, flush=True)
+        ro = one(None)
+        most = max([most] + ro.iters["fwd"] + ro.iters["adj"])
+    if solve_mode == "device":
+        budget = budget if budget > 0 else 8 * math.ceil((most + 2) / 8)
+        sim.set_solve_mode("device", budget)
+    print(f"[bench] {precision}: warmup done ({solve_mode} solves"
+          f"{f', budget {budget}' if solve_mode == 'device' else ''})", file=sys.stderr, flush=True)
     timer = StepTimer(torch)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -180,6 +198,13 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
             iters[k] += ro.iters[k]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    unconverged = 0
+    for kind, st in device_stats:
+        rep = st.as_dict()
+        iters[kind].append(rep["iters"])
+        unconverged += 0 if rep["converged"] else 1
+    if solve_mode == "device":
+        sim.set_solve_mode("host")
     print(f"[bench] {precision}: {steps} rollouts in {wall:.2f} s", file=sys.stderr, flush=True)
     prof = None
     if roofline_pass:
@@ -202,7 +227,11 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True):
         "replay_ms_p50": pct(rep, 50), "replay_ms_p99": pct(rep, 99),
         "cg_iters": iter_summary(iters),
         "loss": float(J.item()),
+        "solve_mode": solve_mode,
     }
+    if solve_mode == "device":
+        out["solve_budget"] = budget
+        out["unconverged_solves"] = unconverged
     sim.close()
     return out, prof
 
@@ -577,10 +606,12 @@ def main():
         run_serving(args, torch)
         return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
-    main_form, prof = run_form(args.precision, args.steps, args.warmup, scene, torch)
+    main_form, prof = run_form(args.precision, args.steps, args.warmup, scene, torch, solve_mode=args.solve_mode,
+                               budget=args.solve_budget)
     cmp_form = None
     if not args.no_compare and args.precision != "fp32":
-        cmp_form, cmp_prof = run_form("fp32", args.steps, args.warmup, scene, torch)
+        cmp_form, cmp_prof = run_form("fp32", args.steps, args.warmup, scene, torch, solve_mode=args.solve_mode,
+                                      budget=args.solve_budget)
     rec = {
         "metric": "fwd+adjoint cell-steps/s at 128^3 (mixed vs FP32); p50/p99 step latency",
         "value": round(main_form["cell_steps_per_s"], 1),
@@ -604,6 +635,7 @@ def main():
                        "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"],
                        "replay_p50": main_form["replay_ms_p50"], "replay_p99": main_form["replay_ms_p99"]},
         "cg_iters": main_form["cg_iters"],
+        "solve": {k: main_form[k] for k in ("solve_mode", "solve_budget", "unconverged_solves") if k in main_form},
         "roofline": roofline(prof, args.precision),
     }
     if cmp_form:
@@ -611,6 +643,8 @@ def main():
                        "ms_per_step": round(cmp_form["ms_per_rollout"], 3),
                        "step_p50_ms": cmp_form["step_ms_p50"], "step_p99_ms": cmp_form["step_ms_p99"],
                        "cg_iters": cmp_form["cg_iters"],
+                       "solve": {k: cmp_form[k] for k in ("solve_mode", "solve_budget", "unconverged_solves")
+                                 if k in cmp_form},
                        "roofline": roofline(cmp_prof, "fp32", traffic=False)}
         rec["mixed_over_fp32"] = round(main_form["cell_steps_per_s"] / cmp_form["cell_steps_per_s"], 3)
     if oracle_path:
