@@ -24,6 +24,14 @@ step forward + adjoint, once on one thread and once with every core allowed.
 oracle_error compares the GPU's rollout of that sample (both precision forms,
 benchmark tolerance) with the oracle's: final velocity, loss, shape and
 control gradients.
+
+Nested legs (objects in the same line, each skippable): "channel" (the
+256x256x512 inflow / outflow channel with the B-spline wall, 200 steps
+forward + adjoint), "serving" (a seeded request stream through the
+continuous-batching loop against the same requests run serially in FP32),
+"solids" (a 128^3 static union of four parametric solids, forward + adjoint
+with the solids' parameter gradient) and "karman" (flow past a cylinder on
+the x-independent slab at 512 x 1024 in the plane, forward steps).
 """
 from __future__ import annotations
 
@@ -107,6 +115,10 @@ def parse():
     ap.add_argument("--serve-rates", default="10,20,50,100,150,200", help="arrival rates (--workload serving)")
     ap.add_argument("--no-channel", action="store_true", help="skip the nested channel leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the nested serving leg")
+    ap.add_argument("--no-solids", action="store_true", help="skip the nested parametric-solid leg")
+    ap.add_argument("--no-karman", action="store_true", help="skip the nested Karman slab leg")
+    ap.add_argument("--nested-solids-steps", type=int, default=32)
+    ap.add_argument("--nested-karman-steps", type=int, default=50)
     ap.add_argument("--nested-channel-steps", type=int, default=200)
     ap.add_argument("--nested-serve-requests", type=int, default=48)
     ap.add_argument("--nested-serve-rate", type=float, default=100.0)
@@ -435,6 +447,102 @@ def channel_leg(args, torch, steps, precision, profile=True):
     return out
 
 
+def family_us(sim, family, run, torch):
+    """Average HIP-event time (us) of one kernel family's working launches
+    while `run()` executes."""
+    sim.profile(family)
+    run()
+    torch.cuda.synchronize()
+    ms, cnt = sim.profile_read(min_ms=NOOP_MS)
+    sim.profile(None)
+    return round(1e3 * ms / cnt, 2) if cnt else None
+
+
+def solids_leg(torch, steps, precision):
+    """The parametric-solid geometry: a static CSG union of four polar-Bezier
+    solids in the 128^3 closed box, `steps` steps forward + adjoint with the
+    octant loss and dJ/dtheta of all 4 x 44 solid parameters."""
+    import scenes
+    from paper_2405_14903_amd.sim import Config, Sim
+    from paper_2405_14903_amd.rollout import Rollout
+    n = N
+    sc = scenes.scene_solids(seed=0, n=n, count=4)
+    th = sc.extra["theta"]
+    cfg = Config(n=sc.n, dx=sc.dx, dt=sc.dt, geom="bezier", n_solids=4, tol=CG_TOL, precision=precision,
+                 max_iter=200)
+    sim = Sim(cfg)
+    u0 = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
+
+    def one(T, timer):
+        ro = Rollout(sim, T, lambda k: (th, None), every=EVERY, grad_geometry=True, timer=timer)
+        J, g = sim.loss_box(ro.forward(u0))
+        ro.backward(g)
+        return ro, J
+
+    one(4, None)
+    torch.cuda.synchronize()
+    timer = StepTimer(torch)
+    t0 = time.perf_counter()
+    ro, J = one(steps, timer)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gth = ro.g_steps.sum(dim=0)
+    phi_us = family_us(sim, "geom_phi", lambda: one(2, None), torch)
+    adj_us = family_us(sim, "adj_faces", lambda: one(2, None), torch)
+    fwd, adj = timer.latencies("fwd"), timer.latencies("adj")
+    print(f"[bench] solids: {steps} steps forward + adjoint in {wall:.2f} s", file=sys.stderr, flush=True)
+    out = {
+        "value": round(n ** 3 * steps / wall, 1), "unit": "cell-steps/s", "wall_s": round(wall, 3),
+        "workload": f"{n}^3 closed box, static union of 4 parametric solids (polar Bezier cross-sections, "
+                    f"3 key sections, 4 x 44 parameters), {steps} steps forward + adjoint, checkpoint every "
+                    f"{EVERY}, octant loss, dJ/dtheta",
+        "precision": precision, "cg_tol": CG_TOL,
+        "latency_ms": {"fwd_p50": pct(fwd, 50), "fwd_p99": pct(fwd, 99), "adj_p50": pct(adj, 50),
+                       "adj_p99": pct(adj, 99)},
+        "cg_iters": iter_summary(ro.iters),
+        "geometry_us": {"phi_solids": phi_us, "adjoint_faces_and_solids": adj_us},
+        "loss": float(J.item()), "theta_gradient_norm": float(gth.norm()),
+    }
+    sim.close()
+    return out
+
+
+def karman_leg(torch, steps, precision, n=(32, 512, 1024)):
+    """Flow past a cylinder on the x-independent slab at the paper's 512 x 1024
+    resolution in the plane (32 cells thick, the least that coarsens to the
+    multigrid bottom): `steps` forward steps at Re = 100, timed."""
+    import scenes
+    from paper_2405_14903_amd.sim import Config, Sim
+    sc = scenes.scene_karman(n=n, diameter=0.1, dt=1e-3)
+    th = sc.extra["theta"]
+    cfg = Config(n=sc.n, dx=sc.dx, dt=sc.dt, nu=1e-3, bc=sc.extra["bc"], inflow_speed=sc.extra["inflow"],
+                 geom="bezier", n_solids=1, tol=CG_TOL, precision=precision, max_iter=400)
+    sim = Sim(cfg)
+    a = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    iters = []
+    for _ in range(3):
+        b, st = sim.step(a, th, u_out=b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b, st = sim.step(a, th, u_out=b)
+        iters.append(st["iters"])
+        a, b = b, a
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    C = n[0] * n[1] * n[2]
+    print(f"[bench] karman: {steps} steps in {wall:.2f} s", file=sys.stderr, flush=True)
+    sim.close()
+    return {"value": round(C * steps / wall, 1), "unit": "cell-steps/s", "wall_s": round(wall, 3),
+            "ms_per_step": round(1e3 * wall / steps, 3),
+            "workload": f"flow past a cylinder (diameter 0.1, Re 100, nu 1e-3, inflow 1), x-independent slab "
+                        f"{n[0]} x {n[1]} x {n[2]} ({n[1]} x {n[2]} in the plane), dt 1e-3, {steps} forward "
+                        f"steps after 3 warm-up steps",
+            "precision": precision, "cg_tol": CG_TOL, "cg_iters": iter_summary({"fwd": iters})}
+
+
 def run_channel(args, torch):
     """--workload channel: the channel leg as the one JSON line."""
     leg = channel_leg(args, torch, args.channel_steps, args.precision)
@@ -653,6 +761,10 @@ def main():
         rec["channel"] = channel_leg(args, torch, args.nested_channel_steps, args.precision, profile=False)
     if not args.no_serving:
         rec["serving"] = serving_leg(torch, args.nested_serve_requests, [args.nested_serve_rate], args.precision)
+    if not args.no_solids:
+        rec["solids"] = solids_leg(torch, args.nested_solids_steps, args.precision)
+    if not args.no_karman:
+        rec["karman"] = karman_leg(torch, args.nested_karman_steps, args.precision)
     rec["cpu_baseline"] = cpu
     print(json.dumps(rec), flush=True)
 

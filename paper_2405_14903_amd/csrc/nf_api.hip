@@ -34,6 +34,7 @@ struct sim_ctx {
   double* wall_cols = nullptr;  // B-spline wall: per-column totals of its adjoint
   double* solids = nullptr;     // parametric solids: the packed solids of the current call
   double* solids_part = nullptr;  // parametric solids: partial sums of their gradient
+  unsigned char* solid_term = nullptr;  // parametric solids: CSG term of every node
   std::vector<double> solids_host;  // host staging of the packed solids
   std::vector<void*> allocs;
   GeomParams last_geom;
@@ -156,6 +157,7 @@ void for_each_buffer(const sim_desc* d, const Plan& p, sim_ctx* t, F alloc) {
   if (d->geom == SIM_GEOM_BEZIER) {
     alloc(solids_buffer_doubles() * 8, (void**)&t->solids);
     alloc(solids_partials_doubles() * 8, (void**)&t->solids_part);
+    alloc(d0.nodes(), (void**)&t->solid_term);
   }
   for (int l = 0; l < p.nlev; ++l) {
     const Dims& dl = p.dims[l];
@@ -198,6 +200,7 @@ int make_geom(sim_ctx* c, const double* theta, const double* ctrl, GeomParams& g
                        hipMemcpyHostToDevice, st) != hipSuccess)
       return SIM_EHIP;
     g.solids = c->solids;
+    g.solid_term = c->solid_term;
     return SIM_OK;
   }
   if (g.kind == SIM_GEOM_WALL) {

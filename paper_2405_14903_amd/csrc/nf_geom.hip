@@ -69,8 +69,9 @@ __global__ __launch_bounds__(kBlock) void k_phi_solids(Dims d, double dx, GeomPa
   const int i = (int)(n % sx);
   const long t = n / sx;
   const int j = (int)(t % sy), k = (int)(t / sy);
-  int active;
-  phi[n] = scene_phi(G.solids, G.nsolid, i * dx, j * dx, k * dx, active);
+  unsigned char term;
+  phi[n] = scene_phi_fast(G.solids, G.nsolid, G.solid_far, i * dx, j * dx, k * dx, term);
+  G.solid_term[n] = term;
 }
 
 // Fraction along an edge from the corner with value a to the sign change.
@@ -220,22 +221,23 @@ int pack_solids(const sim_desc& d, const double* theta, double* host, GeomParams
     host[2 * r + 1] = std::sin(ang);
   }
   const int n[3] = {d.n[0], d.n[1], d.n[2]};
+  double reach[SIM_MAX_SOLIDS], Ti[SIM_MAX_SOLIDS][3][3], det[SIM_MAX_SOLIDS];
+  double lip = 1.0;   // bound on the scene's |grad phi| (the CSG of the solids' bounds)
   for (int q = 0; q < m; ++q) {
     const double* th = theta + 1 + m + (size_t)q * kShapeParams;
     double* S = host + kShapeHead + (size_t)q * kShapeStride;
     if (!(th[13] > th[12])) return SIM_EINVAL;
     for (int t = 0; t < 14; ++t) S[t] = th[t];
     S[14] = q == 0 ? 0.0 : theta[1 + q];
-    S[15] = 0.0;
     const double* C = th + 14;
     const double* P = th + 14 + 2 * kKeys;
     for (int t = 0; t < 2 * kKeys; ++t) S[kOffC + t] = C[t];
     for (int t = 0; t < kRadii * kKeys; ++t) S[kOffRho + t] = P[t];
-    double reach = 0.0;   // bound on |vertex| in the solid's frame (a vertex is c plus a convex mix of rho dir)
+    reach[q] = 0.0;   // bound on |vertex| in the solid's frame (a vertex is c plus a convex mix of rho dir)
     for (int key = 0; key < kKeys; ++key) {
       double rmax = 0.0;
       for (int r = 0; r < kRadii; ++r) rmax = std::max(rmax, std::fabs(P[kRadii * key + r]));
-      reach = std::max(reach, std::hypot(C[2 * key], C[2 * key + 1]) + rmax);
+      reach[q] = std::max(reach[q], std::hypot(C[2 * key], C[2 * key + 1]) + rmax);
       for (int v = 0; v < kVerts; ++v) {
         int rr[4];
         double w[4];
@@ -249,32 +251,72 @@ int pack_solids(const sim_desc& d, const double* theta, double* host, GeomParams
         S[kOffVert + 2 * (kVerts * key + v) + 1] = vy;
       }
     }
-    // A node within 2 dx of the zero set whose CSG term is this solid has a
-    // distance in [-2 dx, 2 dx] to it, so its frame point p lies in the box
-    // [-reach - e, reach + e]^2 x [z0 - e, z1 + e], e = 2 dx: the world
-    // bounds of that box's corners x = o + (R^T)^-1 p, widened by one node.
-    // T = R^T: T[a][b] = R[b][a]; (R^T)^-1 = adj(T) / det(T).
-    double T[3][3], Ti[3][3];
+    S[15] = reach[q];
+    // |d(cross-section distance)/dp_z| <= how fast a polygon vertex moves with p_z
+    double slope = 0.0;
+    for (int key = 0; key + 1 < kKeys; ++key)
+      for (int v = 0; v < kVerts; ++v) {
+        const double* a = S + kOffVert + 2 * (kVerts * key + v);
+        const double* b = a + 2 * kVerts;
+        slope = std::max(slope, std::hypot(b[0] - a[0], b[1] - a[1]) * (kKeys - 1) / (th[13] - th[12]));
+      }
+    // T = R^T (p = T (x - o)): T[a][b] = R[b][a]; (R^T)^-1 = adj(T) / det(T)
+    double T[3][3];
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) T[a][b] = th[3 + 3 * b + a];
-    Ti[0][0] = T[1][1] * T[2][2] - T[1][2] * T[2][1];
-    Ti[0][1] = T[0][2] * T[2][1] - T[0][1] * T[2][2];
-    Ti[0][2] = T[0][1] * T[1][2] - T[0][2] * T[1][1];
-    Ti[1][0] = T[1][2] * T[2][0] - T[1][0] * T[2][2];
-    Ti[1][1] = T[0][0] * T[2][2] - T[0][2] * T[2][0];
-    Ti[1][2] = T[0][2] * T[1][0] - T[0][0] * T[1][2];
-    Ti[2][0] = T[1][0] * T[2][1] - T[1][1] * T[2][0];
-    Ti[2][1] = T[0][1] * T[2][0] - T[0][0] * T[2][1];
-    Ti[2][2] = T[0][0] * T[1][1] - T[0][1] * T[1][0];
-    const double det = T[0][0] * Ti[0][0] + T[0][1] * Ti[1][0] + T[0][2] * Ti[2][0];
-    if (!(std::fabs(det) > 1e-12)) return SIM_EINVAL;
-    const double e = 2.0 * d.dx;
+    double (&I)[3][3] = Ti[q];
+    I[0][0] = T[1][1] * T[2][2] - T[1][2] * T[2][1];
+    I[0][1] = T[0][2] * T[2][1] - T[0][1] * T[2][2];
+    I[0][2] = T[0][1] * T[1][2] - T[0][2] * T[1][1];
+    I[1][0] = T[1][2] * T[2][0] - T[1][0] * T[2][2];
+    I[1][1] = T[0][0] * T[2][2] - T[0][2] * T[2][0];
+    I[1][2] = T[0][2] * T[1][0] - T[0][0] * T[1][2];
+    I[2][0] = T[1][0] * T[2][1] - T[1][1] * T[2][0];
+    I[2][1] = T[0][1] * T[2][0] - T[0][0] * T[2][1];
+    I[2][2] = T[0][0] * T[1][1] - T[0][1] * T[1][0];
+    det[q] = T[0][0] * I[0][0] + T[0][1] * I[1][0] + T[0][2] * I[2][0];
+    if (!(std::fabs(det[q]) > 1e-12)) return SIM_EINVAL;
+    // |grad_x| <= ||T||_2 |grad_p|, |grad_p| <= sqrt(1 + slope^2); ||T||_2^2 is the
+    // largest eigenvalue of the symmetric T^T T (closed form for 3 x 3)
+    double A[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) A[a][b] = T[0][a] * T[0][b] + T[1][a] * T[1][b] + T[2][a] * T[2][b];
+    double lmax;
+    const double p1 = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    if (p1 == 0.0) {
+      lmax = std::max(A[0][0], std::max(A[1][1], A[2][2]));
+    } else {
+      const double qm = (A[0][0] + A[1][1] + A[2][2]) / 3.0;
+      const double p2 = (A[0][0] - qm) * (A[0][0] - qm) + (A[1][1] - qm) * (A[1][1] - qm) +
+                        (A[2][2] - qm) * (A[2][2] - qm) + 2.0 * p1;
+      const double pp = std::sqrt(p2 / 6.0);
+      double Bm[3][3];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) Bm[a][b] = (A[a][b] - (a == b ? qm : 0.0)) / pp;
+      const double r = 0.5 * (Bm[0][0] * (Bm[1][1] * Bm[2][2] - Bm[1][2] * Bm[2][1]) -
+                              Bm[0][1] * (Bm[1][0] * Bm[2][2] - Bm[1][2] * Bm[2][0]) +
+                              Bm[0][2] * (Bm[1][0] * Bm[2][1] - Bm[1][1] * Bm[2][0]));
+      lmax = qm + 2.0 * pp * std::cos(std::acos(std::min(1.0, std::max(-1.0, r))) / 3.0);
+    }
+    lip = std::max(lip, 1.001 * std::sqrt(std::max(lmax, 0.0)) * std::sqrt(1.0 + slope * slope));
+  }
+  // dJ/dphi is nonzero only at the corners of cut faces (corners of both
+  // signs), so |phi| <= lip sqrt(2) dx there; where the node's CSG term is
+  // solid q, its distance to q is the same, so its frame point p lies in the
+  // box [-reach - e, reach + e]^2 x [z0 - e, z1 + e], e = lip sqrt(2) dx:
+  // the world bounds of that box's corners x = o + (R^T)^-1 p, widened by
+  // one node.
+  const double e = lip * std::sqrt(2.0) * d.dx;
+  // nodes whose phi bound exceeds e (with a margin) touch no cut face
+  G.solid_far = 1.01 * e;
+  for (int q = 0; q < m; ++q) {
+    const double* th = theta + 1 + m + (size_t)q * kShapeParams;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int c = 0; c < 8; ++c) {
-      const double p[3] = {(c & 1) ? reach + e : -reach - e, (c & 2) ? reach + e : -reach - e,
+      const double p[3] = {(c & 1) ? reach[q] + e : -reach[q] - e, (c & 2) ? reach[q] + e : -reach[q] - e,
                            (c & 4) ? th[13] + e : th[12] - e};
       for (int a = 0; a < 3; ++a) {
-        const double w = th[a] + (Ti[a][0] * p[0] + Ti[a][1] * p[1] + Ti[a][2] * p[2]) / det;
+        const double w = th[a] + (Ti[q][a][0] * p[0] + Ti[q][a][1] * p[1] + Ti[q][a][2] * p[2]) / det[q];
         lo[a] = std::min(lo[a], w);
         hi[a] = std::max(hi[a], w);
       }

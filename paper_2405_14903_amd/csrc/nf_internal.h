@@ -51,12 +51,16 @@ struct GeomParams {
   double wall_s, wall_sd, amp;
   double ly, lz;               // extent of the wall side along y and z
   int wall_imax;               // faces with i > wall_imax are fully fluid
-  // parametric solids: the packed solids (device) and, per solid, the node
-  // box (lo x3, extent x3) outside which it cannot be the CSG term of a node
-  // within two cells of the zero set
+  // parametric solids: the packed solids (device); per solid, the node box
+  // (lo x3, extent x3) outside which it cannot be the CSG term of a node
+  // whose fractions carry gradient; the distance beyond which no face at a
+  // node can be cut (phi there is a lower bound, not exact); and the CSG term
+  // of every node (device, one byte per node, kNoSolid in the far field)
   const double* solids;
   int nsolid;
   int sbox[SIM_MAX_SOLIDS][6];
+  double solid_far;
+  unsigned char* solid_term;
 };
 
 struct Domain {

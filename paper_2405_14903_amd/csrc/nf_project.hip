@@ -499,8 +499,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_knots(Domain D, GeomParams 
 //
 // dJ/dtheta_q = sum over nodes whose CSG term is solid q of dJ/dphi_node
 // d(distance to q)/dtheta_q.  Block row blockIdx.y = q walks q's node box
-// (nodes outside it have dJ/dphi = 0 or another CSG term); a node with a
-// nonzero dJ/dphi evaluates the whole scene to find its term.  Partials:
+// (nodes outside it have dJ/dphi = 0 or another CSG term); the term of every
+// node was recorded by the forward geometry kernel (a node with a nonzero
+// dJ/dphi is a corner of a cut face, never in the far field).  Partials:
 // partials[(q * kShapeParams + s) * gridDim.x + blockIdx.x].
 __global__ __launch_bounds__(kBlock) void k_adj_solids(Domain D, GeomParams G, float kk,
                                                         const float* __restrict__ alpha,
@@ -522,13 +523,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_solids(Domain D, GeomParams G, f
     const int i = box[0] + (int)(t % ex);
     const int j = box[1] + (int)((t / ex) % ey);
     const int k = box[2] + (int)(t / ((long)ex * ey));
+    // the node's CSG term, recorded by the forward geometry kernel
+    if (G.solid_term[D.d.node(i, j, k)] != (unsigned char)q) continue;
     const double gphi = node_phi_adjoint(D, G, kk, alpha, phi, g, y, uhat, p, i, j, k);
     if (gphi == 0.0) continue;
-    const double x0 = i * D.dx, x1 = j * D.dx, x2 = k * D.dx;
-    int active;
-    scene_phi(G.solids, G.nsolid, x0, x1, x2, active);
-    if (active != q) continue;
-    solid_distance_grad(dirs, S, x0, x1, x2, gphi, acc);
+    solid_distance_grad(dirs, S, i * D.dx, j * D.dx, k * D.dx, gphi, acc);
   }
   block_partials<kShapeParams>(acc, partials + (size_t)q * kShapeParams * gridDim.x);
 }
@@ -542,7 +541,7 @@ __global__ __launch_bounds__(kFinBlock) void k_fin_adj_solids(int nb, int m, con
   if (threadIdx.x == 0) g_theta[1 + m + (size_t)q * kShapeParams + s] += tot[0];
 }
 
-constexpr int kSolidBlocks = 128;   // blocks per solid of the gradient walk
+constexpr int kSolidBlocks = 512;   // blocks per solid of the gradient walk (at most)
 size_t solids_partials_doubles() { return (size_t)SIM_MAX_SOLIDS * kShapeParams * kSolidBlocks; }
 
 // J = scale * sum over the outlet faces (z faces with k = nz) of w u; g = scale w

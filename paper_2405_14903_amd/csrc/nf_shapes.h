@@ -23,7 +23,8 @@
 //
 // Device layout of the packed solids (doubles): kShapeDirs control-angle unit
 // vectors (cos, sin) at offset 0, then per solid q at kShapeHead +
-// q * kShapeStride: o(3) R(9, row-major, body -> world) z0 z1 op pad, the key
+// q * kShapeStride: o(3) R(9, row-major, body -> world) z0 z1 op reach (the
+// radius in the solid's frame of a disk that holds every cross-section), the key
 // centres (K x 2), the key radii (K x 2N, key-major), and the polygon
 // vertices of every key cross-section (K x kVerts x 2), computed on the host.
 // The polygon at s is then the linear interpolation of the two bracketing
@@ -147,19 +148,51 @@ __device__ inline double solid_distance(const double* __restrict__ S, double x, 
   return h.val;
 }
 
-// CSG value of the scene at (x, y, z) and the index of the solid it takes.
-__device__ inline double scene_phi(const double* __restrict__ shapes, int m, double x, double y, double z,
-                                   int& active) {
+constexpr unsigned char kNoSolid = 0xff;   // CSG term of a far-field node
+
+// A lower bound of solid S's distance at (x, y, z): every cross-section lies
+// in the disk of radius `reach` about the frame's axis, so the distance to the
+// polygon is at least |p_xy| - reach (also inside, where the polygon's
+// boundary is nearer than the disk's), and the caps' terms are exact.
+__device__ inline double solid_lower_bound(const double* __restrict__ S, double x, double y, double z) {
+  const double r0 = x - S[0], r1 = y - S[1], r2 = z - S[2];
+  const double* R = S + 3;
+  const double px = R[0] * r0 + R[3] * r1 + R[6] * r2;
+  const double py = R[1] * r0 + R[4] * r1 + R[7] * r2;
+  const double pz = R[2] * r0 + R[5] * r1 + R[8] * r2;
+  return fmax(sqrt(px * px + py * py) - S[15], fmax(S[12] - pz, pz - S[13]));
+}
+
+// phi of the scene at (x, y, z) and its CSG term.  The CSG of the solids'
+// lower bounds bounds phi from below (min and max are monotone); beyond
+// `far` no face at the node can be cut, so there that bound stands in for phi
+// (positive: fluid) and the term is kNoSolid.  Nearer, phi is exact: a union
+// member whose bound is not below the running value cannot lower it, so its
+// polygon walk is skipped.
+__device__ inline double scene_phi_fast(const double* __restrict__ shapes, int m, double far, double x, double y,
+                                        double z, unsigned char& term) {
+  double lb[SIM_MAX_SOLIDS];
+  double lbs = 0.0;
+  for (int q = 0; q < m; ++q) {
+    const double* S = shapes + kShapeHead + (size_t)q * kShapeStride;
+    lb[q] = solid_lower_bound(S, x, y, z);
+    lbs = q == 0 ? lb[q] : (S[14] == 0.0 ? fmin(lbs, lb[q]) : fmax(lbs, lb[q]));
+  }
+  if (lbs > far) {
+    term = kNoSolid;
+    return lbs;
+  }
   SolidHit h;
   double phi = solid_distance<false>(shapes + kShapeHead, x, y, z, h);
-  active = 0;
+  term = 0;
   for (int q = 1; q < m; ++q) {
     const double* S = shapes + kShapeHead + (size_t)q * kShapeStride;
+    const bool uni = S[14] == 0.0;
+    if (uni && lb[q] >= phi) continue;
     const double v = solid_distance<false>(S, x, y, z, h);
-    const bool take = S[14] == 0.0 ? v < phi : v > phi;
-    if (take) {
+    if (uni ? v < phi : v > phi) {
       phi = v;
-      active = q;
+      term = (unsigned char)q;
     }
   }
   return phi;

@@ -84,6 +84,38 @@ def test_solid_step_and_adjoint_parity_32():
     np.testing.assert_allclose(host(gth2), 2.0 * gt, rtol=1e-12, atol=0)
 
 
+def test_tapered_solid_in_a_skewed_frame_adjoint_parity_32():
+    """A solid whose radii change fast along its axis (the distance's slope
+    along z is about 2) in a frame that is not orthonormal: the nodes whose
+    fractions carry gradient lie farther from the surface than for a straight
+    extrusion, and the gradient walk must still reach all of them."""
+    announce("tapered parametric solid in a skewed frame, step adjoint 32^3")
+    sc = scenes.scene_solids(seed=6, n=32, count=1)
+    th = sc.extra["theta"].copy()
+    s0 = 2                                    # first parameter of the solid
+    th[s0 + 12], th[s0 + 13] = -0.1, 0.1      # z0, z1
+    rho = np.array([[0.06] * 8, [0.22] * 8, [0.08] * 8])
+    th[s0 + 20:s0 + 44] = rho.ravel()
+    R = np.array(th[s0 + 3:s0 + 12]).reshape(3, 3) @ np.diag([1.0, 1.3, 0.8])
+    th[s0 + 3:s0 + 12] = R.ravel()
+    g = Grid(sc.n, sc.dx)
+    geo = B.BezierGeometry(g, th)
+    st_o = Step(StepParams(g, sc.dt, tol=1e-12), sc.u0, geo.alpha, geo.us)
+    gbar = np.random.default_rng(9).standard_normal(g.nfaces)
+    _, galpha, _ = st_o.vjp(gbar)
+    gth_o = geo.vjp(galpha)
+    with Sim(_cfg(sc, 1)) as sim:
+        u0 = dev(sc.u0)
+        P = torch.empty(g.ncells, dtype=torch.float32, device="cuda")
+        u1, _ = sim.step(u0, th, p_out=P)
+        gth = torch.zeros(len(th), dtype=torch.float64, device="cuda")
+        sim.step_adjoint(u0, dev(gbar), th, p_n1=P, g_theta=gth)
+        torch.cuda.synchronize()
+    ef, e_th = rel_l2(host(u1), st_o.result), rel_l2(host(gth), gth_o)
+    announce(f"  forward rel-L2 {ef:.2e}, dJ/dtheta rel-L2 {e_th:.2e}")
+    assert ef <= 1e-5 and e_th <= 1e-3, (ef, e_th)
+
+
 def test_solid_fractions_sampled_128():
     announce("parametric-solid fractions 128^3, four-solid union, sampled faces")
     n = 128
