@@ -90,6 +90,9 @@ def parse():
     ap.add_argument("--solve-mode", default="host", choices=["host", "device"],
                     help="device: fixed iteration budget per solve, nothing waits on the host")
     ap.add_argument("--solve-budget", type=int, default=0, help="device solve mode's budget (0: from the warm-up)")
+    ap.add_argument("--cold-start", action="store_true",
+                    help="start every solve of the rollouts from zero (default: each adjoint solve starts from "
+                         "the previous adjoint pressure)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=1, help="steps of the oracle's sample rollout")
     ap.add_argument("--cpu-n", type=int, default=64, help="grid of the oracle's sample rollout")
@@ -161,7 +164,7 @@ class StepTimer:
         return [a.elapsed_time(b) for a, b in self.pairs[kind]]
 
 
-def run_form(precision, steps, warmup, scene, torch, roofline_pass=True, solve_mode="host", budget=0):
+def run_form(precision, steps, warmup, scene, torch, roofline_pass=True, solve_mode="host", budget=0, warm=True):
     """Time `steps` rollouts of one precision form (graph-replayed CG, no
     profiling), then, outside the timed region, one more rollout with the
     finest-level k_mg_up timed by HIP events (the roofline kernel).
@@ -183,7 +186,8 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True, solve_m
     device_stats = []
 
     def one(timer):
-        ro = Rollout.ellipsoid(sim, scene.theta0, scene.ctrl, every=EVERY, timer=timer)
+        ro = Rollout.ellipsoid(sim, scene.theta0, scene.ctrl, every=EVERY, timer=timer,
+                               warm_start="adjoint" if warm else False)
         if solve_mode == "device" and timer is not None:
             ro.device_stats = device_stats
         uT = ro.forward(u0)
@@ -240,6 +244,7 @@ def run_form(precision, steps, warmup, scene, torch, roofline_pass=True, solve_m
         "cg_iters": iter_summary(iters),
         "loss": float(J.item()),
         "solve_mode": solve_mode,
+        "solve_start": "adjoint solves warm-started" if warm else "zero",
     }
     if solve_mode == "device":
         out["solve_budget"] = budget
@@ -362,8 +367,9 @@ def cpu_baseline(n, steps):
 
 def oracle_check(path, n, steps, torch):
     """Error against the FP64 oracle on the same scene at n^3 and `steps`
-    steps: the GPU rollout (benchmark tolerance) in both precision forms,
-    final velocity and shape / control gradients."""
+    steps: the GPU rollout as the benchmark runs it (benchmark tolerance,
+    warm-started adjoint solves) in both precision forms, final velocity and
+    shape / control gradients."""
     import numpy as np
     import scenes
     from paper_2405_14903_amd.sim import Config, Sim
@@ -376,7 +382,7 @@ def oracle_check(path, n, steps, torch):
         cfg = Config(n=sc.n, dx=sc.dx, dt=sc.dt, geom="ellipsoid", tol=CG_TOL, precision=prec, max_iter=200)
         with Sim(cfg) as sim:
             u0 = torch.tensor(sc.u0, dtype=torch.float32, device="cuda")
-            ro = Rollout.ellipsoid(sim, sc.theta0, sc.ctrl, every=EVERY)
+            ro = Rollout.ellipsoid(sim, sc.theta0, sc.ctrl, every=EVERY, warm_start="adjoint")
             uT = ro.forward(u0)
             J, g = sim.loss_box(uT)
             ro.backward(g)
@@ -715,11 +721,11 @@ def main():
         return
     scene = scenes.scene_ellipsoid_rollout(seed=0, n=N, steps=T)
     main_form, prof = run_form(args.precision, args.steps, args.warmup, scene, torch, solve_mode=args.solve_mode,
-                               budget=args.solve_budget)
+                               budget=args.solve_budget, warm=not args.cold_start)
     cmp_form = None
     if not args.no_compare and args.precision != "fp32":
         cmp_form, cmp_prof = run_form("fp32", args.steps, args.warmup, scene, torch, solve_mode=args.solve_mode,
-                                      budget=args.solve_budget)
+                                      budget=args.solve_budget, warm=not args.cold_start)
     rec = {
         "metric": "fwd+adjoint cell-steps/s at 128^3 (mixed vs FP32); p50/p99 step latency",
         "value": round(main_form["cell_steps_per_s"], 1),
@@ -743,7 +749,8 @@ def main():
                        "adj_p50": main_form["adj_ms_p50"], "adj_p99": main_form["adj_ms_p99"],
                        "replay_p50": main_form["replay_ms_p50"], "replay_p99": main_form["replay_ms_p99"]},
         "cg_iters": main_form["cg_iters"],
-        "solve": {k: main_form[k] for k in ("solve_mode", "solve_budget", "unconverged_solves") if k in main_form},
+        "solve": {k: main_form[k] for k in ("solve_mode", "solve_start", "solve_budget", "unconverged_solves")
+                  if k in main_form},
         "roofline": roofline(prof, args.precision),
     }
     if cmp_form:
@@ -751,8 +758,8 @@ def main():
                        "ms_per_step": round(cmp_form["ms_per_rollout"], 3),
                        "step_p50_ms": cmp_form["step_ms_p50"], "step_p99_ms": cmp_form["step_ms_p99"],
                        "cg_iters": cmp_form["cg_iters"],
-                       "solve": {k: cmp_form[k] for k in ("solve_mode", "solve_budget", "unconverged_solves")
-                                 if k in cmp_form},
+                       "solve": {k: cmp_form[k] for k in ("solve_mode", "solve_start", "solve_budget",
+                                                          "unconverged_solves") if k in cmp_form},
                        "roofline": roofline(cmp_prof, "fp32", traffic=False)}
         rec["mixed_over_fp32"] = round(main_form["cell_steps_per_s"] / cmp_form["cell_steps_per_s"], 3)
     if oracle_path:

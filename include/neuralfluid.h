@@ -312,6 +312,26 @@ int32_t sim_max_speed(sim_handle h, const float* u, double* vmax, hipStream_t st
 typedef enum { SIM_SOLVE_HOST = 0, SIM_SOLVE_DEVICE = 1 } sim_solve_mode;
 int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget);
 
+/* Warm-started solves (this library's addition; the paper does not say how
+ * its solves start).  kinds, a combination of the bits below: with
+ * SIM_WARM_PRESSURE the pressure solve of sim_step / sim_project starts from
+ * the pressure of the handle's previous such solve, with SIM_WARM_ADJOINT
+ * the adjoint pressure solve of sim_step_adjoint from the previous adjoint
+ * solution, instead of zero.  The tolerance and the stopping test are
+ * unchanged, so results agree with zero-started ones to the solver
+ * tolerance, not bitwise.  Consecutive adjoint steps of a rollout have close
+ * adjoint pressures (at 128^3 the adjoint solves then take 8.0 instead of 9.0
+ * iterations); a step's pressure corrects that step's own advection and is
+ * not close to the previous one, so SIM_WARM_PRESSURE saves nothing there.
+ * Each call forgets the held pressures: the next solve of each kind starts
+ * from zero, which makes a sequence of calls that begins with
+ * sim_set_warm_start deterministic.  A forward re-solve inside
+ * sim_step_adjoint (p_n1 NULL) starts from zero and ends the forward chain.
+ * Host only; enqueues nothing.  Returns SIM_EINVAL for a NULL handle or
+ * unknown bits. */
+typedef enum { SIM_WARM_PRESSURE = 1, SIM_WARM_ADJOINT = 2 } sim_warm_kind;
+int32_t sim_set_warm_start(sim_handle h, int32_t kinds);
+
 /* Connected fluid regions (Sec. Projection: cells joined through faces with
  * alpha > 0).  A region that reaches no OUTFLOW face is floating: its pressure
  * is defined up to a constant and its right-hand side sums to zero over it up

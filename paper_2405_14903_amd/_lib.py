@@ -15,6 +15,7 @@ SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EHIP, SIM_EUNSUPPORTED = 0, -1, -2, -3, -4
 SIM_WNOCONV, SIM_WNONFINITE = 1, 2
 SIM_SOLVE_HOST, SIM_SOLVE_DEVICE = 0, 1
 SIM_REGIONS_AUTO, SIM_REGIONS_ALWAYS, SIM_REGIONS_NEVER = 0, 1, 2
+SIM_WARM_PRESSURE, SIM_WARM_ADJOINT = 1, 2
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
 SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL, SIM_GEOM_BEZIER = 0, 1, 2, 3, 4
@@ -29,7 +30,7 @@ EXPORTS = [
     "sim_step", "sim_step_replay", "sim_project", "sim_step_adjoint", "poisson_solve", "sim_set_geometry",
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
     "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
-    "sim_loss_box_noalloc", "sim_set_dt", "sim_max_speed",
+    "sim_loss_box_noalloc", "sim_set_dt", "sim_max_speed", "sim_set_warm_start",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -107,6 +108,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_set_solve_mode": (C.c_int32, [_vp, C.c_int32, C.c_int32]),
         "sim_set_regions": (C.c_int32, [_vp, C.c_int32]),
         "sim_set_dt": (C.c_int32, [_vp, C.c_double]),
+        "sim_set_warm_start": (C.c_int32, [_vp, C.c_int32]),
         "sim_max_speed": (C.c_int32, [_vp, _fp, C.POINTER(C.c_double), _vp]),
         "sim_loss_box_noalloc": (C.c_int32, [C.POINTER(C.c_int32), C.c_double, _fp, _dp, _dp, _vp, _fp, _vp]),
         "sim_regions": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),

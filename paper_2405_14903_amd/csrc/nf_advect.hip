@@ -394,6 +394,11 @@ size_t advect_stage_floats(const Dims& d) {
   return nb * 3 * kWin3;
 }
 
+__global__ void k_copy(const float* __restrict__ src, float* __restrict__ dst, long n) {
+  long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
 __global__ void k_fill(float* __restrict__ p, long n, float v) {
   long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -451,6 +456,10 @@ __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 void launch_max_abs(size_t n, const float* u, unsigned* out_bits, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, out_bits);
   if (n) hipLaunchKernelGGL(k_max_abs, dim3(nblocks(n)), dim3(kBlock), 0, s, (long)n, u, out_bits);
+}
+
+void launch_copy(const float* src, float* dst, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy, dim3(nblocks(n)), dim3(kBlock), 0, s, src, dst, (long)n);
 }
 
 void launch_fill(float* p, size_t n, float v, hipStream_t s) {

@@ -40,6 +40,11 @@ struct sim_ctx {
   GeomParams last_geom;
   bool have_geom = false;
   bool levels_current = false;   // the solver's hierarchy was built from the current fractions
+  // warm start (sim_set_warm_start): P and y hold the last step's pressure and
+  // the last adjoint pressure, the initial guesses of the next solves of their kind
+  int warm = 0;          // SIM_WARM_* bits
+  bool warm_p = false;   // h->P holds the previous step's pressure
+  bool warm_y = false;   // h->y holds the previous adjoint pressure
   unsigned* maxbits = nullptr;   // bits of the largest |u_f| (sim_max_speed)
   Profiler prof;
 };
@@ -444,10 +449,15 @@ static int32_t project_common(sim_handle h, const float* uhat, const GeomParams&
                               sim_stats* st, hipStream_t stream) {
   const double kk = k_factor(h->desc);
   NF_TIMED(&h->prof, SIM_K_RHS, stream, launch_rhs(h->dom, g, 1.0 / kk, h->alpha, uhat, h->b, stream));
-  float* P = p_out ? p_out : h->P;
-  launch_fill(P, h->dom.d.cells(), 0.0f, stream);
+  // warm start: the solve runs in h->P, which holds the previous solve's
+  // pressure, and the result is copied out
+  const bool warm = (h->warm & SIM_WARM_PRESSURE) != 0;
+  float* P = (p_out && !warm) ? p_out : h->P;
+  if (!(warm && h->warm_p)) launch_fill(P, h->dom.d.cells(), 0.0f, stream);
   const int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
   if (r < 0) return r;
+  h->warm_p = warm;
+  if (p_out && P != p_out) launch_copy(P, p_out, h->dom.d.cells(), stream);
   NF_TIMED(&h->prof, SIM_K_UPDATE, stream, launch_update(h->dom, g, kk, h->alpha, uhat, P, u_out, stream));
   const int e = last_hip_error();
   return e != SIM_OK ? e : r;
@@ -514,12 +524,15 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
     if (r < 0) return r;
     warn = r;
     P = h->P;
+    h->warm_p = false;   // h->P no longer holds the last step's pressure
   }
   // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T S g
   NF_TIMED(&h->prof, SIM_K_ADJ_DIV, stream, launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream));
-  launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
+  const bool warm_adj = (h->warm & SIM_WARM_ADJOINT) != 0;
+  if (!(warm_adj && h->warm_y)) launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
   int r = solver_solve(h->S, kSolveAdjoint, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
   if (r < 0) return r;
+  h->warm_y = warm_adj;
   warn = merge_status(warn, r);
   NF_TIMED(&h->prof, SIM_K_ADJ_FACES, stream,
            launch_adj_faces(h->dom, g, grad, kk, h->alpha, h->phi, g_u_n1, h->y, h->uhat, P ? P : h->y, h->gu,
@@ -618,6 +631,13 @@ int32_t sim_max_speed(sim_handle h, const float* u, double* vmax, hipStream_t st
   std::memcpy(&v, &bits, sizeof(v));
   *vmax = (double)v;
   return last_hip_error();
+}
+
+int32_t sim_set_warm_start(sim_handle h, int32_t kinds) {
+  if (!h || kinds < 0 || kinds > (SIM_WARM_PRESSURE | SIM_WARM_ADJOINT)) return SIM_EINVAL;
+  h->warm = kinds;
+  h->warm_p = h->warm_y = false;   // the next solve of each kind starts from zero
+  return SIM_OK;
 }
 
 int32_t sim_set_solve_mode(sim_handle h, int32_t mode, int32_t budget) {

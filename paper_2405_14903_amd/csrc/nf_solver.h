@@ -167,6 +167,7 @@ void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, cons
                           float* cax, float* cay, float* caz, hipStream_t s);
 // nf_advect.hip
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
+void launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
 void launch_viscosity(const Dims& d, double c, const float* in, float* out, hipStream_t s);
 void launch_max_abs(size_t n, const float* u, unsigned* out_bits, hipStream_t s);
 void launch_advect(const Dims& d, double dx, double dt, const double* grav, const float* u, float* out,

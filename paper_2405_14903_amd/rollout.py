@@ -38,9 +38,21 @@ class Rollout:
     """
 
     def __init__(self, sim: Sim, T: int, schedule, every=8, grad_geometry=False, timer=None, step_loss=None,
-                 store_pressure=True):
+                 store_pressure=True, warm_start=False):
         self.sim, self.T, self.schedule = sim, int(T), schedule
         self.store_pressure = store_pressure
+        # warm_start: False, "adjoint" (each adjoint solve starts from the
+        # previous adjoint pressure) or "all" (the forward solves too, from
+        # the previous step's pressure).  The handle forgets the held
+        # pressures at the start of each pass, so the passes are
+        # deterministic; with forward warm starts the recomputation must
+        # replay the stored pressures (re-solving would not retrace the
+        # first pass).
+        if warm_start not in (False, "adjoint", "all"):
+            raise ValueError(f"warm_start must be False, 'adjoint' or 'all', not {warm_start!r}")
+        if warm_start == "all" and not store_pressure:
+            raise ValueError("warm-started forward solves need the stored pressures (store_pressure=True)")
+        self.warm_start = warm_start
         self.K = checkpoint_stride(self.T, every)
         self.grad_geometry = grad_geometry
         self.timer = timer
@@ -56,11 +68,11 @@ class Rollout:
         self.step_loss = step_loss
 
     @staticmethod
-    def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None, store_pressure=True):
+    def ellipsoid(sim: Sim, theta0, ctrl, every=8, timer=None, store_pressure=True, warm_start=False):
         ctrl = np.asarray(ctrl, np.float64).reshape(-1, 6)
         poses = ellipsoid_poses(theta0, ctrl, sim.cfg.dt)
         ro = Rollout(sim, ctrl.shape[0], lambda n: (poses[n], ctrl[n]), every, grad_geometry=True, timer=timer,
-                     store_pressure=store_pressure)
+                     store_pressure=store_pressure, warm_start=warm_start)
         ro.theta0 = np.asarray(theta0, np.float64).ravel()
         ro.ctrl = ctrl
         return ro
@@ -117,6 +129,8 @@ class Rollout:
         self.J = torch.zeros(1, dtype=torch.float64, device=u0.device) if self.step_loss else None
         self.P = torch.empty((self.T, self.sim.nc), dtype=getattr(self.sim, "pressure_dtype", torch.float32),
                              device=u0.device) if self.store_pressure else None
+        if self.warm_start:
+            self.sim.set_warm_start(pressure=self.warm_start == "all")
         for n in range(self.T):
             self._step(n, a, b, self.P[n] if self.P is not None else None)
             a, b = b, a
@@ -126,6 +140,8 @@ class Rollout:
                 self.ckpt[n + 1] = a.clone()
             self.uT = a
             yield "fwd"
+        if self.warm_start:
+            self.sim.set_warm_start()
         self.uT = a
 
     def backward(self, gT: torch.Tensor):
@@ -147,6 +163,8 @@ class Rollout:
         states = [torch.empty_like(g) for _ in range(K + 1)]
         stored = getattr(self, "P", None) is not None
         press = None if stored else [torch.empty(sim.nc, dtype=torch.float32, device=dev) for _ in range(K)]
+        if self.warm_start:
+            sim.set_warm_start(adjoint=True)
         for s in reversed(seg_starts):
             e = min(s + K, T)
             states[0].copy_(self.ckpt[s])
@@ -180,6 +198,8 @@ class Rollout:
                 g, gprev = gprev, g
                 self.g0 = g
                 yield "adj"
+        if self.warm_start:
+            sim.set_warm_start()
         self.g0 = g
 
     def geometry_gradients(self):

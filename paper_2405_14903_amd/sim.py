@@ -169,6 +169,14 @@ class Sim:
                 "sim_max_speed")
         return v.value
 
+    def set_warm_start(self, pressure: bool = False, adjoint: bool = False):
+        """Start each pressure solve from the previous step's pressure and / or
+        each adjoint solve from the previous adjoint pressure (same tolerance;
+        the held pressures are forgotten by every call, so the next solves
+        start from zero)."""
+        kinds = (L.SIM_WARM_PRESSURE if pressure else 0) | (L.SIM_WARM_ADJOINT if adjoint else 0)
+        L.check(self.lib.sim_set_warm_start(self.h, kinds), "sim_set_warm_start")
+
     def set_solve_mode(self, mode: str = "host", budget: int = 0):
         """"host": solves wait on the stream for convergence checks (default);
         "device": nothing waits on the host, each solve runs at most

@@ -64,17 +64,26 @@ def test_step_128_at_bench_tolerance_vs_oracle(step128, precision):
     assert st["converged"] and e <= 1e-5, (e, st)
 
 
-@pytest.mark.timeout(900)
-def test_rollout_gradients_32_at_configuration_length():
-    """64 steps with a checkpoint every 8 on the 32^3 copy (FP32)."""
-    from paper_2405_14903_amd.rollout import EllipsoidRolloutFn
-    T, every = 64, 8
-    announce(f"ellipsoid rollout gradients 32^3 x {T}, checkpoints every {every}")
+@pytest.fixture(scope="module")
+def rollout32():
+    """The oracle's 64-step rollout of the benchmark scene's 32^3 copy and its gradients."""
+    T = 64
+    announce(f"oracle: ellipsoid rollout 32^3 x {T} and its adjoint (FP64)")
     sc = scenes.scene_ellipsoid_rollout(seed=0, n=32, steps=T)
     g = Grid(sc.n, sc.dx)
     ro_o = EllipsoidRollout(StepParams(g, sc.dt, tol=1e-11), sc.u0, sc.theta0, sc.ctrl)
     J_o, gT = octant_loss(g, ro_o.forward())
     _, gth_o, gct_o = ro_o.backward(gT)
+    return sc, g, J_o, gth_o, gct_o
+
+
+@pytest.mark.timeout(900)
+def test_rollout_gradients_32_at_configuration_length(rollout32):
+    """64 steps with a checkpoint every 8 on the 32^3 copy (FP32)."""
+    from paper_2405_14903_amd.rollout import EllipsoidRolloutFn
+    T, every = 64, 8
+    announce(f"ellipsoid rollout gradients 32^3 x {T}, checkpoints every {every}")
+    sc, g, J_o, gth_o, gct_o = rollout32
     m = torch.tensor(octant_mask(g), device="cuda")
 
     with Sim(ellipsoid_cfg(sc.n, tol=1e-7)) as sim:
@@ -105,6 +114,37 @@ def test_rollout_gradients_32_at_configuration_length():
     # central differences straddle the kinks of the trilinear interpolation and
     # of the marching-squares cases: a few percent, as for the oracle itself
     assert e_fd <= 5e-2, (gth[comps], fd)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_bench_rollout_path_32_against_oracle(rollout32, precision):
+    """The rollout exactly as the benchmark drives it (bench tolerance, stored
+    pressures replayed, adjoint solves warm-started from the previous adjoint
+    pressure) on the 32^3 copy: loss and shape / control gradients against
+    the oracle, and against the same rollout with every solve started from
+    zero."""
+    from paper_2405_14903_amd.rollout import Rollout
+    sc, g, J_o, gth_o, gct_o = rollout32
+    announce(f"benchmark rollout path 32^3 x 64, {precision}, warm-started adjoint solves, against the oracle")
+    out = {}
+    with Sim(ellipsoid_cfg(sc.n, tol=BENCH_TOL, precision=precision)) as sim:
+        u0 = dev(sc.u0)
+        for warm in ("adjoint", False):
+            ro = Rollout.ellipsoid(sim, sc.theta0, sc.ctrl, every=8, warm_start=warm)
+            J, gT = sim.loss_box(ro.forward(u0))
+            ro.backward(gT)
+            gth, gct = ro.geometry_gradients()
+            out[warm] = (float(J.item()), gth, gct, list(ro.iters["adj"]))
+    J, gth, gct, it = out["adjoint"]
+    e_th, e_ct = rel_l2(gth, gth_o), rel_l2(gct, gct_o)
+    d_th, d_ct = rel_l2(gth, out[False][1]), rel_l2(gct, out[False][2])
+    announce(f"  J {J:.6f} vs {J_o:.6f}; theta rel {e_th:.2e}, ctrl rel {e_ct:.2e} against the oracle; "
+             f"{d_th:.1e} / {d_ct:.1e} against zero-started solves; adjoint iterations "
+             f"{np.mean(it):.2f} warm, {np.mean(out[False][3]):.2f} from zero")
+    assert abs(J - J_o) <= 1e-4 * abs(J_o)
+    assert e_th <= 1e-3 and e_ct <= 1e-3, (e_th, e_ct)
+    assert d_th <= 1e-4 and d_ct <= 1e-4, (d_th, d_ct)
 
 
 @pytest.fixture(scope="module")

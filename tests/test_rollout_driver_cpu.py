@@ -25,6 +25,11 @@ class OracleHandle:
         self.steps_done = 0
         self.replays = 0
         self.pressure_dtype = torch.float64
+        self.warm_calls = []
+
+    def set_warm_start(self, pressure=False, adjoint=False):
+        # the oracle solves exactly, so warm starts change nothing but the record
+        self.warm_calls.append((pressure, adjoint))
 
     def _geo(self, th, ct):
         g = self.prm.grid
@@ -145,3 +150,23 @@ def test_frame_rollout_substeps_and_gradient():
     for st in reversed(us):
         gref = st.vjp(gref)[0]
     np.testing.assert_allclose(gu.numpy(), gref, rtol=1e-9, atol=1e-12 * np.abs(gref).max())
+
+
+@pytest.mark.parametrize("warm", ["adjoint", "all"])
+def test_warm_start_passes_reset_and_restore_the_handle(warm):
+    """Each pass turns the handle's warm starts on (which also forgets the held
+    pressures, so every pass starts its chain from zero) and off at its end;
+    forward warm starts refuse a rollout that would re-solve its segments."""
+    sc = scenes.scene_sphere_rollout(seed=0, n=8, steps=3)
+    g = Grid(sc.n, sc.dx)
+    prm = StepParams(g, sc.dt, tol=1e-12)
+    h = OracleHandle(prm, "spheres", sc.spheres)
+    ro = R.Rollout(h, 3, lambda n: (sc.spheres.ravel(), None), every=2, warm_start=warm)
+    ro.forward(torch.from_numpy(sc.u0.copy()))
+    assert h.warm_calls == [(warm == "all", False), (False, False)]
+    ro.backward(torch.zeros(g.nfaces, dtype=torch.float64))
+    assert h.warm_calls[2:] == [(False, True), (False, False)]
+    with pytest.raises(ValueError):
+        R.Rollout(h, 3, lambda n: (sc.spheres.ravel(), None), warm_start="all", store_pressure=False)
+    with pytest.raises(ValueError):
+        R.Rollout(h, 3, lambda n: (sc.spheres.ravel(), None), warm_start=True)
