@@ -453,8 +453,8 @@ static int32_t project_common(sim_handle h, const float* uhat, const GeomParams&
   // pressure, and the result is copied out
   const bool warm = (h->warm & SIM_WARM_PRESSURE) != 0;
   float* P = (p_out && !warm) ? p_out : h->P;
-  if (!(warm && h->warm_p)) launch_fill(P, h->dom.d.cells(), 0.0f, stream);
-  const int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream);
+  const int r = solver_solve(h->S, kSolvePressure, h->b, P, h->desc.tol, h->desc.max_iter, st, stream,
+                             !(warm && h->warm_p));
   if (r < 0) return r;
   h->warm_p = warm;
   if (p_out && P != p_out) launch_copy(P, p_out, h->dom.d.cells(), stream);
@@ -519,8 +519,7 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   if (!P && grad) {
     // no stored pressure: solve the forward system again
     launch_rhs(h->dom, g, 1.0 / kk, h->alpha, h->uhat, h->b, stream);
-    launch_fill(h->P, h->dom.d.cells(), 0.0f, stream);
-    int r = solver_solve(h->S, kSolvePressure, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream);
+    int r = solver_solve(h->S, kSolvePressure, h->b, h->P, h->desc.tol, h->desc.max_iter, nullptr, stream, true);
     if (r < 0) return r;
     warn = r;
     P = h->P;
@@ -529,8 +528,8 @@ int32_t sim_step_adjoint(sim_handle h, const float* u_n, const float* p_n1, cons
   // dJ/dP and the adjoint pressure system (G^T S G) y = -G^T S g
   NF_TIMED(&h->prof, SIM_K_ADJ_DIV, stream, launch_adj_div(h->dom.d, h->alpha, g_u_n1, h->b, stream));
   const bool warm_adj = (h->warm & SIM_WARM_ADJOINT) != 0;
-  if (!(warm_adj && h->warm_y)) launch_fill(h->y, h->dom.d.cells(), 0.0f, stream);
-  int r = solver_solve(h->S, kSolveAdjoint, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream);
+  int r = solver_solve(h->S, kSolveAdjoint, h->b, h->y, h->desc.tol, h->desc.max_iter, st, stream,
+                       !(warm_adj && h->warm_y));
   if (r < 0) return r;
   h->warm_y = warm_adj;
   warn = merge_status(warn, r);

@@ -196,8 +196,10 @@ void launch_loss_box(const Domain& D, const double* lo, const double* hi, const 
 // nf_solver.hip
 void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st);
 enum SolveKind { kSolvePressure = 0, kSolveAdjoint = 1, kSolveUser = 2 };
+// zero_guess: the solve starts from x = 0 whatever x holds on entry (x is
+// then output only).
 int solver_solve(Solver& S, SolveKind kind, const float* b, float* x, double tol, int maxit, sim_stats* stats,
-                 hipStream_t st);
+                 hipStream_t st, bool zero_guess = false);
 void solver_init_device(Solver& S);
 // nf_components.hip
 void components_label(Solver& S, hipStream_t st);

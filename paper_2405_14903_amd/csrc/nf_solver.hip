@@ -35,6 +35,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cstdio>
 
 namespace nf {
@@ -154,6 +155,27 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
     v[1] = rc * rc;
     v[2] = rc;
     v[3] = act ? 1.0 : 0.0;
+  }
+  block_partials<4>(v, partials);
+}
+
+// The same for a zero initial guess: r = b on active cells (1/diag > 0) and
+// x = 0, without the stencil; a bounded grid-stride grid keeps the partials
+// few (k_fin_init totals them in one block).
+constexpr int kInitBlocks = 1024;
+__global__ __launch_bounds__(kBlock) void k_cg_init_zero(long n, const float* __restrict__ invd,
+                                                          const float* __restrict__ b, double* __restrict__ x,
+                                                          float* __restrict__ r, double* partials) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
+    const bool act = invd[c] > 0.0f;
+    const double bc = act ? (double)b[c] : 0.0;
+    x[c] = 0.0;
+    r[c] = (float)bc;
+    v[0] += bc * bc;
+    v[1] += bc * bc;
+    v[2] += bc;
+    v[3] += act ? 1.0 : 0.0;
   }
   block_partials<4>(v, partials);
 }
@@ -2012,6 +2034,9 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
       ly = cy;
       lz = cz;
     }
+    // the fused V-cycle reads level 0's coefficients from the packed records
+    // (below): its 2-byte arrays would go unread
+    if (l == 0 && S.fused && S.rec0) continue;
     launch_invdiag(d, lx, ly, lz, S.scratch_inv, st);
     if (S.precision == SIM_MIXED_FP16)
       cast_level<__half>(d, lx, ly, lz, S.scratch_inv, S.lev[l], cap, st);
@@ -2170,18 +2195,39 @@ static void solve_on_device(Solver& S, const float* b, double* x, int budget, hi
   }
 }
 
+// The finest level's 1/diag in FP32 (0 on inactive cells), or NULL where the
+// level keeps it only in 2-byte storage.
+static const float* fine_invd32(const Solver& S) {
+  if (S.precision == SIM_FP32) return (const float*)S.lev[0].invd;
+  if (S.rec0) return (const float*)((const Rec16*)S.rec0 + S.lev[0].d.cells());
+  return nullptr;
+}
+
 int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double tol, int maxit, sim_stats* stats,
-                 hipStream_t st) {
+                 hipStream_t st, bool zero_guess) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
   CGScalars* sc = S.sc;
   double* x = S.x;
   if (S.device_mode && S.budget > 0 && S.budget < maxit) maxit = S.budget;
-  hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
-  NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
-                              S.partials);
-  hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
-                     S.project);
+  const float* invd32 = zero_guess ? fine_invd32(S) : nullptr;
+  if (zero_guess && !invd32) {
+    // no FP32 1/diag to find the active cells by: start from an explicit zero
+    launch_fill(xio, (size_t)n, 0.0f, st);
+    zero_guess = false;
+  }
+  if (zero_guess) {
+    const int nb = (int)std::min<size_t>(nblocks(n), kInitBlocks);
+    NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init_zero, dim3(nb), dim3(kBlock), 0, st, n, invd32, b, x, S.r,
+              S.partials);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, sc, tol, maxit, n, S.project);
+  } else {
+    hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
+    NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x,
+              S.r, S.partials);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
+                       S.project);
+  }
   if (S.comp.valid)
     components_project_start(S, st);
   else if (S.project)
@@ -2237,7 +2283,7 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     const CGScalars& h = *S.host_sc;
     if (!h.converged && !h.nonfinite && !S.comp.valid && S.comp.mode == SIM_REGIONS_AUTO) {
       components_label(S, st);
-      return solver_solve(S, kind, b, xio, tol, maxit, stats, st);
+      return solver_solve(S, kind, b, xio, tol, maxit, stats, st, zero_guess);
     }
   }
   S.last_iters[kind] = S.host_sc->iters;
