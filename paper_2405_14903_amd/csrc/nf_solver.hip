@@ -372,16 +372,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_true_residual(Dims d, const float
                                                               int allow, const CGScalars* sc, double* partials) {
   if (!sc->done || sc->final_) return;
   const bool rep = may_replace(sc, allow);
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[3] = {0.0, 0.0, 0.0};
-  if (c < (long)d.cells()) {
+  // a bounded grid-stride grid (k_fin_true totals the partials in one block)
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < (long)d.cells(); c += (long)gridDim.x * blockDim.x) {
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<float> fw(d, ax, ay, az, i, j, k);
     double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
-    v[0] = rc * rc;
-    v[1] = rc;
-    v[2] = fw.diag() > 0.0f ? 1.0 : 0.0;
+    v[0] += rc * rc;
+    v[1] += rc;
+    v[2] += fw.diag() > 0.0f ? 1.0 : 0.0;
     if (rep) r[c] = (float)rc;
   }
   block_partials<3>(v, partials);
@@ -454,6 +454,22 @@ __global__ __launch_bounds__(kBlock) void k_sub_mean(Dims d, const float* __rest
   cdec(d, c, i, j, k);
   Faces<float> fw(d, ax, ay, az, i, j, k);
   if (fw.diag() > 0.0f) r[c] = (float)((double)r[c] - mu);
+}
+
+// k_sub_mean and k_x_store telling active cells by an FP32 1/diag (> 0)
+// instead of their six face fractions.
+__global__ __launch_bounds__(kBlock) void k_sub_mean_inv(long n, const float* __restrict__ invd,
+                                                          float* __restrict__ r, const CGScalars* sc) {
+  if (sc->done) return;
+  const double mu = sc->mu;
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && invd[c] > 0.0f) r[c] = (float)((double)r[c] - mu);
+}
+
+__global__ void k_x_store_inv(long n, const float* __restrict__ invd, const double* __restrict__ x,
+                              float* __restrict__ xout) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) xout[c] = invd[c] > 0.0f ? (float)x[c] : 0.0f;
 }
 
 // rho = r . z and the flexible (Polak-Ribiere) direction coefficient
@@ -2164,6 +2180,34 @@ static int snapshot(Solver& S, hipStream_t st) {
 // Solves that never wait on the host: a fixed budget of iterations with a
 // true-residual check (and a conditional restart) behind every chunk; every
 // kernel enqueued after convergence exits at once on the device.
+// The finest level's 1/diag in FP32 (0 on inactive cells), or NULL where the
+// level keeps it only in 2-byte storage.
+static const float* fine_invd32(const Solver& S) {
+  if (S.precision == SIM_FP32) return (const float*)S.lev[0].invd;
+  if (S.rec0) return (const float*)((const Rec16*)S.rec0 + S.lev[0].d.cells());
+  return nullptr;
+}
+
+// r -= its mean over the active cells (closed domains without region labels).
+static void sub_mean(Solver& S, hipStream_t st) {
+  const Dims& d = S.lev[0].d;
+  const long n = (long)d.cells();
+  if (const float* id = fine_invd32(S))
+    hipLaunchKernelGGL(k_sub_mean_inv, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, S.r, S.sc);
+  else
+    hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, S.sc);
+}
+
+// The solve's output: the iterate on active cells, 0 elsewhere.
+static void x_store(Solver& S, const double* x, float* xout, hipStream_t st) {
+  const Dims& d = S.lev[0].d;
+  const long n = (long)d.cells();
+  if (const float* id = fine_invd32(S))
+    hipLaunchKernelGGL(k_x_store_inv, dim3(nblocks(n)), dim3(kBlock), 0, st, n, id, x, xout);
+  else
+    hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xout);
+}
+
 static void solve_on_device(Solver& S, const float* b, double* x, int budget, hipStream_t st) {
   const Dims& d = S.lev[0].d;
   const long n = (long)d.cells();
@@ -2180,27 +2224,19 @@ static void solve_on_device(Solver& S, const float* b, double* x, int budget, hi
       enqueue_iterations(S, x, c, st);
       left -= c;
     }
-    hipLaunchKernelGGL(k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r, 1,
-                       S.sc, S.partials);
-    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, S.sc, 1, n,
-                       S.project);
+    const int nbt = (int)std::min<size_t>(nblocks(n), kInitBlocks);
+    hipLaunchKernelGGL(k_cg_true_residual, dim3(nbt), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r, 1, S.sc,
+                       S.partials);
+    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, nbt, S.partials, S.sc, 1, n, S.project);
     if (left <= 0) break;
     hipLaunchKernelGGL(k_hold_restart, dim3(1), dim3(1), 0, st, S.sc);
     if (S.comp.valid)
       components_subtract(S, st);
     else if (S.project)
-      hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, S.sc);
+      sub_mean(S, st);
     precondition(S, st);
     hipLaunchKernelGGL(k_release_restart, dim3(1), dim3(1), 0, st, S.sc);
   }
-}
-
-// The finest level's 1/diag in FP32 (0 on inactive cells), or NULL where the
-// level keeps it only in 2-byte storage.
-static const float* fine_invd32(const Solver& S) {
-  if (S.precision == SIM_FP32) return (const float*)S.lev[0].invd;
-  if (S.rec0) return (const float*)((const Rec16*)S.rec0 + S.lev[0].d.cells());
-  return nullptr;
 }
 
 int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double tol, int maxit, sim_stats* stats,
@@ -2231,12 +2267,12 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
   if (S.comp.valid)
     components_project_start(S, st);
   else if (S.project)
-    hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
+    sub_mean(S, st);
   precondition(S, st);
   S.pcur = 0;
   if (S.device_mode) {
     solve_on_device(S, b, x, maxit, st);
-    hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
+    x_store(S, x, xio, st);
     if (stats) hipLaunchKernelGGL(k_write_stats, dim3(1), dim3(1), 0, st, sc, stats);
     return SIM_OK;
   }
@@ -2252,10 +2288,10 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
   for (;;) {
     const int allow = restarts < kMaxRestarts ? 1 : 0;
     (void)cg_iterations(S, x, batch, st);
-    NF_LAUNCH(S.prof, SIM_K_CG_TRUE, k_cg_true_residual, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay,
-              S.az, b, x, S.r, allow, sc, S.partials);
-    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, allow, n,
-                       S.project);
+    const int nbt = (int)std::min<size_t>(nblocks(n), kInitBlocks);
+    NF_LAUNCH(S.prof, SIM_K_CG_TRUE, k_cg_true_residual, dim3(nbt), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x,
+              S.r, allow, sc, S.partials);
+    hipLaunchKernelGGL(k_fin_true, dim3(1), dim3(kFinBlock), 0, st, nbt, S.partials, sc, allow, n, S.project);
     int r = snapshot(S, st);
     if (r != SIM_OK) return r;
     batch = chunk;
@@ -2271,7 +2307,7 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     if (S.comp.valid)
       components_subtract(S, st);
     else if (S.project)
-      hipLaunchKernelGGL(k_sub_mean, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, S.r, sc);
+      sub_mean(S, st);
     precondition(S, st);
   }
   {
@@ -2287,7 +2323,7 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     }
   }
   S.last_iters[kind] = S.host_sc->iters;
-  hipLaunchKernelGGL(k_x_store, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, x, xio);
+  x_store(S, x, xio, st);
   const CGScalars& h = *S.host_sc;
   if (stats) {
     stats->iters = h.iters;
