@@ -146,6 +146,66 @@ def test_solid_fractions_sampled_128():
     np.testing.assert_allclose(ag[faces], a_o, atol=1e-7, rtol=0)
 
 
+def test_eight_solids_with_one_outside_the_domain_32():
+    """The largest scene (SIM_MAX_SOLIDS = 8, mixed unions and intersections),
+    one solid wholly outside the box: fractions and dJ/dtheta against the
+    oracle, and no gradient for the solid that touches no face."""
+    announce("eight parametric solids, one outside the box, 32^3: fractions and step adjoint")
+    rng = np.random.default_rng(12)
+    n = 32
+    solids = [scenes.random_solid(rng, lo=0.25, hi=0.75) for _ in range(8)]
+    solids[5][:3] = [5.0, 5.0, 5.0]
+    ops = [0, 0, 0, 1, 0, 0, 0, 0]
+    th = scenes.solids_theta(solids, ops)
+    u0 = scenes.curl_noise((n, n, n), 1.0 / n, rng)
+    g = Grid((n, n, n), 1.0 / n)
+    geo = B.BezierGeometry(g, th)
+    st_o = Step(StepParams(g, 0.5 / n, tol=1e-12), u0, geo.alpha, geo.us)
+    gbar = rng.standard_normal(g.nfaces)
+    _, galpha, _ = st_o.vjp(gbar)
+    gth_o = geo.vjp(galpha)
+    cfg = Config(n=(n, n, n), dx=1.0 / n, dt=0.5 / n, geom="bezier", n_solids=8, tol=1e-7)
+    with Sim(cfg) as sim:
+        out = torch.empty(g.nfaces, dtype=torch.float32, device="cuda")
+        sim.set_geometry(th, None, alpha_out=out)
+        P = torch.empty(g.ncells, dtype=torch.float32, device="cuda")
+        ud = dev(u0)
+        u1, _ = sim.step(ud, th, p_out=P)
+        gth = torch.zeros(len(th), dtype=torch.float64, device="cuda")
+        sim.step_adjoint(ud, dev(gbar), th, p_n1=P, g_theta=gth)
+        torch.cuda.synchronize()
+    ag, gt = host(out), host(gth)
+    assert np.array_equal(ag > 0, geo.alpha > 0)
+    np.testing.assert_allclose(ag, geo.alpha, atol=1e-7, rtol=0)
+    ef, e_th = rel_l2(host(u1), st_o.result), rel_l2(gt, gth_o)
+    out5 = slice(1 + 8 + 5 * B.SHAPE_PARAMS, 1 + 8 + 6 * B.SHAPE_PARAMS)
+    announce(f"  forward rel-L2 {ef:.2e}, dJ/dtheta rel-L2 {e_th:.2e}; outside solid |grad| {np.abs(gt[out5]).max()}")
+    assert ef <= 1e-5 and e_th <= 1e-3, (ef, e_th)
+    assert np.all(gt[out5] == 0.0) and np.all(gth_o[out5] == 0.0)
+
+
+def test_empty_intersection_is_the_open_box():
+    """Two disjoint solids intersected: no solid at all, so the fractions and
+    the step are those of the empty box."""
+    announce("empty CSG intersection: fractions and step equal the empty box's")
+    sc = scenes.scene_solids(seed=4, n=16, count=2, ops=(0, 1))
+    th = sc.extra["theta"].copy()
+    th[3:6] = [0.25, 0.25, 0.25]
+    th[3 + B.SHAPE_PARAMS:6 + B.SHAPE_PARAMS] = [0.75, 0.75, 0.75]
+    g = Grid(sc.n, sc.dx)
+    geo = B.BezierGeometry(g, th)
+    assert np.all(geo.phi_nodes > 0)
+    with Sim(_cfg(sc, 2)) as sim, Sim(Config(n=sc.n, dx=sc.dx, dt=sc.dt, tol=1e-7)) as empty:
+        out = torch.empty(g.nfaces, dtype=torch.float32, device="cuda")
+        sim.set_geometry(th, None, alpha_out=out)
+        u = dev(sc.u0)
+        a, _ = sim.step(u, th)
+        b, _ = empty.step(u)
+        torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(out), geo.alpha)
+    assert rel_l2(host(a), host(b)) <= 1e-6
+
+
 def test_invalid_scene_vectors_are_rejected():
     announce("parametric-solid scene validation")
     sc = scenes.scene_solids(seed=3, n=16, count=2)
