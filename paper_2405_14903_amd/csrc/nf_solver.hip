@@ -1365,6 +1365,8 @@ struct Bottom {
   const A* invd[kMaxLevels];
   int off[kMaxLevels];    // LDS offset (floats) of level l's three vectors r, z, t
   int coff[kMaxLevels];   // LDS offset of the level's staged fractions and 1/diag (FP32), -1: read from memory
+  int cg;                 // > 0: the coarsest level is solved by at most cg Jacobi-preconditioned CG iterations
+  int red_off;            // with cg: LDS offset (floats, even) of one double per wave for its workgroup totals
 };
 
 // Coefficients of one level, from LDS (P = float) or from memory (P = storage type).
@@ -1513,6 +1515,72 @@ __device__ inline void bottom_coarsest(const Dims& d, const Coef<P>& K, const fl
   }
 }
 
+// Sum of v over the workgroup in a fixed order, returned to every thread
+// (red: one double per wave; two barriers, so red can be reused at once).
+__device__ inline double block_allsum(double v, double* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  v = wave_sum(v);
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int q = 0; q < nw; ++q) s += red[q];
+  __syncthreads();
+  return s;
+}
+
+// Coarsest level of a grid whose thinnest extent stopped the coarsening
+// early (e.g. 2 x 32 x 64 under a 32 x 512 x 1024 slab): its smooth modes
+// span tens of cells, which Jacobi sweeps barely reach, so it gets a
+// Jacobi-preconditioned CG from z = 0 instead, for at most `maxit`
+// iterations or until r . D^-1 r falls by 1e-8.  Only for grounded systems
+// (an OUTFLOW side), whose coarse operator is definite.  r is overwritten
+// (it is the residual); t holds the direction.  The outer CG is the flexible
+// form, so a preconditioner that depends on its input this way is allowed.
+// Every branch depends on workgroup totals only, so all threads take it.
+template <typename P>
+__device__ inline void bottom_coarsest_cg(const Dims& d, const Coef<P>& K, float* r, float* z, float* p, int maxit,
+                                          double* red) {
+  const int n = (int)d.cells(), T = blockDim.x;
+  double part = 0.0;
+  for (int c = threadIdx.x; c < n; c += T) {
+    const float sc = ld(K.invd, c) * r[c];
+    z[c] = 0.0f;
+    p[c] = sc;
+    part += (double)r[c] * (double)sc;
+  }
+  double rho = block_allsum(part, red);
+  const double stop = 1e-8 * rho;
+  for (int it = 0; it < maxit && rho > stop; ++it) {
+    part = 0.0;
+    for (int c = threadIdx.x; c < n; c += T) {
+      int i, j, k;
+      cdec(d, c, i, j, k);
+      Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+      const float Ap = apply_A(d, fw, i, j, k, c, p[c], [&](long q) { return p[q]; });
+      part += (double)p[c] * (double)Ap;
+    }
+    const double pAp = block_allsum(part, red);
+    if (!(pAp > 0.0)) break;
+    const float alpha = (float)(rho / pAp);
+    part = 0.0;
+    for (int c = threadIdx.x; c < n; c += T) {
+      int i, j, k;
+      cdec(d, c, i, j, k);
+      Faces<P> fw(d, K.ax, K.ay, K.az, i, j, k);
+      const float Ap = apply_A(d, fw, i, j, k, c, p[c], [&](long q) { return p[q]; });
+      z[c] += alpha * p[c];
+      const float rc = r[c] - alpha * Ap;
+      r[c] = rc;
+      part += (double)rc * (double)(ld(K.invd, c) * rc);
+    }
+    const double rho_new = block_allsum(part, red);
+    const float beta = (float)(rho_new / rho);
+    rho = rho_new;
+    for (int c = threadIdx.x; c < n; c += T) p[c] = ld(K.invd, c) * r[c] + beta * p[c];
+    __syncthreads();
+  }
+}
+
 // z' = z + 8 e(parent); t = z' + w D^-1 (r - A z'); z = t + w D^-1 (r - A t).
 template <typename P>
 __device__ inline void bottom_up(const Dims& d, const Dims& cd, const Coef<P>& K, const float* r, float* z, float* t,
@@ -1580,7 +1648,16 @@ __global__ __launch_bounds__(1024) void k_mg_bottom(Bottom<A> B, const R* __rest
     else
       bottom_down(B.d[l], B.d[l + 1], global(l), R_(l), Z_(l), T_(l), R_(l + 1));
   }
-  if (B.coff[L - 1] >= 0)
+  if (B.cg > 0) {
+    // the totals' slots live in the dynamic LDS (the kernel has no static LDS:
+    // its dynamic limit is set to the device's whole per-workgroup LDS)
+    double* red = (double*)(lds + B.red_off);
+    if (B.coff[L - 1] >= 0)
+      bottom_coarsest_cg(B.d[L - 1], staged(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1), B.cg, red);
+    else
+      bottom_coarsest_cg(B.d[L - 1], global(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1), B.cg, red);
+    __syncthreads();
+  } else if (B.coff[L - 1] >= 0)
     bottom_coarsest(B.d[L - 1], staged(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1));
   else
     bottom_coarsest(B.d[L - 1], global(L - 1), R_(L - 1), Z_(L - 1), T_(L - 1));
@@ -1814,6 +1891,14 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
   const long n0 = (long)S.lev[0].d.cells();
   Bottom<T> B;
   B.nl = L - G;
+  {
+    // grounded systems whose coarsest level stayed large: CG there (at most
+    // twice its largest extent in iterations)
+    const Dims& dc = S.lev[L - 1].d;
+    const int ext = std::max(dc.nx, std::max(dc.ny, dc.nz));
+    B.cg = (!S.project && dc.cells() > (size_t)kBottomCells) ? std::min(2 * ext, 256) : 0;
+  }
+  B.red_off = 0;
   int off = 0;
   for (int q = 0; q < B.nl; ++q) {
     const int l = G + q;
@@ -1827,6 +1912,10 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
     off += 3 * (int)S.lev[l].d.cells();
   }
   const size_t lds_lanes = (size_t)off * sizeof(float);
+  if (B.cg > 0) {
+    B.red_off = (off + 1) & ~1;                 // 8-byte aligned (the dynamic LDS base is)
+    off = B.red_off + 2 * (1024 / 64);          // one double per wave of the largest workgroup
+  }
   // stage coefficients in LDS from the coarsest level up, while they fit
   for (int q = B.nl - 1; q >= 0; --q) {
     const Dims& d = S.lev[G + q].d;
@@ -2150,7 +2239,10 @@ void solver_init_device(Solver& S) {
                         (const void*)k_mg_bottom<__half, __half, __half>,
                         (const void*)k_mg_bottom<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16>};
   for (const void* f : fns)
-    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) return;
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, v) != hipSuccess) {
+      (void)hipGetLastError();   // keep the default limit and leave no error behind
+      return;
+    }
   S.lds_bytes = (size_t)v;
 }
 
