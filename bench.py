@@ -576,26 +576,34 @@ def serving_leg(torch, n_req, rates, precision, seed=0):
     forward-only and half forward + adjoint), served with continuous batching
     and the mixed-precision form within an HBM budget, against the same
     requests run one at a time in plain FP32 on the same arrival schedule."""
-    from paper_2405_14903_amd.serving import make_stream, serve, serve_serial
+    from paper_2405_14903_amd.serving import make_stream, serve, serve_pool, serve_serial
     budget = 200 << 30
     sizes = (32, 48, 64, 96, 128, 192)
     out = {"workload": f"{n_req} requests per rate, Poisson arrivals, grids {{32..192}}^3, 8-64 steps, 10% pressure "
                        f"projections, the rest half forward-only and half forward + adjoint; continuous batching "
                        f"(8 episodes, {budget >> 30} GiB budget) with the {precision} V-cycle and device-mode "
-                       f"solves, against serial plain FP32 on the same schedule",
+                       f"solves, by the Python scheduler (served) and by the library's native pool (native_pool), "
+                       f"against serial plain FP32 on the same schedule",
            "rates": {}}
     for rate in rates:
         served = serve(make_stream(n_req, rate, seed=seed), budget_bytes=budget, precision=precision, max_active=8,
                        realtime=True, warm_sizes=sizes)
+        native = serve_pool(make_stream(n_req, rate, seed=seed), budget_bytes=budget, precision=precision,
+                            max_active=8, realtime=True, warm_sizes=sizes)
         serial = serve_serial(make_stream(n_req, rate, seed=seed), precision="fp32", warm_sizes=sizes)
-        print(f"[bench] serving at {rate:g} req/s: served {served['cell_steps_per_s'] / 1e6:.1f} M, serial "
-              f"{serial['cell_steps_per_s'] / 1e6:.1f} M cell-steps/s", file=sys.stderr, flush=True)
+        print(f"[bench] serving at {rate:g} req/s: served {served['cell_steps_per_s'] / 1e6:.1f} M, native pool "
+              f"{native['cell_steps_per_s'] / 1e6:.1f} M, serial {serial['cell_steps_per_s'] / 1e6:.1f} M "
+              f"cell-steps/s", file=sys.stderr, flush=True)
         keep = ("completed", "failed", "rejected", "rerun_host_checked", "wall_s", "cell_steps_per_s", "step_ms_p50", "step_ms_p99",
                 "request_s_p50", "request_s_p99")
         out["rates"][f"{rate:g}"] = {
             "served": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in served.items() if k in keep},
+            "native_pool": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in native.items()
+                            if k in keep and not k.startswith("step_ms")},
             "serial_fp32": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in serial.items() if k in keep},
             "throughput_over_serial": round(served["cell_steps_per_s"] / serial["cell_steps_per_s"], 3)
+            if serial["cell_steps_per_s"] else None,
+            "native_pool_over_serial": round(native["cell_steps_per_s"] / serial["cell_steps_per_s"], 3)
             if serial["cell_steps_per_s"] else None,
             "step_p99_over_serial": round(served["step_ms_p99"] / serial["step_ms_p99"], 3)
             if served["step_ms_p99"] and serial["step_ms_p99"] else None}

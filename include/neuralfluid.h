@@ -74,6 +74,7 @@ typedef enum {
   SIM_ENOMEM = -2,        /* device allocation failed in sim_create       */
   SIM_EHIP = -3,          /* a HIP runtime call failed                    */
   SIM_EUNSUPPORTED = -4,  /* valid request this library does not implement */
+  SIM_EBUSY = -5,         /* a pool has no free slot or budget for it now  */
   SIM_WNOCONV = 1,        /* ran; a Poisson solve stopped short of the tolerance */
   SIM_WNONFINITE = 2      /* ran; a Poisson solve met a NaN / Inf            */
 } sim_status;
@@ -394,6 +395,89 @@ int32_t sim_ellipsoid_poses(const double* theta0, const double* ctrl, int32_t T,
 int32_t sim_ellipsoid_poses_adjoint(const double* theta0, const double* ctrl, int32_t T, double dt,
                                     const double* g_theta_steps, const double* g_ctrl_direct,
                                     double* g_theta0, double* g_ctrl);
+
+/* ---------------------------------------------------------------------------
+ * Serving pool: many episodes at once, as a simulation server runs them.
+ * A pool runs many episodes concurrently, each on a library handle and a HIP
+ * stream of its own, and interleaves their work unit by unit: sim_pool_tick
+ * enqueues the next unit (one step, one replayed step, one adjoint step, the
+ * loss, or one projection) of every active episode that may take one, so the
+ * episodes' kernels overlap on the device.  At most two units of an episode
+ * are in flight at once and, when inflight_cells > 0, the units in flight
+ * cover at most that many grid cells in total (one unit may always run): a
+ * bound on the concurrent working set.  Admission is by HBM footprint: every
+ * handle the pool holds (busy or idle), every live episode's buffer and the
+ * released buffers it keeps for reuse count against budget_bytes; an episode
+ * reuses a released buffer of up to twice its size and an idle handle of its
+ * descriptor, and room is made by freeing kept buffers, then idle handles
+ * (least recently used first).  The first episode on a grid runs its
+ * solves host-checked (each waits for its convergence state) and sets that
+ * grid's iteration budget, half as many again as its most iterations plus
+ * two, in whole batches of 8; later episodes run in the device solve mode
+ * with that budget (sim_set_solve_mode), their solver reports written on the
+ * device.  Adjoint episodes keep every step's pressure, replay their
+ * segments from them, and warm-start their adjoint solves
+ * (sim_set_warm_start).  A pool is not thread-safe; it uses the HIP device
+ * current at sim_pool_create.
+ * ------------------------------------------------------------------------- */
+typedef struct sim_pool* sim_pool_handle;
+
+typedef enum {
+  SIM_EP_FORWARD = 0,          /* steps forward steps: u_T                                 */
+  SIM_EP_FORWARD_ADJOINT = 1,  /* the same, then J = box loss of u_T (sim_loss_box) and the
+                                  adjoint: dJ/du_0, per-step dJ/dtheta and dJ/dctrl        */
+  SIM_EP_PROJECT = 2           /* one pressure projection of u_0 (sim_project): u_out      */
+} sim_episode_kind;
+
+typedef struct {
+  sim_desc desc;          /* grid, geometry and solver settings of the episode        */
+  int32_t kind;           /* sim_episode_kind                                         */
+  int32_t steps;          /* >= 1 (PROJECT: 1)                                        */
+  int32_t every;          /* velocity checkpoint stride of adjoint episodes (>= 1)    */
+  int32_t pad;
+  const double* theta;    /* host, steps x desc.n_params (copied at admission)        */
+  const double* ctrl;     /* host, steps x desc.n_ctrl (copied at admission)          */
+  double box_lo[3];       /* loss box of adjoint episodes (sim_loss_box)              */
+  double box_hi[3];
+} sim_episode;
+
+/* A pool of at most max_active concurrent episodes (1 .. 64) within
+ * budget_bytes of device memory.  SIM_EINVAL for bad arguments (checked
+ * before any HIP call), SIM_EHIP if a stream cannot be created. */
+int32_t sim_pool_create(size_t budget_bytes, int32_t max_active, int64_t inflight_cells, sim_pool_handle* out);
+/* Waits for every episode's work, then frees all handles and buffers. */
+int32_t sim_pool_destroy(sim_pool_handle pool);
+/* Admit an episode; u0 (device, the handle layout's velocity) is copied on
+ * the episode's stream, which does not wait for other streams: u0 must be
+ * complete when the call is made and unchanged until the slot's result has
+ * been collected.  Returns the slot in *slot.  SIM_EBUSY: no free slot,
+ * or its footprint does not fit the budget even after freeing idle handles
+ * (nothing was done; try again after sim_pool_result has released work).
+ * SIM_EINVAL: invalid episode (descriptor, kind, steps, every, NULL arrays
+ * that the geometry needs); SIM_ENOMEM / SIM_EHIP: allocation failures. */
+int32_t sim_pool_admit(sim_pool_handle pool, const sim_episode* ep, const float* u0, int32_t* slot);
+/* Enqueue the next unit of every active episode whose work is not all
+ * enqueued yet and which the in-flight bounds allow, starting from a
+ * different slot each call; *pending (nullable) = the number of such
+ * episodes left.  When no unit could be enqueued and units are in flight,
+ * waits for the oldest of them to complete (so a caller's loop does not
+ * spin).  Host-checked solves (an episode on a new grid) wait for their
+ * stream.  A negative status leaves that episode failed (its result reports
+ * it). */
+int32_t sim_pool_tick(sim_pool_handle pool, int32_t* pending);
+/* *done = 1 once all of the slot's work has completed on the device (an
+ * event query, no wait), else 0. */
+int32_t sim_pool_poll(sim_pool_handle pool, int32_t slot, int32_t* done);
+/* Wait for the slot's work, copy its results out and release the slot (its
+ * handle becomes idle).  Every output is nullable.  u_out (device): u_T, or
+ * the projected field.  g_u0 (device): dJ/du_0.  g_theta (device doubles,
+ * steps x n_params) and g_ctrl (steps x n_ctrl): per-step partials, as
+ * sim_step_adjoint accumulates them.  J (host): the loss.  worst (host): the
+ * episode's solves summarised: most iterations, converged only if all did,
+ * nonfinite if any did, the largest residuals.  Returns the status of the
+ * first failed unit, or a warning when a solve missed the tolerance. */
+int32_t sim_pool_result(sim_pool_handle pool, int32_t slot, float* u_out, float* g_u0, double* g_theta,
+                        double* g_ctrl, double* J, sim_stats* worst);
 
 #ifdef __cplusplus
 }

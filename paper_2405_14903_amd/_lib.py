@@ -16,6 +16,8 @@ SIM_WNOCONV, SIM_WNONFINITE = 1, 2
 SIM_SOLVE_HOST, SIM_SOLVE_DEVICE = 0, 1
 SIM_REGIONS_AUTO, SIM_REGIONS_ALWAYS, SIM_REGIONS_NEVER = 0, 1, 2
 SIM_WARM_PRESSURE, SIM_WARM_ADJOINT = 1, 2
+SIM_EBUSY = -5
+SIM_EP_FORWARD, SIM_EP_FORWARD_ADJOINT, SIM_EP_PROJECT = 0, 1, 2
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
 SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL, SIM_GEOM_BEZIER = 0, 1, 2, 3, 4
@@ -31,6 +33,7 @@ EXPORTS = [
     "sim_ellipsoid_poses", "sim_ellipsoid_poses_adjoint", "sim_loss_box", "sim_loss_outlet", "sim_profile",
     "sim_profile_read", "sim_set_solve_mode", "sim_set_regions", "sim_regions",
     "sim_loss_box_noalloc", "sim_set_dt", "sim_max_speed", "sim_set_warm_start",
+    "sim_pool_create", "sim_pool_destroy", "sim_pool_admit", "sim_pool_tick", "sim_pool_poll", "sim_pool_result",
 ]
 
 #: sim_kernel ids (include/neuralfluid.h)
@@ -72,6 +75,20 @@ class SimStats(C.Structure):
                 "rel_res": self.rel_res, "true_rel_res": self.true_rel_res}
 
 
+class SimEpisode(C.Structure):
+    _fields_ = [
+        ("desc", SimDesc),
+        ("kind", C.c_int32),
+        ("steps", C.c_int32),
+        ("every", C.c_int32),
+        ("pad", C.c_int32),
+        ("theta", C.POINTER(C.c_double)),
+        ("ctrl", C.POINTER(C.c_double)),
+        ("box_lo", C.c_double * 3),
+        ("box_hi", C.c_double * 3),
+    ]
+
+
 _lib = None
 
 _vp, _dp, _fp = C.c_void_p, C.POINTER(C.c_double), C.c_void_p
@@ -109,6 +126,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         "sim_set_regions": (C.c_int32, [_vp, C.c_int32]),
         "sim_set_dt": (C.c_int32, [_vp, C.c_double]),
         "sim_set_warm_start": (C.c_int32, [_vp, C.c_int32]),
+        "sim_pool_create": (C.c_int32, [C.c_size_t, C.c_int32, C.c_int64, C.POINTER(_vp)]),
+        "sim_pool_destroy": (C.c_int32, [_vp]),
+        "sim_pool_admit": (C.c_int32, [_vp, C.POINTER(SimEpisode), _fp, C.POINTER(C.c_int32)]),
+        "sim_pool_tick": (C.c_int32, [_vp, C.POINTER(C.c_int32)]),
+        "sim_pool_poll": (C.c_int32, [_vp, C.c_int32, C.POINTER(C.c_int32)]),
+        "sim_pool_result": (C.c_int32, [_vp, C.c_int32, _fp, _fp, _vp, _vp, _dp, C.POINTER(SimStats)]),
         "sim_max_speed": (C.c_int32, [_vp, _fp, C.POINTER(C.c_double), _vp]),
         "sim_loss_box_noalloc": (C.c_int32, [C.POINTER(C.c_int32), C.c_double, _fp, _dp, _dp, _vp, _fp, _vp]),
         "sim_regions": (C.c_int32, [_vp, _vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), _vp]),

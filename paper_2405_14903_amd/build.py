@@ -9,7 +9,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["nf_geom.hip", "nf_advect.hip", "nf_project.hip", "nf_solver.hip", "nf_components.hip", "nf_api.hip"]
+SOURCES = ["nf_geom.hip", "nf_advect.hip", "nf_project.hip", "nf_solver.hip", "nf_components.hip", "nf_api.hip",
+           "nf_pool.hip"]
 LIB = os.path.join(HERE, "libneuralfluid.so")
 
 FLAGS = [

@@ -318,6 +318,7 @@ const char* sim_status_string(int32_t s) {
     case SIM_ENOMEM: return "device allocation failed";
     case SIM_EHIP: return "HIP runtime error";
     case SIM_EUNSUPPORTED: return "unsupported configuration";
+    case SIM_EBUSY: return "no free slot or budget in the pool now";
     case SIM_WNOCONV: return "a Poisson solve did not reach the tolerance";
     case SIM_WNONFINITE: return "a Poisson solve met a non-finite value";
     default: return "unknown status";

@@ -520,6 +520,77 @@ def serve_serial(requests, precision="fp32", timing=True, on_done=None, realtime
     return summarize(requests, wall, [])
 
 
+def serve_pool(requests, budget_bytes, precision="fp16", max_active=8, realtime=True, warm_sizes=(),
+               on_done=None, every=8, inflight_cells=2 * 192 ** 3):
+    """The same request stream through the library's native pool
+    (:class:`paper_2405_14903_amd.pool.Pool`: admission by footprint, one
+    unit of every active episode per tick within the in-flight bounds,
+    device-mode solves after a grid's first episode).  Requests are admitted
+    no earlier than their arrival and in arrival order; one whose footprint
+    does not fit waits until a result has released capacity.  The pool
+    reports whole requests, so step latencies are not measured."""
+    from .pool import Pool
+    from .sim import ellipsoid_poses
+
+    def job(req):
+        theta0, ctrl = request_scene(req)
+        T = 1 if req.mode == "poisson" else req.steps
+        poses = ellipsoid_poses(theta0, ctrl[:T], 0.5 / req.n)
+        return dict(cfg=handle_config(req.n, precision), kind=req.mode, u0=device_curl_noise(req.n, req.seed),
+                    theta=np.asarray(poses)[:T], ctrl=ctrl[:T], steps=T, every=every)
+
+    pool = Pool(budget_bytes, max_active, inflight_cells)
+    try:
+        # each grid's first episode runs host-checked and sets its iteration
+        # budget: do that before the clock starts (the kernels load then too)
+        warm = [Request(-1 - i, 0.0, n, 2, "fwd+adj", 7) for i, n in enumerate(warm_sizes)]
+        if warm:
+            pool.run([job(r) for r in warm])
+        queue = sorted(requests, key=lambda r: r.arrival)
+        live = {}
+        head = None                  # the admission arguments of queue[0], built once
+        retry = True                 # the head may fit (a result released capacity since it last did not)
+        t0 = time.perf_counter()
+        while queue or live:
+            now = time.perf_counter() - t0
+            while queue and retry and (not realtime or queue[0].arrival <= now):
+                req = queue[0]
+                if head is None:
+                    head = job(req)
+                slot = pool.admit(**head)
+                if slot is None:
+                    if not live:
+                        req.error = "does not fit the pool's budget"
+                        queue.pop(0)
+                        head = None
+                        continue
+                    retry = False
+                    break
+                req.admitted = time.perf_counter() - t0
+                live[slot] = req
+                queue.pop(0)
+                head = None
+            if not live:
+                if queue and realtime:
+                    time.sleep(max(0.0, queue[0].arrival - (time.perf_counter() - t0)))
+                continue
+            pool.tick()
+            for slot in [q for q in live if pool.poll(q)]:
+                req = live.pop(slot)
+                r = pool.result(slot)
+                retry = True
+                req.finished = time.perf_counter() - t0
+                req.result = r
+                if r["status"] != 0:
+                    req.error = f"status {r['status']}: {r['worst']}"
+                if on_done:
+                    on_done(req)
+        wall = time.perf_counter() - t0
+    finally:
+        pool.close()
+    return summarize(requests, wall, [])
+
+
 def summarize(requests, wall, rejected):
     ok = [r for r in requests if not r.error]
     steps = [ms for r in ok for ms in r.step_ms]

@@ -72,6 +72,21 @@ def test_footprint_and_validation():
         assert sim_footprint(_cfg(n=n)) > 0
 
 
+def test_pool_arguments_are_checked_before_any_device_call():
+    lib = L.load()
+    h = C.c_void_p()
+    for budget, slots, cells in [(0, 1, 0), (1 << 30, 0, 0), (1 << 30, 65, 0), (1 << 30, 1, -1)]:
+        assert lib.sim_pool_create(budget, slots, cells, C.byref(h)) == L.SIM_EINVAL, (budget, slots, cells)
+    assert lib.sim_pool_create(1 << 30, 1, 0, None) == L.SIM_EINVAL
+    slot, n = C.c_int32(0), C.c_int32(0)
+    assert lib.sim_pool_destroy(None) == L.SIM_EINVAL
+    assert lib.sim_pool_admit(None, None, None, C.byref(slot)) == L.SIM_EINVAL
+    assert lib.sim_pool_tick(None, C.byref(n)) == L.SIM_EINVAL
+    assert lib.sim_pool_poll(None, 0, C.byref(n)) == L.SIM_EINVAL
+    assert lib.sim_pool_result(None, 0, None, None, None, None, None, None) == L.SIM_EINVAL
+    assert lib.sim_status_string(L.SIM_EBUSY).decode().startswith("no free slot")
+
+
 def test_null_handle_calls_are_rejected():
     lib = L.load()
     assert lib.sim_destroy(None) == L.SIM_EINVAL
