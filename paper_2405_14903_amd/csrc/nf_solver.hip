@@ -37,6 +37,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <type_traits>
 
 namespace nf {
 
@@ -835,6 +836,15 @@ struct alignas(16) Rec16 {
 template <typename A> struct RecOf { using T = Rec16; };
 template <typename A> constexpr bool kHasRecords = sizeof(A) == 2;
 
+// Minimum waves per SIMD of a tile kernel.  A 512-lane tile puts 2 waves on
+// each SIMD, so 7 waves per SIMD (65-72 VGPRs) hold 3 tiles per CU and 8
+// (at most 64 VGPRs) hold 4: the 1024 finest-level tiles of a 128^3 grid then
+// all fit the 256 CUs at once.  Asked only where the kernel fits 64 VGPRs
+// without spilling (the FP16 finest level: k_mg_up 21.1 -> 20.7 us at 128^3);
+// elsewhere the compiler's own choice stands.
+template <class S, typename A>
+constexpr int kTileWaves = (std::is_same<S, FineTile>::value && std::is_same<A, __half>::value) ? 8 : 1;
+
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename A> __device__ inline float dec_lo(unsigned w);
@@ -926,12 +936,15 @@ __device__ inline void cell_put(Rsrc v, unsigned ce, int kr, const Lev& L, float
 }
 
 // Body of k_mg_down for one tile; ZIN: the tile's +2 region lies inside the
-// domain along z (no plane checks).  PRE: issue the loads of all three phases
-// before the first one computes (one memory latency per launch instead of
-// three; for the small coarse levels, whose launches are latency-bound and few
-// tiles wide).  Without PRE each phase loads what it needs, which keeps
-// registers low for the finest level.
-template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool ZIN, bool REC>
+// domain along z (no plane checks).  PRE = 1: issue the loads of all three
+// phases before the first one computes (one memory latency per launch instead
+// of three; for the small coarse levels, whose launches are latency-bound and
+// few tiles wide); PRE = 2: those of the first two phases.  With PRE = 0 each
+// phase loads what it needs, which keeps registers low for the finest level
+// (at 128^3 the finest k_mg_up took 20.7 us with PRE = 0 and 8 waves per SIMD,
+// 21.5 us with PRE = 2 and 22.7 us with PRE = 1 at the occupancy their
+// registers allow).
+template <class S, typename A, typename R, typename Z, typename RC, int PRE, bool ZIN, bool REC>
 __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                              const A* invd, const R* r, Z* z2out, RC* rc, CGScalars* sc, int lvl0,
                                              const double* rr_parts, int nrr, long ncells, int i0, int j0, int k0,
@@ -1006,10 +1019,8 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
       rv1[u] = cell_at<R, W2::kUniform>(vr, on_plane<ZIN>(cr, m2, u), l2.z + u, L);
     }
   }
-  if (PRE) {
-    load2();
-    load3();
-  }
+  if (PRE != 0) load2();
+  if (PRE == 1) load3();
   float s0;
   if (nrr > 0) {
     // right after the CG update (the loads above are already in flight):
@@ -1028,7 +1039,7 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
     for (int u = 0; u < W2::T; ++u) z1s[l2.q + u * W2::PL] = kOmega * id1[u] * (s0 * rv1[u]);
   }
   __syncthreads();
-  if (!PRE) load2();
+  if (PRE == 0) load2();
   if (l1.on) {
     // the tile's own cells of the +1 walk are stored for the way up
     const bool own_xy = l1.x >= 2 && l1.x < S::TX + 2 && l1.y >= 2 && l1.y < S::TY + 2;
@@ -1047,7 +1058,7 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
     }
   }
   __syncthreads();
-  if (!PRE) load3();
+  if (PRE != 1) load3();
   if (l0.on) {
     // residual r - A z2 of the tile's cells (into the first sweep's array)
     const int q1 = (l0.x - 1) + W1::X * (l0.y - 1) + W1::PL * (l0.z - 1);
@@ -1080,8 +1091,8 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
 }
 
 // REC (finest level): the coefficients come from the packed records `rec`.
-template <class S, typename A, typename R, typename Z, typename RC, bool PRE, bool REC = false>
-__global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
+template <class S, typename A, typename R, typename Z, typename RC, int PRE, bool REC = false>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kTileWaves<S, A>))) void k_mg_down(Dims d, Dims cd, const A* __restrict__ ax,
                                                           const A* __restrict__ ay, const A* __restrict__ az,
                                                           const A* __restrict__ invd, const R* __restrict__ r,
                                                           Z* __restrict__ z2out, RC* __restrict__ rc,
@@ -1103,7 +1114,7 @@ __global__ __launch_bounds__(kTileThreads) void k_mg_down(Dims d, Dims cd, const
 }
 
 // Body of k_mg_up for one tile (ZIN, PRE as for mg_down_tile).
-template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool ZIN, bool REC>
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, int PRE, bool ZIN, bool REC>
 __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                            const A* invd, const R* r, const Z* z2, const E* e, O* zout, float s0,
                                            float inv, bool first, int i0, int j0, int k0, float* zp, float* z3s,
@@ -1177,16 +1188,14 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
       ev[u] = vld<E>(ve, a.v, a.s);
     }
   }
-  if (PRE) {
-    load2();
-    load3();
-  }
+  if (PRE != 0) load2();
+  if (PRE == 1) load3();
   if (l2.on) {
 #pragma unroll
     for (int u = 0; u < W2::T; ++u) zp[l2.q + u * W2::PL] = zv[u] + 8.0f * ev[u];
   }
   __syncthreads();
-  if (!PRE) load2();
+  if (PRE == 0) load2();
   if (l1.on) {
     const int q2 = l1.x + W2::X * l1.y + W2::PL * l1.z;
 #pragma unroll
@@ -1198,7 +1207,7 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
     }
   }
   __syncthreads();
-  if (!PRE) load3();
+  if (PRE != 1) load3();
   if (l0.on) {
     const int q1 = (l0.x - 1) + W1::X * (l0.y - 1) + W1::PL * (l0.z - 1);
     const unsigned co = lane_bytes(l0.in, l0.ce, eO);
@@ -1221,8 +1230,8 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
 }
 
 // REC (finest level): the coefficients come from the packed records `rec`.
-template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, bool PRE, bool REC = false>
-__global__ __launch_bounds__(kTileThreads) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
+template <class S, typename A, typename R, typename Z, typename E, typename O, bool LVL0, int PRE, bool REC = false>
+__global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kTileWaves<S, A>))) void k_mg_up(Dims d, Dims cd, const A* __restrict__ ax,
                                                         const A* __restrict__ ay, const A* __restrict__ az,
                                                         const A* __restrict__ invd, const R* __restrict__ r,
                                                         const Z* __restrict__ z2, const E* __restrict__ e,
@@ -1955,7 +1964,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
         bool done = false;
         if constexpr (kHasRecords<T>) {
           if (S.rec0) {
-            NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, false, true>),
+            NF_LAUNCH(S.prof, SIM_K_MG_DOWN, (k_mg_down<FineTile, T, float, float, T, 0, true>),
                       dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0,
                       (float*)S.lev[0].ta, rc, sc, 1, S.partials_rr, nrr, n0, (const void*)S.rec0);
             done = true;
@@ -1983,7 +1992,7 @@ static void vcycle(const Solver& S, const float* r0, float* z0, hipStream_t st, 
         bool done = false;
         if constexpr (kHasRecords<T>) {
           if (S.rec0) {
-            NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, false, true>),
+            NF_LAUNCH(S.prof, SIM_K_MG_UP, (k_mg_up<FineTile, T, float, float, T, float, true, 0, true>),
                       dim3(tiles_of<FineTile>(d)), dim3(kTileThreads), 0, st, d, cd, A(0), Ay(0), Az(0), ID(0), r0,
                       (const float*)S.lev[0].ta, e, z0, sc, merged ? S.partials_rz : S.partials, (const void*)S.rec0);
             done = true;
