@@ -1021,6 +1021,14 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   }
   if (PRE != 0) load2();
   if (PRE == 1) load3();
+  // with every load issued up front (the coarse levels) the solver's state is
+  // read beside them rather than before them; a launch after convergence
+  // still exits before it stores anything (the empty asm keeps the compiler
+  // from moving the loads below the check)
+  if (PRE == 1) {
+    asm volatile("" ::: "memory");
+    if (sc->done) return;
+  }
   float s0;
   if (nrr > 0) {
     // right after the CG update (the loads above are already in flight):
@@ -1102,7 +1110,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kT
   __shared__ float z1s[Walk<S, 2>::N];   // first sweep on the +2 region; then the tile's residual
   __shared__ float z2s[Walk<S, 1>::N];
   __shared__ double rr_sh;
-  if (sc->done) return;
+  if (PRE != 1 && sc->done) return;   // PRE == 1: checked after the loads
   int i0, j0, k0;
   tile_origin<S>(d, i0, j0, k0);
   if (planes_inside<S>(k0, d.nz))
@@ -1118,7 +1126,7 @@ template <class S, typename A, typename R, typename Z, typename E, typename O, b
 __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const A* ax, const A* ay, const A* az,
                                            const A* invd, const R* r, const Z* z2, const E* e, O* zout, float s0,
                                            float inv, bool first, int i0, int j0, int k0, float* zp, float* z3s,
-                                           double (&acc)[4], const void* rec) {
+                                           double (&acc)[4], const void* rec, const CGScalars* sc) {
   using W2 = Walk<S, 2>;
   using W1 = Walk<S, 1>;
   using W0 = Walk<S, 0>;
@@ -1190,6 +1198,10 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
   }
   if (PRE != 0) load2();
   if (PRE == 1) load3();
+  if (PRE == 1) {   // as in mg_down_tile
+    asm volatile("" ::: "memory");
+    if (sc->done) return;
+  }
   if (l2.on) {
 #pragma unroll
     for (int u = 0; u < W2::T; ++u) zp[l2.q + u * W2::PL] = zv[u] + 8.0f * ev[u];
@@ -1239,7 +1251,7 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kT
                                                         const void* rec = nullptr) {
   __shared__ float zp[Walk<S, 2>::N];
   __shared__ float z3s[Walk<S, 1>::N];
-  if (sc->done) return;
+  if (PRE != 1 && sc->done) return;   // PRE == 1: checked after the loads
   const float s0 = LVL0 ? (float)sc->vscale : 1.0f;
   const float inv = LVL0 ? (float)(1.0 / sc->vscale) : 1.0f;
   const bool first = sc->first;
@@ -1248,10 +1260,10 @@ __global__ __launch_bounds__(kTileThreads) __attribute__((amdgpu_waves_per_eu(kT
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   if (planes_inside<S>(k0, d.nz))
     mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, true, REC>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0, j0,
-                                                       k0, zp, z3s, acc, rec);
+                                                       k0, zp, z3s, acc, rec, sc);
   else
     mg_up_tile<S, A, R, Z, E, O, LVL0, PRE, false, REC>(d, cd, ax, ay, az, invd, r, z2, e, zout, s0, inv, first, i0,
-                                                        j0, k0, zp, z3s, acc, rec);
+                                                        j0, k0, zp, z3s, acc, rec, sc);
   if (LVL0) block_partials<4, kTileThreads>(acc, partials);
 }
 
@@ -1754,7 +1766,6 @@ __device__ inline const float* lane_coarsest(const Dims& d, const LaneCell<A>& q
 template <typename A, typename R, typename Z>
 __global__ __launch_bounds__(1024) void k_mg_bottom_lanes(Bottom<A> B, const R* __restrict__ rin,
                                                           Z* __restrict__ zout, const CGScalars* sc, int lvl0) {
-  if (sc->done) return;
   extern __shared__ float lds[];
   const int t = threadIdx.x, L = B.nl;
   const float s0 = level_scale(sc, lvl0);
@@ -1787,6 +1798,11 @@ __global__ __launch_bounds__(1024) void k_mg_bottom_lanes(Bottom<A> B, const R* 
     }
   }
   if (o[0].on) rv[0] = s0 * ld(rin, o[0].c);
+  // the solver's state is read beside the batch above, not before it; a
+  // launch after convergence still exits before it writes anything (the
+  // empty asm keeps the compiler from moving the loads below the check)
+  asm volatile("" ::: "memory");
+  if (sc->done) return;
 
   // down: kBottomSweeps sweeps from 0 on every level but the coarsest, then
   // the residual's mean over the 8 children into the parent, with the
