@@ -118,6 +118,51 @@ __device__ inline void corner_grad(const Corners& c, const Tap& t, double g[3]) 
   g[2] = (t.inside & 4) ? (1 - fy) * (hi - lo) + fy * (hi2 - lo2) : 0.0;
 }
 
+// The corners of the tap of component e != comp at the centre of a face of
+// component comp with coordinates idx.  There the back-trace's fractions are
+// fixed: 1/2 along comp between cell indices idx - 1 and idx (one index, with
+// weight 1, at the two ends of the axis, where the coordinate is clamped), 1/2
+// along e between face indices idx and idx + 1, and 0 along the third axis.
+// So the tap is the mean of the lattice values at flat indices p[0..n-1]
+// (n = 4, or 2 at the ends), and its adjoint adds 1/n of the incoming weight
+// to each: the weights of the trilinear formula at these fractions, exactly.
+// Returns n; with n = 2 the points are p[0], p[1] (p[2], p[3] repeat them).
+__device__ inline int face_centre_corners(const Dims& d, int e, int comp, const int idx[3], int p[4], int ix[4][3]) {
+  int m[3];
+  lattice(d, e, m);
+  int lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (a == comp) {
+      lo[a] = max(idx[a] - 1, 0);
+      hi[a] = min(idx[a], m[a] - 1);
+    } else if (a == e) {
+      lo[a] = idx[a];
+      hi[a] = idx[a] + 1;
+    } else {
+      lo[a] = hi[a] = idx[a];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    // q bit 0: e axis, bit 1: comp axis
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ix[q][a] = a == e ? ((q & 1) ? hi[a] : lo[a]) : (a == comp ? ((q & 2) ? hi[a] : lo[a]) : lo[a]);
+    p[q] = ix[q][0] + m[0] * (ix[q][1] + m[1] * ix[q][2]);
+  }
+  // (selects, not an index by the run-time comp: that would go through scratch)
+  const bool one = comp == 0 ? lo[0] == hi[0] : (comp == 1 ? lo[1] == hi[1] : lo[2] == hi[2]);
+  return one ? 2 : 4;
+}
+
+__device__ inline double face_centre_value(const Dims& d, const float* __restrict__ ue, int e, int comp,
+                                           const int idx[3]) {
+  int p[4], ix[4][3];
+  const int n = face_centre_corners(d, e, comp, idx, p, ix);
+  const double a = 0.5 * ((double)ue[p[0]] + (double)ue[p[1]]);
+  return n == 2 ? a : 0.5 * (a + 0.5 * ((double)ue[p[2]] + (double)ue[p[3]]));
+}
+
 __device__ inline void face_pos(int comp, int i, int j, int k, double X[3]) {
   X[0] = (double)i + (comp == 0 ? 0.0 : 0.5);
   X[1] = (double)j + (comp == 1 ? 0.0 : 0.5);
@@ -140,9 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_advect(Dims d, double cfl, float g0,
   face_pos(comp, i, j, k, Xf);
   // the face's own component at the face is the face's value: its lattice
   // coordinates are integers, so every fraction is 0 (or 1 on the last face,
-  // where the lerp returns the upper value exactly)
+  // where the lerp returns the upper value exactly); the others are the mean
+  // of 4 lattice values (face_centre_corners)
+  const int idx[3] = {i, j, k};
 #pragma unroll
-  for (int e = 0; e < 3; ++e) v0[e] = e == comp ? (double)u[f] : tap_value(uc[e], make_tap(d, e, Xf));
+  for (int e = 0; e < 3; ++e) v0[e] = e == comp ? (double)u[f] : face_centre_value(d, uc[e], e, comp, idx);
 #pragma unroll
   for (int a = 0; a < 3; ++a) Xm[a] = Xf[a] - 0.5 * cfl * v0[a];
 #pragma unroll
@@ -227,6 +274,37 @@ __device__ inline void scatter_w(const Window& W, float* __restrict__ g, int e, 
           __hip_atomic_fetch_add(g + t.base + bx + by * t.sx + bz * t.sxy, (float)ww, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
       }
+}
+
+// Add w to N lattice points of component e (flat indices p, lattice
+// coordinates ix): the same fixed-point window or float-atomic paths as
+// scatter_w, with its criterion (every point inside the window and the
+// scaled value within the fixed-point range, else every point goes to global
+// memory as float atomics).
+template <int N>
+__device__ inline void scatter_points(const Window& W, float* __restrict__ g, int e, const int p[4], const int ix[4][3],
+                                      double w) {
+  if (w == 0.0) return;
+  const double ws = w * W.scale;
+  bool inside = true;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int la = ix[q][0] - W.o[0], lb = ix[q][1] - W.o[1], lc = ix[q][2] - W.o[2];
+    inside = inside && la >= 0 && lb >= 0 && lc >= 0 && la < kWinX && lb < kWinY && lc < kWinZ;
+  }
+  if (inside && fabs(ws) <= W.limit) {
+    const long long v = fixed_round(ws);
+    if (v == 0) return;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int la = ix[q][0] - W.o[0], lb = ix[q][1] - W.o[1], lc = ix[q][2] - W.o[2];
+      atomicAdd(W.lds + e * kWin3 + la + kWinX * (lb + kWinY * lc), (unsigned long long)v);
+    }
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q)
+    __hip_atomic_fetch_add(g + p[q], (float)w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One workgroup per brick of kBX x kBY x kBZ cells; its threads walk the faces
@@ -350,8 +428,25 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
 #pragma unroll
       for (int a = 0; a < 3; ++a) gXm[a] += gv1 * ge[a];
     }
+    // the taps at the face centre (face_centre_corners): the face itself for
+    // its own component, a quarter of the weight on 4 lattice points for the
+    // others
+    const int idx[3] = {i, j, k};
 #pragma unroll
-    for (int e = 0; e < 3; ++e) scatter_w(W, gc[e], e, make_tap(d, e, Xf), -0.5 * cfl * gXm[e]);
+    for (int e = 0; e < 3; ++e) {
+      const double w = -0.5 * cfl * gXm[e];
+      if (e == comp) {
+        const int own[4][3] = {{i, j, k}, {i, j, k}, {i, j, k}, {i, j, k}};
+        const int p[4] = {(int)(f - (long)(gc[comp] - gin)), 0, 0, 0};
+        scatter_points<1>(W, gc[e], e, p, own, w);
+      } else {
+        int p[4], ix[4][3];
+        if (face_centre_corners(d, e, comp, idx, p, ix) == 2)
+          scatter_points<2>(W, gc[e], e, p, ix, 0.5 * w);
+        else
+          scatter_points<4>(W, gc[e], e, p, ix, 0.25 * w);
+      }
+    }
   }
   __syncthreads();
   // store the three windows of this brick (back from fixed point)
