@@ -1889,6 +1889,56 @@ __global__ void k_cast(long n, const float* __restrict__ src, T* __restrict__ ds
   if (i < n) dst[i] = cvt<T>(fminf(src[i], cap));
 }
 
+// One coarse level of the FP16 / BF16 hierarchy in one pass: the coarse
+// fractions (kCoarseAlphaScale times the sum of the 2 x 2 fine faces a coarse
+// face covers) in FP32, which the next level coarsens, and in the storage
+// type T (what k_cast would make of the FP32 values).
+template <typename T>
+__global__ void k_coarsen_store(Dims fd, Dims cd, const float* __restrict__ fax, const float* __restrict__ fay,
+                                const float* __restrict__ faz, float* __restrict__ cax, float* __restrict__ cay,
+                                float* __restrict__ caz, T* __restrict__ tax, T* __restrict__ tay,
+                                T* __restrict__ taz) {
+  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= (long)cd.faces()) return;
+  int comp, I, J, K;
+  face_decode(cd, f, comp, I, J, K);
+  const int i = 2 * I, j = 2 * J, k = 2 * K;
+  float s;
+  if (comp == 0) {
+    s = fax[fd.fx(i, j, k)] + fax[fd.fx(i, j + 1, k)] + fax[fd.fx(i, j, k + 1)] + fax[fd.fx(i, j + 1, k + 1)];
+    const float v = kCoarseAlphaScale * s;
+    cax[cd.fx(I, J, K)] = v;
+    tax[cd.fx(I, J, K)] = cvt<T>(fminf(v, 3e38f));
+  } else if (comp == 1) {
+    s = fay[fd.fy(i, j, k)] + fay[fd.fy(i + 1, j, k)] + fay[fd.fy(i, j, k + 1)] + fay[fd.fy(i + 1, j, k + 1)];
+    const float v = kCoarseAlphaScale * s;
+    cay[cd.fy(I, J, K)] = v;
+    tay[cd.fy(I, J, K)] = cvt<T>(fminf(v, 3e38f));
+  } else {
+    s = faz[fd.fz(i, j, k)] + faz[fd.fz(i + 1, j, k)] + faz[fd.fz(i, j + 1, k)] + faz[fd.fz(i + 1, j + 1, k)];
+    const float v = kCoarseAlphaScale * s;
+    caz[cd.fz(I, J, K)] = v;
+    taz[cd.fz(I, J, K)] = cvt<T>(fminf(v, 3e38f));
+  }
+}
+
+// 1 / diag of a level (1 / the sum of its cell's 6 FP32 fractions, 0 for an
+// inactive cell) capped at `cap`, straight into the storage type T.
+template <typename T>
+__global__ void k_invdiag_store(Dims d, const float* __restrict__ ax, const float* __restrict__ ay,
+                                const float* __restrict__ az, T* __restrict__ invd, float cap) {
+  const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (long)d.cells()) return;
+  const int i = (int)(c % d.nx);
+  const long t = c / d.nx;
+  const int j = (int)(t % d.ny);
+  const int k = (int)(t / d.ny);
+  const float s = ax[d.fx(i, j, k)] + ax[d.fx(i + 1, j, k)] + ay[d.fy(i, j, k)] + ay[d.fy(i, j + 1, k)] +
+                  az[d.fz(i, j, k)] + az[d.fz(i, j, k + 1)];
+  const float v = s > 0.0f ? 1.0f / s : 0.0f;
+  invd[c] = cvt<T>(fminf(v, cap));
+}
+
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 // ---------------------------------------------------------------------------
@@ -2139,31 +2189,32 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     // coarser levels store their iterates in FP16 and keep the tighter cap
     const float cap = S.precision != SIM_MIXED_FP16 ? 3e38f : (l == 0 ? kHalfMax : kHalfInvDiagMax);
     const Dims& d = S.lev[l].d;
-    const float *lx, *ly, *lz;
-    if (l == 0) {
-      lx = fx;
-      ly = fy;
-      lz = fz;
-    } else {
+    if (l > 0) {
+      // coarse levels: two launches, each storing its FP32 result and the
+      // copy in the storage type (instead of a cast launch per array)
       const Dims& fd = S.lev[l - 1].d;
       float* cx = S.scratch_a + S.scratch_off[l];
       float* cy = cx + d.nfx();
       float* cz = cy + d.nfy();
-      const float *px, *py, *pz;
-      if (l == 1) {
-        px = fx;
-        py = fy;
-        pz = fz;
+      const float* px = l == 1 ? fx : S.scratch_a + S.scratch_off[l - 1];
+      const float* py = l == 1 ? fy : px + fd.nfx();
+      const float* pz = l == 1 ? fz : py + fd.nfy();
+      const Level& L = S.lev[l];
+      if (S.precision == SIM_MIXED_FP16) {
+        hipLaunchKernelGGL(k_coarsen_store<__half>, dim3(nblocks(d.faces())), dim3(kBlock), 0, st, fd, d, px, py, pz,
+                           cx, cy, cz, (__half*)L.a[0], (__half*)L.a[1], (__half*)L.a[2]);
+        hipLaunchKernelGGL(k_invdiag_store<__half>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cx, cy, cz,
+                           (__half*)L.invd, cap);
       } else {
-        px = S.scratch_a + S.scratch_off[l - 1];
-        py = px + fd.nfx();
-        pz = py + fd.nfy();
+        hipLaunchKernelGGL(k_coarsen_store<__hip_bfloat16>, dim3(nblocks(d.faces())), dim3(kBlock), 0, st, fd, d, px,
+                           py, pz, cx, cy, cz, (__hip_bfloat16*)L.a[0], (__hip_bfloat16*)L.a[1],
+                           (__hip_bfloat16*)L.a[2]);
+        hipLaunchKernelGGL(k_invdiag_store<__hip_bfloat16>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cx, cy,
+                           cz, (__hip_bfloat16*)L.invd, cap);
       }
-      launch_coarsen_alpha(fd, d, px, py, pz, cx, cy, cz, st);
-      lx = cx;
-      ly = cy;
-      lz = cz;
+      continue;
     }
+    const float *lx = fx, *ly = fy, *lz = fz;
     // the fused V-cycle reads level 0's coefficients from the packed records
     // (below): its 2-byte arrays would go unread
     if (l == 0 && S.fused && S.rec0) continue;
