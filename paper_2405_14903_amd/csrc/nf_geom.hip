@@ -169,36 +169,6 @@ __global__ void k_invdiag(Dims d, const float* __restrict__ ax, const float* __r
   invd[c] = s > 0.0f ? 1.0f / s : 0.0f;
 }
 
-// Coarse face fractions: a coarse face covers 2 x 2 fine faces; its weight is
-// kCoarseAlphaScale times their sum (the piecewise-constant Galerkin operator
-// scaled by 1/2).
-__global__ void k_coarsen_alpha(Dims fd, Dims cd, const float* __restrict__ fax,
-                                const float* __restrict__ fay, const float* __restrict__ faz,
-                                float* __restrict__ cax, float* __restrict__ cay,
-                                float* __restrict__ caz) {
-  long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= (long)cd.faces()) return;
-  int comp, I, J, K;
-  face_decode(cd, f, comp, I, J, K);
-  float s;
-  if (comp == 0) {
-    int i = 2 * I, j = 2 * J, k = 2 * K;
-    s = fax[fd.fx(i, j, k)] + fax[fd.fx(i, j + 1, k)] + fax[fd.fx(i, j, k + 1)] +
-        fax[fd.fx(i, j + 1, k + 1)];
-    cax[cd.fx(I, J, K)] = kCoarseAlphaScale * s;
-  } else if (comp == 1) {
-    int i = 2 * I, j = 2 * J, k = 2 * K;
-    s = fay[fd.fy(i, j, k)] + fay[fd.fy(i + 1, j, k)] + fay[fd.fy(i, j, k + 1)] +
-        fay[fd.fy(i + 1, j, k + 1)];
-    cay[cd.fy(I, J, K)] = kCoarseAlphaScale * s;
-  } else {
-    int i = 2 * I, j = 2 * J, k = 2 * K;
-    s = faz[fd.fz(i, j, k)] + faz[fd.fz(i + 1, j, k)] + faz[fd.fz(i, j + 1, k)] +
-        faz[fd.fz(i + 1, j + 1, k)];
-    caz[cd.fz(I, J, K)] = kCoarseAlphaScale * s;
-  }
-}
-
 static inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 size_t solids_buffer_doubles() { return shape_buffer_doubles(); }
@@ -347,12 +317,6 @@ void launch_alpha(const Domain& D, const double* phi, float* alpha, hipStream_t 
 void launch_invdiag(const Dims& d, const float* ax, const float* ay, const float* az, float* invd,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_invdiag, dim3(nblocks(d.cells())), dim3(kBlock), 0, s, d, ax, ay, az, invd);
-}
-
-void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, const float* fay,
-                          const float* faz, float* cax, float* cay, float* caz, hipStream_t s) {
-  hipLaunchKernelGGL(k_coarsen_alpha, dim3(nblocks(cd.faces())), dim3(kBlock), 0, s, fd, cd, fax, fay,
-                     faz, cax, cay, caz);
 }
 
 }  // namespace nf

@@ -163,8 +163,6 @@ size_t solids_buffer_doubles();
 size_t solids_partials_doubles();
 void launch_alpha(const Domain& D, const double* phi, float* alpha, hipStream_t s);
 void launch_invdiag(const Dims& d, const float* ax, const float* ay, const float* az, float* invd, hipStream_t s);
-void launch_coarsen_alpha(const Dims& fd, const Dims& cd, const float* fax, const float* fay, const float* faz,
-                          float* cax, float* cay, float* caz, hipStream_t s);
 // nf_advect.hip
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
 void launch_copy(const float* src, float* dst, size_t n, hipStream_t s);

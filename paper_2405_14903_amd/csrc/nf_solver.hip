@@ -1889,52 +1889,59 @@ __global__ void k_cast(long n, const float* __restrict__ src, T* __restrict__ ds
   if (i < n) dst[i] = cvt<T>(fminf(src[i], cap));
 }
 
-// One coarse level of the FP16 / BF16 hierarchy in one pass: the coarse
-// fractions (kCoarseAlphaScale times the sum of the 2 x 2 fine faces a coarse
-// face covers) in FP32, which the next level coarsens, and in the storage
-// type T (what k_cast would make of the FP32 values).
+// One coarse level of the hierarchy in one launch, one thread per coarse
+// cell.  A coarse face is kCoarseAlphaScale times the sum of the 2 x 2 fine
+// faces it covers; the thread forms its cell's six (a face shared with a
+// neighbour gets the same bits from both threads: same arithmetic, same
+// order), stores the ones it owns (its lower faces, and the upper faces of
+// the domain's last cells) in FP32 (the next level coarsens them) and, when T
+// is a 2-byte type, in T as well, and stores 1 / diag (1 / the sum of the six,
+// 0 for an inactive cell, capped at `cap`) in T.  The same values, bit for
+// bit, as coarsening the faces in one launch and forming 1 / diag from the
+// stored faces in another.
 template <typename T>
-__global__ void k_coarsen_store(Dims fd, Dims cd, const float* __restrict__ fax, const float* __restrict__ fay,
-                                const float* __restrict__ faz, float* __restrict__ cax, float* __restrict__ cay,
-                                float* __restrict__ caz, T* __restrict__ tax, T* __restrict__ tay,
-                                T* __restrict__ taz) {
-  const long f = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= (long)cd.faces()) return;
-  int comp, I, J, K;
-  face_decode(cd, f, comp, I, J, K);
-  const int i = 2 * I, j = 2 * J, k = 2 * K;
-  float s;
-  if (comp == 0) {
-    s = fax[fd.fx(i, j, k)] + fax[fd.fx(i, j + 1, k)] + fax[fd.fx(i, j, k + 1)] + fax[fd.fx(i, j + 1, k + 1)];
-    const float v = kCoarseAlphaScale * s;
-    cax[cd.fx(I, J, K)] = v;
-    tax[cd.fx(I, J, K)] = cvt<T>(fminf(v, 3e38f));
-  } else if (comp == 1) {
-    s = fay[fd.fy(i, j, k)] + fay[fd.fy(i + 1, j, k)] + fay[fd.fy(i, j, k + 1)] + fay[fd.fy(i + 1, j, k + 1)];
-    const float v = kCoarseAlphaScale * s;
-    cay[cd.fy(I, J, K)] = v;
-    tay[cd.fy(I, J, K)] = cvt<T>(fminf(v, 3e38f));
-  } else {
-    s = faz[fd.fz(i, j, k)] + faz[fd.fz(i + 1, j, k)] + faz[fd.fz(i, j + 1, k)] + faz[fd.fz(i + 1, j + 1, k)];
-    const float v = kCoarseAlphaScale * s;
-    caz[cd.fz(I, J, K)] = v;
-    taz[cd.fz(I, J, K)] = cvt<T>(fminf(v, 3e38f));
-  }
+__device__ inline void store_face(float v, float* __restrict__ c32, T* __restrict__ cT, long f) {
+  c32[f] = v;
+  if constexpr (!std::is_same<T, float>::value) cT[f] = cvt<T>(fminf(v, 3e38f));
 }
 
-// 1 / diag of a level (1 / the sum of its cell's 6 FP32 fractions, 0 for an
-// inactive cell) capped at `cap`, straight into the storage type T.
 template <typename T>
-__global__ void k_invdiag_store(Dims d, const float* __restrict__ ax, const float* __restrict__ ay,
-                                const float* __restrict__ az, T* __restrict__ invd, float cap) {
+__global__ void k_coarse_level(Dims fd, Dims cd, const float* __restrict__ fax, const float* __restrict__ fay,
+                               const float* __restrict__ faz, float* __restrict__ cax, float* __restrict__ cay,
+                               float* __restrict__ caz, T* __restrict__ tax, T* __restrict__ tay, T* __restrict__ taz,
+                               T* __restrict__ invd, float cap) {
   const long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (long)d.cells()) return;
-  const int i = (int)(c % d.nx);
-  const long t = c / d.nx;
-  const int j = (int)(t % d.ny);
-  const int k = (int)(t / d.ny);
-  const float s = ax[d.fx(i, j, k)] + ax[d.fx(i + 1, j, k)] + ay[d.fy(i, j, k)] + ay[d.fy(i, j + 1, k)] +
-                  az[d.fz(i, j, k)] + az[d.fz(i, j, k + 1)];
+  if (c >= (long)cd.cells()) return;
+  const int I = (int)(c % cd.nx);
+  const long t = c / cd.nx;
+  const int J = (int)(t % cd.ny);
+  const int K = (int)(t / cd.ny);
+  // coarse faces of the three components at coarse face coordinates
+  auto fxv = [&](int a, int b, int e) {
+    const int i = 2 * a, j = 2 * b, k = 2 * e;
+    const float s = fax[fd.fx(i, j, k)] + fax[fd.fx(i, j + 1, k)] + fax[fd.fx(i, j, k + 1)] + fax[fd.fx(i, j + 1, k + 1)];
+    return kCoarseAlphaScale * s;
+  };
+  auto fyv = [&](int a, int b, int e) {
+    const int i = 2 * a, j = 2 * b, k = 2 * e;
+    const float s = fay[fd.fy(i, j, k)] + fay[fd.fy(i + 1, j, k)] + fay[fd.fy(i, j, k + 1)] + fay[fd.fy(i + 1, j, k + 1)];
+    return kCoarseAlphaScale * s;
+  };
+  auto fzv = [&](int a, int b, int e) {
+    const int i = 2 * a, j = 2 * b, k = 2 * e;
+    const float s = faz[fd.fz(i, j, k)] + faz[fd.fz(i + 1, j, k)] + faz[fd.fz(i, j + 1, k)] + faz[fd.fz(i + 1, j + 1, k)];
+    return kCoarseAlphaScale * s;
+  };
+  const float x0 = fxv(I, J, K), x1 = fxv(I + 1, J, K);
+  const float y0 = fyv(I, J, K), y1 = fyv(I, J + 1, K);
+  const float z0 = fzv(I, J, K), z1 = fzv(I, J, K + 1);
+  store_face<T>(x0, cax, tax, cd.fx(I, J, K));
+  if (I == cd.nx - 1) store_face<T>(x1, cax, tax, cd.fx(I + 1, J, K));
+  store_face<T>(y0, cay, tay, cd.fy(I, J, K));
+  if (J == cd.ny - 1) store_face<T>(y1, cay, tay, cd.fy(I, J + 1, K));
+  store_face<T>(z0, caz, taz, cd.fz(I, J, K));
+  if (K == cd.nz - 1) store_face<T>(z1, caz, taz, cd.fz(I, J, K + 1));
+  const float s = x0 + x1 + y0 + y1 + z0 + z1;
   const float v = s > 0.0f ? 1.0f / s : 0.0f;
   invd[c] = cvt<T>(fminf(v, cap));
 }
@@ -2175,11 +2182,12 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     for (int l = 1; l < S.nlev; ++l) {
       const Dims& fd = S.lev[l - 1].d;
       const Dims& cd = S.lev[l].d;
-      launch_coarsen_alpha(fd, cd, (const float*)S.lev[l - 1].a[0], (const float*)S.lev[l - 1].a[1],
-                           (const float*)S.lev[l - 1].a[2], (float*)S.lev[l].a[0], (float*)S.lev[l].a[1],
-                           (float*)S.lev[l].a[2], st);
-      launch_invdiag(cd, (const float*)S.lev[l].a[0], (const float*)S.lev[l].a[1], (const float*)S.lev[l].a[2],
-                     (float*)S.lev[l].invd, st);
+      float* cx = (float*)S.lev[l].a[0];
+      float* cy = (float*)S.lev[l].a[1];
+      float* cz = (float*)S.lev[l].a[2];
+      hipLaunchKernelGGL(k_coarse_level<float>, dim3(nblocks(cd.cells())), dim3(kBlock), 0, st, fd, cd,
+                         (const float*)S.lev[l - 1].a[0], (const float*)S.lev[l - 1].a[1],
+                         (const float*)S.lev[l - 1].a[2], cx, cy, cz, cx, cy, cz, (float*)S.lev[l].invd, 3e38f);
     }
     return;
   }
@@ -2190,8 +2198,8 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
     const float cap = S.precision != SIM_MIXED_FP16 ? 3e38f : (l == 0 ? kHalfMax : kHalfInvDiagMax);
     const Dims& d = S.lev[l].d;
     if (l > 0) {
-      // coarse levels: two launches, each storing its FP32 result and the
-      // copy in the storage type (instead of a cast launch per array)
+      // coarse levels: one launch storing the FP32 faces and the copies in
+      // the storage type (instead of coarsening, 1 / diag and a cast per array)
       const Dims& fd = S.lev[l - 1].d;
       float* cx = S.scratch_a + S.scratch_off[l];
       float* cy = cx + d.nfx();
@@ -2200,18 +2208,13 @@ void solver_setup_levels(Solver& S, const float* fine_alpha, hipStream_t st) {
       const float* py = l == 1 ? fy : px + fd.nfx();
       const float* pz = l == 1 ? fz : py + fd.nfy();
       const Level& L = S.lev[l];
-      if (S.precision == SIM_MIXED_FP16) {
-        hipLaunchKernelGGL(k_coarsen_store<__half>, dim3(nblocks(d.faces())), dim3(kBlock), 0, st, fd, d, px, py, pz,
-                           cx, cy, cz, (__half*)L.a[0], (__half*)L.a[1], (__half*)L.a[2]);
-        hipLaunchKernelGGL(k_invdiag_store<__half>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cx, cy, cz,
-                           (__half*)L.invd, cap);
-      } else {
-        hipLaunchKernelGGL(k_coarsen_store<__hip_bfloat16>, dim3(nblocks(d.faces())), dim3(kBlock), 0, st, fd, d, px,
+      if (S.precision == SIM_MIXED_FP16)
+        hipLaunchKernelGGL(k_coarse_level<__half>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, fd, d, px, py, pz,
+                           cx, cy, cz, (__half*)L.a[0], (__half*)L.a[1], (__half*)L.a[2], (__half*)L.invd, cap);
+      else
+        hipLaunchKernelGGL(k_coarse_level<__hip_bfloat16>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, fd, d, px,
                            py, pz, cx, cy, cz, (__hip_bfloat16*)L.a[0], (__hip_bfloat16*)L.a[1],
-                           (__hip_bfloat16*)L.a[2]);
-        hipLaunchKernelGGL(k_invdiag_store<__hip_bfloat16>, dim3(nblocks(d.cells())), dim3(kBlock), 0, st, d, cx, cy,
-                           cz, (__hip_bfloat16*)L.invd, cap);
-      }
+                           (__hip_bfloat16*)L.a[2], (__hip_bfloat16*)L.invd, cap);
       continue;
     }
     const float *lx = fx, *ly = fy, *lz = fz;
