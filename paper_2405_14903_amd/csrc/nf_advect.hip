@@ -233,6 +233,35 @@ constexpr int kHalo = 2;
 constexpr int kWinX = kBX + 1 + 2 * kHalo, kWinY = kBY + 1 + 2 * kHalo, kWinZ = kBZ + 1 + 2 * kHalo;
 constexpr int kWin3 = kWinX * kWinY * kWinZ;
 
+// q / e for 0 <= q < 2^12 and 1 <= e <= 2^7 from a float reciprocal:
+// (q + 1/2) / e lies at least 1 / (2e) >= 2^-8 from an integer, and the float
+// product is within 2^-22 q / e <= 2^-10 of it.
+__device__ inline int small_div(int q, float inv_e) { return (int)(((float)q + 0.5f) * inv_e); }
+
+// Face q of a brick (faces of component 0 first, then 1, then 2, x fastest):
+// its component and coordinates in the brick, from the components' first
+// indices s1, s2, their extents along x and y (e*0, e*1) and the reciprocals
+// of e*0 and e*0 * e*1 (selects rather than an index by the run-time
+// component).
+struct BrickFace {
+  int comp, li, lj, lk;
+};
+__device__ __forceinline__ BrickFace brick_face(int q, int s1, int s2, int ea0, int ea1, int eb0, int eb1, int ec0,
+                                                int ec1, float ra0, float ra01, float rb0, float rb01, float rc0,
+                                                float rc01) {
+  BrickFace b;
+  b.comp = q < s1 ? 0 : (q < s2 ? 1 : 2);
+  const bool c0 = b.comp == 0, c1 = b.comp == 1;
+  const int lq = q - (c0 ? 0 : (c1 ? s1 : s2));
+  const int e0 = c0 ? ea0 : (c1 ? eb0 : ec0);
+  const int e1 = c0 ? ea1 : (c1 ? eb1 : ec1);
+  const int q0 = small_div(lq, c0 ? ra0 : (c1 ? rb0 : rc0));
+  b.lk = small_div(lq, c0 ? ra01 : (c1 ? rb01 : rc01));
+  b.li = lq - q0 * e0;
+  b.lj = q0 - b.lk * e1;
+  return b;
+}
+
 // v rounded to the nearest integer (ties to even) as a 64-bit integer, for
 // |v| <= 2^51: adding 1.5 * 2^52 leaves the integer in the low mantissa bits.
 __device__ inline long long fixed_round(double v) {
@@ -361,11 +390,16 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
     total += ext[e][0] * ext[e][1] * ext[e][2];
   }
   start[3] = total;
+  // the brick's faces by index (brick_face)
+  const int s1 = start[1], s2 = start[2];
+  const int ea0 = ext[0][0], ea1 = ext[0][1], eb0 = ext[1][0], eb1 = ext[1][1], ec0 = ext[2][0], ec1 = ext[2][1];
+  const float ra0 = 1.0f / (float)ea0, ra01 = 1.0f / (float)(ea0 * ea1);
+  const float rb0 = 1.0f / (float)eb0, rb01 = 1.0f / (float)(eb0 * eb1);
+  const float rc0 = 1.0f / (float)ec0, rc01 = 1.0f / (float)(ec0 * ec1);
   float gm = 0.0f;
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int comp = q < start[1] ? 0 : (q < start[2] ? 1 : 2);
-    const int lq = q - start[comp];
-    const int li = lq % ext[comp][0], lj = (lq / ext[comp][0]) % ext[comp][1], lk = lq / (ext[comp][0] * ext[comp][1]);
+    const BrickFace bf = brick_face(q, s1, s2, ea0, ea1, eb0, eb1, ec0, ec1, ra0, ra01, rb0, rb01, rc0, rc01);
+    const int comp = bf.comp, li = bf.li, lj = bf.lj, lk = bf.lk;
     const long f = comp == 0 ? (long)d.fx(i0 + li, j0 + lj, k0 + lk)
                              : (comp == 1 ? (long)d.nfx() + d.fy(i0 + li, j0 + lj, k0 + lk)
                                           : (long)d.nfx() + d.nfy() + d.fz(i0 + li, j0 + lj, k0 + lk));
@@ -392,9 +426,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
     W.limit = 2251799813685248.0;                                                  // 2^51 (fixed_round's range)
   }
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int comp = q < start[1] ? 0 : (q < start[2] ? 1 : 2);
-    const int lq = q - start[comp];
-    const int li = lq % ext[comp][0], lj = (lq / ext[comp][0]) % ext[comp][1], lk = lq / (ext[comp][0] * ext[comp][1]);
+    const BrickFace bf = brick_face(q, s1, s2, ea0, ea1, eb0, eb1, ec0, ec1, ra0, ra01, rb0, rb01, rc0, rc01);
+    const int comp = bf.comp, li = bf.li, lj = bf.lj, lk = bf.lk;
     const int i = i0 + li, j = j0 + lj, k = k0 + lk;
     const long f = comp == 0 ? (long)d.fx(i, j, k)
                              : (comp == 1 ? (long)d.nfx() + d.fy(i, j, k) : (long)d.nfx() + d.nfy() + d.fz(i, j, k));

@@ -136,15 +136,18 @@ __global__ void k_x_store(Dims d, const float* __restrict__ ax, const float* __r
 
 // r = b - A x; partials of b.b (active cells), r.r, sum of r and the number
 // of active cells.
+// A bounded grid-stride grid keeps the partials few (k_fin_init totals them
+// in one block).
+constexpr int kInitBlocks = 1024;
 __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restrict__ ax,
                                                      const float* __restrict__ ay,
                                                      const float* __restrict__ az,
                                                      const float* __restrict__ b,
                                                      const double* __restrict__ x, float* __restrict__ r,
                                                      double* partials) {
-  long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
-  if (c < (long)d.cells()) {
+  const long n = (long)d.cells();
+  for (long c = (long)blockIdx.x * blockDim.x + threadIdx.x; c < n; c += (long)gridDim.x * blockDim.x) {
     int i, j, k;
     cdec(d, c, i, j, k);
     Faces<float> fw(d, ax, ay, az, i, j, k);
@@ -152,18 +155,16 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(Dims d, const float* __restr
     double bc = act ? (double)b[c] : 0.0;
     double rc = true_residual_at(d, ax, ay, az, b, x, i, j, k, c);
     r[c] = (float)rc;
-    v[0] = bc * bc;
-    v[1] = rc * rc;
-    v[2] = rc;
-    v[3] = act ? 1.0 : 0.0;
+    v[0] += bc * bc;
+    v[1] += rc * rc;
+    v[2] += rc;
+    v[3] += act ? 1.0 : 0.0;
   }
   block_partials<4>(v, partials);
 }
 
 // The same for a zero initial guess: r = b on active cells (1/diag > 0) and
-// x = 0, without the stencil; a bounded grid-stride grid keeps the partials
-// few (k_fin_init totals them in one block).
-constexpr int kInitBlocks = 1024;
+// x = 0, without the stencil.
 __global__ __launch_bounds__(kBlock) void k_cg_init_zero(long n, const float* __restrict__ invd,
                                                           const float* __restrict__ b, double* __restrict__ x,
                                                           float* __restrict__ r, double* partials) {
@@ -2430,10 +2431,10 @@ int solver_solve(Solver& S, SolveKind kind, const float* b, float* xio, double t
     hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, sc, tol, maxit, n, S.project);
   } else {
     hipLaunchKernelGGL(k_x_load, dim3(nblocks(n)), dim3(kBlock), 0, st, n, xio, x);
-    NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nblocks(n)), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x,
-              S.r, S.partials);
-    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, (int)nblocks(n), S.partials, sc, tol, maxit, n,
-                       S.project);
+    const int nb = (int)std::min<size_t>(nblocks(n), kInitBlocks);
+    NF_LAUNCH(S.prof, SIM_K_CG_INIT, k_cg_init, dim3(nb), dim3(kBlock), 0, st, d, S.ax, S.ay, S.az, b, x, S.r,
+              S.partials);
+    hipLaunchKernelGGL(k_fin_init, dim3(1), dim3(kFinBlock), 0, st, nb, S.partials, sc, tol, maxit, n, S.project);
   }
   if (S.comp.valid)
     components_project_start(S, st);
