@@ -368,16 +368,21 @@ __global__ __launch_bounds__(kAdjThreads) void k_advect_adjoint(Dims d, double c
   // leaves room for 2^12 adds per entry below 2^62.  A scatter whose value
   // still exceeds 2^51 (corners outside the window region) takes the float
   // path.
+  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) lds[q] = 0ull;
+  // largest |u| over the window region (coordinates clamped to the lattice),
+  // one x row of a component per thread
   float um = 0.0f;
-  for (int q = threadIdx.x; q < 3 * kWin3; q += blockDim.x) {
-    lds[q] = 0ull;
-    const int e = q / kWin3, r = q % kWin3;
-    int m[3];
-    lattice(d, e, m);
-    const int a = min(max(W.o[0] + r % kWinX, 0), m[0] - 1);
-    const int b = min(max(W.o[1] + (r / kWinX) % kWinY, 0), m[1] - 1);
-    const int c = min(max(W.o[2] + r / (kWinX * kWinY), 0), m[2] - 1);
-    um = fmaxf(um, fabsf(uc[e][a + m[0] * (b + m[1] * c)]));
+  for (int row = threadIdx.x; row < 3 * kWinY * kWinZ; row += blockDim.x) {
+    const int e = row / (kWinY * kWinZ), rr = row - e * (kWinY * kWinZ);
+    const int m0 = d.nx + (e == 0), m1 = d.ny + (e == 1), m2 = d.nz + (e == 2);
+    const int b = min(max(W.o[1] + rr % kWinY, 0), m1 - 1);
+    const int c = min(max(W.o[2] + rr / kWinY, 0), m2 - 1);
+    const float* base = e == 0 ? u : (e == 1 ? u + d.nfx() : u + d.nfx() + d.nfy());
+    const float* rowp = base + (size_t)m0 * ((size_t)b + (size_t)m1 * c);
+    // a fixed, unrolled row (clamped like the coordinates): its loads are
+    // independent and go out together
+#pragma unroll
+    for (int t = 0; t < kWinX; ++t) um = fmaxf(um, fabsf(rowp[min(max(W.o[0] + t, 0), m0 - 1)]));
   }
   // faces of the brick, per component: extents along each axis
   int ext[3][3];
