@@ -615,10 +615,13 @@ def run_serving(args, torch):
     rates = [float(r) for r in args.serve_rates.split(",")]
     leg = serving_leg(torch, args.serve_requests, rates, args.precision)
     first = leg["rates"][f"{rates[0]:g}"]
+    # the headline is the library's own serving pool (sim_pool_*); the Python
+    # scheduler and serial FP32 are reported beside it
     rec = {
-        "metric": "serving: cell-steps/s and p50/p99 step latency against serial FP32",
-        "value": round(first["served"]["cell_steps_per_s"], 1), "unit": "cell-steps/s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "ms_per_step": round(1e3 * first["served"]["wall_s"], 3), "higher_is_better": True,
+        "metric": "serving: cell-steps/s of the native pool (Python scheduler and serial FP32 beside it)",
+        "value": round(first["native_pool"]["cell_steps_per_s"], 1), "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * first["native_pool"]["wall_s"], 3),
+        "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": dtype_of(args.precision), "data": "synthetic",
         "config": {"workload": leg["workload"], "rates": rates, "precision": args.precision},
         "serving": leg, "roofline": None, "cpu_baseline": None,

@@ -415,7 +415,11 @@ int32_t sim_ellipsoid_poses_adjoint(const double* theta0, const double* ctrl, in
  * grid's iteration budget, half as many again as its most iterations plus
  * two, in whole batches of 8; later episodes run in the device solve mode
  * with that budget (sim_set_solve_mode), their solver reports written on the
- * device.  Adjoint episodes keep every step's pressure, replay their
+ * device.  A device-mode episode whose solve missed the tolerance reports
+ * SIM_WNOCONV and doubles its descriptor's budget (up to max_iter); a
+ * host-checked episode (the first one, or one admitted with
+ * SIM_EP_HOST_CHECKED) raises the budget to its own estimate if that is
+ * larger.  Adjoint episodes keep every step's pressure, replay their
  * segments from them, and warm-start their adjoint solves
  * (sim_set_warm_start).  A pool is not thread-safe; it uses the HIP device
  * current at sim_pool_create.
@@ -429,12 +433,17 @@ typedef enum {
   SIM_EP_PROJECT = 2           /* one pressure projection of u_0 (sim_project): u_out      */
 } sim_episode_kind;
 
+/* sim_episode.flags: run every solve host-checked (each waits for its
+ * convergence state), whatever budget the episode's descriptor has learned;
+ * for rerunning an episode whose device-mode solve missed the tolerance. */
+#define SIM_EP_HOST_CHECKED 1
+
 typedef struct {
   sim_desc desc;          /* grid, geometry and solver settings of the episode        */
   int32_t kind;           /* sim_episode_kind                                         */
   int32_t steps;          /* >= 1 (PROJECT: 1)                                        */
   int32_t every;          /* velocity checkpoint stride of adjoint episodes (>= 1)    */
-  int32_t pad;
+  int32_t flags;          /* 0 or SIM_EP_HOST_CHECKED                                 */
   const double* theta;    /* host, steps x desc.n_params (copied at admission)        */
   const double* ctrl;     /* host, steps x desc.n_ctrl (copied at admission)          */
   double box_lo[3];       /* loss box of adjoint episodes (sim_loss_box)              */
@@ -453,8 +462,9 @@ int32_t sim_pool_destroy(sim_pool_handle pool);
  * been collected.  Returns the slot in *slot.  SIM_EBUSY: no free slot,
  * or its footprint does not fit the budget even after freeing idle handles
  * (nothing was done; try again after sim_pool_result has released work).
- * SIM_EINVAL: invalid episode (descriptor, kind, steps, every, NULL arrays
- * that the geometry needs); SIM_ENOMEM / SIM_EHIP: allocation failures. */
+ * SIM_EINVAL: invalid episode (descriptor, kind, steps, every, flags, NULL
+ * arrays that the geometry needs); SIM_ENOMEM / SIM_EHIP: allocation
+ * failures. */
 int32_t sim_pool_admit(sim_pool_handle pool, const sim_episode* ep, const float* u0, int32_t* slot);
 /* Enqueue the next unit of every active episode whose work is not all
  * enqueued yet and which the in-flight bounds allow, starting from a

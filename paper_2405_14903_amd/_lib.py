@@ -18,6 +18,7 @@ SIM_REGIONS_AUTO, SIM_REGIONS_ALWAYS, SIM_REGIONS_NEVER = 0, 1, 2
 SIM_WARM_PRESSURE, SIM_WARM_ADJOINT = 1, 2
 SIM_EBUSY = -5
 SIM_EP_FORWARD, SIM_EP_FORWARD_ADJOINT, SIM_EP_PROJECT = 0, 1, 2
+SIM_EP_HOST_CHECKED = 1
 SIM_FP32, SIM_MIXED_FP16, SIM_MIXED_BF16 = 0, 1, 2
 SIM_BC_WALL, SIM_BC_INFLOW, SIM_BC_OUTFLOW, SIM_BC_PERIODIC = 0, 1, 2, 3
 SIM_GEOM_NONE, SIM_GEOM_SPHERES, SIM_GEOM_ELLIPSOID, SIM_GEOM_WALL, SIM_GEOM_BEZIER = 0, 1, 2, 3, 4
@@ -81,7 +82,7 @@ class SimEpisode(C.Structure):
         ("kind", C.c_int32),
         ("steps", C.c_int32),
         ("every", C.c_int32),
-        ("pad", C.c_int32),
+        ("flags", C.c_int32),
         ("theta", C.POINTER(C.c_double)),
         ("ctrl", C.POINTER(C.c_double)),
         ("box_lo", C.c_double * 3),

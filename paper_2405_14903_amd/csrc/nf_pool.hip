@@ -143,6 +143,12 @@ int learned_budget(const sim_pool* p, const sim_desc& d) {
   return 0;
 }
 
+BudgetEntry* budget_entry(sim_pool* p, const sim_desc& d) {
+  for (BudgetEntry& b : p->budgets)
+    if (same_desc(b.desc, d)) return &b;
+  return nullptr;
+}
+
 void free_handle(sim_pool* p, PoolHandle* ph) {
   (void)sim_destroy(ph->h);
   p->used -= ph->bytes;
@@ -310,10 +316,14 @@ void unit(sim_pool* p, int slot) {
   if (E.phase == kFinished && !E.enqueued) {
     if (hipEventRecord(p->done[slot], st) != hipSuccess && E.status >= 0) E.status = SIM_EHIP;
     E.enqueued = true;
-    // the first episode on a grid sets the grid's budget
-    if (E.host_checked && E.status >= 0 && E.most_iters > 0 && !learned_budget(p, E.ph->desc)) {
-      const int b = 8 * (int)std::ceil((1.5 * E.most_iters + 2.0) / 8.0);
-      p->budgets.push_back(BudgetEntry{E.ph->desc, std::min(b, E.ph->desc.max_iter)});
+    // a host-checked episode sets its descriptor's budget, or raises it
+    if (E.host_checked && E.status >= 0 && E.most_iters > 0) {
+      const int b = std::min(8 * (int)std::ceil((1.5 * E.most_iters + 2.0) / 8.0), E.ph->desc.max_iter);
+      BudgetEntry* be = budget_entry(p, E.ph->desc);
+      if (be)
+        be->budget = std::max(be->budget, b);
+      else
+        p->budgets.push_back(BudgetEntry{E.ph->desc, b});
     }
   }
 }
@@ -382,6 +392,7 @@ int32_t sim_pool_admit(sim_pool_handle p, const sim_episode* ep, const float* u0
   const int T = ep->kind == SIM_EP_PROJECT ? 1 : ep->steps;
   if (T < 1 || (ep->kind == SIM_EP_PROJECT && ep->steps != 1)) return SIM_EINVAL;
   if (ep->kind == SIM_EP_FORWARD_ADJOINT && ep->every < 1) return SIM_EINVAL;
+  if (ep->flags != 0 && ep->flags != SIM_EP_HOST_CHECKED) return SIM_EINVAL;
   if ((ep->desc.n_params > 0 && !ep->theta) || (ep->desc.n_ctrl > 0 && !ep->ctrl)) return SIM_EINVAL;
   size_t hb = 0;
   int v = sim_footprint(&ep->desc, &hb);
@@ -447,7 +458,7 @@ int32_t sim_pool_admit(sim_pool_handle p, const sim_episode* ep, const float* u0
     p->handles.push_back(ph);
     p->used += hb;
   }
-  const int budget = learned_budget(p, ep->desc);
+  const int budget = (ep->flags & SIM_EP_HOST_CHECKED) ? 0 : learned_budget(p, ep->desc);
   v = sim_set_solve_mode(ph->h, budget > 0 ? SIM_SOLVE_DEVICE : SIM_SOLVE_HOST, budget);
   if (v == SIM_OK) v = sim_set_warm_start(ph->h, 0);
   if (v != SIM_OK) {
@@ -606,9 +617,16 @@ int32_t sim_pool_result(sim_pool_handle p, int32_t slot, float* u_out, float* g_
     (void)hipGetLastError();
     if (E.status >= 0) E.status = SIM_EHIP;
   }
+  bool missed = false;
   for (const sim_stats& s : rep) {
     fold(E, s);
     if (E.status == SIM_OK && !(s.converged && !s.nonfinite)) E.status = s.nonfinite ? SIM_WNONFINITE : SIM_WNOCONV;
+    missed = missed || (!s.converged && !s.nonfinite);
+  }
+  if (missed) {
+    // the device-mode budget was too small for this descriptor: double it
+    BudgetEntry* be = budget_entry(p, E.ph->desc);
+    if (be) be->budget = std::min(2 * be->budget, E.ph->desc.max_iter);
   }
   if (J) *J = Jh;
   if (worst) *worst = E.worst;

@@ -47,7 +47,10 @@ class Pool:
         self.close()
 
     def admit(self, cfg: Config, kind: str, u0: torch.Tensor, theta=None, ctrl=None, steps: int = 1, every: int = 8,
-              box=((0.5, 0.5, 0.5), (1.0, 1.0, 1.0))):
+              box=((0.5, 0.5, 0.5), (1.0, 1.0, 1.0)), host_checked: bool = False):
+        """host_checked: every solve waits for its convergence state, whatever
+        budget the grid has learned (to rerun an episode whose device-mode
+        solve missed the tolerance; that also doubled the grid's budget)."""
         d = cfg.desc()
         T = 1 if kind == "poisson" else int(steps)
         ep = L.SimEpisode()
@@ -55,6 +58,7 @@ class Pool:
         ep.kind = _KIND[kind]
         ep.steps = T
         ep.every = int(every)
+        ep.flags = L.SIM_EP_HOST_CHECKED if host_checked else 0
         th, thp = _host_doubles(theta, T * d.n_params, "theta")
         ct, ctp = _host_doubles(ctrl, T * d.n_ctrl, "ctrl")
         ep.theta, ep.ctrl = thp, ctp

@@ -527,8 +527,12 @@ def serve_pool(requests, budget_bytes, precision="fp16", max_active=8, realtime=
     unit of every active episode per tick within the in-flight bounds,
     device-mode solves after a grid's first episode).  Requests are admitted
     no earlier than their arrival and in arrival order; one whose footprint
-    does not fit waits until a result has released capacity.  The pool
-    reports whole requests, so step latencies are not measured."""
+    does not fit waits until a result has released capacity.  A request
+    whose device-mode solve missed the tolerance (the pool then doubles its
+    grid's budget) is run again at once with host-checked solves, as the
+    Python scheduler does.  The pool reports whole requests, so step
+    latencies are not measured."""
+    from . import _lib as L
     from .pool import Pool
     from .sim import ellipsoid_poses
 
@@ -549,11 +553,25 @@ def serve_pool(requests, budget_bytes, precision="fp16", max_active=8, realtime=
         queue = sorted(requests, key=lambda r: r.arrival)
         live = {}
         head = None                  # the admission arguments of queue[0], built once
+        rerun = []                   # requests to run again host-checked, before the queue
         retry = True                 # the head may fit (a result released capacity since it last did not)
         t0 = time.perf_counter()
-        while queue or live:
+        while queue or live or rerun:
             now = time.perf_counter() - t0
-            while queue and retry and (not realtime or queue[0].arrival <= now):
+            while rerun and retry:
+                req = rerun[0]
+                slot = pool.admit(**job(req), host_checked=True)
+                if slot is None:
+                    if not live:
+                        req.error = "does not fit the pool's budget"
+                        req.finished = time.perf_counter() - t0
+                        rerun.pop(0)
+                        continue
+                    retry = False
+                    break
+                live[slot] = req
+                rerun.pop(0)
+            while queue and retry and not rerun and (not realtime or queue[0].arrival <= now):
                 req = queue[0]
                 if head is None:
                     head = job(req)
@@ -570,7 +588,7 @@ def serve_pool(requests, budget_bytes, precision="fp16", max_active=8, realtime=
                 live[slot] = req
                 queue.pop(0)
                 head = None
-            if not live:
+            if not live and not rerun:
                 if queue and realtime:
                     time.sleep(max(0.0, queue[0].arrival - (time.perf_counter() - t0)))
                 continue
@@ -579,6 +597,10 @@ def serve_pool(requests, budget_bytes, precision="fp16", max_active=8, realtime=
                 req = live.pop(slot)
                 r = pool.result(slot)
                 retry = True
+                if r["status"] == L.SIM_WNOCONV and not getattr(req, "retried", 0):
+                    req.retried = 1
+                    rerun.append(req)
+                    continue
                 req.finished = time.perf_counter() - t0
                 req.result = r
                 if r["status"] != 0:

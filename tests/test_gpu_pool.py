@@ -12,14 +12,17 @@
   and buffer are reused by the next episode on its grid, and idle handles
   make room for a new grid.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 import torch
 
 import scenes
+from paper_2405_14903_amd import _lib as L
 from paper_2405_14903_amd.pool import Pool
 from paper_2405_14903_amd.rollout import Rollout
-from paper_2405_14903_amd.sim import Config, Sim, ellipsoid_poses, sim_footprint
+from paper_2405_14903_amd.sim import Config, Sim, _host_doubles, ellipsoid_poses, sim_footprint
 from tests.gpu_common import announce, dev, host, rel_l2
 
 pytestmark = pytest.mark.gpu
@@ -132,3 +135,32 @@ def test_pool_admission_busy_reuse_and_eviction():
         while pool.tick():
             pass
         pool.result(s)
+
+
+def test_pool_host_checked_episode_and_flags():
+    announce("serving pool: an episode admitted host-checked equals the device-mode one; unknown flags rejected")
+    c32 = _cfg(32)
+    s32, p32, k32 = _episode(32, 7, 4)
+    job = dict(cfg=c32, kind="fwd", u0=dev(s32.u0), theta=p32, ctrl=k32, steps=4)
+    with Pool(budget_bytes=8 << 30, max_active=2) as pool:
+        first = pool.run([job])[0]                       # learns the budget (host-checked)
+        a = pool.admit(**job)                            # device mode
+        b = pool.admit(**job, host_checked=True)         # host-checked again
+        while pool.tick():
+            pass
+        ra, rb = pool.result(a), pool.result(b)
+        # flags other than SIM_EP_HOST_CHECKED are rejected before anything runs
+        d = c32.desc()
+        ep = L.SimEpisode()
+        ep.desc, ep.kind, ep.steps, ep.every, ep.flags = d, L.SIM_EP_FORWARD, 4, 1, 2
+        th, thp = _host_doubles(p32, 4 * d.n_params, "theta")
+        ct, ctp = _host_doubles(k32, 4 * d.n_ctrl, "ctrl")
+        ep.theta, ep.ctrl = thp, ctp
+        slot = C.c_int32(-1)
+        u0 = dev(s32.u0)
+        assert pool.lib.sim_pool_admit(pool.h, C.byref(ep), C.c_void_p(u0.data_ptr()), C.byref(slot)) == L.SIM_EINVAL
+    for r in (first, ra, rb):
+        assert r["status"] == 0, r["worst"]
+    ref = host(first["u"])
+    np.testing.assert_allclose(host(ra["u"]), ref, rtol=0, atol=1e-6 * float(np.abs(ref).max()))
+    np.testing.assert_allclose(host(rb["u"]), ref, rtol=0, atol=1e-6 * float(np.abs(ref).max()))
