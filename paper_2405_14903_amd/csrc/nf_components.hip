@@ -23,12 +23,7 @@ namespace {
 
 inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-__device__ inline void cell_of(const Dims& d, long c, int& i, int& j, int& k) {
-  i = (int)(c % d.nx);
-  const long t = c / d.nx;
-  j = (int)(t % d.ny);
-  k = (int)(t / d.ny);
-}
+__device__ inline void cell_of(const Dims& d, long c, int& i, int& j, int& k) { cell_coords(d, c, i, j, k); }
 
 __device__ inline bool cell_active(const Dims& d, const float* ax, const float* ay, const float* az, int i, int j,
                                    int k) {

@@ -52,11 +52,8 @@ __global__ void k_phi_nodes(Dims d, double dx, GeomParams G, double* __restrict_
   long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   long total = (long)d.nodes();
   if (n >= total) return;
-  int sx = d.nx + 1, sy = d.ny + 1;
-  int i = (int)(n % sx);
-  long t = n / sx;
-  int j = (int)(t % sy);
-  int k = (int)(t / sy);
+  int i, j, k;
+  node_coords(d, n, i, j, k);
   phi[n] = phi_at(G, i * dx, j * dx, k * dx);
 }
 
@@ -65,10 +62,8 @@ __global__ void k_phi_nodes(Dims d, double dx, GeomParams G, double* __restrict_
 __global__ __launch_bounds__(kBlock) void k_phi_solids(Dims d, double dx, GeomParams G, double* __restrict__ phi) {
   const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= (long)d.nodes()) return;
-  const int sx = d.nx + 1, sy = d.ny + 1;
-  const int i = (int)(n % sx);
-  const long t = n / sx;
-  const int j = (int)(t % sy), k = (int)(t / sy);
+  int i, j, k;
+  node_coords(d, n, i, j, k);
   unsigned char term;
   phi[n] = scene_phi_fast(G.solids, G.nsolid, G.solid_far, i * dx, j * dx, k * dx, term);
   G.solid_term[n] = term;
@@ -160,10 +155,8 @@ __global__ void k_invdiag(Dims d, const float* __restrict__ ax, const float* __r
                           const float* __restrict__ az, float* __restrict__ invd) {
   long c = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= (long)d.cells()) return;
-  int i = (int)(c % d.nx);
-  long t = c / d.nx;
-  int j = (int)(t % d.ny);
-  int k = (int)(t / d.ny);
+  int i, j, k;
+  cell_coords(d, c, i, j, k);
   float s = ax[d.fx(i, j, k)] + ax[d.fx(i + 1, j, k)] + ay[d.fy(i, j, k)] + ay[d.fy(i, j + 1, k)] +
             az[d.fz(i, j, k)] + az[d.fz(i, j, k + 1)];
   invd[c] = s > 0.0f ? 1.0f / s : 0.0f;

@@ -24,8 +24,26 @@ constexpr double kVcycleRms = 1.0 / 64.0;   // RMS of the (scaled) residual ente
 constexpr float kHalfInvDiagMax = 1024.0f;  // cap of 1/diag in FP16 storage
 constexpr float kHalfMax = 65504.0f;         // largest finite FP16 value
 
+// Division of any 32-bit n by a fixed d (1 <= d < 2^32) by multiplication:
+// with M = floor((2^64 - 1) / d) + 1 = ceil(2^64 / d), floor(n / d) is the
+// high 64 bits of M n (Lemire, Kaser and Kurz, Faster remainder by direct
+// computation, 2019: the error term is below n / 2^64 < 1 / d).  d = 1 has
+// no 64-bit M and is stored as 0.
+__host__ __device__ inline unsigned long long div_magic(int d) {
+  return d > 1 ? ~0ull / (unsigned long long)d + 1ull : 0ull;
+}
+__device__ inline unsigned div_fast(unsigned n, unsigned long long M) {
+  return M ? (unsigned)__umul64hi(M, (unsigned long long)n) : n;
+}
+
 struct Dims {
   int nx, ny, nz;
+  // division multipliers (div_magic) of nx, nx + 1, ny and ny + 1, for the
+  // cell, face and node decodes
+  unsigned long long mnx, mnx1, mny, mny1;
+  Dims() = default;
+  __host__ __device__ Dims(int x, int y, int z)
+      : nx(x), ny(y), nz(z), mnx(div_magic(x)), mnx1(div_magic(x + 1)), mny(div_magic(y)), mny1(div_magic(y + 1)) {}
   __host__ __device__ size_t cells() const { return (size_t)nx * ny * nz; }
   __host__ __device__ size_t nfx() const { return (size_t)(nx + 1) * ny * nz; }
   __host__ __device__ size_t nfy() const { return (size_t)nx * (ny + 1) * nz; }
@@ -226,25 +244,49 @@ __device__ inline double face_solid_velocity(const Domain& D, const GeomParams& 
 __device__ inline void face_decode(const Dims& d, long f, int& comp, int& i, int& j, int& k) {
   const unsigned nfx = (unsigned)d.nfx(), nfy = (unsigned)d.nfy();
   unsigned fu = (unsigned)f, sx, sy;
+  unsigned long long mx, my;
   if (fu < nfx) {
     comp = 0;
     sx = d.nx + 1;
     sy = d.ny;
+    mx = d.mnx1;
+    my = d.mny;
   } else if (fu < nfx + nfy) {
     comp = 1;
     fu -= nfx;
     sx = d.nx;
     sy = d.ny + 1;
+    mx = d.mnx;
+    my = d.mny1;
   } else {
     comp = 2;
     fu -= nfx + nfy;
     sx = d.nx;
     sy = d.ny;
+    mx = d.mnx;
+    my = d.mny;
   }
-  const unsigned t = fu / sx;
+  const unsigned t = div_fast(fu, mx);
   i = (int)(fu - t * sx);
-  k = (int)(t / sy);
+  k = (int)div_fast(t, my);
   j = (int)(t - (unsigned)k * sy);
+}
+
+// Cell index c (x fastest) into (i, j, k); node index n likewise on the
+// (nx + 1) x (ny + 1) node lattice.  32-bit, as face_decode.
+__device__ inline void cell_coords(const Dims& d, long c, int& i, int& j, int& k) {
+  const unsigned cu = (unsigned)c;
+  const unsigned t = div_fast(cu, d.mnx);
+  i = (int)(cu - t * (unsigned)d.nx);
+  k = (int)div_fast(t, d.mny);
+  j = (int)(t - (unsigned)k * (unsigned)d.ny);
+}
+__device__ inline void node_coords(const Dims& d, long n, int& i, int& j, int& k) {
+  const unsigned nu = (unsigned)n;
+  const unsigned t = div_fast(nu, d.mnx1);
+  i = (int)(nu - t * (unsigned)(d.nx + 1));
+  k = (int)div_fast(t, d.mny1);
+  j = (int)(t - (unsigned)k * (unsigned)(d.ny + 1));
 }
 
 __device__ inline double wave_sum(double v) {

@@ -27,12 +27,7 @@
 
 namespace nf {
 
-__device__ inline void cell_decode(const Dims& d, long c, int& i, int& j, int& k) {
-  i = (int)(c % d.nx);
-  long t = c / d.nx;
-  j = (int)(t % d.ny);
-  k = (int)(t / d.ny);
-}
+__device__ inline void cell_decode(const Dims& d, long c, int& i, int& j, int& k) { cell_coords(d, c, i, j, k); }
 
 // Flux alpha u + (1 - alpha) u_s through face f of component comp.
 __device__ inline double face_flux(const Domain& D, const GeomParams& G, const float* __restrict__ alpha,

@@ -52,13 +52,7 @@ template <> __device__ inline float cvt<float>(float v) { return v; }
 template <> __device__ inline __half cvt<__half>(float v) { return __float2half(v); }
 template <> __device__ inline __hip_bfloat16 cvt<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
 
-__device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) {
-  const unsigned cu = (unsigned)c, nx = (unsigned)d.nx, ny = (unsigned)d.ny;
-  const unsigned t = cu / nx;
-  i = (int)(cu - t * nx);
-  k = (int)(t / ny);
-  j = (int)(t - (unsigned)k * ny);
-}
+__device__ inline void cdec(const Dims& d, long c, int& i, int& j, int& k) { cell_coords(d, c, i, j, k); }
 
 // The 6 face weights of cell (i,j,k): lower / upper along x, y, z.
 template <typename A>
