@@ -556,11 +556,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_pre(Dims d, const A* __restrict__
   cdec(d, c, i, j, k);
   Faces<A> fw(d, ax, ay, az, i, j, k);
   float idc = ld(invd, c);
-  auto z1 = [&](long t) { return kOmega * ld(invd, t) * (s0 * ld(r, t)); };
+  auto z1 = [&](long t) { return kOmega1 * ld(invd, t) * (s0 * ld(r, t)); };
   float rc = s0 * ld(r, c);
-  float z1c = kOmega * idc * rc;
+  float z1c = kOmega1 * idc * rc;
   float Az = apply_A(d, fw, i, j, k, c, z1c, z1);
-  z2[c] = cvt<Z>(z1c + kOmega * idc * (rc - Az));
+  z2[c] = cvt<Z>(z1c + kOmega2 * idc * (rc - Az));
 }
 
 // r_coarse(I,J,K) = mean over the 8 children of (r - A z).
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post1(Dims d, Dims cd, const A* _
   Az += fw.w[3] * (zc - nb(j < d.ny - 1, c + d.nx, !(j & 1), pc + psy));
   Az += fw.w[4] * (zc - nb(k > 0, c - sxy, (k & 1), pc - psz));
   Az += fw.w[5] * (zc - nb(k < d.nz - 1, c + sxy, !(k & 1), pc + psz));
-  zout[c] = cvt<Z>(zc + kOmega * ld(invd, c) * (s0 * ld(r, c) - Az));
+  zout[c] = cvt<Z>(zc + kOmega1 * ld(invd, c) * (s0 * ld(r, c) - Az));
 }
 
 // z_out = z_in + w D^-1 (r - A z_in); at level 0 the output is scaled back to
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_post2(Dims d, const A* __restrict
     float rraw = ld(r, c);
     float Az = apply_A(d, fw, i, j, k, c, zc, zv);
     const float idc = ld(invd, c);
-    float zo = (zc + kOmega * idc * (s0 * rraw - Az)) * inv;
+    float zo = (zc + kOmega2 * idc * (s0 * rraw - Az)) * inv;
     if (LVL0 && !(idc > 0.0f)) zo = 0.0f;   // inactive cell: no unknown
     if (LVL0 && !first) v[1] = (double)rraw * (double)ld(zout, c);   // r_new . z_old
     zout[c] = cvt<O>(zo);
@@ -1039,7 +1039,7 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
   }
   if (l2.on) {
 #pragma unroll
-    for (int u = 0; u < W2::T; ++u) z1s[l2.q + u * W2::PL] = kOmega * id1[u] * (s0 * rv1[u]);
+    for (int u = 0; u < W2::T; ++u) z1s[l2.q + u * W2::PL] = kOmega1 * id1[u] * (s0 * rv1[u]);
   }
   __syncthreads();
   if (PRE == 0) load2();
@@ -1054,8 +1054,8 @@ __device__ __forceinline__ void mg_down_tile(const Dims& d, const Dims& cd, cons
       const int qq = q2 + u * W2::PL;
       const float rr = s0 * rv2[u];
       const float z2 =
-          REC ? rnd<Z>(z1s[qq] + kOmega * (id2[u] * rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)))
-              : rnd<Z>(z1s[qq] + kOmega * id2[u] * (rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)));
+          REC ? rnd<Z>(z1s[qq] + kOmega2 * (id2[u] * rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)))
+              : rnd<Z>(z1s[qq] + kOmega2 * id2[u] * (rr - apply_local(fw2[u], z1s, qq, W2::X, W2::PL)));
       cell_put<Z, W1::kUniform>(vz, (z >= 2 && z < S::TZ + 2) ? on_plane<ZIN>(oz, m1, u) : kNoCell, z, L, z2);
       z2s[l1.q + u * W1::PL] = z2;
     }
@@ -1210,7 +1210,7 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
       const int qq = q2 + u * W2::PL;
       const float Az = apply_local(fw2[u], zp, qq, W2::X, W2::PL);
       z3s[l1.q + u * W1::PL] =
-          REC ? zp[qq] + kOmega * (id2[u] * (s0 * rv2[u]) - Az) : zp[qq] + kOmega * id2[u] * (s0 * rv2[u] - Az);
+          REC ? zp[qq] + kOmega1 * (id2[u] * (s0 * rv2[u]) - Az) : zp[qq] + kOmega1 * id2[u] * (s0 * rv2[u] - Az);
     }
   }
   __syncthreads();
@@ -1222,8 +1222,8 @@ __device__ __forceinline__ void mg_up_tile(const Dims& d, const Dims& cd, const 
     for (int u = 0; u < W0::T; ++u) {
       const int qq = q1 + u * W1::PL;
       const float Az = apply_local(fw3[u], z3s, qq, W1::X, W1::PL);
-      float zo = (REC ? z3s[qq] + kOmega * (id3[u] * (s0 * rv3[u]) - Az)
-                      : z3s[qq] + kOmega * id3[u] * (s0 * rv3[u] - Az)) * inv;
+      float zo = (REC ? z3s[qq] + kOmega2 * (id3[u] * (s0 * rv3[u]) - Az)
+                      : z3s[qq] + kOmega2 * id3[u] * (s0 * rv3[u] - Az)) * inv;
       if (LVL0 && !(id3[u] > 0.0f)) zo = 0.0f;   // inactive cell (and every cell outside the domain): no unknown
       cell_put<O, W0::kUniform>(vzo, on_plane<ZIN>(co, m0, u), l0.z + u, L, zo);
       if (LVL0) {
