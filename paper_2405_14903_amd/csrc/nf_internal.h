@@ -24,8 +24,8 @@ constexpr float kOmega = 6.0f / 7.0f;   // damped-Jacobi weight: the smoothing o
 // represent.  Two such sweeps shrink it by at most 1 / T_2(7/5) = 0.34,
 // against 0.51 for two sweeps with kOmega; the sweeps commute, so the
 // V-cycle stays symmetric, and |1 - w1 l| |1 - w2 l| < 1 on (0, 2].
-constexpr float kOmega1 = 0.569500f;   // 1 / (7/6 + (5/6) cos(pi/4))
-constexpr float kOmega2 = 1.731970f;   // 1 / (7/6 - (5/6) cos(pi/4))
+constexpr float kOmega1 = 0.569501f;   // 1 / (7/6 + (5/6) cos(pi/4))
+constexpr float kOmega2 = 1.731869f;   // 1 / (7/6 - (5/6) cos(pi/4))
 constexpr int kCoarseSweepsMax = 40;   // coarsest level: min(40, 2 * (largest extent)^2) sweeps
 constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces
 constexpr double kVcycleRms = 1.0 / 64.0;   // RMS of the (scaled) residual entering the V-cycle

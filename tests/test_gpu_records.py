@@ -3,9 +3,9 @@ records against the same kernels reading the separate 2-byte fraction and
 1/diag arrays (NF_MG_RECORDS=0).  The records hold the face weights
 alpha_f / diag in 2 bytes and 1/diag in FP32, so the two preconditioners differ
 by rounding (and where the arrays cap 1/diag): both solves must converge, the
-FP16 records with no more CG iterations, and steps and the adjoint must agree to
-the solver tolerance (BF16, which needs no cap: within one iteration over the
-three solves).  Grids with ragged tiles along every axis, both 2-byte
+records within one CG iteration of the arrays over three solves (the cap's
+cost was far larger), and steps and the adjoint must agree to the solver
+tolerance.  Grids with ragged tiles along every axis, both 2-byte
 storage types (FP32 storage keeps the arrays)."""
 import os
 
@@ -52,11 +52,12 @@ def test_records_match_arrays(n3, precision):
     ref, gref, it_ref = _run(n3, precision, False)
     got, g, it = _run(n3, precision, True)
     announce(f"  CG iterations arrays {it_ref} records {it}")
-    # FP16: the arrays cap 1/diag (FP16 range) and the records do not, so the
-    # records take no more iterations; BF16 has the range, the two differ only
-    # by rounding, and the smoother's weights (one above 1) turn that into an
-    # iteration either way over the three solves
-    assert sum(it) <= sum(it_ref) + (1 if precision == "bf16" else 0)
+    # the arrays cap 1/diag in FP16 and the records do not: that cap once cost
+    # 10-13% more iterations over a rollout.  Otherwise the two differ only by
+    # the rounding of the smoother's coefficients, which the smoother's
+    # weights (one above 1) turn into an iteration either way over the three
+    # solves
+    assert sum(it) <= sum(it_ref) + 1
     for a, b in zip(ref, got):
         assert torch.isfinite(b).all()
         e = float((b.double() - a.double()).norm() / a.double().norm())
