@@ -19,13 +19,15 @@ constexpr int kPreSweeps = 2;        // damped-Jacobi sweeps before / after coar
 constexpr int kBottomSweeps = 4;     // the same on the levels of the one-workgroup bottom solve (even)
 constexpr float kOmega = 6.0f / 7.0f;   // damped-Jacobi weight: the smoothing optimum for the 7-point stencil in 3D
 // The two sweeps per side of the grid levels use two weights instead: the
-// reciprocals of the roots of the degree-2 Chebyshev polynomial on [1/3, 2],
-// the part of the spectrum of D^-1 A that a grid twice as coarse cannot
-// represent.  Two such sweeps shrink it by at most 1 / T_2(7/5) = 0.34,
-// against 0.51 for two sweeps with kOmega; the sweeps commute, so the
+// reciprocals of the roots of the degree-2 Chebyshev polynomial on [2/5, 2].
+// The eigenvalues of D^-1 A lie in (0, 2]; the modes a grid twice as coarse
+// cannot represent have them in [1/3, 2], and of the intervals [a, 2] tried
+// (a = 1/6, 1/4, 1/3, 2/5, 1/2) a = 2/5 took the fewest CG iterations.  Two
+// such sweeps shrink [2/5, 2] by at most 1 / T_2(3/2) = 0.29 and [1/3, 2] by
+// 0.39, against 0.51 for two sweeps with kOmega; the sweeps commute, so the
 // V-cycle stays symmetric, and |1 - w1 l| |1 - w2 l| < 1 on (0, 2].
-constexpr float kOmega1 = 0.569501f;   // 1 / (7/6 + (5/6) cos(pi/4))
-constexpr float kOmega2 = 1.731869f;   // 1 / (7/6 - (5/6) cos(pi/4))
+constexpr float kOmega1 = 0.566352f;   // 1 / (6/5 + (4/5) cos(pi/4))
+constexpr float kOmega2 = 1.576505f;   // 1 / (6/5 - (4/5) cos(pi/4))
 constexpr int kCoarseSweepsMax = 40;   // coarsest level: min(40, 2 * (largest extent)^2) sweeps
 constexpr float kCoarseAlphaScale = 0.5f;   // coarse face = 0.5 * sum of the 4 fine faces
 constexpr double kVcycleRms = 1.0 / 64.0;   // RMS of the (scaled) residual entering the V-cycle
